@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for the Update & Fuse step and the LDM composite.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the library.  The arithmetic lives
+in ``quark_oracle.c`` (plain double-precision loops, one function per step of
+the method); this module builds it with gcc, loads it with ctypes and
+marshals NumPy arrays in and out.  It shares no code with the GPU library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "quark_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE double)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fvisibility=hidden",
+               "-fno-fast-math", "-ffp-contract=off", "-std=c11", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or \
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        L.or_reprojection_matrix.restype = ctypes.c_int
+        L.or_reproject.restype = ctypes.c_int
+        L.or_reproject_T.restype = ctypes.c_int
+        L.or_update_fuse.restype = ctypes.c_int
+        L.or_num_threads.restype = ctypes.c_int
+        for name in ("or_reprojection_matrix", "or_reproject", "or_reproject_T"):
+            pass
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Step-level entry points (each maps to one C function)
+# --------------------------------------------------------------------------
+
+def scale_intrinsics(K, w0, h0, w1, h1) -> np.ndarray:
+    K = _f64(K)
+    out = np.zeros(9)
+    lib().or_scale_intrinsics(_d(K), int(w0), int(h0), int(w1), int(h1), _d(out))
+    return out.reshape(3, 3)
+
+
+def reprojection_matrix(Kn, En, Km, Em) -> np.ndarray:
+    Kn, En, Km, Em = map(_f64, (Kn, En, Km, Em))
+    T = np.zeros(16)
+    rc = lib().or_reprojection_matrix(_d(Kn), _d(En), _d(Km), _d(Em), _d(T))
+    if rc != 0:
+        raise ValueError("singular camera matrix")
+    return T.reshape(4, 4)
+
+
+def reproject(Kn, En, Km, Em, u, v, d):
+    """Returns ((u_m, v_m), valid)."""
+    Kn, En, Km, Em = map(_f64, (Kn, En, Km, Em))
+    out = np.zeros(2)
+    rc = lib().or_reproject(_d(Kn), _d(En), _d(Km), _d(Em), ctypes.c_double(u),
+                            ctypes.c_double(v), ctypes.c_double(d), _d(out))
+    if rc < 0:
+        raise ValueError("singular camera matrix")
+    return (float(out[0]), float(out[1])), bool(rc == 1)
+
+
+def bilinear(I, u, v) -> np.ndarray:
+    I = _f64(I)
+    Hf, Wf, C = I.shape
+    s = np.zeros(C)
+    lib().or_bilinear(_d(I), Hf, Wf, C, ctypes.c_double(u), ctypes.c_double(v), _d(s))
+    return s
+
+
+def rmsnorm(x) -> np.ndarray:
+    x = _f64(x)
+    y = np.zeros_like(x)
+    lib().or_rmsnorm(_d(x), x.shape[0], _d(y))
+    return y
+
+
+def attention(F, S, heads, dh, Wq, Wk, Wv, Wo, folded: bool = False):
+    """One layer-pixel: returns (F', p[heads][V]) (p is None when folded)."""
+    F, S, Wq, Wk, Wv, Wo = map(_f64, (F, S, Wq, Wk, Wv, Wo))
+    C = F.shape[0]
+    V, Cf = S.shape
+    out = np.zeros(C)
+    if folded:
+        lib().or_attention_folded(_d(F), C, _d(S), V, Cf, heads, dh, _d(Wq), _d(Wk), _d(Wv),
+                                  _d(Wo), _d(out))
+        return out, None
+    p = np.zeros((heads, V))
+    lib().or_attention(_d(F), C, _d(S), V, Cf, heads, dh, _d(Wq), _d(Wk), _d(Wv), _d(Wo),
+                       _d(out), _d(p))
+    return out, p
+
+
+def decode(Fp, w_sigma, w_depth, W_color, alpha, depth, li, L, near, far, mode=0):
+    """Returns (alpha', depth', color'[3])."""
+    Fp, w_sigma, w_depth, W_color = map(_f64, (Fp, w_sigma, w_depth, W_color))
+    a = ctypes.c_double()
+    d = ctypes.c_double()
+    c = np.zeros(3)
+    lib().or_decode(_d(Fp), Fp.shape[0], _d(w_sigma), _d(w_depth), _d(W_color),
+                    ctypes.c_double(alpha), ctypes.c_double(depth), int(li), int(L),
+                    ctypes.c_double(near), ctypes.c_double(far), int(mode), ctypes.byref(a),
+                    ctypes.byref(d), _d(c))
+    return a.value, d.value, c
+
+
+def composite(color, alpha, back_to_front: bool = False):
+    """color [L][...][3], alpha [L][...] -> (rgb [...][3], acc [...])."""
+    color = _f64(color)
+    alpha = _f64(alpha)
+    L = alpha.shape[0]
+    pix_shape = alpha.shape[1:]
+    npix = int(np.prod(pix_shape)) if pix_shape else 1
+    rgb = np.zeros((npix, 3))
+    acc = np.zeros(npix)
+    if back_to_front:
+        lib().or_composite_back_to_front(L, ctypes.c_long(npix), _d(color), _d(alpha), _d(rgb))
+        return rgb.reshape(pix_shape + (3,)), None
+    lib().or_composite(L, ctypes.c_long(npix), _d(color), _d(alpha), _d(rgb), _d(acc))
+    return rgb.reshape(pix_shape + (3,)), acc.reshape(pix_shape)
+
+
+# --------------------------------------------------------------------------
+# Whole step over a scene level
+# --------------------------------------------------------------------------
+
+def _as_f64_array(a: np.ndarray) -> np.ndarray:
+    if a.dtype == np.uint16:          # bfloat16 bit patterns -> exact values
+        return (a.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def update_fuse(in_cams, novel, near, far, level, *, F=None, depth=None, alpha=None,
+                rows: Optional[Sequence[int]] = None, mode: int = 0, attn_form: int = 0,
+                want_samples: bool = False, feats64: Optional[List[np.ndarray]] = None
+                ) -> Dict[str, np.ndarray]:
+    """One Update & Fuse step of ``level`` (a ``synth.Level``) on the given
+    rows (default: all).  ``F``/``depth``/``alpha`` override the level's state
+    (full-size arrays, used for multi-step runs)."""
+    V = len(in_cams)
+    L, H, W, C, Cf = level.L, level.H, level.W, level.C, level.Cf
+    rows = np.arange(H, dtype=np.int32) if rows is None else np.asarray(rows, dtype=np.int32)
+    R = int(rows.shape[0])
+    Kin = _f64(np.stack([c.K for c in in_cams]))
+    Ein = _f64(np.stack([c.E for c in in_cams]))
+    cam_wh = np.ascontiguousarray([[c.width, c.height] for c in in_cams], dtype=np.int32)
+    if feats64 is None:
+        feats64 = [_as_f64_array(f) for f in level.feats]
+    feat_hw = np.ascontiguousarray([[f.shape[0], f.shape[1]] for f in feats64], dtype=np.int32)
+    fptrs = (_dp * V)(*[_d(f) for f in feats64])
+    F64 = _as_f64_array(level.F if F is None else F)
+    d64 = _as_f64_array(level.depth if depth is None else depth)
+    a64 = _as_f64_array(level.alpha if alpha is None else alpha)
+    w = {k: _f64(v) for k, v in level.weights.items()}
+    nov_wh = np.array([novel.width, novel.height], dtype=np.int32)
+    Kn, En = _f64(novel.K), _f64(novel.E)
+    F_out = np.zeros((L, R, W, C))
+    d_out = np.zeros((L, R, W))
+    a_out = np.zeros((L, R, W))
+    c_out = np.zeros((L, R, W, 3))
+    s_out = np.zeros((L, R, W, V, Cf)) if want_samples else None
+    rc = lib().or_update_fuse(
+        V, _d(Kin), _d(Ein), cam_wh.ctypes.data_as(_ip), fptrs, feat_hw.ctypes.data_as(_ip), Cf,
+        _d(Kn), _d(En), nov_wh.ctypes.data_as(_ip), ctypes.c_double(near), ctypes.c_double(far),
+        L, H, W, C, _d(F64), _d(d64), _d(a64), level.heads, level.head_dim,
+        _d(w["Wq"]), _d(w["Wk"]), _d(w["Wv"]), _d(w["Wo"]), _d(w["w_sigma"]), _d(w["w_depth"]),
+        _d(w["W_color"]), int(mode), int(attn_form), rows.ctypes.data_as(_ip), R,
+        _d(F_out), _d(d_out), _d(a_out), _d(c_out),
+        _d(s_out) if s_out is not None else ctypes.cast(None, _dp))
+    if rc != 0:
+        raise ValueError("oracle update_fuse failed (singular camera?)")
+    out = {"F": F_out, "depth": d_out, "alpha": a_out, "color": c_out, "rows": rows}
+    if s_out is not None:
+        out["samples"] = s_out
+    return out
+
+
+def run_level(scene, level, *, steps: Optional[int] = None, rows=None, mode: int = 0,
+              attn_form: int = 0, composite_out: Optional[bool] = None):
+    """``steps`` Update & Fuse steps of one level on the given rows, then (if
+    requested) the composite of the last step.  Multi-step runs feed
+    (F', depth', alpha') back in; layer-pixels are independent, so sampled rows
+    are exact."""
+    steps = scene.steps if steps is None else steps
+    composite_out = level.composite if composite_out is None else composite_out
+    feats64 = [_as_f64_array(f) for f in level.feats]
+    H = level.H
+    rows_arr = np.arange(H, dtype=np.int32) if rows is None else np.asarray(rows, dtype=np.int32)
+    F = _as_f64_array(level.F)
+    d = _as_f64_array(level.depth)
+    a = _as_f64_array(level.alpha)
+    out = None
+    for s in range(steps):
+        out = update_fuse(scene.in_cams, scene.novel, scene.near, scene.far, level, F=F,
+                          depth=d, alpha=a, rows=rows_arr, mode=mode, attn_form=attn_form,
+                          feats64=feats64)
+        if s + 1 < steps:
+            # write the sampled rows back into full-size state for the next step
+            F = F.copy(); d = d.copy(); a = a.copy()
+            F[:, rows_arr] = out["F"]
+            d[:, rows_arr] = out["depth"]
+            a[:, rows_arr] = out["alpha"]
+    if composite_out:
+        rgb, acc = composite(out["color"], out["alpha"])
+        out["rgb"] = rgb
+        out["acc"] = acc
+    return out
+
+
+def run_scene(scene, *, rows_per_level=None, mode: int = 0, attn_form: int = 0):
+    """All levels of a scene.  ``rows_per_level`` is a list (one entry per
+    level, None = all rows)."""
+    res = []
+    for i, lvl in enumerate(scene.levels):
+        rows = None if rows_per_level is None else rows_per_level[i]
+        res.append(run_level(scene, lvl, rows=rows, mode=mode, attn_form=attn_form))
+    return res

@@ -1,0 +1,501 @@
+/*
+ * quark_oracle.c -- plain FP64 CPU reference ("oracle") for one Update & Fuse
+ * step of a layered depth map (LDM) and its front-to-back composite, after
+ * Quark: Real-time, High-resolution, and General Neural View Synthesis
+ * (Flynn et al., ACM TOG 43(6), 2024).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with
+ * the GPU library: every formula below is written out here from the paper.
+ *
+ * Style: slow, plain loops in double precision, one function per step of the
+ * method, each citing the passage it follows.  No blocking, fusion or
+ * reordering beyond what the definitions state.  OpenMP only splits the
+ * independent layer-pixels across threads.
+ *
+ * Readings of points the paper leaves open (each is also listed in the design
+ * notes of the repository):
+ *   - pixel (x, y) has its centre at (x + 0.5, y + 0.5) in the continuous
+ *     coordinates that K maps rays to; rescaling a camera to another grid is
+ *     K' = diag(W'/W, H'/H, 1) K;
+ *   - "depth" is z-depth along the novel camera's optical axis;
+ *   - E is the world-to-camera transform, OpenCV axes;
+ *   - bilinear sampling uses zero padding outside the feature map, and a
+ *     sample whose point lies behind view m (Z_m <= 1e-6 d) is the zero
+ *     vector; such samples stay in the softmax (no mask);
+ *   - attention scale 1/sqrt(d_h) (per-head width), RMSNorm with unit gain
+ *     and eps = 1e-6 inside the square root, applied to the query input only;
+ *     no biases anywhere;
+ *   - layer index 0 is the nearest layer; the paper's layer index l (whose
+ *     l = 1 is the farthest band) is L - index;
+ *   - colour of a layer is sigmoid(F' W_c); depth and alpha are updated
+ *     residually by default (mode 0) or decoded absolutely as in the paper's
+ *     depth activation (mode 1).
+ *
+ * Parity status: every function has a pin in the CPU tests (closed forms,
+ * library routines, invariants, brute force).
+ */
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------ */
+/* Small dense linear algebra                                               */
+/* ------------------------------------------------------------------------ */
+
+/* 4x4 inverse by Gauss-Jordan elimination with partial pivoting. */
+static int inv4(const double *A, double *Ainv)
+{
+    double M[4][8];
+    for (int r = 0; r < 4; ++r) {
+        for (int c = 0; c < 4; ++c) {
+            M[r][c] = A[4 * r + c];
+            M[r][4 + c] = (r == c) ? 1.0 : 0.0;
+        }
+    }
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (fabs(M[piv][col]) < 1e-300) return -1;
+        if (piv != col)
+            for (int c = 0; c < 8; ++c) {
+                double t = M[col][c]; M[col][c] = M[piv][c]; M[piv][c] = t;
+            }
+        double p = M[col][col];
+        for (int c = 0; c < 8; ++c) M[col][c] /= p;
+        for (int r = 0; r < 4; ++r) {
+            if (r == col) continue;
+            double f = M[r][col];
+            for (int c = 0; c < 8; ++c) M[r][c] -= f * M[col][c];
+        }
+    }
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) Ainv[4 * r + c] = M[r][4 + c];
+    return 0;
+}
+
+static void mul4(const double *A, const double *B, double *C)
+{
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += A[4 * r + k] * B[4 * k + c];
+            C[4 * r + c] = s;
+        }
+}
+
+/* Embed a 3x3 intrinsic matrix in a 4x4 homogeneous one. */
+static void k_to_4x4(const double *K, double *K4)
+{
+    memset(K4, 0, 16 * sizeof(double));
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) K4[4 * r + c] = K[3 * r + c];
+    K4[15] = 1.0;
+}
+
+/* Rescale intrinsics from a (w0, h0) grid to a (w1, h1) grid with half-pixel
+ * centres: continuous pixel coordinates scale by w1/w0 and h1/h0. */
+OR_EXPORT void or_scale_intrinsics(const double *K, int w0, int h0, int w1, int h1,
+                                   double *Ks)
+{
+    double sx = (double)w1 / (double)w0, sy = (double)h1 / (double)h0;
+    for (int c = 0; c < 3; ++c) {
+        Ks[c] = sx * K[c];
+        Ks[3 + c] = sy * K[3 + c];
+        Ks[6 + c] = K[6 + c];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Back-projection operator P^T_theta, first half: reprojection             */
+/* (Sec. 3.1, the operator that carries input images onto the depth layers;  */
+/*  Sec. 3.2.2, back-projection of update features through decoded depth).  */
+/* ------------------------------------------------------------------------ */
+
+/* Full 4x4 chain from the novel camera's pixel space (scaled by depth) to
+ * view m's pixel space:  T = K4_m * E_m * inv(E_n) * inv(K4_n). */
+OR_EXPORT int or_reprojection_matrix(const double *Kn, const double *En,
+                                     const double *Km, const double *Em, double *T)
+{
+    double Kn4[16], Km4[16], Kn4i[16], Eni[16], A[16], B[16];
+    k_to_4x4(Kn, Kn4);
+    k_to_4x4(Km, Km4);
+    if (inv4(Kn4, Kn4i) != 0) return -1;
+    if (inv4(En, Eni) != 0) return -1;
+    mul4(Eni, Kn4i, A);     /* novel pixel*depth -> world */
+    mul4(Em, A, B);         /* -> camera m                */
+    mul4(Km4, B, T);        /* -> view m pixel*depth      */
+    return 0;
+}
+
+/* Reproject the centre of novel-grid pixel coordinate (u, v) lifted to
+ * z-depth d into view m.  Returns 1 and writes (u_m, v_m) if the point lies
+ * in front of view m (Z_m > 1e-6 d), else returns 0. */
+OR_EXPORT int or_reproject_T(const double *T, double u, double v, double d, double *uv_out)
+{
+    double X[4] = {u * d, v * d, d, 1.0};
+    double P[4];
+    for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 4; ++c) s += T[4 * r + c] * X[c];
+        P[r] = s;
+    }
+    /* P = (Km X_m, 1) with X_m the point in camera m: P[2] = Z_m. */
+    if (!(P[2] > 1e-6 * d)) return 0;
+    uv_out[0] = P[0] / P[2];
+    uv_out[1] = P[1] / P[2];
+    return 1;
+}
+
+OR_EXPORT int or_reproject(const double *Kn, const double *En, const double *Km,
+                           const double *Em, double u, double v, double d, double *uv_out)
+{
+    double T[16];
+    if (or_reprojection_matrix(Kn, En, Km, Em, T) != 0) return -1;
+    return or_reproject_T(T, u, v, d, uv_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Back-projection operator, second half: bilinear sampling of a feature map */
+/* I[Hf][Wf][C] at continuous coordinate (u, v), zero padding.              */
+/* ------------------------------------------------------------------------ */
+
+OR_EXPORT void or_bilinear(const double *I, int Hf, int Wf, int C, double u, double v,
+                           double *s)
+{
+    double x = u - 0.5, y = v - 0.5;        /* pixel centres at integer + 0.5 */
+    double xf = floor(x), yf = floor(y);
+    double fx = x - xf, fy = y - yf;
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    if (!(fabs(x) < 1e9 && fabs(y) < 1e9)) return;   /* far outside: all taps padded */
+    long x0 = (long)xf, y0 = (long)yf;
+    const long tx[4] = {x0, x0 + 1, x0, x0 + 1};
+    const long ty[4] = {y0, y0, y0 + 1, y0 + 1};
+    const double w[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+    for (int t = 0; t < 4; ++t) {
+        if (tx[t] < 0 || tx[t] >= Wf || ty[t] < 0 || ty[t] >= Hf) continue;
+        const double *p = I + ((size_t)ty[t] * Wf + (size_t)tx[t]) * C;
+        for (int c = 0; c < C; ++c) s[c] += w[t] * p[c];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fusion-block attention (Sec. 3.3): V' = V + MultiHead(N(V), Delta), with  */
+/* MultiHead(Q, K, Val) = concat(head_1..head_h) W^O and                     */
+/* head_i = Attention(Q W_i^q, K W_i^k, Val W_i^val),                        */
+/* Attention(Q, K, Val) = softmax(Q K^T / sqrt(d_h)) Val.                    */
+/* Here the query is one layer-pixel's feature F (C values) and the keys and */
+/* values come from its V samples S (V x Cf).  Weights row-major [in][out].  */
+/* ------------------------------------------------------------------------ */
+
+/* RMSNorm with unit gain: x / sqrt(mean(x^2) + 1e-6). */
+OR_EXPORT void or_rmsnorm(const double *x, int C, double *y)
+{
+    double ss = 0.0;
+    for (int c = 0; c < C; ++c) ss += x[c] * x[c];
+    double r = sqrt(ss / C + 1e-6);
+    for (int c = 0; c < C; ++c) y[c] = x[c] / r;
+}
+
+/* y[n_out] = x[n_in] @ W[n_in][n_out] */
+static void vecmat(const double *x, const double *W, int n_in, int n_out, double *y)
+{
+    for (int j = 0; j < n_out; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n_in; ++i) s += x[i] * W[(size_t)i * n_out + j];
+        y[j] = s;
+    }
+}
+
+/* Standard cross-attention from one query to V samples; writes
+ * F_out = F + concat_i(o_i) W_o, and (optionally) the softmax weights
+ * p[h][V] used by each head. */
+OR_EXPORT void or_attention(const double *F, int C, const double *S, int V, int Cf,
+                            int heads, int dh, const double *Wq, const double *Wk,
+                            const double *Wv, const double *Wo, double *F_out, double *p_out)
+{
+    int hd = heads * dh;
+    double *xn = malloc(sizeof(double) * C);
+    double *q = malloc(sizeof(double) * hd);
+    double *k = malloc(sizeof(double) * (size_t)V * hd);
+    double *v = malloc(sizeof(double) * (size_t)V * hd);
+    double *o = malloc(sizeof(double) * hd);
+    double *a = malloc(sizeof(double) * V);
+
+    or_rmsnorm(F, C, xn);
+    vecmat(xn, Wq, C, hd, q);
+    for (int m = 0; m < V; ++m) {
+        vecmat(S + (size_t)m * Cf, Wk, Cf, hd, k + (size_t)m * hd);
+        vecmat(S + (size_t)m * Cf, Wv, Cf, hd, v + (size_t)m * hd);
+    }
+    double scale = 1.0 / sqrt((double)dh);
+    for (int h = 0; h < heads; ++h) {
+        double amax = -INFINITY;
+        for (int m = 0; m < V; ++m) {
+            double s = 0.0;
+            for (int j = 0; j < dh; ++j) s += q[h * dh + j] * k[(size_t)m * hd + h * dh + j];
+            a[m] = s * scale;
+            if (a[m] > amax) amax = a[m];
+        }
+        double z = 0.0;
+        for (int m = 0; m < V; ++m) { a[m] = exp(a[m] - amax); z += a[m]; }
+        for (int m = 0; m < V; ++m) a[m] /= z;
+        if (p_out) for (int m = 0; m < V; ++m) p_out[h * V + m] = a[m];
+        for (int j = 0; j < dh; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < V; ++m) s += a[m] * v[(size_t)m * hd + h * dh + j];
+            o[h * dh + j] = s;
+        }
+    }
+    vecmat(o, Wo, hd, C, F_out);
+    for (int c = 0; c < C; ++c) F_out[c] += F[c];
+    free(xn); free(q); free(k); free(v); free(o); free(a);
+}
+
+/* One-to-many (folded) attention (Sec. 3.3, "Optimized Attention", and the
+ * appendix on its complexity): the key projection is folded into the query,
+ * q~_i = N(F) W_i^q (W_i^k)^T / sqrt(d_h), and the value projection into the
+ * output, F' = F + sum_i (sum_m p_im s_m) (W_i^val W^O_i), where W^O_i is the
+ * i-th row block of W^O.  Exactly equal to or_attention in real arithmetic. */
+OR_EXPORT void or_attention_folded(const double *F, int C, const double *S, int V, int Cf,
+                                   int heads, int dh, const double *Wq, const double *Wk,
+                                   const double *Wv, const double *Wo, double *F_out)
+{
+    int hd = heads * dh;
+    double *xn = malloc(sizeof(double) * C);
+    double *q = malloc(sizeof(double) * hd);
+    double *qt = malloc(sizeof(double) * Cf);
+    double *a = malloc(sizeof(double) * V);
+    double *ob = malloc(sizeof(double) * Cf);
+    double *ov = malloc(sizeof(double) * dh);
+
+    or_rmsnorm(F, C, xn);
+    vecmat(xn, Wq, C, hd, q);
+    for (int c = 0; c < C; ++c) F_out[c] = F[c];
+    double scale = 1.0 / sqrt((double)dh);
+    for (int h = 0; h < heads; ++h) {
+        /* q~ = q_h W_k,h^T / sqrt(dh)   (Cf values) */
+        for (int i = 0; i < Cf; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < dh; ++j) s += q[h * dh + j] * Wk[(size_t)i * hd + h * dh + j];
+            qt[i] = s * scale;
+        }
+        double amax = -INFINITY;
+        for (int m = 0; m < V; ++m) {
+            double s = 0.0;
+            for (int i = 0; i < Cf; ++i) s += qt[i] * S[(size_t)m * Cf + i];
+            a[m] = s;
+            if (s > amax) amax = s;
+        }
+        double z = 0.0;
+        for (int m = 0; m < V; ++m) { a[m] = exp(a[m] - amax); z += a[m]; }
+        for (int i = 0; i < Cf; ++i) {
+            double s = 0.0;
+            for (int m = 0; m < V; ++m) s += a[m] * S[(size_t)m * Cf + i];
+            ob[i] = s / z;
+        }
+        /* (ob W_v,h) W_o,h : the folded output projection */
+        for (int j = 0; j < dh; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < Cf; ++i) s += ob[i] * Wv[(size_t)i * hd + h * dh + j];
+            ov[j] = s;
+        }
+        for (int c = 0; c < C; ++c) {
+            double s = 0.0;
+            for (int j = 0; j < dh; ++j) s += ov[j] * Wo[(size_t)(h * dh + j) * C + c];
+            F_out[c] += s;
+        }
+    }
+    free(xn); free(q); free(qt); free(a); free(ob); free(ov);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decode of the intermediate LDM (Sec. 3.2.2 "Decoding and rendering the    */
+/* intermediate LDM", Sec. 3.2.3 depth anchors and depth activation).        */
+/* ------------------------------------------------------------------------ */
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Given the updated feature F' of layer `li` (0 = nearest) of an L-layer LDM,
+ * the layer-pixel's incoming alpha and depth, produce alpha', depth' and the
+ * layer colour c' = sigmoid(F' W_c).
+ *   mode 0 (residual update): alpha' = sigmoid(logit(clamp(alpha)) + F'.w_sigma),
+ *          disparity' = clamp(1/d + (0.5/L)(1/near - 1/far) tanh(F'.w_depth),
+ *                             1/far, 1/near), d' = 1/disparity'.
+ *   mode 1 (the paper's absolute decode): alpha' = sigmoid(F'.w_sigma),
+ *          d' = 1 / ((delta + (0.5/L) tanh(F'.w_depth)) (1/near - 1/far) + 1/far)
+ *          with the anchor delta = (l - 0.5)/L of paper layer l = L - li. */
+OR_EXPORT void or_decode(const double *Fp, int C, const double *w_sigma, const double *w_depth,
+                         const double *W_color, double alpha, double depth, int li, int L,
+                         double near_, double far_, int mode, double *alpha_out,
+                         double *depth_out, double *color_out)
+{
+    double xs = 0.0, xd = 0.0, xc[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < C; ++c) {
+        xs += Fp[c] * w_sigma[c];
+        xd += Fp[c] * w_depth[c];
+        for (int j = 0; j < 3; ++j) xc[j] += Fp[c] * W_color[c * 3 + j];
+    }
+    for (int j = 0; j < 3; ++j) color_out[j] = sigmoid(xc[j]);
+    double band = (1.0 / near_ - 1.0 / far_);
+    if (mode == 0) {
+        double a = alpha;
+        if (a < 1e-6) a = 1e-6;
+        if (a > 1.0 - 1e-6) a = 1.0 - 1e-6;
+        *alpha_out = sigmoid(log(a / (1.0 - a)) + xs);
+        double disp = 1.0 / depth + (0.5 / L) * band * tanh(xd);
+        if (disp < 1.0 / far_) disp = 1.0 / far_;
+        if (disp > 1.0 / near_) disp = 1.0 / near_;
+        *depth_out = 1.0 / disp;
+    } else {
+        *alpha_out = sigmoid(xs);
+        int l_paper = L - li;
+        double delta = (l_paper - 0.5) / L;
+        *depth_out = 1.0 / ((delta + (0.5 / L) * tanh(xd)) * band + 1.0 / far_);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Over composite O (Sec. 3.1): layers composited with "over".  Written here */
+/* front to back (layer 0 nearest), which equals the paper's back-to-front    */
+/* order by associativity of "over"; black background, accumulated alpha     */
+/* A = 1 - prod(1 - alpha) returned alongside.                               */
+/* color [L][npix][3], alpha [L][npix] -> rgb [npix][3], acc [npix]          */
+/* ------------------------------------------------------------------------ */
+
+OR_EXPORT void or_composite(int L, long npix, const double *color, const double *alpha,
+                            double *rgb, double *acc)
+{
+    for (long p = 0; p < npix; ++p) {
+        double T = 1.0, r[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < L; ++l) {
+            double a = alpha[(size_t)l * npix + p];
+            for (int j = 0; j < 3; ++j) r[j] += T * a * color[((size_t)l * npix + p) * 3 + j];
+            T *= (1.0 - a);
+        }
+        for (int j = 0; j < 3; ++j) rgb[p * 3 + j] = r[j];
+        if (acc) acc[p] = 1.0 - T;
+    }
+}
+
+/* Back-to-front form of the same operator, kept separately for the
+ * order-equivalence check. */
+OR_EXPORT void or_composite_back_to_front(int L, long npix, const double *color,
+                                          const double *alpha, double *rgb)
+{
+    for (long p = 0; p < npix; ++p) {
+        double r[3] = {0.0, 0.0, 0.0};
+        for (int l = L - 1; l >= 0; --l) {
+            double a = alpha[(size_t)l * npix + p];
+            for (int j = 0; j < 3; ++j)
+                r[j] = a * color[((size_t)l * npix + p) * 3 + j] + (1.0 - a) * r[j];
+        }
+        for (int j = 0; j < 3; ++j) rgb[p * 3 + j] = r[j];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One Update & Fuse step over a set of LDM rows (every layer of each row).  */
+/* For each layer li, row y in rows[], column x and view m: reproject the    */
+/* layer-pixel through its depth into view m, sample view m's feature map,   */
+/* then attend across the V samples, then decode.  Layer-pixels are          */
+/* independent, so any subset of rows gives the exact values of those rows.  */
+/*                                                                           */
+/* Inputs (all double, row-major):                                           */
+/*   V views: Kin[V][9], Ein[V][16], cam_wh[V][2] (grid of Kin),             */
+/*            feats[V] -> [Hf][Wf][Cf], feat_hw[V][2] = (Hf, Wf)             */
+/*   novel:   Kn[9], En[16], nov_wh[2] (grid of Kn)                          */
+/*   LDM:     L, H, W, C; F[L][H][W][C], depth[L][H][W], alpha[L][H][W]      */
+/*   weights: Wq[C][hd], Wk[Cf][hd], Wv[Cf][hd], Wo[hd][C], w_sigma[C],      */
+/*            w_depth[C], W_color[C][3]                                      */
+/* Outputs, packed over the selected rows (R = nrows):                       */
+/*   F_out[L][R][W][C], depth_out[L][R][W], alpha_out[L][R][W],              */
+/*   color_out[L][R][W][3]; samples_out[L][R][W][V][Cf] if non-NULL.         */
+/* attn_form: 0 standard, 1 one-to-many (folded).                            */
+/* ------------------------------------------------------------------------ */
+
+OR_EXPORT int or_update_fuse(int V, const double *Kin, const double *Ein, const int *cam_wh,
+                             const double *const *feats, const int *feat_hw, int Cf,
+                             const double *Kn, const double *En, const int *nov_wh,
+                             double near_, double far_, int L, int H, int W, int C,
+                             const double *F, const double *depth, const double *alpha,
+                             int heads, int dh, const double *Wq, const double *Wk,
+                             const double *Wv, const double *Wo, const double *w_sigma,
+                             const double *w_depth, const double *W_color, int mode,
+                             int attn_form, const int *rows, int nrows, double *F_out,
+                             double *depth_out, double *alpha_out, double *color_out,
+                             double *samples_out)
+{
+    double Kns[9];
+    or_scale_intrinsics(Kn, nov_wh[0], nov_wh[1], W, H, Kns);
+    double *T = malloc(sizeof(double) * 16 * (size_t)V);
+    for (int m = 0; m < V; ++m) {
+        double Kms[9];
+        or_scale_intrinsics(Kin + 9 * m, cam_wh[2 * m], cam_wh[2 * m + 1], feat_hw[2 * m + 1],
+                            feat_hw[2 * m], Kms);
+        if (or_reprojection_matrix(Kns, En, Kms, Ein + 16 * m, T + 16 * m) != 0) {
+            free(T);
+            return -1;
+        }
+    }
+    long total = (long)L * nrows * W;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *S = malloc(sizeof(double) * (size_t)V * Cf);
+        double *Fp = malloc(sizeof(double) * C);
+#pragma omp for schedule(dynamic, 64)
+        for (long idx = 0; idx < total; ++idx) {
+            int x = (int)(idx % W);
+            long t = idx / W;
+            int r = (int)(t % nrows);
+            int li = (int)(t / nrows);
+            int y = rows[r];
+            size_t src = ((size_t)li * H + y) * W + x;      /* layer-pixel in full arrays */
+            size_t dst = ((size_t)li * nrows + r) * W + x;  /* packed output position     */
+            double d = depth[src];
+            double u = x + 0.5, v = y + 0.5;
+            for (int m = 0; m < V; ++m) {
+                double uv[2];
+                double *s = S + (size_t)m * Cf;
+                if (or_reproject_T(T + 16 * m, u, v, d, uv) == 1) {
+                    or_bilinear(feats[m], feat_hw[2 * m], feat_hw[2 * m + 1], Cf, uv[0], uv[1], s);
+                } else {
+                    for (int c = 0; c < Cf; ++c) s[c] = 0.0;
+                }
+            }
+            if (samples_out)
+                memcpy(samples_out + dst * (size_t)V * Cf, S, sizeof(double) * (size_t)V * Cf);
+            if (attn_form == 0)
+                or_attention(F + src * C, C, S, V, Cf, heads, dh, Wq, Wk, Wv, Wo, Fp, NULL);
+            else
+                or_attention_folded(F + src * C, C, S, V, Cf, heads, dh, Wq, Wk, Wv, Wo, Fp);
+            memcpy(F_out + dst * C, Fp, sizeof(double) * C);
+            or_decode(Fp, C, w_sigma, w_depth, W_color, alpha[src], d, li, L, near_, far_, mode,
+                      alpha_out + dst, depth_out + dst, color_out + dst * 3);
+        }
+        free(S);
+        free(Fp);
+    }
+    free(T);
+    return err;
+}
+
+OR_EXPORT int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,353 @@
+"""Seeded synthetic inputs for the Update & Fuse step and the LDM composite.
+
+This module only *draws* inputs: cameras, encoded feature pyramids, LDM state
+(depth, alpha, features) and random-init weights, in the shapes and value
+distributions of the paper's 1080p setting (Sec. 3.2, Tabs. of the network
+appendix: 8 input views up to ~30 cm apart, C = 32 channels, d_k = 32).  It
+holds none of the method's arithmetic: no projection, sampling, attention,
+decode or composite.  Both the GPU path and the FP64 oracle receive exactly
+the arrays produced here.
+
+Conventions shared by every consumer of these arrays
+-----------------------------------------------------
+* Cameras: ``K`` is 3x3 row-major in pixel units of the camera's own
+  ``(width, height)`` grid with half-pixel centres (pixel ``(x, y)`` has its
+  centre at ``(x + 0.5, y + 0.5)``).  ``E`` is the 4x4 row-major
+  world-to-camera transform with OpenCV axes (+x right, +y down, +z forward).
+* Layouts are channel-last and layer-major: ``F[L][H][W][C]``,
+  ``depth[L][H][W]``, ``alpha[L][H][W]``, feature map ``I[Hf][Wf][C]``.
+  Layer 0 is the nearest layer.
+* Values are drawn in float64 with NumPy's PCG64 and cast once, to float32,
+  or to bfloat16 (round-to-nearest-even, stored as uint16 bit patterns) for
+  the reduced-precision form.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+__all__ = [
+    "Camera", "Level", "Scene", "make_inputs", "make_custom", "f32_to_bf16_bits",
+    "bf16_bits_to_f32", "CONFIG_NAMES",
+]
+
+CONFIG_NAMES = {
+    1: "c1-tiny-64x48-V2",
+    2: "c2-quarter1080p-480x270-V4-2step",
+    3: "c3-multiscale-1080p-V8",
+    4: "c4-backward-960x540-V4",
+    5: "c5-serving-scene",
+}
+
+
+# ----------------------------------------------------------------------------
+# bfloat16 storage helpers (a storage cast, not arithmetic of the method)
+# ----------------------------------------------------------------------------
+
+def f32_to_bf16_bits(a: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest-even); return uint16 bits."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    rounding = ((u >> 16) & 1) + 0x7FFF
+    return ((u + rounding) >> 16).astype(np.uint16)
+
+
+def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(b, dtype=np.uint16)
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# Data containers
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Camera:
+    K: np.ndarray          # (3, 3) float64
+    E: np.ndarray          # (4, 4) float64, world -> camera
+    width: int
+    height: int
+
+
+@dataclass
+class Level:
+    """One LDM level: its state, the matching feature maps and its weights."""
+    L: int
+    H: int
+    W: int
+    C: int                 # LDM feature channels
+    Cf: int                # input feature channels
+    heads: int
+    head_dim: int
+    feats: List[np.ndarray]            # V arrays [Hf][Wf][Cf] (float32 or bf16 bits)
+    depth: np.ndarray                  # [L][H][W] float32
+    alpha: np.ndarray                  # [L][H][W] float32
+    F: np.ndarray                      # [L][H][W][C] float32 or bf16 bits
+    weights: Dict[str, np.ndarray]     # float32 masters
+    composite: bool = True             # render this level to RGB
+
+    @property
+    def N(self) -> int:
+        return self.L * self.H * self.W
+
+
+@dataclass
+class Scene:
+    config: int
+    name: str
+    seed: int
+    dtype: str                         # "f32" or "bf16"
+    in_cams: List[Camera]
+    novel: Camera
+    near: float
+    far: float
+    levels: List[Level]
+    steps: int = 1
+    target: Optional[np.ndarray] = None   # [H][W][3] float32 (loss target)
+    depth_mode: str = "iid"
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def V(self) -> int:
+        return len(self.in_cams)
+
+
+# ----------------------------------------------------------------------------
+# Camera rigs
+# ----------------------------------------------------------------------------
+
+def _intrinsics(f: float, cx: float, cy: float) -> np.ndarray:
+    return np.array([[f, 0.0, cx], [0.0, f, cy], [0.0, 0.0, 1.0]], dtype=np.float64)
+
+
+def _fov_intrinsics(width: int, height: int, hfov_deg: float) -> np.ndarray:
+    f = (width / 2.0) / math.tan(math.radians(hfov_deg) / 2.0)
+    return _intrinsics(f, width / 2.0, height / 2.0)
+
+
+def _extrinsic(R_wc: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    """World-to-camera 4x4 from the camera's rotation (rows = camera axes in
+    world coordinates) and its centre in world coordinates."""
+    E = np.eye(4, dtype=np.float64)
+    E[:3, :3] = R_wc
+    E[:3, 3] = -R_wc @ centre
+    return E
+
+
+def _look_at_yaw(centre: np.ndarray, target: np.ndarray) -> np.ndarray:
+    """Rotation whose +z axis points from ``centre`` to ``target`` (in the
+    x-z plane), +y pointing down (world +y)."""
+    fwd = target - centre
+    fwd = fwd / np.linalg.norm(fwd)
+    down = np.array([0.0, 1.0, 0.0])
+    right = np.cross(down, fwd)
+    right = right / np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    return np.stack([right, down, fwd], axis=0)
+
+
+def _arc_rig(rng, V: int, arc_len: float, radius: float, width: int, height: int,
+             hfov: float, novel_radius_jitter: float = 0.0):
+    """V cameras evenly spaced on an arc of length ``arc_len`` of a circle of
+    ``radius`` around a scene centre ``radius`` ahead of the origin, all
+    looking at the centre.  The novel camera sits at a uniform angle inside
+    the arc's span (radius optionally jittered)."""
+    K = _fov_intrinsics(width, height, hfov)
+    scene_c = np.array([0.0, 0.0, radius])
+    span = arc_len / radius
+    # draw order: novel angle, then novel radius
+    theta_n = rng.uniform(-span / 2, span / 2)
+    r_n = radius + (rng.uniform(-novel_radius_jitter, novel_radius_jitter)
+                    if novel_radius_jitter > 0 else 0.0)
+
+    def cam_at(theta, r):
+        c = scene_c + r * np.array([math.sin(theta), 0.0, -math.cos(theta)])
+        return Camera(K.copy(), _extrinsic(_look_at_yaw(c, scene_c), c), width, height)
+
+    cams = []
+    for i in range(V):
+        th = -span / 2 + span * (i / (V - 1) if V > 1 else 0.5)
+        cams.append(cam_at(th, radius))
+    return cams, cam_at(theta_n, r_n)
+
+
+# ----------------------------------------------------------------------------
+# Draw helpers
+# ----------------------------------------------------------------------------
+
+def _normal(rng, shape, std=1.0):
+    return (rng.standard_normal(size=shape, dtype=np.float64) * std).astype(np.float32)
+
+
+def _cast(a32: np.ndarray, dtype: str) -> np.ndarray:
+    return f32_to_bf16_bits(a32) if dtype == "bf16" else a32
+
+
+def _sorted_depths(rng, L, H, W, lo, hi, dist: str, mode: str) -> np.ndarray:
+    if mode == "smooth":
+        # log-uniform marginal pushed through a 16-px-block bilinear field
+        gh, gw = H // 16 + 2, W // 16 + 2
+        g = rng.uniform(0.0, 1.0, size=(L, gh, gw))
+        ys = (np.arange(H) + 0.5) / 16.0
+        xs = (np.arange(W) + 0.5) / 16.0
+        y0 = np.floor(ys).astype(int); x0 = np.floor(xs).astype(int)
+        fy = (ys - y0)[None, :, None]; fx = (xs - x0)[None, None, :]
+        u = (g[:, y0][:, :, x0] * (1 - fy) * (1 - fx) + g[:, y0 + 1][:, :, x0] * fy * (1 - fx)
+             + g[:, y0][:, :, x0 + 1] * (1 - fy) * fx + g[:, y0 + 1][:, :, x0 + 1] * fy * fx)
+    else:
+        u = rng.uniform(0.0, 1.0, size=(L, H, W))
+    if dist == "uniform":
+        d = lo + (hi - lo) * u
+    else:  # log-uniform
+        d = np.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * u)
+    d.sort(axis=0)                     # layer 0 nearest
+    return d.astype(np.float32)
+
+
+def _alpha(rng, shape, dist: str) -> np.ndarray:
+    if dist == "uniform":
+        a = rng.uniform(0.0, 1.0, size=shape)
+    else:
+        a = rng.beta(0.5, 0.5, size=shape)
+    return a.astype(np.float32)
+
+
+def _weights(rng, C: int, Cf: int, heads: int, head_dim: int) -> Dict[str, np.ndarray]:
+    hd = heads * head_dim
+    w = {}
+    w["Wq"] = _normal(rng, (C, hd), 1.0 / math.sqrt(C))
+    w["Wk"] = _normal(rng, (Cf, hd), 1.0 / math.sqrt(Cf))
+    w["Wv"] = _normal(rng, (Cf, hd), 1.0 / math.sqrt(Cf))
+    w["Wo"] = _normal(rng, (hd, C), 1.0 / math.sqrt(hd))
+    w["w_sigma"] = _normal(rng, (C,), 1.0 / math.sqrt(C))
+    w["w_depth"] = _normal(rng, (C,), 1.0 / math.sqrt(C))
+    w["W_color"] = _normal(rng, (C, 3), 1.0 / math.sqrt(C))
+    return w
+
+
+# ----------------------------------------------------------------------------
+# Configurations
+# ----------------------------------------------------------------------------
+
+def make_inputs(config: int, dtype: str = "f32", seed: Optional[int] = None,
+                depth_mode: str = "iid", c3_levels: Optional[List[int]] = None) -> Scene:
+    """Draw the inputs of workload ``config`` (1..4).
+
+    1: V=2, 64x48, C=16, L=4, d=16, one step + composite.
+    2: V=4, 480x270, C=32, L=16, d=32, two steps + composite.
+    3: V=8, four levels (k=8,4,2,1) of a 1920x1080 frame, C=64/32/16/8,
+       L=32/16/8/4, one step per level, composite of the finest level.
+    4: V=4, 960x540, C=16, L=8, d=16, one step + composite, with a target.
+    ``c3_levels`` optionally restricts config 3 to a subset of its levels
+    (indices 0..3); the draws of the omitted levels are still consumed so the
+    remaining arrays are identical to the full draw.
+    """
+    if dtype not in ("f32", "bf16"):
+        raise ValueError("dtype must be 'f32' or 'bf16'")
+    seed = 1000 + config if seed is None else seed
+    rng = np.random.default_rng(seed)
+
+    if config == 1:
+        W, H, C, L, V = 64, 48, 16, 4, 2
+        K = _intrinsics(60.0, 32.0, 24.0)
+        eye = np.eye(3)
+        in_cams = [Camera(K.copy(), _extrinsic(eye, np.array([0.0, 0, 0])), W, H),
+                   Camera(K.copy(), _extrinsic(eye, np.array([0.1, 0, 0])), W, H)]
+        novel = Camera(K.copy(), _extrinsic(eye, np.array([0.05, 0, 0])), W, H)
+        feats = [_cast(_normal(rng, (H, W, C)), dtype) for _ in range(V)]
+        depth = _sorted_depths(rng, L, H, W, 1.0, 10.0, "uniform", depth_mode)
+        alpha = _alpha(rng, (L, H, W), "uniform")
+        F = _cast(_normal(rng, (L, H, W, C)), dtype)
+        wts = _weights(rng, C, C, 1, 16)
+        lvl = Level(L, H, W, C, C, 1, 16, feats, depth, alpha, F, wts, True)
+        return Scene(1, CONFIG_NAMES[1], seed, dtype, in_cams, novel, 1.0, 10.0, [lvl],
+                     steps=1, depth_mode=depth_mode)
+
+    if config in (2, 4):
+        if config == 2:
+            W, H, C, L, V, steps = 480, 270, 32, 16, 4, 2
+        else:
+            W, H, C, L, V, steps = 960, 540, 16, 8, 4, 1
+        in_cams, novel = _arc_rig(rng, V, 0.3, 2.0, W, H, 60.0)
+        feats = [_cast(_normal(rng, (H, W, C)), dtype) for _ in range(V)]
+        depth = _sorted_depths(rng, L, H, W, 0.5, 20.0, "log", depth_mode)
+        alpha = _alpha(rng, (L, H, W), "beta")
+        F = _cast(_normal(rng, (L, H, W, C)), dtype)
+        wts = _weights(rng, C, C, 1, C)
+        lvl = Level(L, H, W, C, C, 1, C, feats, depth, alpha, F, wts, True)
+        target = None
+        if config == 4:
+            target = rng.uniform(0.0, 1.0, size=(H, W, 3)).astype(np.float32)
+        return Scene(config, CONFIG_NAMES[config], seed, dtype, in_cams, novel, 0.5, 20.0,
+                     [lvl], steps=steps, target=target, depth_mode=depth_mode)
+
+    if config == 3:
+        FW, FH, V = 1920, 1080, 8
+        ks = [8, 4, 2, 1]
+        Cs = [64, 32, 16, 8]
+        Ls = [32, 16, 8, 4]
+        keep = set(range(4)) if c3_levels is None else set(c3_levels)
+        in_cams, novel = _arc_rig(rng, V, 0.5, 1.5, FW, FH, 60.0, novel_radius_jitter=0.05)
+        feats = [[None] * 4 for _ in range(V)]
+        for m in range(V):                      # view-major, then level
+            for li, (k, C) in enumerate(zip(ks, Cs)):
+                shape = (FH // k, FW // k, C)
+                if li in keep:
+                    feats[m][li] = _cast(_normal(rng, shape), dtype)
+                else:
+                    rng.standard_normal(size=shape, dtype=np.float64)
+        depths, alphas, Fs = [], [], []
+        for li, (k, L) in enumerate(zip(ks, Ls)):
+            depths.append(_sorted_depths(rng, L, FH // k, FW // k, 0.5, 20.0, "log", depth_mode))
+        for li, (k, L) in enumerate(zip(ks, Ls)):
+            alphas.append(_alpha(rng, (L, FH // k, FW // k), "beta"))
+        for li, (k, L, C) in enumerate(zip(ks, Ls, Cs)):
+            shape = (L, FH // k, FW // k, C)
+            if li in keep:
+                Fs.append(_cast(_normal(rng, shape), dtype))
+            else:
+                rng.standard_normal(size=shape, dtype=np.float64)
+                Fs.append(None)
+        levels = []
+        for li, (k, L, C) in enumerate(zip(ks, Ls, Cs)):
+            wts = _weights(rng, C, C, 1, C)
+            if li in keep:
+                levels.append(Level(L, FH // k, FW // k, C, C, 1, C,
+                                    [feats[m][li] for m in range(V)], depths[li], alphas[li],
+                                    Fs[li], wts, composite=(li == 3)))
+        sc = Scene(3, CONFIG_NAMES[3], seed, dtype, in_cams, novel, 0.5, 20.0, levels,
+                   steps=1, depth_mode=depth_mode)
+        sc.extra["level_ids"] = sorted(keep)
+        return sc
+
+    raise ValueError(f"unknown config {config}")
+
+
+def make_custom(*, V: int, H: int, W: int, C: int, L: int, heads: int = 1,
+                head_dim: Optional[int] = None, Cf: Optional[int] = None,
+                feat_hw: Optional[tuple] = None, dtype: str = "f32", seed: int = 7,
+                steps: int = 1, near: float = 0.5, far: float = 20.0,
+                arc: float = 0.3, radius: float = 2.0, hfov: float = 60.0,
+                alpha_dist: str = "beta", composite: bool = True,
+                with_target: bool = False) -> Scene:
+    """A small arc-rig scene of arbitrary shape, for edge-case and ragged-tile
+    tests.  Feature maps may have their own grid (``feat_hw``); the input
+    cameras are given on the LDM's grid and rescaled by consumers."""
+    head_dim = C if head_dim is None else head_dim
+    Cf = C if Cf is None else Cf
+    Hf, Wf = (H, W) if feat_hw is None else feat_hw
+    rng = np.random.default_rng(seed)
+    in_cams, novel = _arc_rig(rng, V, arc, radius, W, H, hfov)
+    feats = [_cast(_normal(rng, (Hf, Wf, Cf)), dtype) for _ in range(V)]
+    depth = _sorted_depths(rng, L, H, W, near, far, "log", "iid")
+    alpha = _alpha(rng, (L, H, W), alpha_dist)
+    F = _cast(_normal(rng, (L, H, W, C)), dtype)
+    wts = _weights(rng, C, Cf, heads, head_dim)
+    lvl = Level(L, H, W, C, Cf, heads, head_dim, feats, depth, alpha, F, wts, composite)
+    target = rng.uniform(0.0, 1.0, size=(H, W, 3)).astype(np.float32) if with_target else None
+    return Scene(0, f"custom-V{V}-{W}x{H}-L{L}-C{C}", seed, dtype, in_cams, novel, near, far,
+                 [lvl], steps=steps, target=target)
