@@ -1,0 +1,192 @@
+/*
+ * quark.h -- C-ABI of libquark, the MI355X (gfx950) library for one
+ * Update & Fuse step of a layered depth map (LDM) and the LDM's
+ * front-to-back composite, after Quark: Real-time, High-resolution, and
+ * General Neural View Synthesis (Flynn et al., ACM TOG 43(6), 2024).
+ *
+ * The problem statement follows the paper's Sec. 3.1-3.3: M input views with
+ * cameras theta and encoded feature maps I_k, a target (novel) camera, an LDM
+ * of L layers x [H, W] in the novel frustum (depth d, alpha sigma, features
+ * V), and an output image.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Every call returns a qk_status; nothing throws across the ABI.  On a
+ *    non-OK status qk_last_error() returns a thread-local message.
+ *  - Pointers marked "device" are HIP device pointers owned by the caller; the
+ *    library keeps none of them after the call returns.  Work is enqueued
+ *    asynchronously on the caller's `hip_stream` (a hipStream_t; NULL = the
+ *    default stream), so device buffers must stay valid until that stream
+ *    reaches the point of the call.  Pointers marked "host" are read before
+ *    the call returns.
+ *  - Shapes, dtypes, NULLs and 16-byte alignment of device buffers are
+ *    checked before anything is enqueued; a failed check returns
+ *    QK_ESHAPE / QK_EDTYPE / QK_EINVAL / QK_EUNSUPPORTED and enqueues nothing.
+ *    Launch failures return QK_EHIP.  Device faults surface at the caller's
+ *    next synchronisation.  Values (depth > 0, alpha in [0, 1]) are not
+ *    checked.
+ *  - Layouts are row-major, channel-last and layer-major:
+ *       LDM features  F[L][H][W][C]     (QK_F32 float or QK_BF16 bfloat16)
+ *       depth, alpha  [L][H][W]         float
+ *       feature map   I[Hf][Wf][Cf]     (same dtype as F), one per view
+ *       rgb           [H][W][3] float,  acc_alpha [H][W] float
+ *    Layer 0 is the nearest layer.
+ *  - Cameras (host, double): K is 3x3 row-major in pixel units of the
+ *    camera's own (width, height) grid, pixel (x, y) centred at
+ *    (x + 0.5, y + 0.5).  The library rescales K to whichever grid it is used
+ *    on: K' = diag(W'/width, H'/height, 1) K.  E is the 4x4 row-major
+ *    world-to-camera transform, OpenCV axes (+x right, +y down, +z forward).
+ *    Depth is z-depth along the novel camera's optical axis.
+ */
+#ifndef QUARK_H
+#define QUARK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define QK_API __attribute__((visibility("default")))
+#else
+#define QK_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QK_OK = 0,
+    QK_EINVAL = -1,       /* NULL pointer, bad enum, misaligned buffer      */
+    QK_ESHAPE = -2,       /* inconsistent or out-of-range sizes             */
+    QK_EDTYPE = -3,       /* dtype not allowed for this precision           */
+    QK_ENOMEM = -4,       /* workspace allocation failed                    */
+    QK_EHIP = -5,         /* a HIP runtime call or launch failed            */
+    QK_EUNSUPPORTED = -6  /* valid request outside what the kernels support */
+} qk_status;
+
+typedef enum { QK_F32 = 0, QK_BF16 = 1 } qk_dtype;
+
+/* Arithmetic form of the step.  QK_PREC_FP32: features, samples and
+ * projections in float32.  QK_PREC_BF16: features, samples and the Q/K/V/O
+ * and decode projections in bfloat16 on the matrix cores with float32
+ * accumulation; reprojection, RMSNorm, softmax, decode activations and
+ * compositing stay float32 in both forms. */
+typedef enum { QK_PREC_FP32 = 0, QK_PREC_BF16 = 1 } qk_precision;
+
+/* How the decoded heads update depth and alpha (Sec. 3.2.2-3.2.3):
+ * RESIDUAL  alpha' = sigmoid(logit(clamp(alpha, 1e-6, 1-1e-6)) + F'.w_sigma),
+ *           disp'  = clamp(1/d + (0.5/L)(1/near - 1/far) tanh(F'.w_depth),
+ *                          1/far, 1/near),  d' = 1/disp';
+ * PAPER_DECODE  the paper's absolute decode: alpha' = sigmoid(F'.w_sigma),
+ *           d' = 1/((delta + (0.5/L) tanh(F'.w_depth))(1/near - 1/far) + 1/far)
+ *           with anchor delta = (l - 0.5)/L for the paper's layer l = L - index.
+ * Both: colour c' = sigmoid(F' W_color). */
+typedef enum { QK_UPDATE_RESIDUAL = 0, QK_UPDATE_PAPER_DECODE = 1 } qk_update_mode;
+
+/* Attention form (Sec. 3.3).  STANDARD: per-sample key and value
+ * projections, q = N(F) W_q, k_m = s_m W_k, v_m = s_m W_v,
+ * F' = F + softmax_m(q.k_m / sqrt(d_h)) v_m W_o.  FOLDED ("one-to-many"): the
+ * same result with W_k folded into the query and W_v into the output
+ * projection, so no per-sample matrix multiply is done. */
+typedef enum { QK_ATTN_STANDARD = 0, QK_ATTN_FOLDED = 1 } qk_attn_form;
+
+typedef struct {
+    double K[9];          /* host, row-major intrinsics on (width, height)  */
+    double E[16];         /* host, row-major world-to-camera                */
+    int32_t width, height;
+} qk_camera;
+
+typedef struct {
+    const void *data;     /* device, [H][W][C] contiguous, dtype of the LDM */
+    int32_t H, W;
+} qk_feature_map;
+
+typedef struct {
+    void *F;              /* device [L][H][W][C], dtype `dtype`; may be NULL
+                             in an output LDM to skip writing F'           */
+    float *depth;         /* device [L][H][W]                              */
+    float *alpha;         /* device [L][H][W]                              */
+    int32_t L, H, W, C;
+    qk_dtype dtype;
+} qk_ldm;
+
+/* Projection weights, device float32 masters, row-major [in][out], no biases.
+ *   Wq [C][heads*head_dim]      Wk, Wv [C_feat][heads*head_dim]
+ *   Wo [heads*head_dim][C]      w_sigma, w_depth [C]     W_color [C][3]   */
+typedef struct {
+    const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
+    int32_t C, C_feat, heads, head_dim;
+} qk_weights;
+
+typedef struct qk_context qk_context;
+
+/* Create a context bound to HIP device `device`.  The context owns a small
+ * device workspace (camera tables) and nothing else; it may be used from one
+ * host thread at a time.  Errors: QK_EINVAL (out == NULL), QK_EHIP. */
+QK_API qk_status qk_context_create(int device, qk_context **out);
+QK_API qk_status qk_context_destroy(qk_context *ctx);
+
+/* One Update & Fuse step of one LDM level (Sec. 3.2.2 "Iterative Updates",
+ * Sec. 3.3 fusion block).  For every layer l, pixel p and view m: reproject
+ * the layer-pixel through its depth into view m (the back-projection
+ * operator of Sec. 3.1), bilinearly sample view m's feature map there (zero
+ * padding; a point behind view m samples zero), attend from the
+ * layer-pixel's RMS-normalised feature across its V samples, add the result
+ * to F, and decode depth, alpha and colour from the updated feature.  If
+ * `rgb_out` is non-NULL the updated layers are composited front to back
+ * (Sec. 3.1, the over operator) into rgb_out [H][W][3] and, if non-NULL,
+ * acc_alpha_out [H][W] = 1 - prod(1 - alpha').
+ *
+ *   V           number of views, 1..16
+ *   in_cams     host [V];  feats device maps [V], each [Hf][Wf][C_feat]
+ *   novel       host; its K is rescaled to the LDM grid (H, W)
+ *   near_, far_ LDM frustum planes, 0 < near_ < far_
+ *   ldm_in      current state; ldm_out receives F', depth', alpha'
+ *               (ldm_out may alias ldm_in: each layer-pixel is read before
+ *               it is written, by the same wave)
+ * Supported by the kernels: heads == 1, C == C_feat == head_dim in
+ * {8, 16, 32, 64}; otherwise QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
+ * QK_F32 and QK_PREC_BF16 needs QK_BF16 (else QK_EDTYPE). */
+QK_API qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V,
+                         const qk_camera *in_cams, const qk_feature_map *feats,
+                         const qk_camera *novel, float near_, float far_,
+                         const qk_weights *weights, qk_precision precision,
+                         qk_attn_form attn_form, qk_update_mode update_mode,
+                         const qk_ldm *ldm_in, const qk_ldm *ldm_out,
+                         float *rgb_out, float *acc_alpha_out);
+
+/* Dry run of qk_update_fuse's argument checks: returns the status the call
+ * would return before enqueuing anything, without touching a device.  Takes
+ * the same arguments minus the context and stream. */
+QK_API qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams,
+                               const qk_feature_map *feats, const qk_camera *novel,
+                               float near_, float far_, const qk_weights *weights,
+                               qk_precision precision, qk_attn_form attn_form,
+                               qk_update_mode update_mode, const qk_ldm *ldm_in,
+                               const qk_ldm *ldm_out, float *rgb_out,
+                               float *acc_alpha_out);
+
+/* Front-to-back over composite of L layers (Sec. 3.1): for each pixel,
+ * T = 1; for l = 0..L-1: rgb += T alpha_l color_l; T *= 1 - alpha_l.
+ *   color device [L][H][W][3] float, alpha device [L][H][W] float,
+ *   rgb_out device [H][W][3], acc_alpha_out device [H][W] or NULL. */
+QK_API qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, int32_t W,
+                       const float *color, const float *alpha, float *rgb_out,
+                       float *acc_alpha_out);
+
+/* Per-view reprojection tables the kernels use: for view m on the level
+ * grid, p = A_m (u, v, 1)^T + b_m / d with A_m = K_m R_m R_n^T K_n^-1 and
+ * b_m = K_m (t_m - R_m R_n^T t_n), composed in double on the host and
+ * rounded to float.  out [V][12] host = A row-major then b.  Exposed so the
+ * host composition can be checked without a GPU. */
+QK_API qk_status qk_camera_tables(int32_t V, const qk_camera *in_cams, const int32_t *feat_hw,
+                           const qk_camera *novel, int32_t H, int32_t W, double *out);
+
+QK_API const char *qk_last_error(void);
+QK_API const char *qk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUARK_H */

@@ -1,0 +1,346 @@
+// capi.cpp -- host side of libquark: argument checks, the float64 camera
+// composition, launch planning, error reporting.  Declarations and the
+// contract of every entry point are in include/quark.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "quark.h"
+#include "uf_params.h"
+
+namespace qk {
+hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, hipStream_t s);
+hipError_t launch_composite(const CompParams &p, hipStream_t s);
+}  // namespace qk
+
+struct qk_context {
+    int device;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+qk_status fail(qk_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+qk_status fail(qk_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+// ---- 3x3 helpers (double)
+void mat3_mul(const double *A, const double *B, double *Cm) {
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[3 * r + k] * B[3 * k + c];
+            Cm[3 * r + c] = s;
+        }
+}
+
+// Inverse by the adjugate; returns false when singular.
+bool mat3_inv(const double *A, double *Ai) {
+    const double a = A[0], b = A[1], c = A[2], d = A[3], e = A[4], f = A[5], g = A[6], h = A[7],
+                 i = A[8];
+    const double c00 = e * i - f * h, c01 = -(d * i - f * g), c02 = d * h - e * g;
+    const double det = a * c00 + b * c01 + c * c02;
+    if (!(std::fabs(det) > 1e-300) || !std::isfinite(det)) return false;
+    const double id = 1.0 / det;
+    Ai[0] = c00 * id;
+    Ai[1] = -(b * i - c * h) * id;
+    Ai[2] = (b * f - c * e) * id;
+    Ai[3] = c01 * id;
+    Ai[4] = (a * i - c * g) * id;
+    Ai[5] = -(a * f - c * d) * id;
+    Ai[6] = c02 * id;
+    Ai[7] = -(a * h - b * g) * id;
+    Ai[8] = (a * e - b * d) * id;
+    return true;
+}
+
+qk_status check_camera(const qk_camera *cam, const char *what) {
+    if (cam->width <= 0 || cam->height <= 0)
+        return fail(QK_ESHAPE, "%s: grid %dx%d must be positive", what, cam->width, cam->height);
+    const double *K = cam->K, *E = cam->E;
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(K[k])) return fail(QK_EINVAL, "%s: K not finite", what);
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(E[k])) return fail(QK_EINVAL, "%s: E not finite", what);
+    if (K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0)
+        return fail(QK_EINVAL, "%s: K's last row must be (0, 0, 1)", what);
+    if (E[12] != 0.0 || E[13] != 0.0 || E[14] != 0.0 || E[15] != 1.0)
+        return fail(QK_EINVAL, "%s: E's last row must be (0, 0, 0, 1)", what);
+    double Ki[9], M[9], Mi[9];
+    if (!mat3_inv(K, Ki)) return fail(QK_EINVAL, "%s: K is singular", what);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = E[4 * r + c];
+    if (!mat3_inv(M, Mi)) return fail(QK_EINVAL, "%s: E's 3x3 block is singular", what);
+    return QK_OK;
+}
+
+// K rescaled from the camera's own grid to a (w1, h1) grid (half-pixel centres).
+void scaled_K(const qk_camera *cam, int w1, int h1, double *Ks) {
+    const double sx = (double)w1 / cam->width, sy = (double)h1 / cam->height;
+    for (int c = 0; c < 3; ++c) {
+        Ks[c] = sx * cam->K[c];
+        Ks[3 + c] = sy * cam->K[3 + c];
+        Ks[6 + c] = cam->K[6 + c];
+    }
+}
+
+// A = K_m M_m M_n^-1 K_n^-1 and b = K_m (t_m - M_m M_n^-1 t_n), where E = [M | t]
+// (M is the rotation R for rigid cameras).  Composed in double.
+void compose_table(const qk_camera *nov, int W, int H, const qk_camera *cam, int fw, int fh,
+                   double *out12) {
+    double Kn[9], Km[9], Kni[9], Mn[9], Mni[9], Mm[9], tn[3], tm[3];
+    scaled_K(nov, W, H, Kn);
+    scaled_K(cam, fw, fh, Km);
+    mat3_inv(Kn, Kni);
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            Mn[3 * r + c] = nov->E[4 * r + c];
+            Mm[3 * r + c] = cam->E[4 * r + c];
+        }
+        tn[r] = nov->E[4 * r + 3];
+        tm[r] = cam->E[4 * r + 3];
+    }
+    mat3_inv(Mn, Mni);
+    double R[9], KR[9], A[9];
+    mat3_mul(Mm, Mni, R);      // novel camera frame -> camera m frame (rotation part)
+    mat3_mul(Km, R, KR);
+    mat3_mul(KR, Kni, A);
+    double tr[3];
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += R[3 * r + k] * tn[k];
+        tr[r] = tm[r] - s;
+    }
+    for (int k = 0; k < 9; ++k) out12[k] = A[k];
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += Km[3 * r + k] * tr[k];
+        out12[9 + r] = s;
+    }
+}
+
+bool supported_c(int C) { return C == 8 || C == 16 || C == 32 || C == 64; }
+
+qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_feature_map *feats,
+                            const qk_camera *novel, float near_, float far_, const qk_weights *w,
+                            qk_precision precision, qk_attn_form attn_form,
+                            qk_update_mode update_mode, const qk_ldm *in, const qk_ldm *out,
+                            float *rgb_out, float *acc_out) {
+    if (!in_cams || !feats || !novel || !w || !in || !out)
+        return fail(QK_EINVAL, "NULL argument");
+    if (V < 1 || V > qk::kMaxViews)
+        return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (precision != QK_PREC_FP32 && precision != QK_PREC_BF16)
+        return fail(QK_EINVAL, "unknown precision %d", (int)precision);
+    if (attn_form != QK_ATTN_STANDARD && attn_form != QK_ATTN_FOLDED)
+        return fail(QK_EINVAL, "unknown attention form %d", (int)attn_form);
+    if (update_mode != QK_UPDATE_RESIDUAL && update_mode != QK_UPDATE_PAPER_DECODE)
+        return fail(QK_EINVAL, "unknown update mode %d", (int)update_mode);
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (in->L < 1 || in->H < 1 || in->W < 1 || in->C < 1)
+        return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d C=%d)", in->L, in->H,
+                    in->W, in->C);
+    if (out->L != in->L || out->H != in->H || out->W != in->W || out->C != in->C)
+        return fail(QK_ESHAPE, "ldm_out dims differ from ldm_in");
+    if (in->dtype != QK_F32 && in->dtype != QK_BF16)
+        return fail(QK_EDTYPE, "unknown LDM dtype %d", (int)in->dtype);
+    if (out->dtype != in->dtype) return fail(QK_EDTYPE, "ldm_out dtype differs from ldm_in");
+    const qk_dtype need = precision == QK_PREC_BF16 ? QK_BF16 : QK_F32;
+    if (in->dtype != need)
+        return fail(QK_EDTYPE, "precision %d needs LDM/feature dtype %d", (int)precision, (int)need);
+    if (!in->F || !in->depth || !in->alpha || !out->depth || !out->alpha)
+        return fail(QK_EINVAL, "NULL LDM buffer");
+    if (!w->Wq || !w->Wk || !w->Wv || !w->Wo || !w->w_sigma || !w->w_depth || !w->W_color)
+        return fail(QK_EINVAL, "NULL weight buffer");
+    if (w->C != in->C) return fail(QK_ESHAPE, "weights.C %d != LDM C %d", w->C, in->C);
+    if (w->C_feat < 1 || w->heads < 1 || w->head_dim < 1)
+        return fail(QK_ESHAPE, "weights dims must be positive");
+    if (!aligned16(in->F) || (out->F && !aligned16(out->F)))
+        return fail(QK_EINVAL, "LDM feature buffers must be 16-byte aligned");
+    if (!aligned4(in->depth) || !aligned4(in->alpha) || !aligned4(out->depth) ||
+        !aligned4(out->alpha) || (rgb_out && !aligned4(rgb_out)) || (acc_out && !aligned4(acc_out)))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    if (acc_out && !rgb_out) return fail(QK_EINVAL, "acc_alpha_out needs rgb_out");
+    const int64_t elems = (int64_t)in->L * in->H * in->W * in->C;
+    if (elems >= (int64_t)1 << 31)
+        return fail(QK_EUNSUPPORTED, "LDM of %lld elements exceeds 2^31", (long long)elems);
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    for (int m = 0; m < V; ++m) {
+        char what[32];
+        snprintf(what, sizeof(what), "camera %d", m);
+        st = check_camera(&in_cams[m], what);
+        if (st != QK_OK) return st;
+        if (!feats[m].data) return fail(QK_EINVAL, "feature map %d is NULL", m);
+        if (!aligned16(feats[m].data))
+            return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
+        if (feats[m].H < 1 || feats[m].W < 1)
+            return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
+        if ((int64_t)feats[m].H * feats[m].W * w->C_feat >= (int64_t)1 << 31)
+            return fail(QK_EUNSUPPORTED, "feature map %d exceeds 2^31 elements", m);
+    }
+    if (w->heads != 1 || w->head_dim != in->C || w->C_feat != in->C || !supported_c(in->C))
+        return fail(QK_EUNSUPPORTED,
+                    "kernels support heads == 1 and C == C_feat == head_dim in {8,16,32,64} "
+                    "(got heads=%d head_dim=%d C=%d C_feat=%d)",
+                    w->heads, w->head_dim, in->C, w->C_feat);
+    if (attn_form != QK_ATTN_STANDARD)
+        return fail(QK_EUNSUPPORTED, "folded attention form not built yet");
+    return QK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qk_last_error(void) { return g_err.c_str(); }
+
+const char *qk_version(void) { return "libquark 0.1.0 gfx950"; }
+
+qk_status qk_context_create(int device, qk_context **out) {
+    if (!out) return fail(QK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(QK_EHIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(QK_EINVAL, "device %d of %d", device, n);
+    *out = new qk_context{device};
+    return QK_OK;
+}
+
+qk_status qk_context_destroy(qk_context *ctx) {
+    delete ctx;
+    return QK_OK;
+}
+
+qk_status qk_camera_tables(int32_t V, const qk_camera *in_cams, const int32_t *feat_hw,
+                           const qk_camera *novel, int32_t H, int32_t W, double *out) {
+    if (!in_cams || !feat_hw || !novel || !out) return fail(QK_EINVAL, "NULL argument");
+    if (V < 1 || V > qk::kMaxViews) return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (H < 1 || W < 1) return fail(QK_ESHAPE, "grid must be positive");
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    for (int m = 0; m < V; ++m) {
+        st = check_camera(&in_cams[m], "input camera");
+        if (st != QK_OK) return st;
+        if (feat_hw[2 * m] < 1 || feat_hw[2 * m + 1] < 1) return fail(QK_ESHAPE, "feature grid");
+        compose_table(novel, W, H, &in_cams[m], feat_hw[2 * m + 1], feat_hw[2 * m], out + 12 * m);
+    }
+    return QK_OK;
+}
+
+qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams, const qk_feature_map *feats,
+                               const qk_camera *novel, float near_, float far_,
+                               const qk_weights *weights, qk_precision precision,
+                               qk_attn_form attn_form, qk_update_mode update_mode,
+                               const qk_ldm *ldm_in, const qk_ldm *ldm_out, float *rgb_out,
+                               float *acc_alpha_out) {
+    return check_update_fuse(V, in_cams, feats, novel, near_, far_, weights, precision, attn_form,
+                             update_mode, ldm_in, ldm_out, rgb_out, acc_alpha_out);
+}
+
+qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                         const qk_feature_map *feats, const qk_camera *novel, float near_,
+                         float far_, const qk_weights *w, qk_precision precision,
+                         qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
+                         const qk_ldm *out, float *rgb_out, float *acc_out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_update_fuse(V, in_cams, feats, novel, near_, far_, w, precision,
+                                     attn_form, update_mode, in, out, rgb_out, acc_out);
+    if (st != QK_OK) return st;
+
+    qk::UFParams p;
+    std::memset(&p, 0, sizeof(p));
+    for (int m = 0; m < V; ++m) {
+        p.feat[m] = feats[m].data;
+        p.fH[m] = feats[m].H;
+        p.fW[m] = feats[m].W;
+        double t12[12];
+        compose_table(novel, in->W, in->H, &in_cams[m], feats[m].W, feats[m].H, t12);
+        for (int k = 0; k < 12; ++k) p.cam[m][k] = (float)t12[k];
+    }
+    p.F_in = in->F;
+    p.depth_in = in->depth;
+    p.alpha_in = in->alpha;
+    p.F_out = out->F;
+    p.depth_out = out->depth;
+    p.alpha_out = out->alpha;
+    p.rgb = rgb_out;
+    p.acc = acc_out;
+    p.Wq = w->Wq;
+    p.Wk = w->Wk;
+    p.Wv = w->Wv;
+    p.Wo = w->Wo;
+    p.w_sigma = w->w_sigma;
+    p.w_depth = w->w_depth;
+    p.W_color = w->W_color;
+    p.V = V;
+    p.L = in->L;
+    p.H = in->H;
+    p.W = in->W;
+    p.inv_near = 1.0f / near_;
+    p.inv_far = 1.0f / far_;
+    p.mode = (int)update_mode;
+    p.x_blocks = (in->W + 63) / 64;
+    // Layer chunks: the composite needs every layer of a pixel in one wave;
+    // otherwise split layers until the grid has enough workgroups.
+    const int64_t xy = (int64_t)p.x_blocks * in->H;
+    int chunks = 1;
+    if (!rgb_out) {
+        const int64_t want = 4096;
+        chunks = (int)std::min<int64_t>(in->L, std::max<int64_t>(1, (want + xy - 1) / xy));
+    }
+    p.layers_per_chunk = (in->L + chunks - 1) / chunks;
+    p.chunks = (in->L + p.layers_per_chunk - 1) / p.layers_per_chunk;
+    const int64_t tiles = xy * p.chunks;
+    if (tiles >= ((int64_t)1 << 31)) return fail(QK_EUNSUPPORTED, "grid too large");
+    p.n_tiles = (int32_t)tiles;
+
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipError_t e = qk::launch_update_fuse(p, in->C, precision == QK_PREC_BF16,
+                                          reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "update_fuse launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, int32_t W,
+                       const float *color, const float *alpha, float *rgb_out, float *acc_out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    if (!color || !alpha || !rgb_out) return fail(QK_EINVAL, "NULL buffer");
+    if (L < 1 || H < 1 || W < 1) return fail(QK_ESHAPE, "dims must be positive");
+    if (!aligned4(color) || !aligned4(alpha) || !aligned4(rgb_out) || (acc_out && !aligned4(acc_out)))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    const int64_t npix = (int64_t)H * W;
+    if (npix * L * 3 >= ((int64_t)1 << 40)) return fail(QK_EUNSUPPORTED, "too large");
+    qk::CompParams p{color, alpha, rgb_out, acc_out, L, npix};
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipError_t e = qk::launch_composite(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "composite launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// uf_params.h -- launch parameters shared by the host C-ABI and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace qk {
+
+constexpr int kMaxViews = 16;
+
+// One Update & Fuse launch over one LDM level.  Per view m, cam[m] holds the
+// reprojection table p = A (u, v, 1)^T + b / d: A row-major (9 floats), then
+// b (3 floats), composed in double on the host.
+struct UFParams {
+    const void *feat[kMaxViews];
+    int32_t fH[kMaxViews];
+    int32_t fW[kMaxViews];
+    float cam[kMaxViews][12];
+
+    const void *F_in;
+    const float *depth_in;
+    const float *alpha_in;
+    void *F_out;           // may be NULL (skip F' store)
+    float *depth_out;
+    float *alpha_out;
+    float *rgb;            // may be NULL (no composite)
+    float *acc;            // may be NULL
+
+    const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
+
+    int32_t V, L, H, W;
+    int32_t layers_per_chunk;  // layers handled by one workgroup
+    int32_t x_blocks;          // ceil(W / 64)
+    int32_t n_tiles;           // x_blocks * H * chunks (workgroups in the grid)
+    int32_t chunks;
+    float inv_near, inv_far;
+    int32_t mode;              // 0 residual, 1 paper decode
+};
+
+struct CompParams {
+    const float *color;    // [L][H][W][3]
+    const float *alpha;    // [L][H][W]
+    float *rgb;            // [H][W][3]
+    float *acc;            // [H][W] or NULL
+    int32_t L;
+    int64_t npix;
+};
+
+}  // namespace qk

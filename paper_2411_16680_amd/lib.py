@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libquark (C-ABI in include/quark.h).
+
+Argument marshalling only: every step of the Update & Fuse path runs in the
+library's HIP kernels.  Device buffers are torch tensors on a ROCm device
+(torch supplies memory and streams).  There is no fallback: if the library is
+missing or a call fails, a ``QuarkError`` is raised.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libquark.so")
+
+QK_OK, QK_EINVAL, QK_ESHAPE, QK_EDTYPE, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "QK_OK", -1: "QK_EINVAL", -2: "QK_ESHAPE", -3: "QK_EDTYPE", -4: "QK_ENOMEM",
+                -5: "QK_EHIP", -6: "QK_EUNSUPPORTED"}
+QK_F32, QK_BF16 = 0, 1
+PREC = {"fp32": 0, "bf16": 1}
+ATTN = {"standard": 0, "folded": 1}
+MODE = {"residual": 0, "paper": 1}
+
+# symbols include/quark.h declares (checked by the CPU tests)
+EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
+           "qk_composite", "qk_camera_tables", "qk_last_error", "qk_version"]
+
+
+class QuarkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class qk_camera(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_double * 9), ("E", ctypes.c_double * 16),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class qk_feature_map(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class qk_ldm(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("L", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("C", ctypes.c_int32), ("dtype", ctypes.c_int)]
+
+
+class qk_weights(ctypes.Structure):
+    _fields_ = [("Wq", ctypes.c_void_p), ("Wk", ctypes.c_void_p), ("Wv", ctypes.c_void_p),
+                ("Wo", ctypes.c_void_p), ("w_sigma", ctypes.c_void_p),
+                ("w_depth", ctypes.c_void_p), ("W_color", ctypes.c_void_p),
+                ("C", ctypes.c_int32), ("C_feat", ctypes.c_int32), ("heads", ctypes.c_int32),
+                ("head_dim", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libquark.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QuarkError(QK_EINVAL, f"{LIB_PATH} not built (run python -m paper_2411_16680_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.qk_last_error.restype = ctypes.c_char_p
+    L.qk_version.restype = ctypes.c_char_p
+    P = ctypes.POINTER
+    L.qk_context_create.argtypes = [ctypes.c_int, P(ctypes.c_void_p)]
+    L.qk_context_destroy.argtypes = [ctypes.c_void_p]
+    uf_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
+               ctypes.c_float, P(qk_weights), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+               P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p]
+    L.qk_update_fuse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
+    L.qk_update_fuse_check.argtypes = uf_args
+    L.qk_composite.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    L.qk_camera_tables.argtypes = [ctypes.c_int32, P(qk_camera), P(ctypes.c_int32), P(qk_camera),
+                                   ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
+    for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
+                 "qk_update_fuse_check", "qk_composite", "qk_camera_tables"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != QK_OK:
+        raise QuarkError(st, load().qk_last_error().decode())
+
+
+def version() -> str:
+    return load().qk_version().decode()
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+# --------------------------------------------------------------------------
+
+def make_camera(cam) -> qk_camera:
+    c = qk_camera()
+    K = np.ascontiguousarray(cam.K, dtype=np.float64).reshape(9)
+    E = np.ascontiguousarray(cam.E, dtype=np.float64).reshape(16)
+    for i in range(9):
+        c.K[i] = float(K[i])
+    for i in range(16):
+        c.E[i] = float(E[i])
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.bfloat16:
+        return QK_BF16
+    if t.dtype == torch.float32:
+        return QK_F32
+    return 99
+
+
+def make_ldm(F, depth, alpha) -> qk_ldm:
+    """F: [L][H][W][C] (float32 or bfloat16) or None; depth, alpha: [L][H][W] float32."""
+    L, H, W = (int(s) for s in depth.shape)
+    C = int(F.shape[-1]) if F is not None else 0
+    return qk_ldm(_ptr(F), _ptr(depth), _ptr(alpha), L, H, W, C,
+                  _dtype_code(F) if F is not None else QK_F32)
+
+
+def make_weights(w: Dict, heads: int = 1, head_dim: Optional[int] = None) -> qk_weights:
+    C = int(w["Wq"].shape[0])
+    Cf = int(w["Wk"].shape[0])
+    hd = int(w["Wq"].shape[1])
+    head_dim = hd // heads if head_dim is None else head_dim
+    return qk_weights(_ptr(w["Wq"]), _ptr(w["Wk"]), _ptr(w["Wv"]), _ptr(w["Wo"]),
+                      _ptr(w["w_sigma"]), _ptr(w["w_depth"]), _ptr(w["W_color"]), C, Cf, heads,
+                      head_dim)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """A libquark context bound to one device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.qk_context_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self._lib.qk_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode, ldm_in,
+             ldm_out, rgb_out, acc_out):
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]), int(f.shape[1]))
+                                 for f in feats])
+    nov = make_camera(novel)
+    wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
+    lin = ldm_in if isinstance(ldm_in, qk_ldm) else make_ldm(*ldm_in)
+    lout = ldm_out if isinstance(ldm_out, qk_ldm) else make_ldm(*ldm_out)
+    keep = (cams, fm, nov, wts, lin, lout)
+    args = [V, cams, fm, ctypes.byref(nov), float(near), float(far), ctypes.byref(wts),
+            PREC[precision] if isinstance(precision, str) else int(precision),
+            ATTN[attn_form] if isinstance(attn_form, str) else int(attn_form),
+            MODE[mode] if isinstance(mode, str) else int(mode),
+            ctypes.byref(lin), ctypes.byref(lout), _ptr(rgb_out), _ptr(acc_out)]
+    return args, keep
+
+
+def update_fuse(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
+                precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
+                acc_out=None, stream=None):
+    """qk_update_fuse.  ``ldm_in``/``ldm_out`` are (F, depth, alpha) tuples of
+    device tensors (or prebuilt qk_ldm); ``feats`` a list of [Hf][Wf][C]
+    device tensors; ``weights`` a dict of float32 device tensors."""
+    args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
+                          ldm_in, ldm_out, rgb_out, acc_out)
+    _check(ctx._lib.qk_update_fuse(ctx.handle, _stream_handle(stream), *args))
+
+
+def update_fuse_check(in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
+                      precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
+                      acc_out=None) -> int:
+    """qk_update_fuse_check: the status qk_update_fuse would return (no device use)."""
+    args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
+                          ldm_in, ldm_out, rgb_out, acc_out)
+    return int(load().qk_update_fuse_check(*args))
+
+
+def composite(ctx: Context, color, alpha, rgb_out, acc_out=None, stream=None):
+    L, H, W = (int(s) for s in alpha.shape)
+    _check(ctx._lib.qk_composite(ctx.handle, _stream_handle(stream), L, H, W, _ptr(color),
+                                 _ptr(alpha), _ptr(rgb_out), _ptr(acc_out)))
+
+
+def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:
+    """qk_camera_tables: per-view [12] = A (3x3 row-major) then b, in double."""
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    hw = np.ascontiguousarray(feat_hw, dtype=np.int32).reshape(V, 2)
+    out = np.zeros((V, 12))
+    nov = make_camera(novel)
+    _check(load().qk_camera_tables(V, cams, hw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   ctypes.byref(nov), int(H), int(W),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

@@ -351,3 +351,20 @@ def make_custom(*, V: int, H: int, W: int, C: int, L: int, heads: int = 1,
     target = rng.uniform(0.0, 1.0, size=(H, W, 3)).astype(np.float32) if with_target else None
     return Scene(0, f"custom-V{V}-{W}x{H}-L{L}-C{C}", seed, dtype, in_cams, novel, near, far,
                  [lvl], steps=steps, target=target)
+
+
+def to_bf16(scene: Scene) -> Scene:
+    """The same draws stored in bfloat16 (features and LDM features are
+    rounded to nearest-even; everything else is unchanged)."""
+    import copy
+    if scene.dtype == "bf16":
+        return scene
+    sc = copy.copy(scene)
+    sc.dtype = "bf16"
+    sc.levels = []
+    for lvl in scene.levels:
+        l2 = copy.copy(lvl)
+        l2.feats = [f32_to_bf16_bits(f) for f in lvl.feats]
+        l2.F = f32_to_bf16_bits(lvl.F)
+        sc.levels.append(l2)
+    return sc

@@ -1,0 +1,164 @@
+"""C-ABI contract on the CPU: the library loads, exports every symbol the
+header declares, composes the camera tables in double exactly like the
+oracle's independent 4x4 chain, and rejects bad arguments before touching a
+device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_16680_amd import lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="session", autouse=True)
+def built_library():
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2411_16680_amd import build
+        build.build()
+    return lib.load()
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "quark.h")).read()
+    declared = sorted(set(re.findall(r"QK_API\s+[\w\s\*]*?\b(qk_\w+)\s*\(", hdr)))
+    assert declared, "no declarations found"
+    assert sorted(lib.EXPORTS) == declared
+    L = lib.load()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert "gfx950" in lib.version()
+
+
+def _random_rig(seed):
+    r = np.random.default_rng(seed)
+    sc = synth.make_custom(V=5, H=33, W=47, C=8, L=2, seed=seed, hfov=75.0)
+    return sc
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_camera_tables_match_oracle_chain(seed):
+    sc = _random_rig(seed)
+    H, W = 33, 47
+    feat_hw = [(17, 23)] * sc.V          # feature grid differs from the LDM grid
+    tab = lib.camera_tables(sc.in_cams, feat_hw, sc.novel, H, W)
+    r = np.random.default_rng(seed + 10)
+    for m, cam in enumerate(sc.in_cams):
+        A = tab[m, :9].reshape(3, 3)
+        b = tab[m, 9:]
+        Kn = oracle.scale_intrinsics(sc.novel.K, sc.novel.width, sc.novel.height, W, H)
+        Km = oracle.scale_intrinsics(cam.K, cam.width, cam.height, 23, 17)
+        for _ in range(20):
+            u, v, d = r.uniform(0, W), r.uniform(0, H), r.uniform(0.5, 20)
+            pz = A[2] @ [u, v, 1] + b[2] / d
+            (um, vm), ok = oracle.reproject(Kn, sc.novel.E, Km, cam.E, u, v, d)
+            assert ok == (pz > 1e-6)
+            if ok:
+                px = A[0] @ [u, v, 1] + b[0] / d
+                py = A[1] @ [u, v, 1] + b[1] / d
+                assert abs(px / pz - um) < 1e-9 and abs(py / pz - vm) < 1e-9
+
+
+# ---------------------------------------------------------------- validation
+
+class _FakeT:
+    """Stands in for a device tensor: only the pointer value and shape are
+    read by the argument checks (no device memory is touched)."""
+
+    def __init__(self, shape, addr=0x100000, dtype=None):
+        import torch
+        self.shape = shape
+        self._addr = addr
+        self.dtype = dtype or torch.float32
+
+    def data_ptr(self):
+        return self._addr
+
+
+def _args(C=16, L=4, H=12, W=20, V=3, dtype="f32", heads=1, head_dim=None, Cf=None):
+    import torch
+    sc = synth.make_custom(V=V, H=H, W=W, C=C, L=L, seed=4)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    Cf = C if Cf is None else Cf
+    hd = heads * (C if head_dim is None else head_dim)
+    feats = [_FakeT((H, W, Cf), 0x200000 + 0x10000 * i, tdt) for i in range(V)]
+    F = _FakeT((L, H, W, C), 0x300000, tdt)
+    d = _FakeT((L, H, W), 0x400000)
+    a = _FakeT((L, H, W), 0x500000)
+    w = {"Wq": _FakeT((C, hd), 0x600000), "Wk": _FakeT((Cf, hd), 0x610000),
+         "Wv": _FakeT((Cf, hd), 0x620000), "Wo": _FakeT((hd, C), 0x630000),
+         "w_sigma": _FakeT((C,), 0x640000), "w_depth": _FakeT((C,), 0x650000),
+         "W_color": _FakeT((C, 3), 0x660000)}
+    wts = lib.make_weights(w, heads=heads)
+    return sc, feats, wts, (F, d, a)
+
+
+def _check(sc, feats, wts, ldm, **kw):
+    return lib.update_fuse_check(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, ldm, ldm, **kw)
+
+
+def test_valid_arguments_pass():
+    for C in (8, 16, 32, 64):
+        sc, feats, wts, ldm = _args(C=C)
+        assert _check(sc, feats, wts, ldm) == lib.QK_OK
+        sc, feats, wts, ldm = _args(C=C, dtype="bf16")
+        assert _check(sc, feats, wts, ldm, precision="bf16") == lib.QK_OK
+
+
+def test_rejections():
+    sc, feats, wts, ldm = _args()
+    # precision / dtype mismatch
+    assert _check(sc, feats, wts, ldm, precision="bf16") == lib.QK_EDTYPE
+    # unsupported channel count and heads
+    sc2, f2, w2, l2 = _args(C=24)
+    assert _check(sc2, f2, w2, l2) == lib.QK_EUNSUPPORTED
+    sc2, f2, w2, l2 = _args(C=16, heads=2, head_dim=8)
+    assert _check(sc2, f2, w2, l2) == lib.QK_EUNSUPPORTED
+    # misaligned feature buffer
+    F, d, a = ldm
+    bad = (_FakeT(F.shape, F._addr + 4), d, a)
+    assert _check(sc, feats, wts, bad) == lib.QK_EINVAL
+    # NULL weight
+    w_null = lib.qk_weights.from_buffer_copy(wts)
+    w_null.Wk = None
+    assert _check(sc, feats, w_null, ldm) == lib.QK_EINVAL
+    # near >= far
+    assert lib.update_fuse_check(sc.in_cams, feats, sc.novel, 5.0, 5.0, wts, ldm, ldm) == lib.QK_EINVAL
+    # bad camera: K last row
+    bad_cam = synth.Camera(sc.novel.K.copy(), sc.novel.E.copy(), sc.novel.width, sc.novel.height)
+    bad_cam.K[2, 2] = 2.0
+    assert lib.update_fuse_check(sc.in_cams, feats, bad_cam, sc.near, sc.far, wts, ldm,
+                                 ldm) == lib.QK_EINVAL
+    # out LDM with different dims
+    out = (_FakeT((2, 12, 20, 16), 0x700000), _FakeT((2, 12, 20), 0x710000),
+           _FakeT((2, 12, 20), 0x720000))
+    assert lib.update_fuse_check(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, ldm,
+                                 out) == lib.QK_ESHAPE
+    # acc without rgb
+    assert _check(sc, feats, wts, ldm, acc_out=_FakeT((12, 20))) == lib.QK_EINVAL
+    msg = lib.load().qk_last_error().decode()
+    assert "rgb" in msg
+
+
+def test_null_context_rejected_before_device_use():
+    sc, feats, wts, ldm = _args()
+    args, keep = lib._uf_args(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, "fp32",
+                              "standard", "residual", ldm, ldm, None, None)
+    assert lib.load().qk_update_fuse(None, None, *args) == lib.QK_EINVAL
+    assert lib.load().qk_composite(None, None, 1, 1, 1, None, None, None, None) == lib.QK_EINVAL
+
+
+def test_context_create_without_gpu_reports_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    st = lib.load().qk_context_create(0, ctypes.byref(h))
+    assert st in (lib.QK_EHIP, lib.QK_EINVAL)
+    with pytest.raises(lib.QuarkError):
+        lib.Context(0)

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances
+----------
+RGB (in [0, 1]): float32 form max-abs <= 1e-4; bfloat16 form max-abs <= 2e-2
+and PSNR >= 45 dB.  The other outputs are checked with bounds derived from
+the arithmetic of each form (see the design notes): float32 F' within
+2e-4 + 2e-4|F'|, alpha' within 1e-4, depth' within 1e-4 relative; bfloat16
+F' within 4e-2 + 1.6e-2|F'| (storage rounding 2^-9 relative plus bfloat16
+operand rounding of the projections), alpha' within 2e-2, depth' within
+2e-2 relative.
+"""
+
+import math
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_16680_amd import lib, runner, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {
+    "fp32": {"rgb": 1e-4, "acc": 1e-4, "alpha": 1e-4, "depth_rel": 1e-4, "F_abs": 2e-4, "F_rel": 2e-4},
+    "bf16": {"rgb": 2e-2, "acc": 2e-2, "alpha": 2e-2, "depth_rel": 2e-2, "F_abs": 4e-2, "F_rel": 1.6e-2},
+}
+
+
+def _say(*a):
+    print("[parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib.Context(0)
+
+
+def psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def compare(gpu, ref, form, rows=None, composite=True, label=""):
+    """Compare GPU outputs (full arrays) with oracle outputs (packed rows)."""
+    t = TOL[form]
+    sel = (lambda a: a) if rows is None else (lambda a: a[:, rows])
+    F = sel(gpu["F"]); d = sel(gpu["depth"]); a = sel(gpu["alpha"])
+    errs = {}
+    errs["F"] = float(np.max(np.abs(F - ref["F"]) - t["F_rel"] * np.abs(ref["F"])))
+    errs["alpha"] = float(np.max(np.abs(a - ref["alpha"])))
+    errs["depth_rel"] = float(np.max(np.abs(d - ref["depth"]) / ref["depth"]))
+    if composite:
+        rgb = gpu["rgb"] if rows is None else gpu["rgb"][rows]
+        acc = gpu["acc"] if rows is None else gpu["acc"][rows]
+        errs["rgb"] = float(np.max(np.abs(rgb - ref["rgb"])))
+        errs["acc"] = float(np.max(np.abs(acc - ref["acc"])))
+        errs["psnr"] = psnr(rgb, ref["rgb"])
+    _say(label, form, {k: f"{v:.3g}" for k, v in errs.items()})
+    assert errs["F"] <= t["F_abs"], (label, "F", errs)
+    assert errs["alpha"] <= t["alpha"], (label, "alpha", errs)
+    assert errs["depth_rel"] <= t["depth_rel"], (label, "depth", errs)
+    if composite:
+        assert errs["rgb"] <= t["rgb"], (label, "rgb", errs)
+        assert errs["acc"] <= t["acc"], (label, "acc", errs)
+        if form == "bf16":
+            assert errs["psnr"] >= 45.0, (label, "psnr", errs)
+    return errs
+
+
+def run_gpu_level(ctx, scene, li=0, **kw):
+    lvl = scene.levels[li]
+    dl = runner.level_to_device(lvl)
+    runner.run_level(ctx, scene, dl, **kw)
+    return runner.level_outputs_numpy(dl), dl
+
+
+# ---------------------------------------------------------------- configs
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_c1_full(ctx, form):
+    _say("c1 full", form)
+    sc = synth.make_inputs(1)
+    if form == "bf16":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc)
+    compare(gpu, ref, form, label="c1")
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_c2_two_steps_sampled_rows(ctx, form):
+    _say("c2 sampled", form)
+    sc = synth.make_inputs(2)
+    if form == "bf16":
+        sc = synth.to_bf16(sc)
+    rows = [0, 1, 63, 64, 134, 135, 201, 268, 269]
+    ref = oracle.run_level(sc, sc.levels[0], rows=rows)
+    gpu, _ = run_gpu_level(ctx, sc)
+    compare(gpu, ref, form, rows=rows, label="c2")
+
+
+@pytest.fixture(scope="module")
+def c3_scenes():
+    _say("drawing c3 inputs")
+    sc = synth.make_inputs(3)
+    return {"fp32": sc, "bf16": synth.to_bf16(sc)}
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+@pytest.mark.parametrize("li", [0, 1, 2, 3])
+def test_c3_levels_sampled_rows(ctx, c3_scenes, form, li):
+    # full 1080p-pyramid sizes, launched exactly as the benchmark launches
+    # them (levels 0-2 without composite, level 3 with it)
+    sc = c3_scenes[form]
+    lvl = sc.levels[li]
+    H = lvl.H
+    rows = sorted({0, 1, H // 3, H // 2, H - 2, H - 1})
+    _say("c3 level", li, form, "rows", rows)
+    ref = oracle.run_level(sc, lvl, rows=rows)
+    gpu, _ = run_gpu_level(ctx, sc, li)
+    compare(gpu, ref, form, rows=rows, composite=lvl.composite, label=f"c3 L{li}")
+
+
+# ---------------------------------------------------------------- edge cases
+
+EDGE = [
+    # (name, kwargs for make_custom)
+    ("ragged-W37-H5-L3-C16-V3", dict(V=3, H=5, W=37, C=16, L=3)),
+    ("single-pixel-W1-H1-L2-C8-V2", dict(V=2, H=1, W=1, C=8, L=2)),
+    ("one-layer-W70-H3-C32-V4", dict(V=4, H=3, W=70, C=32, L=1)),
+    ("one-view-W20-H4-C64-L2", dict(V=1, H=4, W=20, C=64, L=2)),
+    ("pad-views-C8-V5", dict(V=5, H=6, W=33, C=8, L=4)),
+    ("pad-views-C16-V3", dict(V=3, H=6, W=19, C=16, L=2)),
+    ("max-views-V16-C32", dict(V=16, H=4, W=40, C=32, L=2, arc=0.6)),
+    ("feature-grid-differs", dict(V=3, H=9, W=30, C=16, L=3, feat_hw=(5, 17))),
+    ("wide-fov-many-invalid", dict(V=4, H=8, W=48, C=8, L=5, arc=1.2, radius=1.0, hfov=100.0)),
+]
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,kw", EDGE, ids=[e[0] for e in EDGE])
+def test_edge_cases(ctx, name, kw, form):
+    _say("edge", name, form)
+    sc = synth.make_custom(dtype="f32", seed=zlib.crc32(name.encode()) % 1000, **kw)
+    if form == "bf16":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc)
+    compare(gpu, ref, form, label=name)
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_paper_decode_mode(ctx, form):
+    _say("paper decode", form)
+    sc = synth.make_custom(V=4, H=7, W=45, C=32, L=6, seed=31)
+    if form == "bf16":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0], mode=1)
+    gpu, _ = run_gpu_level(ctx, sc, mode="paper")
+    compare(gpu, ref, form, label="paper-decode")
+
+
+def test_in_place_and_optional_outputs(ctx):
+    _say("in-place / no F' / no acc")
+    sc = synth.make_custom(V=3, H=6, W=50, C=16, L=4, seed=5)
+    lvl = sc.levels[0]
+    ref = oracle.run_level(sc, lvl)
+    dl = runner.level_to_device(lvl)
+    # in place: ldm_out aliases ldm_in
+    rgb = torch.empty((lvl.H, lvl.W, 3), device="cuda")
+    lib.update_fuse(ctx, sc.in_cams, dl.feats, sc.novel, sc.near, sc.far, dl.weights,
+                    (dl.F, dl.depth, dl.alpha), (dl.F, dl.depth, dl.alpha), rgb_out=rgb)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(rgb.cpu().numpy(), ref["rgb"], atol=1e-4)
+    np.testing.assert_allclose(dl.F.cpu().numpy(), ref["F"], atol=2e-4, rtol=2e-4)
+    np.testing.assert_allclose(dl.alpha.cpu().numpy(), ref["alpha"], atol=1e-4)
+    # F' not written (output F = NULL), composite without acc
+    dl2 = runner.level_to_device(lvl)
+    sentinel = torch.full_like(dl2.F_out, 7.0)
+    dl2.F_out.copy_(sentinel)
+    lib.update_fuse(ctx, sc.in_cams, dl2.feats, sc.novel, sc.near, sc.far, dl2.weights,
+                    (dl2.F, dl2.depth, dl2.alpha), (None, dl2.depth_out, dl2.alpha_out),
+                    rgb_out=rgb)
+    torch.cuda.synchronize()
+    assert bool((dl2.F_out == 7.0).all())
+    np.testing.assert_allclose(rgb.cpu().numpy(), ref["rgb"], atol=1e-4)
+    np.testing.assert_allclose(dl2.depth_out.cpu().numpy(), ref["depth"], rtol=1e-4)
+
+
+def test_identity_camera_single_view_returns_source_pixel(ctx):
+    # the sample of a layer-pixel seen by an identical camera is the source
+    # pixel: with W_v = W_o = I and V = 1, F' = F + I[y][x] exactly
+    _say("identity camera")
+    sc = synth.make_custom(V=1, H=5, W=21, C=16, L=2, seed=3)
+    sc.in_cams[0] = synth.Camera(sc.novel.K.copy(), sc.novel.E.copy(), 21, 5)
+    lvl = sc.levels[0]
+    lvl.weights["Wv"] = np.eye(16, dtype=np.float32)
+    lvl.weights["Wo"] = np.eye(16, dtype=np.float32)
+    gpu, _ = run_gpu_level(ctx, sc)
+    expect = lvl.F.astype(np.float64) + lvl.feats[0].astype(np.float64)[None]
+    np.testing.assert_allclose(gpu["F"], expect, atol=2e-5)
+
+
+def test_runs_are_bitwise_deterministic(ctx):
+    _say("determinism")
+    sc = synth.to_bf16(synth.make_custom(V=4, H=16, W=100, C=32, L=4, seed=9))
+    a, _ = run_gpu_level(ctx, sc)
+    b, _ = run_gpu_level(ctx, sc)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_standalone_composite(ctx):
+    _say("standalone composite")
+    r = np.random.default_rng(4)
+    L, H, W = 7, 13, 29
+    color = r.uniform(0, 1, (L, H, W, 3)).astype(np.float32)
+    alpha = r.uniform(0, 1, (L, H, W)).astype(np.float32)
+    alpha[0, 0, :5] = 1.0
+    alpha[:, 1, :] = 0.0
+    rgb_ref, acc_ref = oracle.composite(color, alpha)
+    c = torch.from_numpy(color).cuda(); a = torch.from_numpy(alpha).cuda()
+    rgb = torch.empty((H, W, 3), device="cuda"); acc = torch.empty((H, W), device="cuda")
+    lib.composite(ctx, c, a, rgb, acc)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(rgb.cpu().numpy(), rgb_ref, atol=1e-6)
+    np.testing.assert_allclose(acc.cpu().numpy(), acc_ref, atol=1e-6)
