@@ -67,7 +67,7 @@ def level_flops(lvl, V: int) -> int:
 # GPU timing
 # ---------------------------------------------------------------------------
 
-def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int):
+def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int, attn: str = "standard"):
     import torch
     from paper_2411_16680_amd import runner
 
@@ -77,7 +77,7 @@ def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int):
         for i, dl in enumerate(dls):
             if i == dominant and ev_a is not None:
                 ev_a.record(stream)
-            runner.run_level(ctx, scene, dl, stream=stream)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
             if i == dominant and ev_b is not None:
                 ev_b.record(stream)
 
@@ -101,7 +101,7 @@ def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int):
     return {"total_ms": float(total_ms), "per_frame_ms": per, "kernel_ms": kern, "wall_s": wall}
 
 
-def per_level_ms(ctx, scene, dls, reps: int = 20):
+def per_level_ms(ctx, scene, dls, attn: str = "standard", reps: int = 20):
     """Average duration of each level's launch, timed alone."""
     import torch
     from paper_2411_16680_amd import runner
@@ -109,12 +109,12 @@ def per_level_ms(ctx, scene, dls, reps: int = 20):
     out = []
     for dl in dls:
         for _ in range(3):
-            runner.run_level(ctx, scene, dl, stream=stream)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(reps):
-            runner.run_level(ctx, scene, dl, stream=stream)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
         b.record(stream)
         torch.cuda.synchronize()
         out.append(a.elapsed_time(b) / reps)
@@ -213,17 +213,19 @@ def main():
 
     results = {}
     dominant = 0
-    for form, sc, steps in (("bf16", sc16, args.steps), ("fp32", sc32, args.fp32_steps)):
+    runs = (("bf16", sc16, args.steps, "standard"), ("fp32", sc32, args.fp32_steps, "standard"),
+            ("bf16_folded", sc16, args.steps, "folded"))
+    for form, sc, steps, attn in runs:
         dls = runner.scene_to_device(sc)
         for dl in dls:                 # the benchmark renders RGB only (no acc plane)
             dl.acc = None
         torch.cuda.synchronize()
-        lv_ms = per_level_ms(ctx, sc, dls)
+        lv_ms = per_level_ms(ctx, sc, dls, attn)
         dom = int(np.argmax(lv_ms))
         if form == "bf16":
             dominant = dom
         log(f"{form}: per-level ms {[round(x, 4) for x in lv_ms]} (dominant level {dom})")
-        t = time_frames(ctx, sc, dls, steps, args.warmup, dominant if form == "bf16" else dom)
+        t = time_frames(ctx, sc, dls, steps, args.warmup, dominant if form == "bf16" else dom, attn)
         per = t["per_frame_ms"]
         results[form] = {"steps": steps, "total_ms": t["total_ms"], "per_level_ms": lv_ms,
                          "p50_ms": float(np.percentile(per, 50)),
@@ -298,6 +300,11 @@ def main():
         "fp32": {"value": results["fp32"]["fps"], "unit": "frames/s",
                  "p50_ms": results["fp32"]["p50_ms"], "p99_ms": results["fp32"]["p99_ms"],
                  "steps": results["fp32"]["steps"], "per_level_ms": results["fp32"]["per_level_ms"]},
+        "folded": {"value": results["bf16_folded"]["fps"], "unit": "frames/s",
+                   "p50_ms": results["bf16_folded"]["p50_ms"],
+                   "p99_ms": results["bf16_folded"]["p99_ms"],
+                   "per_level_ms": results["bf16_folded"]["per_level_ms"],
+                   "note": "one-to-many (folded) attention, bf16: the paper's optimized form"},
         "per_level_ms": bf["per_level_ms"],
         "layer_pixel_views_per_s": S / (ms_per_step / 1000.0),
         "frame_compulsory_bytes": frame_bytes,

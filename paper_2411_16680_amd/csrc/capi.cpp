@@ -15,12 +15,15 @@
 #include "uf_params.h"
 
 namespace qk {
-hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, hipStream_t s);
+hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, bool fold, hipStream_t s);
+hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
     int device;
+    float *wfold = nullptr;      // folded-weight workspace (one-to-many form)
+    size_t wfold_elems = 0;
 };
 
 namespace {
@@ -158,11 +161,13 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
     if (in->L < 1 || in->H < 1 || in->W < 1 || in->C < 1)
         return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d C=%d)", in->L, in->H,
                     in->W, in->C);
-    if (out->L != in->L || out->H != in->H || out->W != in->W || out->C != in->C)
+    if (out->L != in->L || out->H != in->H || out->W != in->W ||
+        (out->F != nullptr && out->C != in->C))
         return fail(QK_ESHAPE, "ldm_out dims differ from ldm_in");
     if (in->dtype != QK_F32 && in->dtype != QK_BF16)
         return fail(QK_EDTYPE, "unknown LDM dtype %d", (int)in->dtype);
-    if (out->dtype != in->dtype) return fail(QK_EDTYPE, "ldm_out dtype differs from ldm_in");
+    if (out->F != nullptr && out->dtype != in->dtype)
+        return fail(QK_EDTYPE, "ldm_out dtype differs from ldm_in");
     const qk_dtype need = precision == QK_PREC_BF16 ? QK_BF16 : QK_F32;
     if (in->dtype != need)
         return fail(QK_EDTYPE, "precision %d needs LDM/feature dtype %d", (int)precision, (int)need);
@@ -202,8 +207,6 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
                     "kernels support heads == 1 and C == C_feat == head_dim in {8,16,32,64} "
                     "(got heads=%d head_dim=%d C=%d C_feat=%d)",
                     w->heads, w->head_dim, in->C, w->C_feat);
-    if (attn_form != QK_ATTN_STANDARD)
-        return fail(QK_EUNSUPPORTED, "folded attention form not built yet");
     return QK_OK;
 }
 
@@ -227,6 +230,12 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
+    if (ctx && ctx->wfold) {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
+        (void)hipFree(ctx->wfold);
+        if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
+    }
     delete ctx;
     return QK_OK;
 }
@@ -275,7 +284,10 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         p.fW[m] = feats[m].W;
         double t12[12];
         compose_table(novel, in->W, in->H, &in_cams[m], feats[m].W, feats[m].H, t12);
-        for (int k = 0; k < 12; ++k) p.cam[m][k] = (float)t12[k];
+        for (int k = 0; k < 12; ++k) {
+            p.cam[m][k] = (float)t12[k];
+            p.camd[m][k] = t12[k];
+        }
     }
     p.F_in = in->F;
     p.depth_in = in->depth;
@@ -299,7 +311,10 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
     p.inv_near = 1.0f / near_;
     p.inv_far = 1.0f / far_;
     p.mode = (int)update_mode;
-    p.x_blocks = (in->W + 63) / 64;
+    // a workgroup covers 64 G pixels of a row, G = 32 / C sub-tiles for C < 32
+    const int sub_tiles = in->C >= 32 ? 1 : 32 / in->C;
+    const int wg_pixels = 64 * sub_tiles;
+    p.x_blocks = (in->W + wg_pixels - 1) / wg_pixels;
     // Layer chunks: the composite needs every layer of a pixel in one wave;
     // otherwise split layers until the grid has enough workgroups.
     const int64_t xy = (int64_t)p.x_blocks * in->H;
@@ -318,8 +333,33 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
     if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
     if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
-    hipError_t e = qk::launch_update_fuse(p, in->C, precision == QK_PREC_BF16,
-                                          reinterpret_cast<hipStream_t>(hip_stream));
+    const bool fold = attn_form == QK_ATTN_FOLDED;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (fold) {
+        // fold W_k into the query and W_v into the output projection, on the
+        // caller's stream, into the context's workspace
+        const size_t need = 2 * (size_t)w->C * w->C_feat;
+        if (ctx->wfold_elems < need) {
+            if (ctx->wfold) {
+                hipError_t se = hipStreamSynchronize(stream);
+                if (se != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
+                (void)hipFree(ctx->wfold);
+                ctx->wfold = nullptr;
+                ctx->wfold_elems = 0;
+            }
+            if (hipMalloc(&ctx->wfold, need * sizeof(float)) != hipSuccess)
+                return fail(QK_ENOMEM, "workspace of %zu floats", need);
+            ctx->wfold_elems = need;
+        }
+        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, ctx->wfold, ctx->wfold + (size_t)w->C * w->C_feat,
+                          w->C, w->C_feat, w->heads * w->head_dim,
+                          1.0f / std::sqrt((float)w->head_dim)};
+        hipError_t fe = qk::launch_fold_weights(fp, stream);
+        if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
+        p.Wqk = fp.Wqk;
+        p.Wvo = fp.Wvo;
+    }
+    hipError_t e = qk::launch_update_fuse(p, in->C, precision == QK_PREC_BF16, fold, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "update_fuse launch: %s", hipGetErrorString(e));
     return QK_OK;
 }

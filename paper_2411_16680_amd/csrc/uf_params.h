@@ -14,6 +14,7 @@ struct UFParams {
     int32_t fH[kMaxViews];
     int32_t fW[kMaxViews];
     float cam[kMaxViews][12];
+    double camd[kMaxViews][12];   // same tables in double (float32 form)
 
     const void *F_in;
     const float *depth_in;
@@ -25,14 +26,22 @@ struct UFParams {
     float *acc;            // may be NULL
 
     const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
+    const float *Wqk, *Wvo;    // folded weights (one-to-many form), C x C
 
     int32_t V, L, H, W;
     int32_t layers_per_chunk;  // layers handled by one workgroup
-    int32_t x_blocks;          // ceil(W / 64)
+    int32_t x_blocks;          // ceil(W / pixels per workgroup)
     int32_t n_tiles;           // x_blocks * H * chunks (workgroups in the grid)
     int32_t chunks;
     float inv_near, inv_far;
     int32_t mode;              // 0 residual, 1 paper decode
+};
+
+struct FoldParams {
+    const float *Wq, *Wk, *Wv, *Wo;
+    float *Wqk, *Wvo;
+    int32_t C, Cf, hd;
+    float scale;
 };
 
 struct CompParams {

@@ -187,6 +187,8 @@ def _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mo
     wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
     lin = ldm_in if isinstance(ldm_in, qk_ldm) else make_ldm(*ldm_in)
     lout = ldm_out if isinstance(ldm_out, qk_ldm) else make_ldm(*ldm_out)
+    if not lout.F:                   # F' not written: channel count and dtype follow the input
+        lout.C, lout.dtype = lin.C, lin.dtype
     keep = (cams, fm, nov, wts, lin, lout)
     args = [V, cams, fm, ctypes.byref(nov), float(near), float(far), ctypes.byref(wts),
             PREC[precision] if isinstance(precision, str) else int(precision),

@@ -5,11 +5,16 @@ Tolerances
 ----------
 RGB (in [0, 1]): float32 form max-abs <= 1e-4; bfloat16 form max-abs <= 2e-2
 and PSNR >= 45 dB.  The other outputs are checked with bounds derived from
-the arithmetic of each form (see the design notes): float32 F' within
-2e-4 + 2e-4|F'|, alpha' within 1e-4, depth' within 1e-4 relative; bfloat16
-F' within 4e-2 + 1.6e-2|F'| (storage rounding 2^-9 relative plus bfloat16
-operand rounding of the projections), alpha' within 2e-2, depth' within
-2e-2 relative.
+the arithmetic of each form (design notes, "Tolerances"):
+  * F' : |err| <= F_abs + F_rel |F'|
+  * alpha' : max-abs
+  * depth' : in disparity, as a fraction of one step's largest update
+    (0.5/L)(1/near - 1/far) -- relative depth error is not a stable measure
+    near the far plane, where a small disparity error is a large depth error.
+Multi-step runs compound: the second step samples at positions moved by the
+first step's depth error, so their bounds on the intermediate outputs scale
+with the step count.  Every measured error is written to
+gpurun_out/parity_report.json when that folder exists.
 """
 
 import math
@@ -26,9 +31,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {
-    "fp32": {"rgb": 1e-4, "acc": 1e-4, "alpha": 1e-4, "depth_rel": 1e-4, "F_abs": 2e-4, "F_rel": 2e-4},
-    "bf16": {"rgb": 2e-2, "acc": 2e-2, "alpha": 2e-2, "depth_rel": 2e-2, "F_abs": 4e-2, "F_rel": 1.6e-2},
+    "fp32": {"rgb": 1e-4, "acc": 1e-4, "alpha": 1e-4, "disp": 1e-3, "F_abs": 2e-4, "F_rel": 2e-4},
+    "bf16": {"rgb": 2e-2, "acc": 2e-2, "alpha": 2e-2, "disp": 1e-1, "F_abs": 4e-2, "F_rel": 1.6e-2},
 }
+REPORT = []
 
 
 def _say(*a):
@@ -48,14 +54,22 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
 
 
-def compare(gpu, ref, form, rows=None, composite=True, label=""):
+def compare(gpu, ref, form, scene, level, rows=None, composite=True, label=""):
     """Compare GPU outputs (full arrays) with oracle outputs (packed rows)."""
-    t = TOL[form]
+    t = dict(TOL[form])
+    steps = scene.steps
+    if steps > 1:                  # compounding through the reprojection (see module doc)
+        for k in ("F_abs", "alpha", "disp"):
+            t[k] *= 5.0 * steps if form == "fp32" else 2.5 * steps
     sel = (lambda a: a) if rows is None else (lambda a: a[:, rows])
     F = sel(gpu["F"]); d = sel(gpu["depth"]); a = sel(gpu["alpha"])
+    step_range = (0.5 / level.L) * (1.0 / scene.near - 1.0 / scene.far)
     errs = {}
-    errs["F"] = float(np.max(np.abs(F - ref["F"]) - t["F_rel"] * np.abs(ref["F"])))
+    errs["F_excess"] = float(np.max(np.abs(F - ref["F"]) - t["F_rel"] * np.abs(ref["F"])))
+    errs["F_maxabs"] = float(np.max(np.abs(F - ref["F"])))
+    errs["F_rms"] = float(np.sqrt(np.mean((F - ref["F"]) ** 2)))
     errs["alpha"] = float(np.max(np.abs(a - ref["alpha"])))
+    errs["disp"] = float(np.max(np.abs(1.0 / d - 1.0 / ref["depth"])) / step_range)
     errs["depth_rel"] = float(np.max(np.abs(d - ref["depth"]) / ref["depth"]))
     if composite:
         rgb = gpu["rgb"] if rows is None else gpu["rgb"][rows]
@@ -64,15 +78,26 @@ def compare(gpu, ref, form, rows=None, composite=True, label=""):
         errs["acc"] = float(np.max(np.abs(acc - ref["acc"])))
         errs["psnr"] = psnr(rgb, ref["rgb"])
     _say(label, form, {k: f"{v:.3g}" for k, v in errs.items()})
-    assert errs["F"] <= t["F_abs"], (label, "F", errs)
+    REPORT.append({"case": label, "form": form, **errs})
+    assert errs["F_excess"] <= t["F_abs"], (label, "F", errs)
     assert errs["alpha"] <= t["alpha"], (label, "alpha", errs)
-    assert errs["depth_rel"] <= t["depth_rel"], (label, "depth", errs)
+    assert errs["disp"] <= t["disp"], (label, "depth", errs)
     if composite:
         assert errs["rgb"] <= t["rgb"], (label, "rgb", errs)
         assert errs["acc"] <= t["acc"], (label, "acc", errs)
         if form == "bf16":
             assert errs["psnr"] >= 45.0, (label, "psnr", errs)
     return errs
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _write_report():
+    yield
+    import json
+    import os
+    if os.path.isdir("gpurun_out") and REPORT:
+        with open(os.path.join("gpurun_out", "parity_report.json"), "w") as f:
+            json.dump(REPORT, f, indent=1)
 
 
 def run_gpu_level(ctx, scene, li=0, **kw):
@@ -84,27 +109,34 @@ def run_gpu_level(ctx, scene, li=0, **kw):
 
 # ---------------------------------------------------------------- configs
 
+ATTN = ["standard", "folded"]
+
+
+@pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
-def test_c1_full(ctx, form):
-    _say("c1 full", form)
+def test_c1_full(ctx, form, attn):
+    # the folded (one-to-many) form is checked against the oracle's standard
+    # definition: the two are equal in exact arithmetic
+    _say("c1 full", form, attn)
     sc = synth.make_inputs(1)
     if form == "bf16":
         sc = synth.to_bf16(sc)
     ref = oracle.run_level(sc, sc.levels[0])
-    gpu, _ = run_gpu_level(ctx, sc)
-    compare(gpu, ref, form, label="c1")
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn)
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"c1 {attn}")
 
 
+@pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
-def test_c2_two_steps_sampled_rows(ctx, form):
-    _say("c2 sampled", form)
+def test_c2_two_steps_sampled_rows(ctx, form, attn):
+    _say("c2 sampled", form, attn)
     sc = synth.make_inputs(2)
     if form == "bf16":
         sc = synth.to_bf16(sc)
     rows = [0, 1, 63, 64, 134, 135, 201, 268, 269]
     ref = oracle.run_level(sc, sc.levels[0], rows=rows)
-    gpu, _ = run_gpu_level(ctx, sc)
-    compare(gpu, ref, form, rows=rows, label="c2")
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn)
+    compare(gpu, ref, form, sc, sc.levels[0], rows=rows, label=f"c2 {attn}")
 
 
 @pytest.fixture(scope="module")
@@ -114,19 +146,20 @@ def c3_scenes():
     return {"fp32": sc, "bf16": synth.to_bf16(sc)}
 
 
+@pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
 @pytest.mark.parametrize("li", [0, 1, 2, 3])
-def test_c3_levels_sampled_rows(ctx, c3_scenes, form, li):
+def test_c3_levels_sampled_rows(ctx, c3_scenes, form, li, attn):
     # full 1080p-pyramid sizes, launched exactly as the benchmark launches
     # them (levels 0-2 without composite, level 3 with it)
     sc = c3_scenes[form]
     lvl = sc.levels[li]
     H = lvl.H
     rows = sorted({0, 1, H // 3, H // 2, H - 2, H - 1})
-    _say("c3 level", li, form, "rows", rows)
+    _say("c3 level", li, form, attn, "rows", rows)
     ref = oracle.run_level(sc, lvl, rows=rows)
-    gpu, _ = run_gpu_level(ctx, sc, li)
-    compare(gpu, ref, form, rows=rows, composite=lvl.composite, label=f"c3 L{li}")
+    gpu, _ = run_gpu_level(ctx, sc, li, attn_form=attn)
+    compare(gpu, ref, form, sc, lvl, rows=rows, composite=lvl.composite, label=f"c3 L{li} {attn}")
 
 
 # ---------------------------------------------------------------- edge cases
@@ -145,27 +178,29 @@ EDGE = [
 ]
 
 
+@pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
 @pytest.mark.parametrize("name,kw", EDGE, ids=[e[0] for e in EDGE])
-def test_edge_cases(ctx, name, kw, form):
-    _say("edge", name, form)
+def test_edge_cases(ctx, name, kw, form, attn):
+    _say("edge", name, form, attn)
     sc = synth.make_custom(dtype="f32", seed=zlib.crc32(name.encode()) % 1000, **kw)
     if form == "bf16":
         sc = synth.to_bf16(sc)
     ref = oracle.run_level(sc, sc.levels[0])
-    gpu, _ = run_gpu_level(ctx, sc)
-    compare(gpu, ref, form, label=name)
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn)
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"{name} {attn}")
 
 
+@pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
-def test_paper_decode_mode(ctx, form):
-    _say("paper decode", form)
+def test_paper_decode_mode(ctx, form, attn):
+    _say("paper decode", form, attn)
     sc = synth.make_custom(V=4, H=7, W=45, C=32, L=6, seed=31)
     if form == "bf16":
         sc = synth.to_bf16(sc)
     ref = oracle.run_level(sc, sc.levels[0], mode=1)
-    gpu, _ = run_gpu_level(ctx, sc, mode="paper")
-    compare(gpu, ref, form, label="paper-decode")
+    gpu, _ = run_gpu_level(ctx, sc, mode="paper", attn_form=attn)
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"paper-decode {attn}")
 
 
 def test_in_place_and_optional_outputs(ctx):
@@ -209,11 +244,12 @@ def test_identity_camera_single_view_returns_source_pixel(ctx):
     np.testing.assert_allclose(gpu["F"], expect, atol=2e-5)
 
 
-def test_runs_are_bitwise_deterministic(ctx):
-    _say("determinism")
+@pytest.mark.parametrize("attn", ATTN)
+def test_runs_are_bitwise_deterministic(ctx, attn):
+    _say("determinism", attn)
     sc = synth.to_bf16(synth.make_custom(V=4, H=16, W=100, C=32, L=4, seed=9))
-    a, _ = run_gpu_level(ctx, sc)
-    b, _ = run_gpu_level(ctx, sc)
+    a, _ = run_gpu_level(ctx, sc, attn_form=attn)
+    b, _ = run_gpu_level(ctx, sc, attn_form=attn)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
