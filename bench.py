@@ -179,6 +179,29 @@ def cpu_baseline(scene, target_s: float = 25.0):
 
 # ---------------------------------------------------------------------------
 
+def profile_run(ctx, steps: int, depth_mode: str):
+    """Frames of the bf16 standard form, then a plain copy of known size, for
+    counter collection (FETCH_SIZE / WRITE_SIZE are scaled by what they read
+    for the copy)."""
+    import torch
+    from paper_2411_16680_amd import runner, synth
+    sc = synth.to_bf16(synth.make_inputs(3, depth_mode=depth_mode))
+    dls = runner.scene_to_device(sc)
+    for dl in dls:
+        dl.acc = None
+    torch.cuda.synchronize()
+    for s in range(steps):
+        runner.run_scene(ctx, sc, dls)
+        torch.cuda.synchronize()
+        log(f"profile frame {s + 1}/{steps}")
+    n = 128 * 1024 * 1024                          # 512 MiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +210,9 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth-mode", default="iid", choices=["iid", "smooth"])
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for rocprofv3: run --steps frames of the bf16 standard form, then a "
+                         "512 MiB device copy (counter calibration), and exit without timing")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,6 +229,10 @@ def main():
         sys.exit(1)
     lib.load()
     ctx = lib.Context(0)
+
+    if args.profile_run:
+        profile_run(ctx, args.steps, args.depth_mode)
+        return
 
     log("drawing the 1080p multi-scale workload (V=8)")
     t0 = time.perf_counter()

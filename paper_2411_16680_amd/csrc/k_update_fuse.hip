@@ -11,26 +11,35 @@
 //   * a workgroup is 4 waves; it covers 64 G consecutive pixels of one LDM row
 //     and a chunk of layers; each wave owns 16 G pixels and walks the layers
 //     of its chunk front to back (so the composite accumulates in registers);
-//   * lane l = 16 g + r.  In the MFMA A-operand layout lane l holds row r
-//     (pixel x0 + r) and K-slots 8g..8g+7 of each 32-wide K chunk; in the
-//     accumulator layout it holds column r and rows 4g..4g+3.
-//   * the bilinear gather of view m writes straight into the A operand: lane
-//     (r, g) reprojects pixel r into the view its slots belong to and loads
-//     8 channels per tap (16 B in bfloat16, 32 B in float32).
-//   * for C < 32 the 32-wide K chunk holds G = 32 / C independent 16-pixel
-//     sub-tiles side by side and every weight is laid out block-diagonally,
-//     so a wave covers 16 G pixels and all its lanes sample the same view at
-//     a time (camera parameters and the feature base stay scalar);
+//   * projections are computed transposed, out^T = W^T x^T, on
+//     v_mfma_f32_16x16x32_bf16 (bfloat16) or v_mfma_f32_16x16x4_f32 (float32):
+//     the weights are the A operand and the per-pixel vectors the B operand,
+//     so pixels run along the output columns.  Lane l = 16 g + n holds, in
+//     the operand layout, K-slots 8g..8g+7 of pixel column n, and in the
+//     accumulator layout output rows 4g..4g+3 of column n.  A pixel's logit
+//     is then a sum inside the lane and across at most four lanes (one or two
+//     permlane swaps), and every lane keeps one or two softmax states;
+//   * the bilinear gather of view m writes straight into the B operand: lane
+//     (n, g) reprojects its pixel and loads 8 channels per tap (16 B in
+//     bfloat16, 32 B in float32);
+//   * for C < 32 a 32-wide K chunk holds G = 32 / C independent 16-pixel
+//     sub-tiles side by side and every weight is block-diagonal, so a wave
+//     covers 16 G pixels and all its lanes sample the same view at a time
+//     (camera parameters and the feature base stay scalar);
+//   * for C = 8 the four bilinear taps run along K instead (lane (n, g) loads
+//     tap g), so the two taps of a row come from adjacent lanes of one load,
+//     and the MFMA forms the weighted tap sum with the weight stacked 4x;
 //   * taps are clamped into the map with zero weight when outside, so the
-//     gather has no divergent branches;
+//     gather has no divergent branches; the loads of view m + 1 are issued
+//     before view m is projected;
 //   * softmax over views is an online update (running max / sum, one exp per
-//     view) on the accumulator layout; logits reduce over the head dimension
-//     across the columns of a lane row with DPP.
+//     state and view);
 //   * weights arrive as float32 masters; each workgroup converts them once
-//     into B-operand fragments in LDS; the K/V fragments are then held in
-//     registers for the whole view loop.
+//     into operand fragments in LDS; the K/V fragments then stay in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "uf_params.h"
 
@@ -42,19 +51,26 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int C>
 struct Shape {
     static constexpr int G = (C >= 32) ? 1 : 32 / C;    // 16-pixel sub-tiles packed along K
-    static constexpr int KC = (C >= 32) ? C / 32 : 1;   // 32-wide K chunks of an A operand
-    static constexpr int NT = (G * C) / 16;             // 16-wide N tiles of Q/K/V/O outputs
-    static constexpr int ND = (G == 1) ? 1 : G / 2;     // N tiles of the decode output
-    static constexpr int NTS = (G == 1) ? 1 : NT;       // softmax states per accumulator row
+    static constexpr int KC = (C >= 32) ? C / 32 : 1;   // 32-wide K chunks of an operand
+    static constexpr int NT = (G * C) / 16;             // 16-row output tiles of Q/K/V/O
+    static constexpr int ND = (G == 1) ? 1 : G / 2;     // output tiles of the decode
     static constexpr int PIX = 16 * G;                  // pixels per wave
-    static constexpr int SLOTS = 32 * KC;               // K slots per A row
-    static constexpr int PITCH = SLOTS + 4;             // LDS tile row pitch (floats)
+    static constexpr int P = C + 4;                     // LDS floats per pixel (padded)
+    // C = 8: the four bilinear taps run along the MFMA K dimension
+    static constexpr bool TAPK = (C == 8);
+};
+
+// Weight-fragment slots in LDS: Q, [K, V,] O, decode.  The K/V slots exist
+// only when the view loop projects per-sample keys and values on MFMA.
+template <int C, bool KV>
+struct Frags {
+    static constexpr int KC = Shape<C>::KC, NT = Shape<C>::NT, ND = Shape<C>::ND;
     static constexpr int OFF_Q = 0;
     static constexpr int OFF_K = KC * NT;
-    static constexpr int OFF_V = 2 * KC * NT;
-    static constexpr int OFF_O = 3 * KC * NT;
-    static constexpr int OFF_D = 4 * KC * NT;
-    static constexpr int NFRAG = OFF_D + KC * ND;
+    static constexpr int OFF_V = OFF_K + (KV ? KC * NT : 0);
+    static constexpr int OFF_O = OFF_V + (KV ? KC * NT : 0);
+    static constexpr int OFF_D = OFF_O + KC * NT;
+    static constexpr int N = OFF_D + KC * ND;
 };
 
 // ---------------------------------------------------------------------------
@@ -147,24 +163,6 @@ __device__ inline typename CoordT<BF16>::type cam_entry(const UFParams &p, int m
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
 
-// DPP lane permutations inside a 16-lane row.
-template <int CTRL>
-__device__ inline float dpp(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 CTRL, 0xF, 0xF, false));
-}
-// Sum over aligned groups of W lanes (W = 8 or 16) of a row: quad xor 1,
-// quad xor 2, then half-row mirror (8) and row mirror (16).
-template <int W>
-__device__ inline float group_sum(float v) {
-    v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
-    v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
-    v += dpp<0x141>(v);    // row_half_mirror
-    if constexpr (W == 16) v += dpp<0x140>(v);   // row_mirror
-    return v;
-}
-
-__device__ inline float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
 __device__ inline void lds_read8(const float *src, float *f) {
     const float4 a = *reinterpret_cast<const float4 *>(src);
@@ -173,19 +171,60 @@ __device__ inline void lds_read8(const float *src, float *f) {
     f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
 }
 
-// Back-projection of one layer-pixel into view m followed by its bilinear
-// sample (half-pixel centres, zero padding): p = A_m (u, v, 1) + b_m / d; a
-// point with p_z <= 1e-6 (behind the view) samples zero.  This lane's share is
-// channels ch0 + 32 kc + [0, 8) of the sample, in FP32.  Taps are clamped into
-// the map and keep weight 0 when outside, so the loads are unconditional.
+// Raw storage of one 8-channel tap: 16 B of bfloat16 or 32 B of float.
+template <bool BF16>
+struct RawTap {
+    uint4 v[BF16 ? 1 : 2];
+};
+
+// The four taps of one bilinear sample (this lane's channels), as loaded, and
+// their weights.  Loading and blending are split so the loads of the next
+// view can be in flight while the current view is projected.
 template <int C, bool BF16>
-__device__ inline void gather_sample(const UFParams &p, int m, typename CoordT<BF16>::type uc,
-                                     typename CoordT<BF16>::type vc,
-                                     typename CoordT<BF16>::type invdc, bool a_ok, int ch0,
-                                     float (&sv)[Shape<C>::KC][8]) {
+struct Taps {
+    RawTap<BF16> t[Shape<C>::KC][4];
+    float w[4];
+};
+
+template <bool BF16>
+__device__ inline void raw_load(const typename Op<BF16>::T *ptr, RawTap<BF16> &r) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(ptr);
+    r.v[0] = q[0];
+    if constexpr (!BF16) r.v[1] = q[1];
+}
+
+template <bool BF16>
+__device__ inline void raw_unpack(const RawTap<BF16> &r, float *f) {
+    if constexpr (BF16) {
+        const uint4 u = r.v[0];
+        f[0] = __uint_as_float(u.x << 16);
+        f[1] = __uint_as_float(u.x & 0xffff0000u);
+        f[2] = __uint_as_float(u.y << 16);
+        f[3] = __uint_as_float(u.y & 0xffff0000u);
+        f[4] = __uint_as_float(u.z << 16);
+        f[5] = __uint_as_float(u.z & 0xffff0000u);
+        f[6] = __uint_as_float(u.w << 16);
+        f[7] = __uint_as_float(u.w & 0xffff0000u);
+    } else {
+        f[0] = __uint_as_float(r.v[0].x); f[1] = __uint_as_float(r.v[0].y);
+        f[2] = __uint_as_float(r.v[0].z); f[3] = __uint_as_float(r.v[0].w);
+        f[4] = __uint_as_float(r.v[1].x); f[5] = __uint_as_float(r.v[1].y);
+        f[6] = __uint_as_float(r.v[1].z); f[7] = __uint_as_float(r.v[1].w);
+    }
+}
+
+// Back-projection of one layer-pixel into view m (the first half of the
+// bilinear sample): p = A_m (u, v, 1) + b_m / d; a point with p_z <= 1e-6
+// (behind the view) samples zero.  Computes this lane's four tap addresses
+// (half-pixel centres; taps clamped into the map, weight 0 when outside, so
+// the loads are unconditional) and issues the loads of channels
+// ch0 + 32 kc + [0, 8).
+template <int C, bool BF16>
+__device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16>::type uc,
+                                  typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
+                                  bool a_ok, int ch0, Taps<C, BF16> &tp) {
     using Coord = typename CoordT<BF16>::type;
-    using OP = Op<BF16>;
-    using T = typename OP::T;
+    using T = typename Op<BF16>::T;
     constexpr int KC = Shape<C>::KC;
     const T *fm = reinterpret_cast<const T *>(p.feat[m]);
     const int fh = p.fH[m], fw = p.fW[m];
@@ -206,78 +245,198 @@ __device__ inline void gather_sample(const UFParams &p, int m, typename CoordT<B
     const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
     const bool vx0 = (unsigned)ix < (unsigned)fw, vx1 = (unsigned)(ix + 1) < (unsigned)fw;
     const bool vy0 = (unsigned)iy < (unsigned)fh, vy1 = (unsigned)(iy + 1) < (unsigned)fh;
-    const float w00 = (vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f;
-    const float w10 = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
-    const float w01 = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
-    const float w11 = (vx1 && vy1) ? wx * wy : 0.0f;
+    tp.w[0] = (vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f;
+    tp.w[1] = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
+    tp.w[2] = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
+    tp.w[3] = (vx1 && vy1) ? wx * wy : 0.0f;
     const int cx0 = min(max(ix, 0), fw - 1), cx1 = min(max(ix + 1, 0), fw - 1);
     const int cy0 = min(max(iy, 0), fh - 1), cy1 = min(max(iy + 1, 0), fh - 1);
     const int o00 = (cy0 * fw + cx0) * C + ch0, o10 = (cy0 * fw + cx1) * C + ch0;
     const int o01 = (cy1 * fw + cx0) * C + ch0, o11 = (cy1 * fw + cx1) * C + ch0;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
-        float t00[8], t10[8], t01[8], t11[8];
-        OP::load8(fm + o00 + 32 * kc, t00);
-        OP::load8(fm + o10 + 32 * kc, t10);
-        OP::load8(fm + o01 + 32 * kc, t01);
-        OP::load8(fm + o11 + 32 * kc, t11);
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            sv[kc][i] = fmaf(w11, t11[i], fmaf(w01, t01[i], fmaf(w10, t10[i], w00 * t00[i])));
+        raw_load<BF16>(fm + o00 + 32 * kc, tp.t[kc][0]);
+        raw_load<BF16>(fm + o10 + 32 * kc, tp.t[kc][1]);
+        raw_load<BF16>(fm + o01 + 32 * kc, tp.t[kc][2]);
+        raw_load<BF16>(fm + o11 + 32 * kc, tp.t[kc][3]);
     }
 }
 
-// Sum of a value over the lanes that share one pixel's channels in the A
-// layout: lanes 16 apart (C = 16) or 16 and 32 apart (C >= 32).  With both
-// operands equal, the two outputs of a permlane swap hold the two rows of each
-// pair broadcast, so their sum is the pair sum.
+// Second half of the bilinear sample: the weighted sum of the four taps in
+// FP32 (tap order 00, 10, 01, 11).
+template <int C, bool BF16>
+__device__ inline void blend_taps(const Taps<C, BF16> &tp, float (&sv)[Shape<C>::KC][8]) {
+#pragma unroll
+    for (int kc = 0; kc < Shape<C>::KC; ++kc) {
+        float t00[8], t10[8], t01[8], t11[8];
+        raw_unpack<BF16>(tp.t[kc][0], t00);
+        raw_unpack<BF16>(tp.t[kc][1], t10);
+        raw_unpack<BF16>(tp.t[kc][2], t01);
+        raw_unpack<BF16>(tp.t[kc][3], t11);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            sv[kc][i] = fmaf(tp.w[3], t11[i], fmaf(tp.w[2], t01[i], fmaf(tp.w[1], t10[i], tp.w[0] * t00[i])));
+    }
+}
+
+// C = 8 taps-along-K: lane (r, g) reprojects its own pixel (16 g + r) into
+// view m, publishes that pixel's four (tap offset, weight) pairs in LDS, and
+// loads tap g of pixel 16 j + r for each row-group j = 0..3.
+template <bool BF16>
+struct TapsK {
+    RawTap<BF16> t[4];
+    float w[4];
+};
+
+template <int C, bool BF16>
+__device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16>::type uc,
+                                  typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
+                                  bool a_ok, int r, int g, int2 *tT, TapsK<BF16> &tp) {
+    using Coord = typename CoordT<BF16>::type;
+    using T = typename Op<BF16>::T;
+    const T *fm = reinterpret_cast<const T *>(p.feat[m]);
+    const int fh = p.fH[m], fw = p.fW[m];
+    const Coord pz = fma(cam_entry<BF16>(p, m, 6), uc,
+                         fma(cam_entry<BF16>(p, m, 7), vc,
+                             fma(cam_entry<BF16>(p, m, 11), invdc, cam_entry<BF16>(p, m, 8))));
+    const Coord qx = fma(cam_entry<BF16>(p, m, 0), uc,
+                         fma(cam_entry<BF16>(p, m, 1), vc,
+                             fma(cam_entry<BF16>(p, m, 9), invdc, cam_entry<BF16>(p, m, 2))));
+    const Coord qy = fma(cam_entry<BF16>(p, m, 3), uc,
+                         fma(cam_entry<BF16>(p, m, 4), vc,
+                             fma(cam_entry<BF16>(p, m, 10), invdc, cam_entry<BF16>(p, m, 5))));
+    const Coord rz = recip(pz);
+    const Coord fxc = qx * rz - (Coord)0.5, fyc = qy * rz - (Coord)0.5;
+    const bool ok = a_ok && (pz > (Coord)1e-6) && (fabs(fxc) < (Coord)1e7) && (fabs(fyc) < (Coord)1e7);
+    const Coord xf = floor(fxc), yf = floor(fyc);
+    const float wx = (float)(fxc - xf), wy = (float)(fyc - yf);
+    const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
+    const bool vx0 = (unsigned)ix < (unsigned)fw, vx1 = (unsigned)(ix + 1) < (unsigned)fw;
+    const bool vy0 = (unsigned)iy < (unsigned)fh, vy1 = (unsigned)(iy + 1) < (unsigned)fh;
+    const int cx0 = min(max(ix, 0), fw - 1), cx1 = min(max(ix + 1, 0), fw - 1);
+    const int cy0 = min(max(iy, 0), fh - 1), cy1 = min(max(iy + 1, 0), fh - 1);
+    int4 ow0, ow1;       // (offset, weight bits) of taps 00, 10 | 01, 11
+    ow0.x = (cy0 * fw + cx0) * C;
+    ow0.y = __float_as_int((vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f);
+    ow0.z = (cy0 * fw + cx1) * C;
+    ow0.w = __float_as_int((vx1 && vy0) ? wx * (1.0f - wy) : 0.0f);
+    ow1.x = (cy1 * fw + cx0) * C;
+    ow1.y = __float_as_int((vx0 && vy1) ? (1.0f - wx) * wy : 0.0f);
+    ow1.z = (cy1 * fw + cx1) * C;
+    ow1.w = __float_as_int((vx1 && vy1) ? wx * wy : 0.0f);
+    int4 *slot = reinterpret_cast<int4 *>(&tT[(g * 16 + r) * 4]);
+    slot[0] = ow0;
+    slot[1] = ow1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int2 e = tT[(j * 16 + r) * 4 + g];
+        tp.w[j] = __int_as_float(e.y);
+        raw_load<BF16>(fm + e.x, tp.t[j]);
+    }
+}
+
+template <int C, bool BF16, typename TP>
+__device__ inline void issue_any(const UFParams &p, int m, typename CoordT<BF16>::type uc,
+                                 typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
+                                 bool a_ok, int ch0, int r, int g, int2 *tT, TP &tp) {
+    if constexpr (Shape<C>::TAPK) issue_tapk<C, BF16>(p, m, uc, vc, invdc, a_ok, r, g, tT, tp);
+    else issue_taps<C, BF16>(p, m, uc, vc, invdc, a_ok, ch0, tp);
+}
+
+// Pair sums across lane rows (a row is 16 lanes): with both operands equal,
+// the two outputs of a permlane swap hold the two rows of each pair
+// broadcast, so their sum is the pair sum (rows 0+1 and 2+3 for the 16-swap,
+// rows 0..1 + 2..3 for the 32-swap).
+__device__ inline float rows_pair_sum16(float v) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+__device__ inline float rows_pair_sum32(float v) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// Value of the odd row of this lane's row pair (for even rows).
+__device__ inline float odd_row_value(float v) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(s[1]);
+}
+
+// Sum over the lanes that hold one pixel's channels in the operand layout:
+// lanes 16 apart (C = 16) or all four rows (C >= 32).
 template <int C>
-__device__ inline float pixel_lane_sum(float v) {
-    if constexpr (C >= 16) {
-        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
-    }
-    if constexpr (C >= 32) {
-        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
-    }
+__device__ inline float operand_pixel_sum(float v) {
+    if constexpr (C >= 16) v = rows_pair_sum16(v);
+    if constexpr (C >= 32) v = rows_pair_sum32(v);
     return v;
 }
+
+// Sum over the lanes that hold one pixel's output channels in the
+// accumulator layout: a row pair (C = 8) or all four rows (C >= 16).
+template <int C>
+__device__ inline float result_pixel_sum(float v) {
+    v = rows_pair_sum16(v);
+    if constexpr (C >= 16) v = rows_pair_sum32(v);
+    return v;
+}
+
+__device__ inline float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+__device__ inline void lds_write4(float *dst, const float *f) {
+    *reinterpret_cast<float4 *>(dst) = make_float4(f[0], f[1], f[2], f[3]);
+}
+
+// Register budget per instance: the waves per SIMD each form reaches without
+// spilling (float32 forms keep the compiler's default).
+template <int C, bool BF16, bool FOLD>
+struct Occupancy {
+    static constexpr int waves = !BF16 ? 1
+                               : (C > 32) ? (FOLD ? 3 : 2)
+                               : ((FOLD && !Shape<C>::TAPK) ? 5 : 4);
+};
 
 // FOLD = false: standard cross-attention (per-sample key and value
 // projections on MFMA).  FOLD = true: one-to-many attention -- the key
 // projection folded into the query (q~ = N(F) W_q W_k^T / sqrt(d)) and the
 // value projection into the output (W_v W_o); the per-view work is a dot
-// product and a weighted sum on the samples themselves.
+// product and a weighted sum on the samples themselves (for C = 8 the same
+// MFMA loop, with the blended sample standing in for keys and values).
 template <int C, bool BF16, bool FOLD>
-__global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(Occupancy<C, BF16, FOLD>::waves)))
+k_update_fuse(const UFParams p) {
     using SH = Shape<C>;
     using OP = Op<BF16>;
     using AF = typename OP::A;
     using T = typename OP::T;
     using Coord = typename CoordT<BF16>::type;
-    constexpr int G = SH::G, KC = SH::KC, NT = SH::NT, ND = SH::ND, NTS = SH::NTS;
-    constexpr int PIX = SH::PIX, PITCH = SH::PITCH;
-    constexpr int DW = (C >= 16) ? 16 : 8;    // columns of one head inside a 16-wide tile
+    constexpr int G = SH::G, KC = SH::KC, NT = SH::NT, ND = SH::ND, PIX = SH::PIX, P = SH::P;
+    constexpr bool TAPK = SH::TAPK;
+    constexpr bool STDLOOP = !FOLD || TAPK;     // the MFMA view loop
+    constexpr int NS = (G == 1) ? 1 : NT;       // softmax states per lane
+    using FR = Frags<C, STDLOOP>;
+    static_assert(!TAPK || 64 * 4 * sizeof(int2) <= PIX * P * sizeof(float),
+                  "tap exchange must fit the o tile it shares");
 
-    __shared__ AF sfrag[SH::NFRAG][64];
-    __shared__ float sF[4][16 * PITCH];
-    __shared__ float sO[4][16 * PITCH];
-    __shared__ float sX[4][PIX * 8];
+    __shared__ AF sfrag[FR::N][64];
+    __shared__ float sF[4][PIX * P];
+    __shared__ float sO[4][PIX * P];   // o tile; for C = 8 also the tap exchange
 
     const int tid = threadIdx.x;
 
-    // ---- B-operand fragments from the float32 master weights, once per
-    // workgroup.  Every projection is block-diagonal over the G sub-tiles.
-    for (int e = tid; e < SH::NFRAG * 64; e += 256) {
+    // ---- weight fragments from the float32 master weights, once per
+    // workgroup.  Fragment lane (c, k) holds element [k-slot 8k..8k+7][c] of
+    // W (the A operand of the transposed products).  Every projection is
+    // block-diagonal over the G sub-tiles.
+    for (int e = tid; e < FR::N * 64; e += 256) {
         const int f = e >> 6, ln = e & 63;
         const int nn = ln & 15, gg = ln >> 4;
-        const int kind = (f < SH::OFF_D) ? f / (KC * NT) : 4;
-        const int fi = (f < SH::OFF_D) ? f % (KC * NT) : f - SH::OFF_D;
+        // kinds: 0 Q, 1 K, 2 V, 3 O, 4 decode
+        int kind = (f < FR::OFF_D) ? f / (KC * NT) : 4;
+        if (!STDLOOP && kind == 1) kind = 3;      // no K/V slots: the O slots follow Q
+        const int fi = (f < FR::OFF_D) ? f % (KC * NT) : f - FR::OFF_D;
         const int ntile = (kind == 4) ? ND : NT;
         const int kc = fi / ntile, t = fi % ntile;
-        const int ng = 16 * t + nn;               // output column of this lane
-        if (FOLD && (kind == 1 || kind == 2)) continue;   // no per-sample projections
+        const int ng = 16 * t + nn;               // output channel row of this lane
         const float *Wm = kind == 0 ? (FOLD ? p.Wqk : p.Wq) : kind == 1 ? p.Wk
                         : kind == 2 ? p.Wv : (FOLD ? p.Wvo : p.Wo);
         float vals[8];
@@ -285,7 +444,14 @@ __global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
         for (int i = 0; i < 8; ++i) {
             const int kap = 32 * kc + 8 * gg + i;   // K slot: sub-tile kap / C, channel kap % C
             float w = 0.0f;
-            if (kind < 4) {
+            if (TAPK && (kind == 1 || kind == 2)) {
+                // K slot kap = tap (kap / 8) x channel (kap % 8); output rows
+                // 8t..8t+7 of the tile hold row-group t of a pair
+                if (nn / 8 == t) {
+                    if (FOLD) w = (kap % 8 == nn % 8) ? 1.0f : 0.0f;     // the blended sample itself
+                    else w = Wm[(kap % 8) * C + (nn % 8)];
+                }
+            } else if (kind < 4) {
                 if (kap / C == ng / C) w = Wm[(kap % C) * C + (ng % C)];
             } else {                                // decode heads: sigma, depth, r, g, b
                 const int s = (G == 1) ? 0 : ng / 8;
@@ -304,7 +470,7 @@ __global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
     // ---- tile of this workgroup: XCD-aware remap of the dispatch order so
     // that each XCD (dispatched round-robin) walks one contiguous band of rows
     const int wave = tid >> 6, lane = tid & 63;
-    const int r = lane & 15, g = lane >> 4;
+    const int n = lane & 15, g = lane >> 4;
     int tile;
     {
         const int nt = p.n_tiles, i = blockIdx.x;
@@ -320,45 +486,53 @@ __global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
     const int l_begin = chunk * p.layers_per_chunk;
     const int l_end = min(p.L, l_begin + p.layers_per_chunk);
 
-    // A-operand row of this lane: pixel xa, channels ch0 + 32 kc + [0, 8)
+    // operand role of this lane: pixel column n of sub-tile sg, channels
+    // ch0 + 32 kc + [0, 8)
     const int sg = (G > 1) ? (8 * g) / C : 0;
     const int ch0 = (G > 1) ? (8 * g) % C : 8 * g;
-    const int xa = x0w + 16 * sg + r;
+    const int pl_b = 16 * sg + n;                      // wave-local pixel
+    const int xa = x0w + pl_b;
     const bool a_ok = xa < p.W;
-    // per-pixel epilogue lane: pixel x0w + lane
-    const bool e_ok = (lane < PIX) && (x0w + lane < p.W);
+    // result role: output rows 4g..4g+3 of tile t belong to sub-tile sd(t),
+    // channels ed(t) + [0, 4)
+    auto sd = [&](int t) { return (G > 1) ? (16 * t + 4 * g) / C : 0; };
+    auto ed = [&](int t) { return (G > 1) ? (16 * t + 4 * g) % C : 16 * t + 4 * g; };
+    // decode owner lanes: heads 0..3 of a pixel sit in an even row, head 4 in
+    // the row after it
+    const bool owner = (G > 1) ? ((g & 1) == 0) : (g == 0);
 
-    constexpr int KCB = FOLD ? 1 : KC, NTB = FOLD ? 1 : NT;
+    constexpr int KCB = STDLOOP ? KC : 1, NTB = STDLOOP ? NT : 1;
     AF Bk[KCB][NTB], Bv[KCB][NTB];
-    if constexpr (!FOLD) {
+    if constexpr (STDLOOP) {
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                Bk[kc][t] = sfrag[SH::OFF_K + kc * NT + t][lane];
-                Bv[kc][t] = sfrag[SH::OFF_V + kc * NT + t][lane];
+                Bk[kc][t] = sfrag[FR::OFF_K + kc * NT + t][lane];
+                Bv[kc][t] = sfrag[FR::OFF_V + kc * NT + t][lane];
             }
     }
 
     float *tF = sF[wave];
     float *tO = sO[wave];
-    float *tX = sX[wave];
     const T *Fin = reinterpret_cast<const T *>(p.F_in);
     T *Fout = reinterpret_cast<T *>(p.F_out);
     const bool do_comp = p.rgb != nullptr;
-    const float scale = 1.0f / sqrtf((float)C);
+    const float scale = FOLD ? 1.0f : 1.0f / sqrtf((float)C);   // folded: W_qk carries it
     const Coord uc = (Coord)(a_ok ? xa : 0) + (Coord)0.5, vc = (Coord)y + (Coord)0.5;
     const float band = p.inv_near - p.inv_far;
     const float half_l = 0.5f / (float)p.L;
 
-    float Tr = 1.0f, cr0 = 0.0f, cr1 = 0.0f, cr2 = 0.0f;
+    float Tr[ND], cr[ND][3];
+#pragma unroll
+    for (int td = 0; td < ND; ++td) { Tr[td] = 1.0f; cr[td][0] = cr[td][1] = cr[td][2] = 0.0f; }
 
     for (int li = l_begin; li < l_end; ++li) {
         const size_t rowbase = ((size_t)li * p.H + y) * p.W;
         const size_t pa = rowbase + (a_ok ? xa : 0);
         const float d = a_ok ? p.depth_in[pa] : 1.0f;
 
-        // ---- LDM feature tile, A layout; copy to LDS for the residual
+        // ---- LDM features of this lane's pixel (operand layout), to LDS
         float fa[KC][8];
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
@@ -366,152 +540,192 @@ __global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
             else
 #pragma unroll
                 for (int i = 0; i < 8; ++i) fa[kc][i] = 0.0f;
-            float *dst = &tF[r * PITCH + 32 * kc + 8 * g];
-            *reinterpret_cast<float4 *>(dst) = make_float4(fa[kc][0], fa[kc][1], fa[kc][2], fa[kc][3]);
-            *reinterpret_cast<float4 *>(dst + 4) = make_float4(fa[kc][4], fa[kc][5], fa[kc][6], fa[kc][7]);
+            float *dst = &tF[pl_b * P + ch0 + 32 * kc];
+            lds_write4(dst, fa[kc]);
+            lds_write4(dst + 4, fa[kc] + 4);
         }
 
-        // ---- RMSNorm (unit gain, eps 1e-6) over the pixel's channels, query
+        // ---- RMSNorm (unit gain, eps 1e-6) over the pixel's channels; query
         float ss = 0.0f;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
             for (int i = 0; i < 8; ++i) ss = fmaf(fa[kc][i], fa[kc][i], ss);
-        if constexpr (C >= 16) ss += __shfl_xor(ss, 16);
-        if constexpr (C >= 32) ss += __shfl_xor(ss, 32);
+        ss = operand_pixel_sum<C>(ss);
         const float inv = 1.0f / sqrtf(ss * (1.0f / (float)C) + 1e-6f);
         f32x4 Q[NT];
         {
-            AF Axn[KC];
+            AF Xn[KC];
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float t8[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) t8[i] = fa[kc][i] * inv;
-                Axn[kc] = OP::make(t8);
+                Xn[kc] = OP::make(t8);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 Q[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
-                    Q[t] = OP::mma(Axn[kc], sfrag[SH::OFF_Q + kc * NT + t][lane], Q[t]);
+                    Q[t] = OP::mma(sfrag[FR::OFF_Q + kc * NT + t][lane], Xn[kc], Q[t]);
             }
         }
 
-        AF Ao[KC];
+        AF Ob[KC];                                     // o, operand layout
         const Coord invdc = recip((Coord)d);
-        if constexpr (!FOLD) {
-            // ---- standard cross-attention over the views: per-sample keys and
-            // values on MFMA, online softmax (finite start so the update is
+        if constexpr (STDLOOP) {
+            // ---- cross-attention over the views on MFMA: per-sample keys and
+            // values (standard form) or, for C = 8 folded, the blended samples
+            // themselves; online softmax (finite start so the update is
             // branch-free; one exp per state and view)
-            float M[NTS][4], Z[NTS][4];
+            float M[NS], Z[NS];
             f32x4 acc[NT];
 #pragma unroll
-            for (int s = 0; s < NTS; ++s)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) { M[s][i] = -1e30f; Z[s][i] = 0.0f; }
+            for (int s = 0; s < NS; ++s) { M[s] = -1e30f; Z[s] = 0.0f; }
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
+            using TapsT = typename std::conditional<TAPK, TapsK<BF16>, Taps<C, BF16>>::type;
+            int2 *tT = reinterpret_cast<int2 *>(sO[wave]);   // free until o is written
+            TapsT cur;
+            issue_any<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, n, g, tT, cur);
             for (int m = 0; m < p.V; ++m) {
-                AF As[KC];
-                {
-                    float sv[KC][8];
-                    gather_sample<C, BF16>(p, m, uc, vc, invdc, a_ok, ch0, sv);
+                // loads of the next view go out before this view is projected
+                TapsT nxt;
+                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, nxt);
+                // keep those loads here: without this fence the compiler sinks
+                // them to their use in the next iteration, serialising every view
+                // on a full memory latency
+                asm volatile("" ::: "memory");
+                // B operands: the blended sample (one per K chunk), or for C = 8
+                // the weighted taps of each 16-pixel row-group
+                constexpr int NA = TAPK ? 4 : KC;
+                AF Sb[NA];
+                if constexpr (TAPK) {
 #pragma unroll
-                    for (int kc = 0; kc < KC; ++kc) As[kc] = OP::make(sv[kc]);
-                }
-                // keys and logits
-                float lg[NTS][4];
-                {
-                    f32x4 Kt[NT];
+                    for (int j = 0; j < 4; ++j) {
+                        float t8[8];
+                        raw_unpack<BF16>(cur.t[j], t8);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        Kt[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) Kt[t] = OP::mma(As[kc], Bk[kc][t], Kt[t]);
+                        for (int i = 0; i < 8; ++i) t8[i] *= cur.w[j];
+                        Sb[j] = OP::make(t8);
                     }
-                    if constexpr (G == 1) {
-                        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                } else {
+                    float sv[KC][8];
+                    blend_taps<C, BF16>(cur, sv);
 #pragma unroll
-                        for (int t = 0; t < NT; ++t)
+                    for (int kc = 0; kc < KC; ++kc) Sb[kc] = OP::make(sv[kc]);
+                }
+                cur = nxt;
+                // keys^T and logits
+                f32x4 Kt[NT];
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) s4[i] = fmaf(Q[t][i], Kt[t][i], s4[i]);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) lg[0][i] = group_sum<16>(s4[i]) * scale;
+                for (int t = 0; t < NT; ++t) {
+                    Kt[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    if constexpr (TAPK) {
+                        Kt[t] = OP::mma(Bk[0][0], Sb[2 * t], Kt[t]);
+                        Kt[t] = OP::mma(Bk[0][1], Sb[2 * t + 1], Kt[t]);
                     } else {
 #pragma unroll
-                        for (int t = 0; t < NT; ++t)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                lg[t][i] = group_sum<DW>(Q[t][i] * Kt[t][i]) * scale;
+                        for (int kc = 0; kc < KC; ++kc) Kt[t] = OP::mma(Bk[kc][t], Sb[kc], Kt[t]);
                     }
                 }
-                // values and the online softmax update
-                float sc[NTS][4], ev[NTS][4];
+                float lg[NS];
+                if constexpr (G == 1) {
+                    float part = 0.0f;
 #pragma unroll
-                for (int s = 0; s < NTS; ++s)
+                    for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float a = lg[s][i];
-                        const float diff = a - M[s][i];
-                        const float x = __expf(-fabsf(diff));
-                        const bool up = diff > 0.0f;
-                        sc[s][i] = up ? x : 1.0f;
-                        ev[s][i] = up ? 1.0f : x;
-                        M[s][i] = up ? a : M[s][i];
-                        Z[s][i] = fmaf(Z[s][i], sc[s][i], ev[s][i]);
+                        for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
+                    lg[0] = result_pixel_sum<C>(part) * scale;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        float part = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
+                        lg[t] = result_pixel_sum<C>(part) * scale;
                     }
+                }
+                // online softmax update
+                float sc[NS], ev[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const float diff = lg[s] - M[s];
+                    const float x = __expf(-fabsf(diff));
+                    const bool up = diff > 0.0f;
+                    sc[s] = up ? x : 1.0f;
+                    ev[s] = up ? 1.0f : x;
+                    M[s] = up ? lg[s] : M[s];
+                    Z[s] = fmaf(Z[s], sc[s], ev[s]);
+                }
+                // values^T
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     f32x4 Vt = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    if constexpr (TAPK && FOLD) {
+                        Vt = Kt[t];                      // values are the samples themselves
+                    } else if constexpr (TAPK) {
+                        Vt = OP::mma(Bv[0][0], Sb[2 * t], Vt);
+                        Vt = OP::mma(Bv[0][1], Sb[2 * t + 1], Vt);
+                    } else {
 #pragma unroll
-                    for (int kc = 0; kc < KC; ++kc) Vt = OP::mma(As[kc], Bv[kc][t], Vt);
+                        for (int kc = 0; kc < KC; ++kc) Vt = OP::mma(Bv[kc][t], Sb[kc], Vt);
+                    }
                     const int s = (G == 1) ? 0 : t;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(acc[t][i], sc[s][i], ev[s][i] * Vt[i]);
+                    for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(acc[t][i], sc[s], ev[s] * Vt[i]);
                 }
             }
 
-            // o = acc / Z: accumulator layout -> LDS -> A layout
+            // o = acc / Z: result layout -> LDS -> operand layout
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const int s = (G == 1) ? 0 : t;
+                const float iz = 1.0f / Z[(G == 1) ? 0 : t];
+                float o4[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) tO[(4 * g + i) * PITCH + 16 * t + r] = acc[t][i] / Z[s][i];
+                for (int i = 0; i < 4; ++i) o4[i] = acc[t][i] * iz;
+                lds_write4(&tO[(16 * sd(t) + n) * P + ed(t)], o4);
             }
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float t8[8];
-                lds_read8(&tO[r * PITCH + 32 * kc + 8 * g], t8);
-                Ao[kc] = OP::make(t8);
+                lds_read8(&tO[pl_b * P + ch0 + 32 * kc], t8);
+                Ob[kc] = OP::make(t8);
             }
         } else {
             // ---- one-to-many attention: q~ (the query with W_k folded in) to
-            // the A layout, then per view a dot product with the FP32 sample and
-            // a weighted running sum of the samples themselves
+            // the operand layout, then per view a dot product with the FP32
+            // sample and a weighted running sum of the samples themselves
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) tO[(4 * g + i) * PITCH + 16 * t + r] = Q[t][i];
+            for (int t = 0; t < NT; ++t) {
+                float q4[4] = {Q[t][0], Q[t][1], Q[t][2], Q[t][3]};
+                lds_write4(&tO[(16 * sd(t) + n) * P + ed(t)], q4);
+            }
             float qa[KC][8], ob[KC][8];
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                lds_read8(&tO[r * PITCH + 32 * kc + 8 * g], qa[kc]);
+                lds_read8(&tO[pl_b * P + ch0 + 32 * kc], qa[kc]);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) ob[kc][i] = 0.0f;
             }
             float Mx = -1e30f, Zs = 0.0f;
+            Taps<C, BF16> cur;
+            issue_taps<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, cur);
             for (int m = 0; m < p.V; ++m) {
+                Taps<C, BF16> nxt;
+                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, nxt);
+                asm volatile("" ::: "memory");     // keep the next view's loads in flight
                 float sv[KC][8];
-                gather_sample<C, BF16>(p, m, uc, vc, invdc, a_ok, ch0, sv);
+                blend_taps<C, BF16>(cur, sv);
+                cur = nxt;
                 float part = 0.0f;
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
                     for (int i = 0; i < 8; ++i) part = fmaf(qa[kc][i], sv[kc][i], part);
-                const float a = pixel_lane_sum<C>(part);
+                const float a = operand_pixel_sum<C>(part);
                 const float diff = a - Mx;
                 const float x = __expf(-fabsf(diff));
                 const bool up = diff > 0.0f;
@@ -529,82 +743,84 @@ __global__ void __launch_bounds__(256) k_update_fuse(const UFParams p) {
                 float t8[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) t8[i] = ob[kc][i] * iz;
-                Ao[kc] = OP::make(t8);
+                Ob[kc] = OP::make(t8);
             }
         }
 
-        // ---- F' = F + o W_o (the accumulator starts from F)
+        // ---- F'^T = W_o^T o^T + F^T (the accumulator starts from F)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            f32x4 Fo;
+            float *fp = &tF[(16 * sd(t) + n) * P + ed(t)];
+            const float4 f4 = *reinterpret_cast<const float4 *>(fp);
+            f32x4 Fo = f32x4{f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Fo[i] = tF[(4 * g + i) * PITCH + 16 * t + r];
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) Fo = OP::mma(Ao[kc], sfrag[SH::OFF_O + kc * NT + t][lane], Fo);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) tF[(4 * g + i) * PITCH + 16 * t + r] = Fo[i];
+            for (int kc = 0; kc < KC; ++kc) Fo = OP::mma(sfrag[FR::OFF_O + kc * NT + t][lane], Ob[kc], Fo);
+            *reinterpret_cast<float4 *>(fp) = make_float4(Fo[0], Fo[1], Fo[2], Fo[3]);
         }
 
-        // ---- F' back to the A layout: store it and decode it
+        // ---- F' back to the operand layout: store it and decode it
         f32x4 X[ND];
 #pragma unroll
         for (int td = 0; td < ND; ++td) X[td] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             float t8[8];
-            lds_read8(&tF[r * PITCH + 32 * kc + 8 * g], t8);
+            lds_read8(&tF[pl_b * P + ch0 + 32 * kc], t8);
             if (Fout != nullptr && a_ok) OP::store8(Fout + pa * C + ch0 + 32 * kc, t8);
             const AF af = OP::make(t8);
 #pragma unroll
-            for (int td = 0; td < ND; ++td) X[td] = OP::mma(af, sfrag[SH::OFF_D + kc * ND + td][lane], X[td]);
-        }
-#pragma unroll
-        for (int td = 0; td < ND; ++td) {
-            const int ng = 16 * td + r;
-            const int s = (G == 1) ? 0 : ng / 8;
-            const int j = (G == 1) ? ng : ng % 8;
-            if (j < 5)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) tX[(16 * s + 4 * g + i) * 8 + j] = X[td][i];
+            for (int td = 0; td < ND; ++td) X[td] = OP::mma(sfrag[FR::OFF_D + kc * ND + td][lane], af, X[td]);
         }
 
-        // ---- decode depth / alpha / colour of pixel x0w + lane, composite
-        if (e_ok) {
-            const size_t pe = rowbase + x0w + lane;
-            const float de = p.depth_in[pe];
-            const float a_in = p.alpha_in[pe];
-            const float *xv = &tX[lane * 8];
-            const float xs = xv[0], xd = xv[1];
-            float an, dn;
-            if (p.mode == 0) {
-                const float a = fminf(fmaxf(a_in, 1e-6f), 1.0f - 1e-6f);
-                an = sigmoidf_(logf(a / (1.0f - a)) + xs);
-                float disp = 1.0f / de + half_l * band * tanhf(xd);
-                disp = fminf(fmaxf(disp, p.inv_far), p.inv_near);
-                dn = 1.0f / disp;
-            } else {
-                an = sigmoidf_(xs);
-                const float delta = ((float)(p.L - li) - 0.5f) / (float)p.L;
-                dn = 1.0f / (fmaf(delta + half_l * tanhf(xd), band, p.inv_far));
-            }
-            p.depth_out[pe] = dn;
-            p.alpha_out[pe] = an;
-            if (do_comp) {
-                const float w = Tr * an;
-                cr0 = fmaf(w, sigmoidf_(xv[2]), cr0);
-                cr1 = fmaf(w, sigmoidf_(xv[3]), cr1);
-                cr2 = fmaf(w, sigmoidf_(xv[4]), cr2);
-                Tr *= (1.0f - an);
+        // ---- decode depth / alpha / colour of this lane's pixels, composite
+#pragma unroll
+        for (int td = 0; td < ND; ++td) {
+            const float head4 = odd_row_value(X[td][0]);       // the blue head
+            const int s = (G > 1) ? 2 * td + g / 2 : 0;
+            const int xe = x0w + 16 * s + n;
+            if (owner && xe < p.W) {
+                const size_t pe = rowbase + xe;
+                const float de = p.depth_in[pe];
+                const float a_in = p.alpha_in[pe];
+                const float xs = X[td][0], xd = X[td][1];
+                float an, dn;
+                if (p.mode == 0) {
+                    const float a = fminf(fmaxf(a_in, 1e-6f), 1.0f - 1e-6f);
+                    an = sigmoidf_(logf(a / (1.0f - a)) + xs);
+                    float disp = 1.0f / de + half_l * band * tanhf(xd);
+                    disp = fminf(fmaxf(disp, p.inv_far), p.inv_near);
+                    dn = 1.0f / disp;
+                } else {
+                    an = sigmoidf_(xs);
+                    const float delta = ((float)(p.L - li) - 0.5f) / (float)p.L;
+                    dn = 1.0f / (fmaf(delta + half_l * tanhf(xd), band, p.inv_far));
+                }
+                p.depth_out[pe] = dn;
+                p.alpha_out[pe] = an;
+                if (do_comp) {
+                    const float w = Tr[td] * an;
+                    cr[td][0] = fmaf(w, sigmoidf_(X[td][2]), cr[td][0]);
+                    cr[td][1] = fmaf(w, sigmoidf_(X[td][3]), cr[td][1]);
+                    cr[td][2] = fmaf(w, sigmoidf_(head4), cr[td][2]);
+                    Tr[td] *= (1.0f - an);
+                }
             }
         }
     }
 
-    if (do_comp && e_ok) {
-        const size_t q = (size_t)y * p.W + x0w + lane;
-        p.rgb[q * 3 + 0] = cr0;
-        p.rgb[q * 3 + 1] = cr1;
-        p.rgb[q * 3 + 2] = cr2;
-        if (p.acc != nullptr) p.acc[q] = 1.0f - Tr;
+    if (do_comp) {
+#pragma unroll
+        for (int td = 0; td < ND; ++td) {
+            const int s = (G > 1) ? 2 * td + g / 2 : 0;
+            const int xe = x0w + 16 * s + n;
+            if (owner && xe < p.W) {
+                const size_t q = (size_t)y * p.W + xe;
+                p.rgb[q * 3 + 0] = cr[td][0];
+                p.rgb[q * 3 + 1] = cr[td][1];
+                p.rgb[q * 3 + 2] = cr[td][2];
+                if (p.acc != nullptr) p.acc[q] = 1.0f - Tr[td];
+            }
+        }
     }
 }
 
