@@ -253,3 +253,75 @@ def run_scene(scene, *, rows_per_level=None, mode: int = 0, attn_form: int = 0):
         rows = None if rows_per_level is None else rows_per_level[i]
         res.append(run_level(scene, lvl, rows=rows, mode=mode, attn_form=attn_form))
     return res
+
+
+def update_fuse_backward(in_cams, novel, near, far, level, *, d_rgb=None, dF_out=None,
+                         d_depth_out=None, d_alpha_out=None, rows=None, mode: int = 0,
+                         F=None, depth=None, alpha=None, feats64=None):
+    """Adjoint of one Update & Fuse step + composite (standard form).
+
+    Upstream gradients are full-size arrays (or None); only ``rows`` (default
+    all) are processed and every other row's upstream gradient counts as
+    zero, so the result is the exact gradient of a loss restricted to those
+    rows.  Returns a dict of float64 gradients: F, depth, alpha, feats (list),
+    Wq, Wk, Wv, Wo, w_sigma, w_depth, W_color."""
+    V = len(in_cams)
+    L, H, W, C, Cf = level.L, level.H, level.W, level.C, level.Cf
+    rows = np.arange(H, dtype=np.int32) if rows is None else np.asarray(rows, dtype=np.int32)
+    Kin = _f64(np.stack([c.K for c in in_cams]))
+    Ein = _f64(np.stack([c.E for c in in_cams]))
+    cam_wh = np.ascontiguousarray([[c.width, c.height] for c in in_cams], dtype=np.int32)
+    if feats64 is None:
+        feats64 = [_as_f64_array(f) for f in level.feats]
+    feat_hw = np.ascontiguousarray([[f.shape[0], f.shape[1]] for f in feats64], dtype=np.int32)
+    fptrs = (_dp * V)(*[_d(f) for f in feats64])
+    F64 = _as_f64_array(level.F if F is None else F)
+    d64 = _as_f64_array(level.depth if depth is None else depth)
+    a64 = _as_f64_array(level.alpha if alpha is None else alpha)
+    w = {k: _f64(v) for k, v in level.weights.items()}
+    nov_wh = np.array([novel.width, novel.height], dtype=np.int32)
+    Kn, En = _f64(novel.K), _f64(novel.E)
+    null = ctypes.cast(None, _dp)
+    ups = [None if a is None else _f64(a) for a in (d_rgb, dF_out, d_depth_out, d_alpha_out)]
+    g = {"F": np.zeros_like(F64), "depth": np.zeros_like(d64), "alpha": np.zeros_like(a64),
+         "feats": [np.zeros_like(f) for f in feats64]}
+    for k in ("Wq", "Wk", "Wv", "Wo", "w_sigma", "w_depth", "W_color"):
+        g[k] = np.zeros_like(w[k])
+    dIptrs = (_dp * V)(*[_d(a) for a in g["feats"]])
+    rc = lib().or_update_fuse_backward(
+        V, _d(Kin), _d(Ein), cam_wh.ctypes.data_as(_ip), fptrs, feat_hw.ctypes.data_as(_ip), Cf,
+        _d(Kn), _d(En), nov_wh.ctypes.data_as(_ip), ctypes.c_double(near), ctypes.c_double(far),
+        L, H, W, C, _d(F64), _d(d64), _d(a64), level.heads, level.head_dim,
+        _d(w["Wq"]), _d(w["Wk"]), _d(w["Wv"]), _d(w["Wo"]), _d(w["w_sigma"]), _d(w["w_depth"]),
+        _d(w["W_color"]), int(mode), rows.ctypes.data_as(_ip), int(rows.shape[0]),
+        *[null if a is None else _d(a) for a in ups],
+        _d(g["F"]), _d(g["depth"]), _d(g["alpha"]), dIptrs,
+        _d(g["Wq"]), _d(g["Wk"]), _d(g["Wv"]), _d(g["Wo"]), _d(g["w_sigma"]), _d(g["w_depth"]),
+        _d(g["W_color"]))
+    if rc != 0:
+        raise ValueError("oracle backward failed (singular camera?)")
+    return g
+
+
+def sample_coordinates(in_cams, novel, level, depth=None):
+    """Sample coordinate (u_m, v_m) of every layer-pixel in every view, NaN
+    where the point is behind the view: array [L][H][W][V][2].  Used to keep
+    finite-difference probes away from the kinks of bilinear sampling."""
+    L, H, W = level.L, level.H, level.W
+    d = _as_f64_array(level.depth if depth is None else depth)
+    out = np.full((L, H, W, len(in_cams), 2), np.nan)
+    Kn = scale_intrinsics(novel.K, novel.width, novel.height, W, H)
+    for m, cam in enumerate(in_cams):
+        Hf, Wf = level.feats[m].shape[:2]
+        Km = scale_intrinsics(cam.K, cam.width, cam.height, Wf, Hf)
+        T = reprojection_matrix(Kn, novel.E, Km, cam.E).reshape(16)
+        uv = np.zeros(2)
+        for li in range(L):
+            for y in range(H):
+                for x in range(W):
+                    ok = lib().or_reproject_T(_d(T), ctypes.c_double(x + 0.5),
+                                              ctypes.c_double(y + 0.5),
+                                              ctypes.c_double(d[li, y, x]), _d(uv))
+                    if ok == 1:
+                        out[li, y, x, m] = uv
+    return out

@@ -499,3 +499,338 @@ OR_EXPORT int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of one Update & Fuse step and its composite.                      */
+/*                                                                          */
+/* Written from the forward definitions above by the chain rule, in the     */
+/* standard (unfolded) form: keys and values are formed per sample and      */
+/* differentiated as such.  Gradients are ACCUMULATED into the outputs,     */
+/* which the caller zero-fills.  Only the listed rows are processed: the    */
+/* upstream gradients of every other row are taken as zero, so the results  */
+/* are the exact gradients of a loss restricted to those rows.              */
+/*                                                                          */
+/* Upstream (any may be NULL = zero), full-size arrays:                     */
+/*   d_rgb[H][W][3], dF_out[L][H][W][C], d_depth_out[L][H][W],              */
+/*   d_alpha_out[L][H][W]                                                   */
+/* Gradients (full-size, accumulated): dF, d_depth, d_alpha [like inputs],  */
+/*   dI[V] -> [Hf][Wf][Cf], dWq, dWk, dWv, dWo, dw_sigma, dw_depth,          */
+/*   dW_color (shapes of the weights).                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int valid;
+    double um, vm;          /* sample coordinate in view m's feature grid */
+    double dum_dd, dvm_dd;  /* its derivative w.r.t. the layer depth      */
+} or_proj;
+
+static void reproject_with_derivative(const double *T, double u, double v, double d, or_proj *pr)
+{
+    double X[4] = {u * d, v * d, d, 1.0}, dX[4] = {u, v, 1.0, 0.0};
+    double P[4], dP[4];
+    for (int r = 0; r < 4; ++r) {
+        double s = 0.0, ds = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            s += T[4 * r + c] * X[c];
+            ds += T[4 * r + c] * dX[c];
+        }
+        P[r] = s;
+        dP[r] = ds;
+    }
+    pr->valid = P[2] > 1e-6 * d;
+    if (!pr->valid) return;
+    pr->um = P[0] / P[2];
+    pr->vm = P[1] / P[2];
+    pr->dum_dd = (dP[0] * P[2] - P[0] * dP[2]) / (P[2] * P[2]);
+    pr->dvm_dd = (dP[1] * P[2] - P[1] * dP[2]) / (P[2] * P[2]);
+}
+
+/* Tap value (zero outside the map). */
+static const double *tap_ptr(const double *I, int Hf, int Wf, int C, long tx, long ty)
+{
+    if (tx < 0 || tx >= Wf || ty < 0 || ty >= Hf) return NULL;
+    return I + ((size_t)ty * Wf + (size_t)tx) * C;
+}
+
+OR_EXPORT int or_update_fuse_backward(
+    int V, const double *Kin, const double *Ein, const int *cam_wh, const double *const *feats,
+    const int *feat_hw, int Cf, const double *Kn, const double *En, const int *nov_wh,
+    double near_, double far_, int L, int H, int W, int C, const double *F, const double *depth,
+    const double *alpha, int heads, int dh, const double *Wq, const double *Wk, const double *Wv,
+    const double *Wo, const double *w_sigma, const double *w_depth, const double *W_color, int mode,
+    const int *rows, int nrows, const double *d_rgb, const double *dF_out,
+    const double *d_depth_out, const double *d_alpha_out, double *dF, double *d_depth,
+    double *d_alpha, double *const *dI, double *dWq, double *dWk, double *dWv, double *dWo,
+    double *dw_sigma, double *dw_depth, double *dW_color)
+{
+    int hd = heads * dh;
+    double Kns[9];
+    or_scale_intrinsics(Kn, nov_wh[0], nov_wh[1], W, H, Kns);
+    double *T = malloc(sizeof(double) * 16 * (size_t)V);
+    for (int m = 0; m < V; ++m) {
+        double Kms[9];
+        or_scale_intrinsics(Kin + 9 * m, cam_wh[2 * m], cam_wh[2 * m + 1], feat_hw[2 * m + 1],
+                            feat_hw[2 * m], Kms);
+        if (or_reprojection_matrix(Kns, En, Kms, Ein + 16 * m, T + 16 * m) != 0) {
+            free(T);
+            return -1;
+        }
+    }
+    const double band = 1.0 / near_ - 1.0 / far_;
+    const double kap = (0.5 / L) * band;
+    const double isq = 1.0 / sqrt((double)dh);
+    const size_t nW = (size_t)C * hd;
+    long npix = (long)nrows * W;
+
+#pragma omp parallel
+    {
+        /* per-thread weight-gradient accumulators */
+        double *gWq = calloc((size_t)C * hd, sizeof(double));
+        double *gWk = calloc((size_t)Cf * hd, sizeof(double));
+        double *gWv = calloc((size_t)Cf * hd, sizeof(double));
+        double *gWo = calloc((size_t)hd * C, sizeof(double));
+        double *gws = calloc((size_t)C, sizeof(double));
+        double *gwd = calloc((size_t)C, sizeof(double));
+        double *gWc = calloc((size_t)C * 3, sizeof(double));
+        /* per-layer forward state of one pixel */
+        double *S = malloc(sizeof(double) * (size_t)L * V * Cf);
+        or_proj *PR = malloc(sizeof(or_proj) * (size_t)L * V);
+        double *XN = malloc(sizeof(double) * (size_t)L * C);
+        double *RR = malloc(sizeof(double) * L);
+        double *Q = malloc(sizeof(double) * (size_t)L * hd);
+        double *Kk = malloc(sizeof(double) * (size_t)L * V * hd);
+        double *Vv = malloc(sizeof(double) * (size_t)L * V * hd);
+        double *Pp = malloc(sizeof(double) * (size_t)L * heads * V);
+        double *O = malloc(sizeof(double) * (size_t)L * hd);
+        double *FP = malloc(sizeof(double) * (size_t)L * C);
+        double *XS = malloc(sizeof(double) * L), *XD = malloc(sizeof(double) * L);
+        double *XC = malloc(sizeof(double) * (size_t)L * 3);
+        double *AL = malloc(sizeof(double) * L), *DN = malloc(sizeof(double) * L);
+        double *CO = malloc(sizeof(double) * (size_t)L * 3);
+        double *Tt = malloc(sizeof(double) * (L + 1)), *Bb = malloc(sizeof(double) * (size_t)(L + 1) * 3);
+        double *dFp = malloc(sizeof(double) * C), *dO = malloc(sizeof(double) * hd);
+        double *dQ = malloc(sizeof(double) * hd), *dXN = malloc(sizeof(double) * C);
+        double *dK = malloc(sizeof(double) * (size_t)V * hd), *dV = malloc(sizeof(double) * (size_t)V * hd);
+        double *dS = malloc(sizeof(double) * Cf);
+        double *dpv = malloc(sizeof(double) * V);
+
+#pragma omp for schedule(dynamic, 16)
+        for (long idx = 0; idx < npix; ++idx) {
+            int x = (int)(idx % W);
+            int y = rows[idx / W];
+            double u = x + 0.5, v = y + 0.5;
+            /* ---- forward recompute of every layer of this pixel */
+            for (int li = 0; li < L; ++li) {
+                size_t src = ((size_t)li * H + y) * W + x;
+                double d = depth[src];
+                for (int m = 0; m < V; ++m) {
+                    or_proj *pr = &PR[li * V + m];
+                    double *s = S + ((size_t)li * V + m) * Cf;
+                    reproject_with_derivative(T + 16 * m, u, v, d, pr);
+                    if (pr->valid)
+                        or_bilinear(feats[m], feat_hw[2 * m], feat_hw[2 * m + 1], Cf, pr->um, pr->vm, s);
+                    else
+                        for (int c = 0; c < Cf; ++c) s[c] = 0.0;
+                }
+                const double *f = F + src * C;
+                double ss = 0.0;
+                for (int c = 0; c < C; ++c) ss += f[c] * f[c];
+                RR[li] = sqrt(ss / C + 1e-6);
+                for (int c = 0; c < C; ++c) XN[li * C + c] = f[c] / RR[li];
+                vecmat(XN + li * C, Wq, C, hd, Q + li * hd);
+                for (int m = 0; m < V; ++m) {
+                    const double *s = S + ((size_t)li * V + m) * Cf;
+                    vecmat(s, Wk, Cf, hd, Kk + ((size_t)li * V + m) * hd);
+                    vecmat(s, Wv, Cf, hd, Vv + ((size_t)li * V + m) * hd);
+                }
+                for (int j = 0; j < hd; ++j) O[li * hd + j] = 0.0;
+                for (int hh = 0; hh < heads; ++hh) {
+                    double amax = -INFINITY, z = 0.0;
+                    double *pp = Pp + ((size_t)li * heads + hh) * V;
+                    for (int m = 0; m < V; ++m) {
+                        double a = 0.0;
+                        for (int j = 0; j < dh; ++j)
+                            a += Q[li * hd + hh * dh + j] * Kk[((size_t)li * V + m) * hd + hh * dh + j];
+                        pp[m] = a * isq;
+                        if (pp[m] > amax) amax = pp[m];
+                    }
+                    for (int m = 0; m < V; ++m) { pp[m] = exp(pp[m] - amax); z += pp[m]; }
+                    for (int m = 0; m < V; ++m) pp[m] /= z;
+                    for (int j = 0; j < dh; ++j) {
+                        double o = 0.0;
+                        for (int m = 0; m < V; ++m) o += pp[m] * Vv[((size_t)li * V + m) * hd + hh * dh + j];
+                        O[li * hd + hh * dh + j] = o;
+                    }
+                }
+                vecmat(O + li * hd, Wo, hd, C, FP + li * C);
+                for (int c = 0; c < C; ++c) FP[li * C + c] += f[c];
+                double xs = 0.0, xd = 0.0, xc[3] = {0, 0, 0};
+                for (int c = 0; c < C; ++c) {
+                    xs += FP[li * C + c] * w_sigma[c];
+                    xd += FP[li * C + c] * w_depth[c];
+                    for (int j = 0; j < 3; ++j) xc[j] += FP[li * C + c] * W_color[c * 3 + j];
+                }
+                XS[li] = xs;
+                XD[li] = xd;
+                for (int j = 0; j < 3; ++j) { XC[li * 3 + j] = xc[j]; CO[li * 3 + j] = sigmoid(xc[j]); }
+                or_decode(FP + li * C, C, w_sigma, w_depth, W_color, alpha[src], d, li, L, near_, far_,
+                          mode, &AL[li], &DN[li], CO + li * 3);
+            }
+            /* ---- composite adjoint: T_l prefix, B_l = back-to-front remainder */
+            Tt[0] = 1.0;
+            for (int li = 0; li < L; ++li) Tt[li + 1] = Tt[li] * (1.0 - AL[li]);
+            for (int j = 0; j < 3; ++j) Bb[(size_t)L * 3 + j] = 0.0;
+            for (int li = L - 1; li >= 0; --li)
+                for (int j = 0; j < 3; ++j)
+                    Bb[li * 3 + j] = AL[li] * CO[li * 3 + j] + (1.0 - AL[li]) * Bb[(li + 1) * 3 + j];
+            const double *g = d_rgb ? d_rgb + ((size_t)y * W + x) * 3 : NULL;
+
+            /* ---- per-layer adjoint */
+            for (int li = 0; li < L; ++li) {
+                size_t src = ((size_t)li * H + y) * W + x;
+                double d = depth[src];
+                double dal = d_alpha_out ? d_alpha_out[src] : 0.0;
+                double ddn = d_depth_out ? d_depth_out[src] : 0.0;
+                double dco[3] = {0, 0, 0};
+                if (g) {
+                    for (int j = 0; j < 3; ++j) {
+                        dco[j] = g[j] * Tt[li] * AL[li];
+                        dal += g[j] * Tt[li] * (CO[li * 3 + j] - Bb[(li + 1) * 3 + j]);
+                    }
+                }
+                /* decode adjoint */
+                double dxc[3], dxs, dxd = 0.0, dd_in = 0.0, da_in = 0.0;
+                for (int j = 0; j < 3; ++j) dxc[j] = dco[j] * CO[li * 3 + j] * (1.0 - CO[li * 3 + j]);
+                dxs = dal * AL[li] * (1.0 - AL[li]);
+                double th = tanh(XD[li]);
+                if (mode == 0) {
+                    double a = alpha[src];
+                    if (a > 1e-6 && a < 1.0 - 1e-6) da_in = dxs / (a * (1.0 - a));
+                    double disp = 1.0 / d + kap * th;
+                    if (disp > 1.0 / far_ && disp < 1.0 / near_) {
+                        double ddisp = -ddn * DN[li] * DN[li];
+                        dd_in += -ddisp / (d * d);
+                        dxd = ddisp * kap * (1.0 - th * th);
+                    }
+                } else {
+                    double ddisp = -ddn * DN[li] * DN[li];
+                    dxd = ddisp * kap * (1.0 - th * th);
+                }
+                for (int c = 0; c < C; ++c) {
+                    double fp = FP[li * C + c];
+                    dFp[c] = (dF_out ? dF_out[src * C + c] : 0.0) + w_sigma[c] * dxs + w_depth[c] * dxd;
+                    for (int j = 0; j < 3; ++j) dFp[c] += W_color[c * 3 + j] * dxc[j];
+                    gws[c] += fp * dxs;
+                    gwd[c] += fp * dxd;
+                    for (int j = 0; j < 3; ++j) gWc[c * 3 + j] += fp * dxc[j];
+                }
+                /* residual and output projection: F' = F + o W_o */
+                for (int c = 0; c < C; ++c) dF[src * C + c] += dFp[c];
+                for (int j = 0; j < hd; ++j) {
+                    double s = 0.0;
+                    for (int c = 0; c < C; ++c) {
+                        s += Wo[(size_t)j * C + c] * dFp[c];
+                        gWo[(size_t)j * C + c] += O[li * hd + j] * dFp[c];
+                    }
+                    dO[j] = s;
+                }
+                /* attention adjoint, per head */
+                for (int j = 0; j < hd; ++j) dQ[j] = 0.0;
+                for (int hh = 0; hh < heads; ++hh) {
+                    const double *pp = Pp + ((size_t)li * heads + hh) * V;
+                    double sum_pdp = 0.0;
+                    for (int m = 0; m < V; ++m) {
+                        double dp = 0.0;
+                        for (int j = 0; j < dh; ++j) {
+                            dp += dO[hh * dh + j] * Vv[((size_t)li * V + m) * hd + hh * dh + j];
+                            dV[(size_t)m * hd + hh * dh + j] = pp[m] * dO[hh * dh + j];
+                        }
+                        dpv[m] = dp;
+                        sum_pdp += pp[m] * dp;
+                    }
+                    for (int m = 0; m < V; ++m) {
+                        double da = pp[m] * (dpv[m] - sum_pdp);
+                        for (int j = 0; j < dh; ++j) {
+                            dQ[hh * dh + j] += da * Kk[((size_t)li * V + m) * hd + hh * dh + j] * isq;
+                            dK[(size_t)m * hd + hh * dh + j] = da * Q[li * hd + hh * dh + j] * isq;
+                        }
+                    }
+                }
+                /* query projection and RMSNorm */
+                for (int c = 0; c < C; ++c) {
+                    double s = 0.0;
+                    for (int j = 0; j < hd; ++j) {
+                        s += Wq[(size_t)c * hd + j] * dQ[j];
+                        gWq[(size_t)c * hd + j] += XN[li * C + c] * dQ[j];
+                    }
+                    dXN[c] = s;
+                }
+                double xdx = 0.0;
+                for (int c = 0; c < C; ++c) xdx += XN[li * C + c] * dXN[c];
+                for (int c = 0; c < C; ++c)
+                    dF[src * C + c] += (dXN[c] - XN[li * C + c] * xdx / C) / RR[li];
+                /* key / value projections and the gather */
+                for (int m = 0; m < V; ++m) {
+                    const or_proj *pr = &PR[li * V + m];
+                    const double *s = S + ((size_t)li * V + m) * Cf;
+                    for (int c = 0; c < Cf; ++c) {
+                        double acc = 0.0;
+                        for (int j = 0; j < hd; ++j) {
+                            acc += Wk[(size_t)c * hd + j] * dK[(size_t)m * hd + j] +
+                                   Wv[(size_t)c * hd + j] * dV[(size_t)m * hd + j];
+                            gWk[(size_t)c * hd + j] += s[c] * dK[(size_t)m * hd + j];
+                            gWv[(size_t)c * hd + j] += s[c] * dV[(size_t)m * hd + j];
+                        }
+                        dS[c] = acc;
+                    }
+                    if (!pr->valid) continue;
+                    int Hf = feat_hw[2 * m], Wf = feat_hw[2 * m + 1];
+                    double X = pr->um - 0.5, Y = pr->vm - 0.5;
+                    if (!(fabs(X) < 1e9 && fabs(Y) < 1e9)) continue;
+                    double xf = floor(X), yf = floor(Y), fx = X - xf, fy = Y - yf;
+                    long x0 = (long)xf, y0 = (long)yf;
+                    const double *I00 = tap_ptr(feats[m], Hf, Wf, Cf, x0, y0);
+                    const double *I10 = tap_ptr(feats[m], Hf, Wf, Cf, x0 + 1, y0);
+                    const double *I01 = tap_ptr(feats[m], Hf, Wf, Cf, x0, y0 + 1);
+                    const double *I11 = tap_ptr(feats[m], Hf, Wf, Cf, x0 + 1, y0 + 1);
+                    double dX = 0.0, dY = 0.0;
+                    for (int c = 0; c < Cf; ++c) {
+                        double i00 = I00 ? I00[c] : 0.0, i10 = I10 ? I10[c] : 0.0;
+                        double i01 = I01 ? I01[c] : 0.0, i11 = I11 ? I11[c] : 0.0;
+                        dX += dS[c] * ((1 - fy) * (i10 - i00) + fy * (i11 - i01));
+                        dY += dS[c] * ((1 - fx) * (i01 - i00) + fx * (i11 - i10));
+                    }
+                    dd_in += dX * pr->dum_dd + dY * pr->dvm_dd;
+                    /* scatter into the feature map */
+                    const long tx[4] = {x0, x0 + 1, x0, x0 + 1}, ty[4] = {y0, y0, y0 + 1, y0 + 1};
+                    const double wt[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+                    for (int t = 0; t < 4; ++t) {
+                        if (tx[t] < 0 || tx[t] >= Wf || ty[t] < 0 || ty[t] >= Hf) continue;
+                        double *dst = dI[m] + ((size_t)ty[t] * Wf + (size_t)tx[t]) * Cf;
+                        for (int c = 0; c < Cf; ++c) {
+#pragma omp atomic
+                            dst[c] += wt[t] * dS[c];
+                        }
+                    }
+                }
+                d_depth[src] += dd_in;
+                d_alpha[src] += da_in;
+            }
+        }
+#pragma omp critical
+        {
+            for (size_t i = 0; i < (size_t)C * hd; ++i) dWq[i] += gWq[i];
+            for (size_t i = 0; i < (size_t)Cf * hd; ++i) { dWk[i] += gWk[i]; dWv[i] += gWv[i]; }
+            for (size_t i = 0; i < (size_t)hd * C; ++i) dWo[i] += gWo[i];
+            for (int c = 0; c < C; ++c) { dw_sigma[c] += gws[c]; dw_depth[c] += gwd[c]; }
+            for (int i = 0; i < C * 3; ++i) dW_color[i] += gWc[i];
+        }
+        free(gWq); free(gWk); free(gWv); free(gWo); free(gws); free(gwd); free(gWc);
+        free(S); free(PR); free(XN); free(RR); free(Q); free(Kk); free(Vv); free(Pp); free(O);
+        free(FP); free(XS); free(XD); free(XC); free(AL); free(DN); free(CO); free(Tt); free(Bb);
+        free(dFp); free(dO); free(dQ); free(dXN); free(dK); free(dV); free(dS); free(dpv);
+    }
+    (void)nW;
+    free(T);
+    return 0;
+}
