@@ -202,6 +202,89 @@ def profile_run(ctx, steps: int, depth_mode: str):
     log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
 
 
+# ---------------------------------------------------------------------------
+# Training step (forward + adjoint) and serving
+# ---------------------------------------------------------------------------
+
+def time_training_step(ctx, steps: int = 50, warmup: int = 5):
+    """The 960x540 backward workload (V=4, C=16, L=8): float32 forward with
+    composite, loss sum((rgb - target)^2), the adjoint into every input and
+    weight.  Times the whole step and each part with HIP events."""
+    import torch
+    from paper_2411_16680_amd import lib, runner, synth
+    sc = synth.make_inputs(4, "f32")
+    lvl = sc.levels[0]
+    dl = runner.level_to_device(lvl)
+    target = torch.from_numpy(sc.target).cuda()
+    dF, dd, da = (torch.empty_like(t) for t in (dl.F, dl.depth, dl.alpha))
+    dfe = [torch.empty_like(f) for f in dl.feats]
+    dW = {k: torch.empty_like(v) for k, v in dl.weights.items()}
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        lib.update_fuse(ctx, sc.in_cams, dl.feats, sc.novel, sc.near, sc.far, dl.weights,
+                        (dl.F, dl.depth, dl.alpha), (dl.F_out, dl.depth_out, dl.alpha_out),
+                        precision="fp32", rgb_out=dl.rgb, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        d_rgb = 2.0 * (dl.rgb - target)
+        if ev:
+            ev[2].record(stream)
+        lib.update_fuse_backward(ctx, sc.in_cams, dl.feats, sc.novel, sc.near, sc.far,
+                                 dl.weights, (dl.F, dl.depth, dl.alpha),
+                                 (dl.F_out, dl.depth_out, dl.alpha_out), (dF, dd, da), dfe, dW,
+                                 d_rgb=d_rgb, stream=stream)
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for s in range(steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    fwd = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    bwd = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    tot = np.array([e[0].elapsed_time(e[3]) for e in evs])
+    N = lvl.L * lvl.H * lvl.W
+    return {"workload": "960x540 L8 C16 V=4, float32, loss sum((rgb - target)^2)",
+            "steps": steps, "step_ms": float(tot.mean()), "forward_ms": float(fwd.mean()),
+            "backward_ms": float(bwd.mean()), "p50_step_ms": float(np.percentile(tot, 50)),
+            "p99_step_ms": float(np.percentile(tot, 99)),
+            "layer_pixels_per_s_backward": N / (bwd.mean() / 1000.0)}
+
+
+def run_serving(n_requests: int = 2000, rate: float = 60.0, n_scenes: int = 16,
+                n_streams: int = 4):
+    """The serving workload: Poisson arrivals, 16 resident scenes (V in
+    {4, 6, 8}, 1080p feature pyramids), outputs 640x360 / 1280x720 /
+    1920x1080, one learned init + bf16 Update & Fuse per level + composite
+    per request, 200 GB admission budget.  Latency = completion - arrival."""
+    import torch
+    from paper_2411_16680_amd import serve, synth
+    scenes, model, reqs = synth.make_serving(n_scenes=n_scenes, n_requests=n_requests, rate=rate)
+    pyr = {s.scene_id: synth.device_pyramid(s) for s in scenes}
+    torch.cuda.synchronize()
+    ex = serve.GpuExecutor({s.scene_id: s for s in scenes}, pyr, model, n_streams=n_streams)
+    # warm-up: each output size once on every stream (allocator, code objects)
+    warm = []
+    for i, (W, H) in enumerate(synth.SERVE_OUTPUTS * n_streams):
+        r = reqs[i % len(reqs)]
+        warm.append(synth.ServeRequest(-1 - i, r.scene_id, W, H, r.novel, 0.0))
+    serve.Server(ex, 200 * 10 ** 9).run(warm)
+    torch.cuda.synchronize()
+    srv = serve.Server(ex, 200 * 10 ** 9)
+    jobs = srv.run(reqs, deadline=1.0 / 30.0)
+    st = serve.summarize(jobs)
+    st.update({"rate_rps": rate, "scenes": n_scenes, "streams": n_streams,
+               "resident_scene_bytes": int(sum(sum(t.numel() * t.element_size() for t in lv)
+                                               for p in pyr.values() for lv in p))})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +293,9 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth-mode", default="iid", choices=["iid", "smooth"])
+    ap.add_argument("--no-train", action="store_true", help="skip the forward+adjoint timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: run --steps frames of the bf16 standard form, then a "
                          "512 MiB device copy (counter calibration), and exit without timing")
@@ -297,6 +383,23 @@ def main():
     frame_bytes = sum(level_bytes(l, V, 2, i == len(sc16.levels) - 1)
                       for i, l in enumerate(sc16.levels))
 
+    train = None
+    if not args.no_train:
+        log("timing the forward + adjoint training step (960x540, V=4, C=16, L=8)")
+        train = time_training_step(ctx)
+        log(f"training step {train['step_ms']:.3f} ms (forward {train['forward_ms']:.3f}, "
+            f"backward {train['backward_ms']:.3f})")
+        torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serve:
+        log(f"serving {args.serve_requests} Poisson requests at 60/s")
+        serving = run_serving(args.serve_requests)
+        log(f"serving p50 {serving.get('p50_ms', float('nan')):.2f} ms, "
+            f"p99 {serving.get('p99_ms', float('nan')):.2f} ms, "
+            f"{serving.get('frac_under_slo', float('nan')) * 100:.1f}% under 33 ms")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a row sample (cpu_baseline)")
@@ -341,6 +444,8 @@ def main():
         "frame_hbm_frac": frame_bytes / (ms_per_step / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "training_step": train,
+        "serving": serving,
         "context": "paper: 30 fps at 1080p for the whole network (encoder, 5 Update&Fuse steps, "
                    "upsample, render) on one NVIDIA A100; not the same work",
     }

@@ -118,11 +118,21 @@ typedef struct {
     int32_t C, C_feat, heads, head_dim;
 } qk_weights;
 
+/* Weight gradients: device float32, the shapes and layouts of qk_weights. */
+typedef struct {
+    float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
+} qk_weight_grads;
+
 typedef struct qk_context qk_context;
 
-/* Create a context bound to HIP device `device`.  The context owns a small
- * device workspace (camera tables) and nothing else; it may be used from one
- * host thread at a time.  Errors: QK_EINVAL (out == NULL), QK_EHIP. */
+/* Create a context bound to HIP device `device`.  The context owns device
+ * workspaces that grow on demand and live until qk_context_destroy: the
+ * folded weights of the one-to-many form (2 C C_feat floats) and the
+ * backward pass's scratch (16 bytes per layer-pixel when d_rgb is given,
+ * plus 5 KiB per backward workgroup).  Growing one synchronises the
+ * caller's stream and allocates.  A context may be used from one host
+ * thread at a time; calls that share it on different streams race on its
+ * workspaces.  Errors: QK_EINVAL (out == NULL), QK_EHIP. */
 QK_API qk_status qk_context_create(int device, qk_context **out);
 QK_API qk_status qk_context_destroy(qk_context *ctx);
 
@@ -166,6 +176,18 @@ QK_API qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams,
                                const qk_ldm *ldm_out, float *rgb_out,
                                float *acc_alpha_out);
 
+/* Learned initialisation of an LDM (Sec. 3.2, "Initialization"): one
+ * C-channel feature f0 broadcast over every layer-pixel, each layer flat at
+ * its depth anchor and alpha one half (the paper leaves the initial alpha
+ * unstated; one half is this library's reading).  Storage layer i (0 =
+ * nearest) is the paper's layer l = L - i, anchored at disparity fraction
+ * delta = (l - 1/2)/L: depth = 1 / (delta (1/near - 1/far) + 1/far).
+ *   f0    device [C] float32; a QK_BF16 LDM gets it rounded to nearest even
+ *   ldm   device, written: F [L][H][W][C] of ldm->dtype, depth and alpha
+ * C must be a positive multiple of 8 (QK_ESHAPE otherwise). */
+QK_API qk_status qk_ldm_init(qk_context *ctx, void *hip_stream, const float *f0, float near_,
+                             float far_, const qk_ldm *ldm);
+
 /* Front-to-back over composite of L layers (Sec. 3.1): for each pixel,
  * T = 1; for l = 0..L-1: rgb += T alpha_l color_l; T *= 1 - alpha_l.
  *   color device [L][H][W][3] float, alpha device [L][H][W] float,
@@ -181,6 +203,55 @@ QK_API qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int3
  * host composition can be checked without a GPU. */
 QK_API qk_status qk_camera_tables(int32_t V, const qk_camera *in_cams, const int32_t *feat_hw,
                            const qk_camera *novel, int32_t H, int32_t W, double *out);
+
+/* Adjoint of one QK_PREC_FP32 Update & Fuse step and of the composite that
+ * followed it.  The paper trains through generic differentiable rendering
+ * and prints no adjoint; this is the chain rule through the forward of
+ * Sec. 3.1-3.3 as qk_update_fuse defines it (reprojection, bilinear
+ * back-projection, attention, decode, over composite).  The loss is any
+ * function of the step's outputs; its gradients with respect to them come
+ * in, the gradients with respect to every input go out.  The samples and
+ * the attention are recomputed, not stored by the forward.
+ *
+ *   V, in_cams, feats, novel, near_, far_, weights, update_mode
+ *               as given to the forward (feature maps QK_F32)
+ *   ldm_in      the forward's input state (QK_F32)
+ *   ldm_out     the forward's output: F' and alpha' are read to
+ *               differentiate the composite; used only when d_rgb != NULL
+ *   d_rgb       device [H][W][3] float, dLoss/drgb, or NULL (the step was
+ *               not composited or rgb does not enter the loss)
+ *   d_out       upstream dLoss/dF', dLoss/ddepth', dLoss/dalpha' as an LDM of
+ *               the same shape (QK_F32); d_out or any of its three buffers
+ *               may be NULL, meaning zero
+ *   d_in        receives dLoss/dF, dLoss/ddepth, dLoss/dalpha (overwritten)
+ *   d_feats     host array [V] of device pointers, each [Hf][Wf][C_feat]
+ *               float: receives dLoss/dI_m (overwritten: cleared, then
+ *               scatter-added with float atomics, so its last bits vary
+ *               from run to run)
+ *   d_weights   receives every weight gradient (overwritten, summed in a
+ *               fixed order: bitwise reproducible)
+ * Through a clamp (alpha outside (1e-6, 1 - 1e-6), disparity outside
+ * (1/far, 1/near)) the gradient is zero; at a bilinear tap boundary the
+ * one-sided derivative of the cell the sample falls in is taken.
+ * Supported: heads == 1, C == C_feat == head_dim in {8, 16}; otherwise
+ * QK_EUNSUPPORTED.  Buffers must not alias one another. */
+QK_API qk_status qk_update_fuse_backward(qk_context *ctx, void *hip_stream, int32_t V,
+                                  const qk_camera *in_cams, const qk_feature_map *feats,
+                                  const qk_camera *novel, float near_, float far_,
+                                  const qk_weights *weights, qk_update_mode update_mode,
+                                  const qk_ldm *ldm_in, const qk_ldm *ldm_out,
+                                  const float *d_rgb, const qk_ldm *d_out, const qk_ldm *d_in,
+                                  float *const *d_feats, const qk_weight_grads *d_weights);
+
+/* Dry run of qk_update_fuse_backward's argument checks (no device use). */
+QK_API qk_status qk_update_fuse_backward_check(int32_t V, const qk_camera *in_cams,
+                                        const qk_feature_map *feats, const qk_camera *novel,
+                                        float near_, float far_, const qk_weights *weights,
+                                        qk_update_mode update_mode, const qk_ldm *ldm_in,
+                                        const qk_ldm *ldm_out, const float *d_rgb,
+                                        const qk_ldm *d_out, const qk_ldm *d_in,
+                                        float *const *d_feats,
+                                        const qk_weight_grads *d_weights);
 
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);

@@ -325,3 +325,22 @@ def sample_coordinates(in_cams, novel, level, depth=None):
                     if ok == 1:
                         out[li, y, x, m] = uv
     return out
+
+
+def ldm_init(L: int, H: int, W: int, f0, near: float, far: float):
+    """The learned initialisation of an LDM (Sec. 3.2, "Initialization"):
+    the single C-channel feature f0 broadcast to every layer-pixel, each layer
+    flat at its depth anchor (Sec. 3.2.3: the paper's layer l sits at
+    disparity fraction (l - 1/2)/L of the band, storage layer i = L - l with
+    0 nearest), alpha one half (the paper leaves it unstated; reading).
+    Returns (F [L][H][W][C], depth [L][H][W], alpha [L][H][W]) in float64."""
+    f0 = _f64(f0)
+    band = 1.0 / near - 1.0 / far
+    depth = np.empty((L, H, W))
+    for i in range(L):
+        l_paper = L - i
+        delta = (l_paper - 0.5) / L
+        depth[i] = 1.0 / (delta * band + 1.0 / far)
+    F = np.broadcast_to(f0, (L, H, W, f0.shape[0])).copy()
+    alpha = np.full((L, H, W), 0.5)
+    return F, depth, alpha

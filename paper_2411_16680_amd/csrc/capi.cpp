@@ -18,12 +18,17 @@ namespace qk {
 hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, bool fold, hipStream_t s);
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
+hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
+hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
     int device;
+    int num_cu = 0;
     float *wfold = nullptr;      // folded-weight workspace (one-to-many form)
     size_t wfold_elems = 0;
+    float *bws = nullptr;        // backward workspace: composite adjoint + partials
+    size_t bws_elems = 0;
 };
 
 namespace {
@@ -210,6 +215,105 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
     return QK_OK;
 }
 
+
+bool supported_backward_c(int C) { return C == 8 || C == 16; }
+
+bool same_grid(const qk_ldm *a, const qk_ldm *b) {
+    return a->L == b->L && a->H == b->H && a->W == b->W;
+}
+
+qk_status check_backward(int32_t V, const qk_camera *in_cams, const qk_feature_map *feats,
+                         const qk_camera *novel, float near_, float far_, const qk_weights *w,
+                         qk_update_mode update_mode, const qk_ldm *in, const qk_ldm *out,
+                         const float *d_rgb, const qk_ldm *d_out, const qk_ldm *d_in,
+                         float *const *d_feats, const qk_weight_grads *dw) {
+    if (!in_cams || !feats || !novel || !w || !in || !d_in || !d_feats || !dw)
+        return fail(QK_EINVAL, "NULL argument");
+    if (d_rgb && !out) return fail(QK_EINVAL, "d_rgb needs ldm_out (F' and alpha')");
+    if (V < 1 || V > qk::kMaxViews)
+        return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (update_mode != QK_UPDATE_RESIDUAL && update_mode != QK_UPDATE_PAPER_DECODE)
+        return fail(QK_EINVAL, "unknown update mode %d", (int)update_mode);
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (in->L < 1 || in->H < 1 || in->W < 1 || in->C < 1)
+        return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d C=%d)", in->L, in->H,
+                    in->W, in->C);
+    if (in->dtype != QK_F32) return fail(QK_EDTYPE, "the backward pass takes float32 LDMs");
+    if (!in->F || !in->depth || !in->alpha) return fail(QK_EINVAL, "NULL LDM buffer");
+    if (d_rgb) {
+        if (!same_grid(out, in) || out->C != in->C) return fail(QK_ESHAPE, "ldm_out dims differ from ldm_in");
+        if (out->dtype != QK_F32) return fail(QK_EDTYPE, "ldm_out must be float32");
+        if (!out->F || !out->alpha) return fail(QK_EINVAL, "d_rgb needs ldm_out F' and alpha'");
+        if (!aligned16(out->F) || !aligned4(out->alpha) || !aligned4(d_rgb))
+            return fail(QK_EINVAL, "ldm_out / d_rgb misaligned");
+    }
+    if (d_out) {
+        if (!same_grid(d_out, in)) return fail(QK_ESHAPE, "d_out dims differ from ldm_in");
+        if (d_out->F && (d_out->C != in->C || d_out->dtype != QK_F32))
+            return fail(QK_ESHAPE, "d_out F must be float32 with C channels");
+        if ((d_out->F && !aligned16(d_out->F)) || (d_out->depth && !aligned4(d_out->depth)) ||
+            (d_out->alpha && !aligned4(d_out->alpha)))
+            return fail(QK_EINVAL, "d_out misaligned");
+    }
+    if (!same_grid(d_in, in) || d_in->C != in->C) return fail(QK_ESHAPE, "d_in dims differ from ldm_in");
+    if (d_in->dtype != QK_F32) return fail(QK_EDTYPE, "d_in must be float32");
+    if (!d_in->F || !d_in->depth || !d_in->alpha) return fail(QK_EINVAL, "NULL d_in buffer");
+    if (!aligned16(in->F) || !aligned16(d_in->F))
+        return fail(QK_EINVAL, "LDM feature buffers must be 16-byte aligned");
+    if (!aligned4(in->depth) || !aligned4(in->alpha) || !aligned4(d_in->depth) ||
+        !aligned4(d_in->alpha))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    if (!w->Wq || !w->Wk || !w->Wv || !w->Wo || !w->w_sigma || !w->w_depth || !w->W_color)
+        return fail(QK_EINVAL, "NULL weight buffer");
+    if (!dw->Wq || !dw->Wk || !dw->Wv || !dw->Wo || !dw->w_sigma || !dw->w_depth || !dw->W_color)
+        return fail(QK_EINVAL, "NULL weight-gradient buffer");
+    if (w->C != in->C) return fail(QK_ESHAPE, "weights.C %d != LDM C %d", w->C, in->C);
+    const int64_t elems = (int64_t)in->L * in->H * in->W * in->C;
+    if (elems >= (int64_t)1 << 31)
+        return fail(QK_EUNSUPPORTED, "LDM of %lld elements exceeds 2^31", (long long)elems);
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    for (int m = 0; m < V; ++m) {
+        char what[32];
+        snprintf(what, sizeof(what), "camera %d", m);
+        st = check_camera(&in_cams[m], what);
+        if (st != QK_OK) return st;
+        if (!feats[m].data || !d_feats[m]) return fail(QK_EINVAL, "feature map %d is NULL", m);
+        if (!aligned16(feats[m].data) || !aligned16(d_feats[m]))
+            return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
+        if (feats[m].H < 1 || feats[m].W < 1)
+            return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
+        if ((int64_t)feats[m].H * feats[m].W * w->C_feat >= (int64_t)1 << 31)
+            return fail(QK_EUNSUPPORTED, "feature map %d exceeds 2^31 elements", m);
+    }
+    if (w->heads != 1 || w->head_dim != in->C || w->C_feat != in->C || !supported_backward_c(in->C))
+        return fail(QK_EUNSUPPORTED,
+                    "the backward kernels support heads == 1 and C == C_feat == head_dim in "
+                    "{8,16} (got heads=%d head_dim=%d C=%d C_feat=%d)",
+                    w->heads, w->head_dim, in->C, w->C_feat);
+    return QK_OK;
+}
+
+// Grow a context buffer to at least `need` floats (synchronising the stream
+// before a buffer in use is replaced).
+qk_status grow(float **buf, size_t *have, size_t need, hipStream_t stream) {
+    if (*have >= need) return QK_OK;
+    if (*buf) {
+        hipError_t se = hipStreamSynchronize(stream);
+        if (se != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+    }
+    if (hipMalloc(buf, need * sizeof(float)) != hipSuccess) {
+        *buf = nullptr;
+        return fail(QK_ENOMEM, "workspace of %zu floats", need);
+    }
+    *have = need;
+    return QK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -225,15 +329,21 @@ qk_status qk_context_create(int device, qk_context **out) {
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess) return fail(QK_EHIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
     if (device < 0 || device >= n) return fail(QK_EINVAL, "device %d of %d", device, n);
-    *out = new qk_context{device};
+    int cu = 0;
+    e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return fail(QK_EHIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    qk_context *ctx = new qk_context{device};
+    ctx->num_cu = cu > 0 ? cu : 1;
+    *out = ctx;
     return QK_OK;
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && ctx->wfold) {
+    if (ctx && (ctx->wfold || ctx->bws)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
-        (void)hipFree(ctx->wfold);
+        if (ctx->wfold) (void)hipFree(ctx->wfold);
+        if (ctx->bws) (void)hipFree(ctx->bws);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -380,6 +490,132 @@ qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, 
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipError_t e = qk::launch_composite(p, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "composite launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_update_fuse_backward_check(int32_t V, const qk_camera *in_cams,
+                                        const qk_feature_map *feats, const qk_camera *novel,
+                                        float near_, float far_, const qk_weights *weights,
+                                        qk_update_mode update_mode, const qk_ldm *ldm_in,
+                                        const qk_ldm *ldm_out, const float *d_rgb,
+                                        const qk_ldm *d_out, const qk_ldm *d_in,
+                                        float *const *d_feats, const qk_weight_grads *d_weights) {
+    return check_backward(V, in_cams, feats, novel, near_, far_, weights, update_mode, ldm_in,
+                          ldm_out, d_rgb, d_out, d_in, d_feats, d_weights);
+}
+
+qk_status qk_update_fuse_backward(qk_context *ctx, void *hip_stream, int32_t V,
+                                  const qk_camera *in_cams, const qk_feature_map *feats,
+                                  const qk_camera *novel, float near_, float far_,
+                                  const qk_weights *w, qk_update_mode update_mode,
+                                  const qk_ldm *in, const qk_ldm *out, const float *d_rgb,
+                                  const qk_ldm *d_out, const qk_ldm *d_in, float *const *d_feats,
+                                  const qk_weight_grads *dw) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_backward(V, in_cams, feats, novel, near_, far_, w, update_mode, in, out,
+                                  d_rgb, d_out, d_in, d_feats, dw);
+    if (st != QK_OK) return st;
+
+    qk::BwdParams p;
+    std::memset(&p, 0, sizeof(p));
+    for (int m = 0; m < V; ++m) {
+        p.feat[m] = static_cast<const float *>(feats[m].data);
+        p.dfeat[m] = d_feats[m];
+        p.fH[m] = feats[m].H;
+        p.fW[m] = feats[m].W;
+        compose_table(novel, in->W, in->H, &in_cams[m], feats[m].W, feats[m].H, p.camd[m]);
+    }
+    p.F_in = static_cast<const float *>(in->F);
+    p.depth_in = in->depth;
+    p.alpha_in = in->alpha;
+    if (d_rgb) {
+        p.F_out = static_cast<const float *>(out->F);
+        p.alpha_out = out->alpha;
+        p.d_rgb = d_rgb;
+    }
+    if (d_out) {
+        p.dF_out = static_cast<const float *>(d_out->F);
+        p.d_depth_out = d_out->depth;
+        p.d_alpha_out = d_out->alpha;
+    }
+    p.dF = static_cast<float *>(d_in->F);
+    p.d_depth = d_in->depth;
+    p.d_alpha = d_in->alpha;
+    p.Wq = w->Wq;
+    p.Wk = w->Wk;
+    p.Wv = w->Wv;
+    p.Wo = w->Wo;
+    p.w_sigma = w->w_sigma;
+    p.w_depth = w->w_depth;
+    p.W_color = w->W_color;
+    p.dWq = dw->Wq;
+    p.dWk = dw->Wk;
+    p.dWv = dw->Wv;
+    p.dWo = dw->Wo;
+    p.dw_sigma = dw->w_sigma;
+    p.dw_depth = dw->w_depth;
+    p.dW_color = dw->W_color;
+    p.V = V;
+    p.L = in->L;
+    p.H = in->H;
+    p.W = in->W;
+    p.C = in->C;
+    p.N = (int64_t)in->L * in->H * in->W;
+    p.inv_near = 1.0f / near_;
+    p.inv_far = 1.0f / far_;
+    p.scale = 1.0f / std::sqrt((float)w->head_dim);
+    p.mode = (int)update_mode;
+    // persistent workgroups: four per compute unit, or fewer for small LDMs
+    const int64_t tiles = (p.N + 255) / 256;
+    p.blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tiles, 4 * (int64_t)ctx->num_cu));
+
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t n_comp = d_rgb ? 4 * (size_t)p.N : 0;
+    const size_t n_part = (size_t)p.blocks * qk::kGradTiles * qk::kGradTileElems;
+    st = grow(&ctx->bws, &ctx->bws_elems, n_comp + n_part, stream);
+    if (st != QK_OK) return st;
+    p.partials = ctx->bws;
+    p.comp = d_rgb ? ctx->bws + n_part : nullptr;
+    hipError_t e = qk::launch_update_fuse_backward(p, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "backward launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_ldm_init(qk_context *ctx, void *hip_stream, const float *f0, float near_, float far_,
+                      const qk_ldm *ldm) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    if (!f0 || !ldm || !ldm->F || !ldm->depth || !ldm->alpha) return fail(QK_EINVAL, "NULL buffer");
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (ldm->L < 1 || ldm->H < 1 || ldm->W < 1 || ldm->C < 8 || ldm->C % 8 != 0)
+        return fail(QK_ESHAPE, "need positive L, H, W and C a multiple of 8 (L=%d H=%d W=%d C=%d)",
+                    ldm->L, ldm->H, ldm->W, ldm->C);
+    if (ldm->dtype != QK_F32 && ldm->dtype != QK_BF16)
+        return fail(QK_EDTYPE, "unknown LDM dtype %d", (int)ldm->dtype);
+    if (!aligned16(f0) || !aligned16(ldm->F) || !aligned4(ldm->depth) || !aligned4(ldm->alpha))
+        return fail(QK_EINVAL, "misaligned buffer");
+    qk::InitParams p;
+    p.f0 = f0;
+    p.F = ldm->F;
+    p.depth = ldm->depth;
+    p.alpha = ldm->alpha;
+    p.npix = (int64_t)ldm->H * ldm->W;
+    p.N = p.npix * ldm->L;
+    p.L = ldm->L;
+    p.C = ldm->C;
+    p.inv_near = 1.0f / near_;
+    p.inv_far = 1.0f / far_;
+    if (p.N * p.C >= ((int64_t)1 << 40)) return fail(QK_EUNSUPPORTED, "LDM too large");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipError_t e = qk::launch_ldm_init(p, ldm->dtype == QK_BF16, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "ldm_init launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -54,3 +54,53 @@ struct CompParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Weight-gradient tiles of the backward pass: 16 x 16 each, in this order:
+// W_q, W_k, W_v, W_o, then the decode heads (columns sigma, depth, r, g, b).
+constexpr int kGradTiles = 5;
+constexpr int kGradTileElems = 256;
+
+// Adjoint of one float32 Update & Fuse step (and of the composite).
+struct BwdParams {
+    const float *feat[kMaxViews];
+    float *dfeat[kMaxViews];
+    int32_t fH[kMaxViews];
+    int32_t fW[kMaxViews];
+    double camd[kMaxViews][12];
+
+    const float *F_in, *depth_in, *alpha_in;
+    const float *F_out, *alpha_out;     // forward outputs (read when d_rgb != NULL)
+    const float *d_rgb;                 // [H][W][3] or NULL
+    const float *dF_out, *d_depth_out, *d_alpha_out;   // upstream, each may be NULL
+    float *dF, *d_depth, *d_alpha;
+
+    const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
+    float *dWq, *dWk, *dWv, *dWo, *dw_sigma, *dw_depth, *dW_color;
+
+    float *comp;        // [L][H][W][4] composite adjoint (dc_r, dc_g, dc_b, dalpha)
+    float *partials;    // [blocks][kGradTiles][256]
+
+    int32_t V, L, H, W, C;
+    int64_t N;          // L * H * W
+    int32_t blocks;     // workgroups of the per-layer-pixel kernel
+    float inv_near, inv_far, scale;
+    int32_t mode;
+};
+
+}  // namespace qk
+
+namespace qk {
+
+// Learned initialisation of an LDM.
+struct InitParams {
+    const float *f0;        // [C] broadcast feature (device, float32)
+    void *F;                // [L][H][W][C]
+    float *depth, *alpha;   // [L][H][W]
+    int64_t N, npix;        // L*H*W, H*W
+    int32_t L, C;
+    float inv_near, inv_far;
+};
+
+}  // namespace qk

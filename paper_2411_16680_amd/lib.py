@@ -27,7 +27,9 @@ MODE = {"residual": 0, "paper": 1}
 
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
-           "qk_composite", "qk_camera_tables", "qk_last_error", "qk_version"]
+           "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
+           "qk_composite",
+           "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
 class QuarkError(RuntimeError):
@@ -59,6 +61,12 @@ class qk_weights(ctypes.Structure):
                 ("head_dim", ctypes.c_int32)]
 
 
+class qk_weight_grads(ctypes.Structure):
+    _fields_ = [("Wq", ctypes.c_void_p), ("Wk", ctypes.c_void_p), ("Wv", ctypes.c_void_p),
+                ("Wo", ctypes.c_void_p), ("w_sigma", ctypes.c_void_p),
+                ("w_depth", ctypes.c_void_p), ("W_color", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -80,13 +88,22 @@ def load() -> ctypes.CDLL:
                P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p]
     L.qk_update_fuse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
     L.qk_update_fuse_check.argtypes = uf_args
+    bwd_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
+                ctypes.c_float, P(qk_weights), ctypes.c_int, P(qk_ldm), P(qk_ldm), ctypes.c_void_p,
+                P(qk_ldm), P(qk_ldm), P(ctypes.c_void_p), P(qk_weight_grads)]
+    L.qk_update_fuse_backward.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + bwd_args
+    L.qk_update_fuse_backward_check.argtypes = bwd_args
+    L.qk_ldm_init.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                              ctypes.c_float, P(qk_ldm)]
     L.qk_composite.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p]
     L.qk_camera_tables.argtypes = [ctypes.c_int32, P(qk_camera), P(ctypes.c_int32), P(qk_camera),
                                    ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
-                 "qk_update_fuse_check", "qk_composite", "qk_camera_tables"):
+                 "qk_update_fuse_check", "qk_update_fuse_backward",
+                 "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
+                 "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -131,8 +148,10 @@ def _dtype_code(t) -> int:
 
 
 def make_ldm(F, depth, alpha) -> qk_ldm:
-    """F: [L][H][W][C] (float32 or bfloat16) or None; depth, alpha: [L][H][W] float32."""
-    L, H, W = (int(s) for s in depth.shape)
+    """F: [L][H][W][C] (float32 or bfloat16) or None; depth, alpha: [L][H][W] float32
+    (either may be None where the call allows it; the grid comes from the others)."""
+    ref = depth if depth is not None else alpha
+    L, H, W = (int(s) for s in (ref.shape if ref is not None else F.shape[:3]))
     C = int(F.shape[-1]) if F is not None else 0
     return qk_ldm(_ptr(F), _ptr(depth), _ptr(alpha), L, H, W, C,
                   _dtype_code(F) if F is not None else QK_F32)
@@ -216,6 +235,75 @@ def update_fuse_check(in_cams, feats, novel, near, far, weights, ldm_in, ldm_out
     args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
                           ldm_in, ldm_out, rgb_out, acc_out)
     return int(load().qk_update_fuse_check(*args))
+
+
+WEIGHT_NAMES = ("Wq", "Wk", "Wv", "Wo", "w_sigma", "w_depth", "W_color")
+
+
+def make_weight_grads(dw: Dict) -> qk_weight_grads:
+    return qk_weight_grads(*[_ptr(dw[k]) for k in WEIGHT_NAMES])
+
+
+def _bwd_args(in_cams, feats, novel, near, far, weights, mode, ldm_in, ldm_out, d_rgb, d_out,
+              d_in, d_feats, d_weights):
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]), int(f.shape[1]))
+                                 for f in feats])
+    nov = make_camera(novel)
+    wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
+    lin = ldm_in if isinstance(ldm_in, qk_ldm) else make_ldm(*ldm_in)
+    lout = None
+    if ldm_out is not None:
+        lout = ldm_out if isinstance(ldm_out, qk_ldm) else make_ldm(*ldm_out)
+    dout = None
+    if d_out is not None:
+        dout = d_out if isinstance(d_out, qk_ldm) else _grad_ldm(lin, *d_out)
+    din = d_in if isinstance(d_in, qk_ldm) else make_ldm(*d_in)
+    dfe = (ctypes.c_void_p * V)(*[_ptr(t) for t in d_feats])
+    dw = d_weights if isinstance(d_weights, qk_weight_grads) else make_weight_grads(d_weights)
+    keep = (cams, fm, nov, wts, lin, lout, dout, din, dfe, dw)
+    args = [V, cams, fm, ctypes.byref(nov), float(near), float(far), ctypes.byref(wts),
+            MODE[mode] if isinstance(mode, str) else int(mode), ctypes.byref(lin),
+            ctypes.byref(lout) if lout is not None else None, _ptr(d_rgb),
+            ctypes.byref(dout) if dout is not None else None, ctypes.byref(din), dfe,
+            ctypes.byref(dw)]
+    return args, keep
+
+
+def _grad_ldm(like: qk_ldm, dF, d_depth, d_alpha) -> qk_ldm:
+    """An LDM of upstream gradients; any of the three may be None (zero)."""
+    return qk_ldm(_ptr(dF), _ptr(d_depth), _ptr(d_alpha), like.L, like.H, like.W, like.C, QK_F32)
+
+
+def update_fuse_backward(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in,
+                         ldm_out, d_in, d_feats, d_weights, *, d_rgb=None, d_out=None,
+                         mode="residual", stream=None):
+    """qk_update_fuse_backward.  ``ldm_in``/``ldm_out`` are the forward's (F,
+    depth, alpha) input and output tuples; ``d_out`` an optional (dF', ddepth',
+    dalpha') tuple whose entries may be None; ``d_in`` the (dF, ddepth, dalpha)
+    tuple written; ``d_feats`` a list of [Hf][Wf][C] float32 tensors and
+    ``d_weights`` a dict with the keys of the weights, both written."""
+    args, keep = _bwd_args(in_cams, feats, novel, near, far, weights, mode, ldm_in, ldm_out,
+                           d_rgb, d_out, d_in, d_feats, d_weights)
+    _check(ctx._lib.qk_update_fuse_backward(ctx.handle, _stream_handle(stream), *args))
+
+
+def update_fuse_backward_check(in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, d_in,
+                               d_feats, d_weights, *, d_rgb=None, d_out=None,
+                               mode="residual") -> int:
+    """qk_update_fuse_backward_check: the status the backward would return."""
+    args, keep = _bwd_args(in_cams, feats, novel, near, far, weights, mode, ldm_in, ldm_out,
+                           d_rgb, d_out, d_in, d_feats, d_weights)
+    return int(load().qk_update_fuse_backward_check(*args))
+
+
+def ldm_init(ctx: Context, f0, near, far, ldm, stream=None):
+    """qk_ldm_init: fill ``ldm`` = (F, depth, alpha) with the learned
+    initialisation (f0 broadcast, layers at their anchors, alpha 1/2)."""
+    l = ldm if isinstance(ldm, qk_ldm) else make_ldm(*ldm)
+    _check(ctx._lib.qk_ldm_init(ctx.handle, _stream_handle(stream), _ptr(f0), float(near),
+                                float(far), ctypes.byref(l)))
 
 
 def composite(ctx: Context, color, alpha, rgb_out, acc_out=None, stream=None):

@@ -368,3 +368,101 @@ def to_bf16(scene: Scene) -> Scene:
         l2.F = f32_to_bf16_bits(lvl.F)
         sc.levels.append(l2)
     return sc
+
+
+# ----------------------------------------------------------------------------
+# Serving workload (many scenes, Poisson requests)
+# ----------------------------------------------------------------------------
+
+SERVE_LEVELS = ((8, 64, 32), (4, 32, 16), (2, 16, 8), (1, 8, 4))   # (k, C, L)
+SERVE_OUTPUTS = ((640, 360), (1280, 720), (1920, 1080))
+
+
+@dataclass
+class ServeScene:
+    scene_id: int
+    in_cams: List[Camera]          # on the 1920x1080 input grid
+    centre: np.ndarray             # the point every input camera looks at
+    centroid: np.ndarray           # mean of the input camera centres
+    feat_hw: List[tuple]           # per level (Hf, Wf)
+    seed: int                      # seed of its feature pyramid
+
+    @property
+    def V(self) -> int:
+        return len(self.in_cams)
+
+
+@dataclass
+class ServeRequest:
+    rid: int
+    scene_id: int
+    width: int
+    height: int
+    novel: Camera                  # on the request's output grid
+    arrival: float                 # seconds after the start
+
+
+@dataclass
+class ServeModel:
+    """Per-level weights and learned initial features (shared by scenes)."""
+    weights: List[Dict[str, np.ndarray]]
+    f0: List[np.ndarray]
+    near: float = 0.5
+    far: float = 20.0
+
+
+def make_serving(n_scenes: int = 16, n_requests: int = 2000, rate: float = 60.0,
+                 seed: int = 5000, views=(4, 6, 8), outputs=SERVE_OUTPUTS,
+                 input_hw=(1080, 1920)):
+    """Scenes, a model and a Poisson request stream.  Each scene has V in
+    ``views`` cameras evenly on a 0.5 m arc of a radius-1.5 m ring facing
+    its centre (60 degree field of view); its feature pyramid has the four
+    levels of ``SERVE_LEVELS`` (drawn on the device from ``seed``).  A
+    request picks a scene and an output size uniformly; its novel camera
+    sits uniformly in a 0.3 m ball around the scene's camera centroid,
+    looking at the centre, 60 degree field of view.  Arrivals are a Poisson
+    process of ``rate`` per second."""
+    rng = np.random.default_rng(seed)
+    FH, FW = input_hw
+    scenes = []
+    for s in range(n_scenes):
+        V = int(views[rng.integers(0, len(views))])
+        cams, _ = _arc_rig(rng, V, 0.5, 1.5, FW, FH, 60.0)
+        centres = np.stack([-c.E[:3, :3].T @ c.E[:3, 3] for c in cams])
+        scenes.append(ServeScene(s, cams, np.array([0.0, 0.0, 1.5]), centres.mean(axis=0),
+                                 [(FH // k, FW // k) for k, _, _ in SERVE_LEVELS],
+                                 seed + 1 + s))
+    weights, f0 = [], []
+    for k, C, L in SERVE_LEVELS:
+        weights.append(_weights(rng, C, C, 1, C))
+        f0.append(_normal(rng, (C,)))
+    model = ServeModel(weights, f0)
+    reqs = []
+    t = 0.0
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        sc = scenes[int(rng.integers(0, n_scenes))]
+        W, H = outputs[int(rng.integers(0, len(outputs)))]
+        while True:                                   # uniform in the ball
+            off = rng.uniform(-0.3, 0.3, size=3)
+            if np.dot(off, off) <= 0.09:
+                break
+        c = sc.centroid + off
+        K = _fov_intrinsics(W, H, 60.0)
+        novel = Camera(K, _extrinsic(_look_at_yaw(c, sc.centre), c), W, H)
+        reqs.append(ServeRequest(i, sc.scene_id, W, H, novel, t))
+    return scenes, model, reqs
+
+
+def device_pyramid(scene: ServeScene, device="cuda", dtype: str = "bf16"):
+    """The scene's feature pyramid, drawn on the device with a seeded torch
+    generator: [level][view] tensors [Hf][Wf][C], standard normal."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(scene.seed))
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    pyr = []
+    for (k, C, L), (Hf, Wf) in zip(SERVE_LEVELS, scene.feat_hw):
+        pyr.append([torch.randn((Hf, Wf, C), generator=g, device=device, dtype=torch.float32)
+                    .to(tdt) for _ in range(scene.V)])
+    return pyr

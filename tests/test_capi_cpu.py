@@ -162,3 +162,63 @@ def test_context_create_without_gpu_reports_error():
     assert st in (lib.QK_EHIP, lib.QK_EINVAL)
     with pytest.raises(lib.QuarkError):
         lib.Context(0)
+
+
+# ------------------------------------------------------- backward validation
+
+def _bwd_check(sc, feats, wts, ldm, *, C=16, L=4, H=12, W=20, d_rgb=True, dfe=None, d_in=None,
+               ldm_out=True, mode="residual"):
+    V = len(feats)
+    dfe = dfe if dfe is not None else [_FakeT(f.shape, 0x800000 + 0x10000 * i)
+                                       for i, f in enumerate(feats)]
+    d_in = d_in if d_in is not None else (_FakeT((L, H, W, C), 0x900000),
+                                          _FakeT((L, H, W), 0x910000),
+                                          _FakeT((L, H, W), 0x920000))
+    dw = {k: _FakeT((1,), 0xa00000 + 0x1000 * i) for i, k in enumerate(lib.WEIGHT_NAMES)}
+    out = ldm if ldm_out else None
+    return lib.update_fuse_backward_check(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, ldm,
+                                          out, d_in, dfe, dw,
+                                          d_rgb=_FakeT((H, W, 3), 0xb00000) if d_rgb else None,
+                                          mode=mode)
+
+
+def test_backward_valid_arguments_pass():
+    for C in (8, 16):
+        sc, feats, wts, ldm = _args(C=C)
+        assert _bwd_check(sc, feats, wts, ldm, C=C) == lib.QK_OK
+        assert _bwd_check(sc, feats, wts, ldm, C=C, d_rgb=False, ldm_out=False) == lib.QK_OK
+        assert _bwd_check(sc, feats, wts, ldm, C=C, mode="paper") == lib.QK_OK
+
+
+def test_backward_rejections():
+    sc, feats, wts, ldm = _args(C=32)
+    assert _bwd_check(sc, feats, wts, ldm, C=32) == lib.QK_EUNSUPPORTED
+    sc, feats, wts, ldm = _args(C=16, dtype="bf16")
+    assert _bwd_check(sc, feats, wts, ldm) == lib.QK_EDTYPE
+    sc, feats, wts, ldm = _args(C=16)
+    # d_rgb needs the forward's outputs
+    assert _bwd_check(sc, feats, wts, ldm, ldm_out=False) == lib.QK_EINVAL
+    # misaligned feature-map gradient
+    dfe = [_FakeT(f.shape, 0x800004 + 0x10000 * i) for i, f in enumerate(feats)]
+    assert _bwd_check(sc, feats, wts, ldm, dfe=dfe) == lib.QK_EINVAL
+    # NULL gradient output
+    d_in = (_FakeT((4, 12, 20, 16), 0x900000), None, _FakeT((4, 12, 20), 0x920000))
+    assert _bwd_check(sc, feats, wts, ldm, d_in=d_in) == lib.QK_EINVAL
+    # gradient LDM with other dims
+    d_in = (_FakeT((4, 12, 21, 16), 0x900000), _FakeT((4, 12, 21), 0x910000),
+            _FakeT((4, 12, 21), 0x920000))
+    assert _bwd_check(sc, feats, wts, ldm, d_in=d_in) == lib.QK_ESHAPE
+    # several heads
+    sc, feats, wts, ldm = _args(C=16, heads=2, head_dim=8)
+    assert _bwd_check(sc, feats, wts, ldm) == lib.QK_EUNSUPPORTED
+
+
+def test_backward_null_context_rejected():
+    sc, feats, wts, ldm = _args()
+    dfe = [_FakeT(f.shape, 0x800000 + 0x10000 * i) for i, f in enumerate(feats)]
+    dw = {k: _FakeT((1,), 0xa00000 + 0x1000 * i) for i, k in enumerate(lib.WEIGHT_NAMES)}
+    d_in = (_FakeT((4, 12, 20, 16), 0x900000), _FakeT((4, 12, 20), 0x910000),
+            _FakeT((4, 12, 20), 0x920000))
+    args, keep = lib._bwd_args(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, "residual", ldm,
+                               ldm, None, None, d_in, dfe, dw)
+    assert lib.load().qk_update_fuse_backward(None, None, *args) == lib.QK_EINVAL

@@ -487,3 +487,20 @@ def test_whole_step_rotated_rig_matches_independent_torch_float64():
     ref = _torch_reimplementation(sc)
     for k in ("F", "alpha", "depth", "rgb", "acc"):
         np.testing.assert_allclose(mine[k], ref[k], atol=1e-10, rtol=1e-10, err_msg=k)
+
+
+def test_ldm_init_anchors_are_the_paper_decode_at_rest():
+    """The initial layers sit exactly where the paper's absolute decode puts
+    a layer whose depth head reads zero (tanh(0) = 0), for every layer."""
+    L, near, far = 6, 0.5, 20.0
+    r = np.random.default_rng(0)
+    f0 = r.standard_normal(8)
+    F, depth, alpha = oracle.ldm_init(L, 2, 3, f0, near, far)
+    zeros = np.zeros(8)
+    for i in range(L):
+        _, d_rest, _ = oracle.decode(f0, zeros, zeros, np.zeros((8, 3)), 0.5, 1.0, i, L, near,
+                                     far, mode=1)
+        assert np.allclose(depth[i], d_rest, rtol=1e-15)
+    assert np.all(np.diff(depth[:, 0, 0]) > 0)             # layer 0 nearest
+    assert near < depth.min() and depth.max() < far
+    assert np.array_equal(F[3, 1, 2], f0) and np.all(alpha == 0.5)
