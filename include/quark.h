@@ -74,7 +74,8 @@ typedef enum { QK_F32 = 0, QK_BF16 = 1 } qk_dtype;
 typedef enum { QK_PREC_FP32 = 0, QK_PREC_BF16 = 1 } qk_precision;
 
 /* How the decoded heads update depth and alpha (Sec. 3.2.2-3.2.3):
- * RESIDUAL  alpha' = sigmoid(logit(clamp(alpha, 1e-6, 1-1e-6)) + F'.w_sigma),
+ * RESIDUAL  alpha' = sigmoid(logit(clamp(alpha, 1e-6, 1-1e-6)) + F'.w_sigma)
+ *           (the clamp bounds are the float32 values nearest 1e-6 and 1-1e-6),
  *           disp'  = clamp(1/d + (0.5/L)(1/near - 1/far) tanh(F'.w_depth),
  *                          1/far, 1/near),  d' = 1/disp';
  * PAPER_DECODE  the paper's absolute decode: alpha' = sigmoid(F'.w_sigma),

@@ -326,10 +326,17 @@ OR_EXPORT void or_attention_folded(const double *F, int C, const double *S, int 
 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
+/* Bounds of the alpha clamp in the residual update: the float32 values
+ * nearest 1e-6 and 1 - 1e-6.  Alphas arrive as float32, so the decision
+ * "clamped or not" is taken against the bounds the float32 kernels apply. */
+#define OR_ALPHA_LO 9.999999974752427e-07
+#define OR_ALPHA_HI 0.9999989867210388
+
 /* Given the updated feature F' of layer `li` (0 = nearest) of an L-layer LDM,
  * the layer-pixel's incoming alpha and depth, produce alpha', depth' and the
  * layer colour c' = sigmoid(F' W_c).
- *   mode 0 (residual update): alpha' = sigmoid(logit(clamp(alpha)) + F'.w_sigma),
+ *   mode 0 (residual update): alpha' = sigmoid(logit(clamp(alpha)) + F'.w_sigma)
+ *          (clamp to [OR_ALPHA_LO, OR_ALPHA_HI]),
  *          disparity' = clamp(1/d + (0.5/L)(1/near - 1/far) tanh(F'.w_depth),
  *                             1/far, 1/near), d' = 1/disparity'.
  *   mode 1 (the paper's absolute decode): alpha' = sigmoid(F'.w_sigma),
@@ -350,8 +357,8 @@ OR_EXPORT void or_decode(const double *Fp, int C, const double *w_sigma, const d
     double band = (1.0 / near_ - 1.0 / far_);
     if (mode == 0) {
         double a = alpha;
-        if (a < 1e-6) a = 1e-6;
-        if (a > 1.0 - 1e-6) a = 1.0 - 1e-6;
+        if (a < OR_ALPHA_LO) a = OR_ALPHA_LO;
+        if (a > OR_ALPHA_HI) a = OR_ALPHA_HI;
         *alpha_out = sigmoid(log(a / (1.0 - a)) + xs);
         double disp = 1.0 / depth + (0.5 / L) * band * tanh(xd);
         if (disp < 1.0 / far_) disp = 1.0 / far_;
@@ -705,7 +712,7 @@ OR_EXPORT int or_update_fuse_backward(
                 double th = tanh(XD[li]);
                 if (mode == 0) {
                     double a = alpha[src];
-                    if (a > 1e-6 && a < 1.0 - 1e-6) da_in = dxs / (a * (1.0 - a));
+                    if (a > OR_ALPHA_LO && a < OR_ALPHA_HI) da_in = dxs / (a * (1.0 - a));
                     double disp = 1.0 / d + kap * th;
                     if (disp > 1.0 / far_ && disp < 1.0 / near_) {
                         double ddisp = -ddn * DN[li] * DN[li];

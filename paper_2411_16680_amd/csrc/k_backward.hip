@@ -405,18 +405,17 @@ k_uf_backward(const BwdParams p) {
             }
             if (p.d_alpha_out) dal += p.d_alpha_out[e];
             if (p.d_depth_out) ddn = p.d_depth_out[e];
+            // sigma'(z) = sigma(z) sigma(-z): the second factor is not taken as
+            // 1 - sigma(z), which loses its digits when sigma(z) is near one
             float h[5];                                   // d x_sigma, d x_depth, d x_color
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float cc = sigm(xc[j]);
-                h[2 + j] = dco[j] * cc * (1.0f - cc);
-            }
+            for (int j = 0; j < 3; ++j) h[2 + j] = dco[j] * sigm(xc[j]) * sigm(-xc[j]);
             const float th = tanhf(xd);
             if (p.mode == 0) {
                 const float a_in = p.alpha_in[e];
                 const float ac = fminf(fmaxf(a_in, 1e-6f), 1.0f - 1e-6f);
-                const float an = sigm(logf(ac / (1.0f - ac)) + xs);
-                h[0] = dal * an * (1.0f - an);
+                const float z = logf(ac / (1.0f - ac)) + xs;
+                h[0] = dal * sigm(z) * sigm(-z);
                 if (a_in > 1e-6f && a_in < 1.0f - 1e-6f) da_in = h[0] / (a_in * (1.0f - a_in));
                 const float disp = 1.0f / d + kap * th;
                 h[1] = 0.f;
@@ -427,8 +426,7 @@ k_uf_backward(const BwdParams p) {
                     h[1] = ddisp * kap * (1.0f - th * th);
                 }
             } else {
-                const float an = sigm(xs);
-                h[0] = dal * an * (1.0f - an);
+                h[0] = dal * sigm(xs) * sigm(-xs);
                 const float delta = ((float)(p.L - li) - 0.5f) / (float)p.L;
                 const float dn = 1.0f / fmaf(delta + half_l * th, band, p.inv_far);
                 h[1] = -ddn * dn * dn * kap * (1.0f - th * th);

@@ -340,11 +340,13 @@ def test_residual_update_is_identity_for_zero_heads_and_clamps():
             an, dn, _ = oracle.decode(RNG.standard_normal(C), z, z, np.zeros((C, 3)), a, d, 1, L,
                                       near, far, mode=0)
             assert abs(an - a) < 1e-14 and abs(dn - d) < 1e-12 * d
-    # alpha clamp: 0 and 1 behave as 1e-6 and 1 - 1e-6
+    # alpha clamp: 0 and 1 behave as the float32 values nearest 1e-6 and 1 - 1e-6
+    lo = float(np.float32(1e-6))
+    hi = float(np.float32(1.0) - np.float32(1e-6))
     an, _, _ = oracle.decode(z, z, z, np.zeros((C, 3)), 0.0, 3.0, 0, L, near, far, mode=0)
-    assert abs(an - 1e-6) < 1e-18
+    assert abs(an - lo) < 1e-18
     an, _, _ = oracle.decode(z, z, z, np.zeros((C, 3)), 1.0, 3.0, 0, L, near, far, mode=0)
-    assert abs(an - (1 - 1e-6)) < 1e-15
+    assert abs(an - hi) < 1e-15
     # depth clamp to [near, far]
     wd = np.zeros(C); wd[0] = 1.0
     _, dn, _ = oracle.decode(np.array([50.0, 0, 0, 0, 0, 0]), z, wd, np.zeros((C, 3)), 0.5, 0.51,
