@@ -390,8 +390,8 @@ __device__ inline void lds_write4(float *dst, const float *f) {
 template <int C, bool BF16, bool FOLD>
 struct Occupancy {
     static constexpr int waves = !BF16 ? 1
-                               : (C > 32) ? (FOLD ? 3 : 2)
-                               : ((FOLD && !Shape<C>::TAPK) ? 5 : 4);
+                               : (C > 32) ? 2
+                               : ((FOLD && !Shape<C>::TAPK) ? 4 : 3);
 };
 
 // FOLD = false: standard cross-attention (per-sample key and value
@@ -588,16 +588,8 @@ k_update_fuse(const UFParams p) {
 
             using TapsT = typename std::conditional<TAPK, TapsK<BF16>, Taps<C, BF16>>::type;
             int2 *tT = reinterpret_cast<int2 *>(sO[wave]);   // free until o is written
-            TapsT cur;
-            issue_any<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, n, g, tT, cur);
-            for (int m = 0; m < p.V; ++m) {
-                // loads of the next view go out before this view is projected
-                TapsT nxt;
-                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, nxt);
-                // keep those loads here: without this fence the compiler sinks
-                // them to their use in the next iteration, serialising every view
-                // on a full memory latency
-                asm volatile("" ::: "memory");
+            // one view: blend -> keys -> logits -> online softmax -> values
+            auto view_step = [&](const TapsT &cur) {
                 // B operands: the blended sample (one per K chunk), or for C = 8
                 // the weighted taps of each 16-pixel row-group
                 constexpr int NA = TAPK ? 4 : KC;
@@ -617,7 +609,6 @@ k_update_fuse(const UFParams p) {
 #pragma unroll
                     for (int kc = 0; kc < KC; ++kc) Sb[kc] = OP::make(sv[kc]);
                 }
-                cur = nxt;
                 // keys^T and logits
                 f32x4 Kt[NT];
 #pragma unroll
@@ -677,6 +668,26 @@ k_update_fuse(const UFParams p) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(acc[t][i], sc[s], ev[s] * Vt[i]);
                 }
+            };
+            // Two tap buffers in turn: the loads of view m + 1 are in flight
+            // while view m is processed, and no buffer is copied.  The
+            // scheduling barriers keep the loads ahead of the arithmetic (left
+            // alone, the scheduler moves the next view's loads after this
+            // view's work, which serialises the views on memory latency).
+            TapsT ta, tb;
+            issue_any<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, n, g, tT, ta);
+            __builtin_amdgcn_sched_barrier(0);
+            // The issues are unconditional (clamped view index; the extra loads
+            // at the end hit the cache) so the wait counts stay exact.
+            for (int m = 0; m < p.V; m += 2) {
+                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, tb);
+                __builtin_amdgcn_sched_barrier(0);
+                view_step(ta);
+                __builtin_amdgcn_sched_barrier(0);
+                issue_any<C, BF16>(p, min(m + 2, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, ta);
+                __builtin_amdgcn_sched_barrier(0);
+                if (m + 1 < p.V) view_step(tb);
+                __builtin_amdgcn_sched_barrier(0);
             }
 
             // o = acc / Z: result layout -> LDS -> operand layout
@@ -711,15 +722,9 @@ k_update_fuse(const UFParams p) {
                 for (int i = 0; i < 8; ++i) ob[kc][i] = 0.0f;
             }
             float Mx = -1e30f, Zs = 0.0f;
-            Taps<C, BF16> cur;
-            issue_taps<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, cur);
-            for (int m = 0; m < p.V; ++m) {
-                Taps<C, BF16> nxt;
-                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, nxt);
-                asm volatile("" ::: "memory");     // keep the next view's loads in flight
+            auto view_step = [&](const Taps<C, BF16> &cur) {
                 float sv[KC][8];
                 blend_taps<C, BF16>(cur, sv);
-                cur = nxt;
                 float part = 0.0f;
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
@@ -736,6 +741,20 @@ k_update_fuse(const UFParams p) {
                 for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
                     for (int i = 0; i < 8; ++i) ob[kc][i] = fmaf(ob[kc][i], sc, ev * sv[kc][i]);
+            };
+            // two tap buffers in turn (see the standard loop)
+            Taps<C, BF16> ta, tb;
+            issue_taps<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, ta);
+            __builtin_amdgcn_sched_barrier(0);
+            for (int m = 0; m < p.V; m += 2) {
+                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, tb);
+                __builtin_amdgcn_sched_barrier(0);
+                view_step(ta);
+                __builtin_amdgcn_sched_barrier(0);
+                issue_taps<C, BF16>(p, min(m + 2, p.V - 1), uc, vc, invdc, a_ok, ch0, ta);
+                __builtin_amdgcn_sched_barrier(0);
+                if (m + 1 < p.V) view_step(tb);
+                __builtin_amdgcn_sched_barrier(0);
             }
             const float iz = 1.0f / Zs;
 #pragma unroll
