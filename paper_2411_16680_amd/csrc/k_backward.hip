@@ -19,7 +19,9 @@
 //                       (o = (sum_m p_m s_m) W_v), then the adjoint of
 //                       decode, residual, W_o, W_v, softmax, W_k, W_q and
 //                       RMSNorm; a second pass over the views scatters dI
-//                       with float atomics and differentiates the sample
+//                       with float atomics (rows of C channels regrouped
+//                       through LDS so that each atomic instruction covers
+//                       whole rows) and differentiates the sample
 //                       position with respect to depth.  Weight gradients are
 //                       sums over layer-pixels of outer products; each wave
 //                       forms them on the matrix cores (v_mfma_f32_16x16x4_f32,
@@ -295,8 +297,10 @@ k_uf_backward(const BwdParams p) {
     static_assert(C == 8 || C == 16, "the backward kernel holds C <= 16 channels per thread");
     __shared__ float s_a[kWaves][64 * 16];
     __shared__ float s_b[kWaves][64 * 16];
+    __shared__ int s_o[kWaves][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float *sa = s_a[wave], *sb = s_b[wave];
+    int *so = s_o[wave];
 
     // The weights live in LDS for the whole kernel; every lane reads the same
     // address (a broadcast).
@@ -482,21 +486,49 @@ k_uf_backward(const BwdParams p) {
             const float da = pm * (sd - delta);
             const float w[4] = {(1.f - S.fx) * (1.f - S.fy), S.fx * (1.f - S.fy),
                                 (1.f - S.fx) * S.fy, S.fx * S.fy};
+            // ds goes straight to the wave's LDS slice (row of this lane),
+            // the tap offsets and weights beside it
             float gX = 0.f, gY = 0.f;
-            float *dI = p.dfeat[m];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                sh[c] = fmaf(da, s[c], sh[c]);
-                const float ds = fmaf(pm, dob[c], da * qt[c]);
-                gX = fmaf(ds, (1.f - S.fy) * (S.t[1][c] - S.t[0][c]) + S.fy * (S.t[3][c] - S.t[2][c]), gX);
-                gY = fmaf(ds, (1.f - S.fx) * (S.t[2][c] - S.t[0][c]) + S.fx * (S.t[3][c] - S.t[1][c]), gY);
-                if (live && S.ok) {
+            for (int c4 = 0; c4 < C / 4; ++c4) {
+                float d4[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (S.in[t]) unsafeAtomicAdd(dI + S.off[t] + c, w[t] * ds);
+                for (int i = 0; i < 4; ++i) {
+                    const int c = 4 * c4 + i;
+                    sh[c] = fmaf(da, s[c], sh[c]);
+                    const float ds = fmaf(pm, dob[c], da * qt[c]);
+                    d4[i] = ds;
+                    gX = fmaf(ds, (1.f - S.fy) * (S.t[1][c] - S.t[0][c]) + S.fy * (S.t[3][c] - S.t[2][c]), gX);
+                    gY = fmaf(ds, (1.f - S.fx) * (S.t[2][c] - S.t[0][c]) + S.fx * (S.t[3][c] - S.t[1][c]), gY);
                 }
+                reinterpret_cast<float4 *>(sa + lane * C)[c4] = make_float4(d4[0], d4[1], d4[2], d4[3]);
             }
             if (S.ok) dd_in = fmaf(gX, S.dXdd, fmaf(gY, S.dYdd, dd_in));
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                so[4 * lane + t] = (live && S.ok && S.in[t]) ? S.off[t] : -1;
+                sb[4 * lane + t] = w[t];
+            }
+            __syncthreads();
+            // dI scatter, channel-coalesced: one atomic instruction covers
+            // 64 / C whole (pixel, tap) rows of C consecutive floats instead
+            // of 64 scattered addresses
+            {
+                float *dI = p.dfeat[m];
+                constexpr int RPI = 64 / C;               // rows per instruction
+                const int c_l = lane % C, r_l = lane / C;
+#pragma unroll 2
+                for (int j = 0; j < C; ++j) {
+                    const int row = r_l + RPI * j;
+                    const float dsr = sa[row * C + c_l];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int o = so[4 * row + t];
+                        if (o >= 0) unsafeAtomicAdd(dI + o + c_l, sb[4 * row + t] * dsr);
+                    }
+                }
+            }
+            __syncthreads();
         }
 
         // ---- dq = scale W_k^T sh; key and query weight gradients; RMSNorm
