@@ -67,7 +67,8 @@ def level_flops(lvl, V: int) -> int:
 # GPU timing
 # ---------------------------------------------------------------------------
 
-def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int, attn: str = "standard"):
+def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int, attn: str = "standard",
+                precision: str = None):
     import torch
     from paper_2411_16680_amd import runner
 
@@ -77,7 +78,7 @@ def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int, attn: s
         for i, dl in enumerate(dls):
             if i == dominant and ev_a is not None:
                 ev_a.record(stream)
-            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn, precision=precision)
             if i == dominant and ev_b is not None:
                 ev_b.record(stream)
 
@@ -101,7 +102,7 @@ def time_frames(ctx, scene, dls, steps: int, warmup: int, dominant: int, attn: s
     return {"total_ms": float(total_ms), "per_frame_ms": per, "kernel_ms": kern, "wall_s": wall}
 
 
-def per_level_ms(ctx, scene, dls, attn: str = "standard", reps: int = 20):
+def per_level_ms(ctx, scene, dls, attn: str = "standard", precision: str = None, reps: int = 20):
     """Average duration of each level's launch, timed alone."""
     import torch
     from paper_2411_16680_amd import runner
@@ -109,12 +110,12 @@ def per_level_ms(ctx, scene, dls, attn: str = "standard", reps: int = 20):
     out = []
     for dl in dls:
         for _ in range(3):
-            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn, precision=precision)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(reps):
-            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn)
+            runner.run_level(ctx, scene, dl, stream=stream, attn_form=attn, precision=precision)
         b.record(stream)
         torch.cuda.synchronize()
         out.append(a.elapsed_time(b) / reps)
@@ -329,19 +330,22 @@ def main():
 
     results = {}
     dominant = 0
-    runs = (("bf16", sc16, args.steps, "standard"), ("fp32", sc32, args.fp32_steps, "standard"),
-            ("bf16_folded", sc16, args.steps, "folded"))
-    for form, sc, steps, attn in runs:
+    runs = (("bf16", sc16, args.steps, "standard", "bf16"),
+            ("fp32", sc32, args.fp32_steps, "standard", "fp32"),
+            ("bf16_folded", sc16, args.steps, "folded", "bf16"),
+            ("fp8proj", sc16, args.steps, "standard", "bf16_fp8proj"))
+    for form, sc, steps, attn, prec in runs:
         dls = runner.scene_to_device(sc)
         for dl in dls:                 # the benchmark renders RGB only (no acc plane)
             dl.acc = None
         torch.cuda.synchronize()
-        lv_ms = per_level_ms(ctx, sc, dls, attn)
+        lv_ms = per_level_ms(ctx, sc, dls, attn, prec)
         dom = int(np.argmax(lv_ms))
         if form == "bf16":
             dominant = dom
         log(f"{form}: per-level ms {[round(x, 4) for x in lv_ms]} (dominant level {dom})")
-        t = time_frames(ctx, sc, dls, steps, args.warmup, dominant if form == "bf16" else dom, attn)
+        t = time_frames(ctx, sc, dls, steps, args.warmup, dominant if form == "bf16" else dom, attn,
+                        prec)
         per = t["per_frame_ms"]
         results[form] = {"steps": steps, "total_ms": t["total_ms"], "per_level_ms": lv_ms,
                          "p50_ms": float(np.percentile(per, 50)),
@@ -433,6 +437,11 @@ def main():
         "fp32": {"value": results["fp32"]["fps"], "unit": "frames/s",
                  "p50_ms": results["fp32"]["p50_ms"], "p99_ms": results["fp32"]["p99_ms"],
                  "steps": results["fp32"]["steps"], "per_level_ms": results["fp32"]["per_level_ms"]},
+        "fp8proj": {"value": results["fp8proj"]["fps"], "unit": "frames/s",
+                    "p50_ms": results["fp8proj"]["p50_ms"], "p99_ms": results["fp8proj"]["p99_ms"],
+                    "per_level_ms": results["fp8proj"]["per_level_ms"],
+                    "note": "bf16 storage, e4m3 Q/K/V/O projection operands (scales measured on "
+                            "the device each frame), standard attention"},
         "folded": {"value": results["bf16_folded"]["fps"], "unit": "frames/s",
                    "p50_ms": results["bf16_folded"]["p50_ms"],
                    "p99_ms": results["bf16_folded"]["p99_ms"],

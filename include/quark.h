@@ -69,9 +69,14 @@ typedef enum { QK_F32 = 0, QK_BF16 = 1 } qk_dtype;
 /* Arithmetic form of the step.  QK_PREC_FP32: features, samples and
  * projections in float32.  QK_PREC_BF16: features, samples and the Q/K/V/O
  * and decode projections in bfloat16 on the matrix cores with float32
- * accumulation; reprojection, RMSNorm, softmax, decode activations and
- * compositing stay float32 in both forms. */
-typedef enum { QK_PREC_FP32 = 0, QK_PREC_BF16 = 1 } qk_precision;
+ * accumulation.  QK_PREC_BF16_FP8PROJ: bfloat16 storage as QK_PREC_BF16, but
+ * the Q/K/V/O projections take OCP e4m3 operands (per-tensor scales: query
+ * input sqrt(C)/224, samples max|I|/224 over the level's feature maps --
+ * measured on the device each call, one extra read of the maps --, weights
+ * max|W|/224, attention output from its convex-combination bound), float32
+ * accumulation; the decode stays bfloat16.  Reprojection, RMSNorm, softmax,
+ * decode activations and compositing stay float32 in every form. */
+typedef enum { QK_PREC_FP32 = 0, QK_PREC_BF16 = 1, QK_PREC_BF16_FP8PROJ = 2 } qk_precision;
 
 /* How the decoded heads update depth and alpha (Sec. 3.2.2-3.2.3):
  * RESIDUAL  alpha' = sigmoid(logit(clamp(alpha, 1e-6, 1-1e-6)) + F'.w_sigma)
@@ -128,7 +133,8 @@ typedef struct qk_context qk_context;
 
 /* Create a context bound to HIP device `device`.  The context owns device
  * workspaces that grow on demand and live until qk_context_destroy: the
- * folded weights of the one-to-many form (2 C C_feat floats) and the
+ * folded weights of the one-to-many form (2 C C_feat floats), the e4m3
+ * scales (8 floats) and the
  * backward pass's scratch (16 bytes per layer-pixel when d_rgb is given,
  * plus 5 KiB per backward workgroup).  Growing one synchronises the
  * caller's stream and allocates.  A context may be used from one host
@@ -157,7 +163,8 @@ QK_API qk_status qk_context_destroy(qk_context *ctx);
  *               it is written, by the same wave)
  * Supported by the kernels: heads == 1, C == C_feat == head_dim in
  * {8, 16, 32, 64}; otherwise QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
- * QK_F32 and QK_PREC_BF16 needs QK_BF16 (else QK_EDTYPE). */
+ * QK_F32, QK_PREC_BF16 and QK_PREC_BF16_FP8PROJ need QK_BF16 (else
+ * QK_EDTYPE). */
 QK_API qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V,
                          const qk_camera *in_cams, const qk_feature_map *feats,
                          const qk_camera *novel, float near_, float far_,

@@ -15,7 +15,8 @@
 #include "uf_params.h"
 
 namespace qk {
-hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, bool fold, hipStream_t s);
+hipError_t launch_update_fuse(const UFParams &p, int C, int prec, bool fold, hipStream_t s);
+hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s);
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
 hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
@@ -29,6 +30,8 @@ struct qk_context {
     size_t wfold_elems = 0;
     float *bws = nullptr;        // backward workspace: composite adjoint + partials
     size_t bws_elems = 0;
+    float *f8 = nullptr;         // e4m3 scales [7] + running maximum [1]
+    size_t f8_elems = 0;
 };
 
 namespace {
@@ -155,7 +158,7 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
         return fail(QK_EINVAL, "NULL argument");
     if (V < 1 || V > qk::kMaxViews)
         return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
-    if (precision != QK_PREC_FP32 && precision != QK_PREC_BF16)
+    if (precision != QK_PREC_FP32 && precision != QK_PREC_BF16 && precision != QK_PREC_BF16_FP8PROJ)
         return fail(QK_EINVAL, "unknown precision %d", (int)precision);
     if (attn_form != QK_ATTN_STANDARD && attn_form != QK_ATTN_FOLDED)
         return fail(QK_EINVAL, "unknown attention form %d", (int)attn_form);
@@ -173,7 +176,7 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
         return fail(QK_EDTYPE, "unknown LDM dtype %d", (int)in->dtype);
     if (out->F != nullptr && out->dtype != in->dtype)
         return fail(QK_EDTYPE, "ldm_out dtype differs from ldm_in");
-    const qk_dtype need = precision == QK_PREC_BF16 ? QK_BF16 : QK_F32;
+    const qk_dtype need = precision == QK_PREC_FP32 ? QK_F32 : QK_BF16;
     if (in->dtype != need)
         return fail(QK_EDTYPE, "precision %d needs LDM/feature dtype %d", (int)precision, (int)need);
     if (!in->F || !in->depth || !in->alpha || !out->depth || !out->alpha)
@@ -339,11 +342,12 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && (ctx->wfold || ctx->bws)) {
+    if (ctx && (ctx->wfold || ctx->bws || ctx->f8)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
         if (ctx->bws) (void)hipFree(ctx->bws);
+        if (ctx->f8) (void)hipFree(ctx->f8);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -469,7 +473,31 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         p.Wqk = fp.Wqk;
         p.Wvo = fp.Wvo;
     }
-    hipError_t e = qk::launch_update_fuse(p, in->C, precision == QK_PREC_BF16, fold, stream);
+    if (precision == QK_PREC_BF16_FP8PROJ) {
+        st = grow(&ctx->f8, &ctx->f8_elems, 8, stream);
+        if (st != QK_OK) return st;
+        qk::F8Params fp8;
+        std::memset(&fp8, 0, sizeof(fp8));
+        for (int m = 0; m < V; ++m) {
+            fp8.feat[m] = static_cast<const uint16_t *>(feats[m].data);
+            fp8.feat_elems[m] = (int64_t)feats[m].H * feats[m].W * w->C_feat;
+        }
+        fp8.V = V;
+        fp8.Wq = fold ? p.Wqk : w->Wq;
+        fp8.Wk = w->Wk;
+        fp8.Wv = w->Wv;
+        fp8.Wo = fold ? p.Wvo : w->Wo;
+        fp8.C = w->C;
+        fp8.Cf = w->C_feat;
+        fp8.hd = fold ? w->C_feat : w->heads * w->head_dim;
+        fp8.fold = fold ? 1 : 0;
+        fp8.amax_bits = reinterpret_cast<unsigned *>(ctx->f8 + 7);
+        fp8.scales = ctx->f8;
+        hipError_t e8 = qk::launch_fp8_scales(fp8, stream);
+        if (e8 != hipSuccess) return fail(QK_EHIP, "fp8 scale launch: %s", hipGetErrorString(e8));
+        p.f8_scales = ctx->f8;
+    }
+    hipError_t e = qk::launch_update_fuse(p, in->C, (int)precision, fold, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "update_fuse launch: %s", hipGetErrorString(e));
     return QK_OK;
 }

@@ -1,0 +1,119 @@
+// k_fp8.hip -- per-tensor scales of the e4m3 projection variant.
+//
+// Codes are value / scale, scale = bound / 224: below the largest finite
+// e4m3 value of both the OCP (448) and the FNUZ (240) encodings, so no code
+// can overflow whichever the hardware uses; e4m3 precision is relative, so
+// the unused top of the range costs nothing but subnormals below
+// bound * 2^-6 / 224:
+//   query input  |N(F)_c| <= sqrt(C) (RMS-normalised, unit gain)
+//   samples      |s| <= max |I| over the level's feature maps (a bilinear
+//                sample is a convex combination of taps); measured here
+//   weights      max |W| per matrix
+//   attention output  standard form |o_j| <= max|I| * max_j sum_c |W_v[c][j]|
+//                (a convex combination of values); folded form |o| <= max|I|
+// Three launches on the caller's stream: clear the running maximum, reduce
+// |I| over every feature map (bfloat16), then derive the seven scales.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "uf_params.h"
+
+namespace qk {
+namespace {
+
+constexpr float kF8Bound = 224.0f;
+
+__global__ void k_f8_clear(const F8Params p) {
+    if (threadIdx.x == 0) p.amax_bits[0] = 0u;
+}
+
+// |x| of a bfloat16 value as float32 bits: order-preserving for an unsigned
+// maximum.  One block-level reduction, one atomic per block.
+__global__ void __launch_bounds__(256) k_f8_feat_amax(const F8Params p) {
+    const int m = blockIdx.y;
+    const int64_t n = p.feat_elems[m];
+    const uint16_t *f = p.feat[m];
+    unsigned mx = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned b = ((unsigned)(f[i] & 0x7fffu)) << 16;
+        mx = b > mx ? b : mx;
+    }
+    __shared__ unsigned red[256];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != 0u) atomicMax(p.amax_bits, red[0]);
+}
+
+__device__ float block_max(float v, float *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ float mat_amax(const float *W, int n, float *red) {
+    float v = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) v = fmaxf(v, fabsf(W[i]));
+    return block_max(v, red);
+}
+
+__device__ float scale_of(float bound) { return bound > 0.0f ? bound / kF8Bound : 1.0f; }
+
+// One block: weight maxima, the value-projection column norm, the scales.
+__global__ void __launch_bounds__(256) k_f8_finalize(const F8Params p) {
+    __shared__ float red[256];
+    const float amax_s = __uint_as_float(p.amax_bits[0]);
+    const float aq = mat_amax(p.Wq, p.C * p.hd, red);
+    const float ao = mat_amax(p.Wo, p.hd * p.C, red);
+    float ak = 0.0f, av = 0.0f, col = 0.0f;
+    if (!p.fold) {
+        ak = mat_amax(p.Wk, p.Cf * p.hd, red);
+        av = mat_amax(p.Wv, p.Cf * p.hd, red);
+        float c1 = 0.0f;
+        for (int j = threadIdx.x; j < p.hd; j += 256) {
+            float s = 0.0f;
+            for (int c = 0; c < p.Cf; ++c) s += fabsf(p.Wv[c * p.hd + j]);
+            c1 = fmaxf(c1, s);
+        }
+        col = block_max(c1, red);
+    }
+    if (threadIdx.x == 0) {
+        float *sc = p.scales;
+        sc[0] = scale_of(sqrtf((float)p.C));
+        sc[1] = scale_of(amax_s);
+        sc[2] = scale_of(aq);
+        sc[3] = p.fold ? 1.0f : scale_of(ak);     // folded: the key slots hold identity
+        sc[4] = p.fold ? 1.0f : scale_of(av);
+        sc[5] = scale_of(ao);
+        sc[6] = p.fold ? scale_of(amax_s) : scale_of(amax_s * col);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s) {
+    hipLaunchKernelGGL(k_f8_clear, dim3(1), dim3(64), 0, s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t most = 1;
+    for (int m = 0; m < p.V; ++m) most = p.feat_elems[m] > most ? p.feat_elems[m] : most;
+    const int64_t want = (most + 255) / 256;
+    const unsigned bx = (unsigned)(want < 512 ? want : 512);
+    hipLaunchKernelGGL(k_f8_feat_amax, dim3(bx, (unsigned)p.V), dim3(256), 0, s, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_f8_finalize, dim3(1), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace qk

@@ -142,6 +142,44 @@ struct Op<false> {
     }
 };
 
+// FP8 projection operands (OCP e4m3, the gfx950 format): 8 values per lane
+// in the K-slot layout of v_mfma_f32_16x16x32_fp8_fp8 (the same slots as the
+// bfloat16 16x16x32 product).  Values are multiplied by an inverse
+// per-tensor scale before rounding (round to nearest even); the caller
+// applies the scales to the float32 result.
+struct OpF8 {
+    struct __attribute__((aligned(8))) A {
+        long v;
+    };
+    __device__ static inline A make(const float *f, float inv) {
+        int lo = 0, hi = 0;
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0] * inv, f[1] * inv, lo, false);
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2] * inv, f[3] * inv, lo, true);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4] * inv, f[5] * inv, hi, false);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6] * inv, f[7] * inv, hi, true);
+        A a;
+        a.v = (long)(((unsigned long)(unsigned)hi << 32) | (unsigned)lo);
+        return a;
+    }
+    __device__ static inline f32x4 mma(const A &a, const A &b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a.v, b.v, c, 0, 0, 0);
+    }
+};
+
+// Projection operands: bfloat16 / float32 (the storage form), or e4m3.
+template <bool BF16, bool F8>
+struct Mm {
+    using A = typename Op<BF16>::A;
+    __device__ static inline A make(const float *f, float) { return Op<BF16>::make(f); }
+    __device__ static inline f32x4 mma(const A &a, const A &b, f32x4 c) { return Op<BF16>::mma(a, b, c); }
+};
+template <>
+struct Mm<true, true> {
+    using A = OpF8::A;
+    __device__ static inline A make(const float *f, float inv) { return OpF8::make(f, inv); }
+    __device__ static inline f32x4 mma(const A &a, const A &b, f32x4 c) { return OpF8::mma(a, b, c); }
+};
+
 // Reprojection arithmetic: float in the bfloat16 form; double in the float32
 // form, whose budget (1e-4 on RGB) the float representation of absolute
 // pixel coordinates (half an ulp = 6e-5 px at 1920) would use up.
@@ -400,13 +438,16 @@ struct Occupancy {
 // value projection into the output (W_v W_o); the per-view work is a dot
 // product and a weighted sum on the samples themselves (for C = 8 the same
 // MFMA loop, with the blended sample standing in for keys and values).
-template <int C, bool BF16, bool FOLD>
+template <int C, bool BF16, bool FOLD, bool F8>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(Occupancy<C, BF16, FOLD>::waves)))
 k_update_fuse(const UFParams p) {
+    static_assert(!F8 || BF16, "e4m3 projections take bfloat16 storage");
     using SH = Shape<C>;
     using OP = Op<BF16>;
     using AF = typename OP::A;
+    using MM = Mm<BF16, F8>;                    // Q/K/V/O operands
+    using MA = typename MM::A;
     using T = typename OP::T;
     using Coord = typename CoordT<BF16>::type;
     constexpr int G = SH::G, KC = SH::KC, NT = SH::NT, ND = SH::ND, PIX = SH::PIX, P = SH::P;
@@ -417,11 +458,20 @@ k_update_fuse(const UFParams p) {
     static_assert(!TAPK || 64 * 4 * sizeof(int2) <= PIX * P * sizeof(float),
                   "tap exchange must fit the o tile it shares");
 
-    __shared__ AF sfrag[FR::N][64];
+    __shared__ AF sfrag[FR::N][64];    // FP8 form: Q/K/V/O slots hold e4m3 codes in their first 8 B
     __shared__ float sF[4][PIX * P];
     __shared__ float sO[4][PIX * P];   // o tile; for C = 8 also the tap exchange
 
     const int tid = threadIdx.x;
+
+    // e4m3 per-tensor scales (value = scale x code): query input, samples,
+    // W_q, W_k, W_v, W_o, attention output
+    float f8s[7] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+    if constexpr (F8) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) f8s[i] = p.f8_scales[i];
+    }
+    const float f8_inv_x = 1.0f / f8s[0], f8_inv_s = 1.0f / f8s[1], f8_inv_o = 1.0f / f8s[6];
 
     // ---- weight fragments from the float32 master weights, once per
     // workgroup.  Fragment lane (c, k) holds element [k-slot 8k..8k+7][c] of
@@ -463,6 +513,12 @@ k_update_fuse(const UFParams p) {
             }
             vals[i] = w;
         }
+        if constexpr (F8) {
+            if (kind < 4) {
+                *reinterpret_cast<MA *>(&sfrag[f][ln]) = MM::make(vals, 1.0f / f8s[2 + kind]);
+                continue;
+            }
+        }
         sfrag[f][ln] = OP::make(vals);
     }
     __syncthreads();
@@ -501,17 +557,25 @@ k_update_fuse(const UFParams p) {
     // the row after it
     const bool owner = (G > 1) ? ((g & 1) == 0) : (g == 0);
 
+    // projection fragment f of this lane (e4m3 copy in the FP8 form)
+    auto pfrag = [&](int f) -> MA {
+        if constexpr (F8) return *reinterpret_cast<const MA *>(&sfrag[f][lane]);
+        else return sfrag[f][lane];
+    };
     constexpr int KCB = STDLOOP ? KC : 1, NTB = STDLOOP ? NT : 1;
-    AF Bk[KCB][NTB], Bv[KCB][NTB];
+    MA Bk[KCB][NTB], Bv[KCB][NTB];
     if constexpr (STDLOOP) {
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                Bk[kc][t] = sfrag[FR::OFF_K + kc * NT + t][lane];
-                Bv[kc][t] = sfrag[FR::OFF_V + kc * NT + t][lane];
+                Bk[kc][t] = pfrag(FR::OFF_K + kc * NT + t);
+                Bv[kc][t] = pfrag(FR::OFF_V + kc * NT + t);
             }
     }
+    // scale of a key logit and of a value in the FP8 form (1 otherwise)
+    const float kscale = f8s[3] * f8s[1];
+    const float vscale = (TAPK && FOLD) ? kscale : f8s[4] * f8s[1];   // folded C = 8: v = k
 
     float *tF = sF[wave];
     float *tO = sO[wave];
@@ -555,24 +619,28 @@ k_update_fuse(const UFParams p) {
         const float inv = 1.0f / sqrtf(ss * (1.0f / (float)C) + 1e-6f);
         f32x4 Q[NT];
         {
-            AF Xn[KC];
+            MA Xn[KC];
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float t8[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) t8[i] = fa[kc][i] * inv;
-                Xn[kc] = OP::make(t8);
+                Xn[kc] = MM::make(t8, f8_inv_x);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 Q[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
-                    Q[t] = OP::mma(sfrag[FR::OFF_Q + kc * NT + t][lane], Xn[kc], Q[t]);
+                    Q[t] = MM::mma(pfrag(FR::OFF_Q + kc * NT + t), Xn[kc], Q[t]);
+                if constexpr (F8) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) Q[t][i] *= f8s[2] * f8s[0];
+                }
             }
         }
 
-        AF Ob[KC];                                     // o, operand layout
+        MA Ob[KC];                                     // o, operand layout
         const Coord invdc = recip((Coord)d);
         if constexpr (STDLOOP) {
             // ---- cross-attention over the views on MFMA: per-sample keys and
@@ -593,7 +661,7 @@ k_update_fuse(const UFParams p) {
                 // B operands: the blended sample (one per K chunk), or for C = 8
                 // the weighted taps of each 16-pixel row-group
                 constexpr int NA = TAPK ? 4 : KC;
-                AF Sb[NA];
+                MA Sb[NA];
                 if constexpr (TAPK) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
@@ -601,13 +669,13 @@ k_update_fuse(const UFParams p) {
                         raw_unpack<BF16>(cur.t[j], t8);
 #pragma unroll
                         for (int i = 0; i < 8; ++i) t8[i] *= cur.w[j];
-                        Sb[j] = OP::make(t8);
+                        Sb[j] = MM::make(t8, f8_inv_s);
                     }
                 } else {
                     float sv[KC][8];
                     blend_taps<C, BF16>(cur, sv);
 #pragma unroll
-                    for (int kc = 0; kc < KC; ++kc) Sb[kc] = OP::make(sv[kc]);
+                    for (int kc = 0; kc < KC; ++kc) Sb[kc] = MM::make(sv[kc], f8_inv_s);
                 }
                 // keys^T and logits
                 f32x4 Kt[NT];
@@ -615,11 +683,11 @@ k_update_fuse(const UFParams p) {
                 for (int t = 0; t < NT; ++t) {
                     Kt[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
                     if constexpr (TAPK) {
-                        Kt[t] = OP::mma(Bk[0][0], Sb[2 * t], Kt[t]);
-                        Kt[t] = OP::mma(Bk[0][1], Sb[2 * t + 1], Kt[t]);
+                        Kt[t] = MM::mma(Bk[0][0], Sb[2 * t], Kt[t]);
+                        Kt[t] = MM::mma(Bk[0][1], Sb[2 * t + 1], Kt[t]);
                     } else {
 #pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) Kt[t] = OP::mma(Bk[kc][t], Sb[kc], Kt[t]);
+                        for (int kc = 0; kc < KC; ++kc) Kt[t] = MM::mma(Bk[kc][t], Sb[kc], Kt[t]);
                     }
                 }
                 float lg[NS];
@@ -629,14 +697,14 @@ k_update_fuse(const UFParams p) {
                     for (int t = 0; t < NT; ++t)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
-                    lg[0] = result_pixel_sum<C>(part) * scale;
+                    lg[0] = result_pixel_sum<C>(part) * (scale * kscale);
                 } else {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         float part = 0.0f;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
-                        lg[t] = result_pixel_sum<C>(part) * scale;
+                        lg[t] = result_pixel_sum<C>(part) * (scale * kscale);
                     }
                 }
                 // online softmax update
@@ -658,11 +726,11 @@ k_update_fuse(const UFParams p) {
                     if constexpr (TAPK && FOLD) {
                         Vt = Kt[t];                      // values are the samples themselves
                     } else if constexpr (TAPK) {
-                        Vt = OP::mma(Bv[0][0], Sb[2 * t], Vt);
-                        Vt = OP::mma(Bv[0][1], Sb[2 * t + 1], Vt);
+                        Vt = MM::mma(Bv[0][0], Sb[2 * t], Vt);
+                        Vt = MM::mma(Bv[0][1], Sb[2 * t + 1], Vt);
                     } else {
 #pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) Vt = OP::mma(Bv[kc][t], Sb[kc], Vt);
+                        for (int kc = 0; kc < KC; ++kc) Vt = MM::mma(Bv[kc][t], Sb[kc], Vt);
                     }
                     const int s = (G == 1) ? 0 : t;
 #pragma unroll
@@ -693,7 +761,7 @@ k_update_fuse(const UFParams p) {
             // o = acc / Z: result layout -> LDS -> operand layout
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const float iz = 1.0f / Z[(G == 1) ? 0 : t];
+                const float iz = vscale / Z[(G == 1) ? 0 : t];
                 float o4[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) o4[i] = acc[t][i] * iz;
@@ -703,7 +771,7 @@ k_update_fuse(const UFParams p) {
             for (int kc = 0; kc < KC; ++kc) {
                 float t8[8];
                 lds_read8(&tO[pl_b * P + ch0 + 32 * kc], t8);
-                Ob[kc] = OP::make(t8);
+                Ob[kc] = MM::make(t8, f8_inv_o);
             }
         } else {
             // ---- one-to-many attention: q~ (the query with W_k folded in) to
@@ -762,7 +830,7 @@ k_update_fuse(const UFParams p) {
                 float t8[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) t8[i] = ob[kc][i] * iz;
-                Ob[kc] = OP::make(t8);
+                Ob[kc] = MM::make(t8, f8_inv_o);
             }
         }
 
@@ -771,9 +839,17 @@ k_update_fuse(const UFParams p) {
         for (int t = 0; t < NT; ++t) {
             float *fp = &tF[(16 * sd(t) + n) * P + ed(t)];
             const float4 f4 = *reinterpret_cast<const float4 *>(fp);
-            f32x4 Fo = f32x4{f4.x, f4.y, f4.z, f4.w};
+            // FP8 form: F' = F + s (W_o o)_codes with s = s_Wo s_o, accumulated
+            // as s (F / s + codes product)
+            const float os = f8s[5] * f8s[6], ios = 1.0f / os;
+            f32x4 Fo = F8 ? f32x4{f4.x * ios, f4.y * ios, f4.z * ios, f4.w * ios}
+                          : f32x4{f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) Fo = OP::mma(sfrag[FR::OFF_O + kc * NT + t][lane], Ob[kc], Fo);
+            for (int kc = 0; kc < KC; ++kc) Fo = MM::mma(pfrag(FR::OFF_O + kc * NT + t), Ob[kc], Fo);
+            if constexpr (F8) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Fo[i] *= os;
+            }
             *reinterpret_cast<float4 *>(fp) = make_float4(Fo[0], Fo[1], Fo[2], Fo[3]);
         }
 
@@ -866,24 +942,26 @@ __global__ void __launch_bounds__(256) k_composite(const CompParams p) {
 // ---------------------------------------------------------------------------
 // Launchers (host side of this translation unit)
 // ---------------------------------------------------------------------------
-template <int C, bool BF16, bool FOLD>
+template <int C, bool BF16, bool FOLD, bool F8>
 static hipError_t launch_uf(const UFParams &p, hipStream_t s) {
-    hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD>), dim3(p.n_tiles), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8>), dim3(p.n_tiles), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
+// prec: 0 float32, 1 bfloat16, 2 bfloat16 storage with e4m3 projections
 template <int C>
-static hipError_t launch_c(const UFParams &p, bool bf16, bool fold, hipStream_t s) {
-    if (bf16) return fold ? launch_uf<C, true, true>(p, s) : launch_uf<C, true, false>(p, s);
-    return fold ? launch_uf<C, false, true>(p, s) : launch_uf<C, false, false>(p, s);
+static hipError_t launch_c(const UFParams &p, int prec, bool fold, hipStream_t s) {
+    if (prec == 2) return fold ? launch_uf<C, true, true, true>(p, s) : launch_uf<C, true, false, true>(p, s);
+    if (prec == 1) return fold ? launch_uf<C, true, true, false>(p, s) : launch_uf<C, true, false, false>(p, s);
+    return fold ? launch_uf<C, false, true, false>(p, s) : launch_uf<C, false, false, false>(p, s);
 }
 
-hipError_t launch_update_fuse(const UFParams &p, int C, bool bf16, bool fold, hipStream_t s) {
+hipError_t launch_update_fuse(const UFParams &p, int C, int prec, bool fold, hipStream_t s) {
     switch (C) {
-        case 8: return launch_c<8>(p, bf16, fold, s);
-        case 16: return launch_c<16>(p, bf16, fold, s);
-        case 32: return launch_c<32>(p, bf16, fold, s);
-        case 64: return launch_c<64>(p, bf16, fold, s);
+        case 8: return launch_c<8>(p, prec, fold, s);
+        case 16: return launch_c<16>(p, prec, fold, s);
+        case 32: return launch_c<32>(p, prec, fold, s);
+        case 64: return launch_c<64>(p, prec, fold, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -27,6 +27,7 @@ struct UFParams {
 
     const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
     const float *Wqk, *Wvo;    // folded weights (one-to-many form), C x C
+    const float *f8_scales;    // [7] e4m3 scales (e4m3 projection form), device
 
     int32_t V, L, H, W;
     int32_t layers_per_chunk;  // layers handled by one workgroup
@@ -101,6 +102,22 @@ struct InitParams {
     int64_t N, npix;        // L*H*W, H*W
     int32_t L, C;
     float inv_near, inv_far;
+};
+
+}  // namespace qk
+
+namespace qk {
+
+// Scales of the e4m3 projection form (see k_fp8.hip).
+struct F8Params {
+    const uint16_t *feat[kMaxViews];   // bfloat16 feature maps
+    int64_t feat_elems[kMaxViews];
+    int32_t V;
+    const float *Wq, *Wk, *Wv, *Wo;    // folded form: Wq = W_qk, Wo = W_vo
+    int32_t C, Cf, hd;
+    int32_t fold;
+    unsigned *amax_bits;               // workspace [1]
+    float *scales;                     // out [7]
 };
 
 }  // namespace qk

@@ -21,7 +21,7 @@ QK_OK, QK_EINVAL, QK_ESHAPE, QK_EDTYPE, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED = 0,
 STATUS_NAMES = {0: "QK_OK", -1: "QK_EINVAL", -2: "QK_ESHAPE", -3: "QK_EDTYPE", -4: "QK_ENOMEM",
                 -5: "QK_EHIP", -6: "QK_EUNSUPPORTED"}
 QK_F32, QK_BF16 = 0, 1
-PREC = {"fp32": 0, "bf16": 1}
+PREC = {"fp32": 0, "bf16": 1, "bf16_fp8proj": 2}
 ATTN = {"standard": 0, "folded": 1}
 MODE = {"residual": 0, "paper": 1}
 

@@ -108,12 +108,15 @@ def test_valid_arguments_pass():
         assert _check(sc, feats, wts, ldm) == lib.QK_OK
         sc, feats, wts, ldm = _args(C=C, dtype="bf16")
         assert _check(sc, feats, wts, ldm, precision="bf16") == lib.QK_OK
+        assert _check(sc, feats, wts, ldm, precision="bf16_fp8proj") == lib.QK_OK
+        assert _check(sc, feats, wts, ldm, precision=3) == lib.QK_EINVAL
 
 
 def test_rejections():
     sc, feats, wts, ldm = _args()
     # precision / dtype mismatch
     assert _check(sc, feats, wts, ldm, precision="bf16") == lib.QK_EDTYPE
+    assert _check(sc, feats, wts, ldm, precision="bf16_fp8proj") == lib.QK_EDTYPE
     # unsupported channel count and heads
     sc2, f2, w2, l2 = _args(C=24)
     assert _check(sc2, f2, w2, l2) == lib.QK_EUNSUPPORTED

@@ -33,7 +33,11 @@ pytestmark = pytest.mark.gpu
 TOL = {
     "fp32": {"rgb": 1e-4, "acc": 1e-4, "alpha": 1e-4, "disp": 1e-3, "F_abs": 2e-4, "F_rel": 2e-4},
     "bf16": {"rgb": 2e-2, "acc": 2e-2, "alpha": 2e-2, "disp": 1e-1, "F_abs": 4e-2, "F_rel": 1.6e-2},
+    # e4m3 projections: each operand rounds to 3 mantissa bits (relative
+    # 2^-4), about 8x the bfloat16 rounding, through the same chain
+    "fp8": {"rgb": 8e-2, "acc": 8e-2, "alpha": 8e-2, "disp": 0.6, "F_abs": 0.3, "F_rel": 0.13},
 }
+PREC = {"fp32": "fp32", "bf16": "bf16", "fp8": "bf16_fp8proj"}
 REPORT = []
 
 
@@ -87,6 +91,8 @@ def compare(gpu, ref, form, scene, level, rows=None, composite=True, label=""):
         assert errs["acc"] <= t["acc"], (label, "acc", errs)
         if form == "bf16":
             assert errs["psnr"] >= 45.0, (label, "psnr", errs)
+        if form == "fp8":
+            assert errs["psnr"] >= 30.0, (label, "psnr", errs)
     return errs
 
 
@@ -269,3 +275,38 @@ def test_standalone_composite(ctx):
     torch.cuda.synchronize()
     np.testing.assert_allclose(rgb.cpu().numpy(), rgb_ref, atol=1e-6)
     np.testing.assert_allclose(acc.cpu().numpy(), acc_ref, atol=1e-6)
+
+
+# ---------------------------------------------------------------- e4m3 projections
+
+@pytest.mark.parametrize("attn", ATTN)
+def test_fp8_c1_full(ctx, attn):
+    _say("c1 full fp8", attn)
+    sc = synth.to_bf16(synth.make_inputs(1))
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn, precision=PREC["fp8"])
+    compare(gpu, ref, "fp8", sc, sc.levels[0], label=f"c1 {attn}")
+
+
+@pytest.mark.parametrize("attn", ATTN)
+@pytest.mark.parametrize("li", [0, 1, 2, 3])
+def test_fp8_c3_levels_sampled_rows(ctx, c3_scenes, li, attn):
+    sc = c3_scenes["bf16"]
+    lvl = sc.levels[li]
+    H = lvl.H
+    rows = sorted({0, H // 2, H - 1})
+    _say("c3 level fp8", li, attn, "rows", rows)
+    ref = oracle.run_level(sc, lvl, rows=rows)
+    gpu, _ = run_gpu_level(ctx, sc, li, attn_form=attn, precision=PREC["fp8"])
+    compare(gpu, ref, "fp8", sc, lvl, rows=rows, composite=lvl.composite,
+            label=f"c3 L{li} {attn}")
+
+
+@pytest.mark.parametrize("attn", ATTN)
+@pytest.mark.parametrize("name,kw", EDGE[:5], ids=[e[0] for e in EDGE[:5]])
+def test_fp8_edge_cases(ctx, name, kw, attn):
+    _say("edge fp8", name, attn)
+    sc = synth.to_bf16(synth.make_custom(dtype="f32", seed=zlib.crc32(name.encode()) % 1000, **kw))
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn, precision=PREC["fp8"])
+    compare(gpu, ref, "fp8", sc, sc.levels[0], label=f"{name} {attn}")
