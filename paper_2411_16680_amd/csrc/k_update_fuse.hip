@@ -32,8 +32,8 @@
 //   * taps are clamped into the map with zero weight when outside, so the
 //     gather has no divergent branches; the loads of view m + 1 are issued
 //     before view m is projected;
-//   * softmax over views is an online update (running max / sum, one exp per
-//     state and view);
+//   * softmax over views is an online update whose reference moves only when
+//     a logit exceeds it by more than 8 (one exp per state and view);
 //   * weights arrive as float32 masters; each workgroup converts them once
 //     into operand fragments in LDS; the K/V fragments then stay in registers.
 #include <hip/hip_runtime.h>
@@ -209,6 +209,30 @@ __device__ inline void lds_read8(const float *src, float *f) {
     f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
 }
 
+// Blended sample from the load layout (pixel pl_ld, channels ch_ld + 32 kc)
+// to the operand layout (pixel pl_b, channels ch0 + 32 kc) through the
+// wave's LDS slice (rows of P floats per pixel).  One wave writes and reads
+// its own slice, in order, so no barrier is needed.
+template <int C>
+__device__ inline void stage_sample(float *slice, int pl_ld, int ch_ld, int pl_b, int ch0,
+                                    float (&sv)[Shape<C>::KC][8]) {
+    constexpr int KC = Shape<C>::KC, P = Shape<C>::P;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        float *dst = &slice[pl_ld * P + ch_ld + 32 * kc];
+        *reinterpret_cast<float4 *>(dst) = make_float4(sv[kc][0], sv[kc][1], sv[kc][2], sv[kc][3]);
+        *reinterpret_cast<float4 *>(dst + 4) = make_float4(sv[kc][4], sv[kc][5], sv[kc][6], sv[kc][7]);
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        const float *src = &slice[pl_b * P + ch0 + 32 * kc];
+        const float4 a = *reinterpret_cast<const float4 *>(src);
+        const float4 b = *reinterpret_cast<const float4 *>(src + 4);
+        sv[kc][0] = a.x; sv[kc][1] = a.y; sv[kc][2] = a.z; sv[kc][3] = a.w;
+        sv[kc][4] = b.x; sv[kc][5] = b.y; sv[kc][6] = b.z; sv[kc][7] = b.w;
+    }
+}
+
 // Raw storage of one 8-channel tap: 16 B of bfloat16 or 32 B of float.
 template <bool BF16>
 struct RawTap {
@@ -319,7 +343,9 @@ __device__ inline void blend_taps(const Taps<C, BF16> &tp, float (&sv)[Shape<C>:
 
 // C = 8 taps-along-K: lane (r, g) reprojects its own pixel (16 g + r) into
 // view m, publishes that pixel's four (tap offset, weight) pairs in LDS, and
-// loads tap g of pixel 16 j + r for each row-group j = 0..3.
+// for each row-group j = 0..3 loads tap (l & 3) of pixel 16 j + (l >> 2)
+// (l = 16 g + r); the weighted taps reach the operand layout (tap g of pixel
+// 16 j + r in lane (r, g)) through the same LDS slice.
 template <bool BF16>
 struct TapsK {
     RawTap<BF16> t[4];
@@ -365,9 +391,12 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
     int4 *slot = reinterpret_cast<int4 *>(&tT[(g * 16 + r) * 4]);
     slot[0] = ow0;
     slot[1] = ow1;
+    // row-group j: lane l loads tap (l & 3) of pixel 16 j + (l >> 2), so each
+    // quad of lanes reads the four taps of one pixel (two 32-byte runs)
+    const int lane = 16 * g + r;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int2 e = tT[(j * 16 + r) * 4 + g];
+        const int2 e = tT[64 * j + lane];
         tp.w[j] = __int_as_float(e.y);
         raw_load<BF16>(fm + e.x, tp.t[j]);
     }
@@ -455,6 +484,8 @@ k_update_fuse(const UFParams p) {
     constexpr bool STDLOOP = !FOLD || TAPK;     // the MFMA view loop
     constexpr int NS = (G == 1) ? 1 : NT;       // softmax states per lane
     using FR = Frags<C, STDLOOP>;
+    static_assert(!TAPK || 64 * sizeof(MA) <= PIX * P * sizeof(float),
+                  "tap staging must fit the o tile it shares");
     static_assert(!TAPK || 64 * 4 * sizeof(int2) <= PIX * P * sizeof(float),
                   "tap exchange must fit the o tile it shares");
 
@@ -549,6 +580,17 @@ k_update_fuse(const UFParams p) {
     const int pl_b = 16 * sg + n;                      // wave-local pixel
     const int xa = x0w + pl_b;
     const bool a_ok = xa < p.W;
+    // load role of this lane (C >= 16): RL adjacent lanes read one pixel's
+    // tap chunk as consecutive 16-byte pieces, which the texture path serves
+    // together (in the operand layout the lanes of a pixel are 16 apart, so
+    // every lane of a quad would hit a different line); the blended sample
+    // then goes to the operand layout through the wave's LDS slice.  C = 8
+    // (taps along K) keeps its own scheme.
+    constexpr int RL = TAPK ? 1 : ((C >= 32) ? 4 : C / 8);
+    const int pl_ld = TAPK ? pl_b : lane / RL;
+    const int ch_ld = TAPK ? ch0 : 8 * (lane % RL);
+    const int x_ld = x0w + pl_ld;
+    const bool ld_ok = x_ld < p.W;
     // result role: output rows 4g..4g+3 of tile t belong to sub-tile sd(t),
     // channels ed(t) + [0, 4)
     auto sd = [&](int t) { return (G > 1) ? (16 * t + 4 * g) / C : 0; };
@@ -584,6 +626,7 @@ k_update_fuse(const UFParams p) {
     const bool do_comp = p.rgb != nullptr;
     const float scale = FOLD ? 1.0f : 1.0f / sqrtf((float)C);   // folded: W_qk carries it
     const Coord uc = (Coord)(a_ok ? xa : 0) + (Coord)0.5, vc = (Coord)y + (Coord)0.5;
+    const Coord uc_ld = (Coord)(ld_ok ? x_ld : 0) + (Coord)0.5;
     const float band = p.inv_near - p.inv_far;
     const float half_l = 0.5f / (float)p.L;
 
@@ -642,11 +685,13 @@ k_update_fuse(const UFParams p) {
 
         MA Ob[KC];                                     // o, operand layout
         const Coord invdc = recip((Coord)d);
+        const float d_ld = TAPK ? d : (ld_ok ? p.depth_in[rowbase + x_ld] : 1.0f);
+        const Coord invdc_ld = TAPK ? invdc : recip((Coord)d_ld);
         if constexpr (STDLOOP) {
             // ---- cross-attention over the views on MFMA: per-sample keys and
             // values (standard form) or, for C = 8 folded, the blended samples
-            // themselves; online softmax (finite start so the update is
-            // branch-free; one exp per state and view)
+            // themselves; online softmax (finite start, so the first view
+            // always moves the reference)
             float M[NS], Z[NS];
             f32x4 acc[NT];
 #pragma unroll
@@ -663,17 +708,22 @@ k_update_fuse(const UFParams p) {
                 constexpr int NA = TAPK ? 4 : KC;
                 MA Sb[NA];
                 if constexpr (TAPK) {
+                    // the slice that held the tap offsets is free again: the
+                    // next view's loads have taken theirs
+                    MA *stage = reinterpret_cast<MA *>(tT);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         float t8[8];
                         raw_unpack<BF16>(cur.t[j], t8);
 #pragma unroll
                         for (int i = 0; i < 8; ++i) t8[i] *= cur.w[j];
-                        Sb[j] = MM::make(t8, f8_inv_s);
+                        stage[16 * (lane & 3) + (lane >> 2)] = MM::make(t8, f8_inv_s);
+                        Sb[j] = stage[lane];
                     }
                 } else {
                     float sv[KC][8];
                     blend_taps<C, BF16>(cur, sv);
+                    stage_sample<C>(tO, pl_ld, ch_ld, pl_b, ch0, sv);
 #pragma unroll
                     for (int kc = 0; kc < KC; ++kc) Sb[kc] = MM::make(sv[kc], f8_inv_s);
                 }
@@ -707,17 +757,27 @@ k_update_fuse(const UFParams p) {
                         lg[t] = result_pixel_sum<C>(part) * (scale * kscale);
                     }
                 }
-                // online softmax update
-                float sc[NS], ev[NS];
+                // online softmax with a lazily moved reference: weights are
+                // exp(logit - M) while the logit stays within e^8 of M; only
+                // a logit beyond that (always the first view, rarely another)
+                // rescales the running sums to a new reference
+                float pw[NS];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const float diff = lg[s] - M[s];
-                    const float x = __expf(-fabsf(diff));
-                    const bool up = diff > 0.0f;
-                    sc[s] = up ? x : 1.0f;
-                    ev[s] = up ? 1.0f : x;
-                    M[s] = up ? lg[s] : M[s];
-                    Z[s] = fmaf(Z[s], sc[s], ev[s]);
+                    float diff = lg[s] - M[s];
+                    if (diff > 8.0f) {
+                        const float r = __expf(-diff);
+                        Z[s] *= r;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            if (G == 1 || t == s)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) acc[t][i] *= r;
+                        M[s] = lg[s];
+                        diff = 0.0f;
+                    }
+                    pw[s] = __expf(diff);
+                    Z[s] += pw[s];
                 }
                 // values^T
 #pragma unroll
@@ -734,7 +794,7 @@ k_update_fuse(const UFParams p) {
                     }
                     const int s = (G == 1) ? 0 : t;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(acc[t][i], sc[s], ev[s] * Vt[i]);
+                    for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(pw[s], Vt[i], acc[t][i]);
                 }
             };
             // Two tap buffers in turn: the loads of view m + 1 are in flight
@@ -743,16 +803,16 @@ k_update_fuse(const UFParams p) {
             // alone, the scheduler moves the next view's loads after this
             // view's work, which serialises the views on memory latency).
             TapsT ta, tb;
-            issue_any<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, n, g, tT, ta);
+            issue_any<C, BF16>(p, 0, uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, ta);
             __builtin_amdgcn_sched_barrier(0);
             // The issues are unconditional (clamped view index; the extra loads
             // at the end hit the cache) so the wait counts stay exact.
             for (int m = 0; m < p.V; m += 2) {
-                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, tb);
+                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, tb);
                 __builtin_amdgcn_sched_barrier(0);
                 view_step(ta);
                 __builtin_amdgcn_sched_barrier(0);
-                issue_any<C, BF16>(p, min(m + 2, p.V - 1), uc, vc, invdc, a_ok, ch0, n, g, tT, ta);
+                issue_any<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, ta);
                 __builtin_amdgcn_sched_barrier(0);
                 if (m + 1 < p.V) view_step(tb);
                 __builtin_amdgcn_sched_barrier(0);
@@ -793,33 +853,41 @@ k_update_fuse(const UFParams p) {
             auto view_step = [&](const Taps<C, BF16> &cur) {
                 float sv[KC][8];
                 blend_taps<C, BF16>(cur, sv);
+                stage_sample<C>(tO, pl_ld, ch_ld, pl_b, ch0, sv);
                 float part = 0.0f;
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
                     for (int i = 0; i < 8; ++i) part = fmaf(qa[kc][i], sv[kc][i], part);
                 const float a = operand_pixel_sum<C>(part);
-                const float diff = a - Mx;
-                const float x = __expf(-fabsf(diff));
-                const bool up = diff > 0.0f;
-                const float sc = up ? x : 1.0f, ev = up ? 1.0f : x;
-                Mx = up ? a : Mx;
-                Zs = fmaf(Zs, sc, ev);
+                float diff = a - Mx;
+                if (diff > 8.0f) {                 // lazily moved reference (see above)
+                    const float r = __expf(-diff);
+                    Zs *= r;
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) ob[kc][i] *= r;
+                    Mx = a;
+                    diff = 0.0f;
+                }
+                const float pw = __expf(diff);
+                Zs += pw;
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) ob[kc][i] = fmaf(ob[kc][i], sc, ev * sv[kc][i]);
+                    for (int i = 0; i < 8; ++i) ob[kc][i] = fmaf(pw, sv[kc][i], ob[kc][i]);
             };
             // two tap buffers in turn (see the standard loop)
             Taps<C, BF16> ta, tb;
-            issue_taps<C, BF16>(p, 0, uc, vc, invdc, a_ok, ch0, ta);
+            issue_taps<C, BF16>(p, 0, uc_ld, vc, invdc_ld, ld_ok, ch_ld, ta);
             __builtin_amdgcn_sched_barrier(0);
             for (int m = 0; m < p.V; m += 2) {
-                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc, vc, invdc, a_ok, ch0, tb);
+                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, tb);
                 __builtin_amdgcn_sched_barrier(0);
                 view_step(ta);
                 __builtin_amdgcn_sched_barrier(0);
-                issue_taps<C, BF16>(p, min(m + 2, p.V - 1), uc, vc, invdc, a_ok, ch0, ta);
+                issue_taps<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, ta);
                 __builtin_amdgcn_sched_barrier(0);
                 if (m + 1 < p.V) view_step(tb);
                 __builtin_amdgcn_sched_barrier(0);
