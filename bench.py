@@ -295,6 +295,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth-mode", default="iid", choices=["iid", "smooth"])
     ap.add_argument("--no-train", action="store_true", help="skip the forward+adjoint timing")
+    ap.add_argument("--profile-train", action="store_true",
+                    help="for rocprofv3: run --steps training steps (float32 forward + adjoint, "
+                         "960x540 V=4) and exit without timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-run", action="store_true",
@@ -319,6 +322,10 @@ def main():
 
     if args.profile_run:
         profile_run(ctx, args.steps, args.depth_mode)
+        return
+    if args.profile_train:
+        t = time_training_step(ctx, steps=args.steps, warmup=1)
+        log(f"profile training steps: {t['step_ms']:.3f} ms each")
         return
 
     log("drawing the 1080p multi-scale workload (V=8)")

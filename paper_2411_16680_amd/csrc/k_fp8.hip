@@ -32,12 +32,17 @@ __global__ void k_f8_clear(const F8Params p) {
 // maximum.  One block-level reduction, one atomic per block.
 __global__ void __launch_bounds__(256) k_f8_feat_amax(const F8Params p) {
     const int m = blockIdx.y;
-    const int64_t n = p.feat_elems[m];
-    const uint16_t *f = p.feat[m];
+    const int64_t n8 = p.feat_elems[m] / 8;          // C is a multiple of 8: whole 16-byte words
+    const uint4 *f = reinterpret_cast<const uint4 *>(p.feat[m]);
     unsigned mx = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const unsigned b = ((unsigned)(f[i] & 0x7fffu)) << 16;
-        mx = b > mx ? b : mx;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n8; i += (int64_t)gridDim.x * 256) {
+        const uint4 w = f[i];
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned lo = (u[k] & 0x7fffu) << 16, hi = u[k] & 0x7fff0000u;
+            mx = max(mx, max(lo, hi));
+        }
     }
     __shared__ unsigned red[256];
     red[threadIdx.x] = mx;
@@ -107,8 +112,8 @@ hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s) {
     if (e != hipSuccess) return e;
     int64_t most = 1;
     for (int m = 0; m < p.V; ++m) most = p.feat_elems[m] > most ? p.feat_elems[m] : most;
-    const int64_t want = (most + 255) / 256;
-    const unsigned bx = (unsigned)(want < 512 ? want : 512);
+    const int64_t want = (most / 8 + 255) / 256;
+    const unsigned bx = (unsigned)(want < 1 ? 1 : (want < 512 ? want : 512));
     hipLaunchKernelGGL(k_f8_feat_amax, dim3(bx, (unsigned)p.V), dim3(256), 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -486,6 +486,8 @@ k_update_fuse(const UFParams p) {
     using FR = Frags<C, STDLOOP>;
     static_assert(!TAPK || 64 * sizeof(MA) <= PIX * P * sizeof(float),
                   "tap staging must fit the o tile it shares");
+    static_assert(TAPK || PIX * (C / 8 + (sizeof(MA) <= 16 ? 1 : 0)) * sizeof(MA) <= PIX * P * sizeof(float),
+                  "sample staging must fit the o tile it shares");
     static_assert(!TAPK || 64 * 4 * sizeof(int2) <= PIX * P * sizeof(float),
                   "tap exchange must fit the o tile it shares");
 
@@ -721,11 +723,18 @@ k_update_fuse(const UFParams p) {
                         Sb[j] = stage[lane];
                     }
                 } else {
+                    // blend and round in the load layout, then move the
+                    // operand words (8 channels each) through the LDS slice;
+                    // rows padded by one word where they are 16 B or less
                     float sv[KC][8];
                     blend_taps<C, BF16>(cur, sv);
-                    stage_sample<C>(tO, pl_ld, ch_ld, pl_b, ch0, sv);
+                    constexpr int RW = C / 8 + (sizeof(MA) <= 16 ? 1 : 0);
+                    MA *st = reinterpret_cast<MA *>(tO);
 #pragma unroll
-                    for (int kc = 0; kc < KC; ++kc) Sb[kc] = MM::make(sv[kc], f8_inv_s);
+                    for (int kc = 0; kc < KC; ++kc)
+                        st[pl_ld * RW + (ch_ld + 32 * kc) / 8] = MM::make(sv[kc], f8_inv_s);
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) Sb[kc] = st[pl_b * RW + (ch0 + 32 * kc) / 8];
                 }
                 // keys^T and logits
                 f32x4 Kt[NT];
