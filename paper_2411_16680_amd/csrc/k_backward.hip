@@ -583,10 +583,22 @@ k_uf_backward(const BwdParams p) {
 }
 
 // Deterministic sum of the workgroup partials into the weight gradients.
+// A block takes 16 consecutive entries of one tile; its 16 lanes per entry
+// sum interleaved partials, then one lane combines the 16 sums in order.
 __global__ void __launch_bounds__(kBlock) k_reduce_wgrad(const BwdParams p) {
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= kGradTiles * kGradTileElems) return;
+    __shared__ double red[16][17];
+    const int e16 = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int gid = blockIdx.x * 16 + e16;                 // entry in [0, 5 * 256)
     const int t = gid / kGradTileElems, rc = gid % kGradTileElems;
+    double s = 0.0;
+    for (int b = part; b < p.blocks; b += 16)
+        s += (double)p.partials[((size_t)b * kGradTiles + t) * kGradTileElems + rc];
+    red[e16][part] = s;
+    __syncthreads();
+    if (part != 0) return;
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tot += red[e16][k];
     const int row = rc / 16, col = rc % 16;
     const int C = p.C;
     float *dst = nullptr;
@@ -603,11 +615,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_wgrad(const BwdParams p) {
             }
             break;
     }
-    if (dst == nullptr) return;
-    double s = 0.0;
-    for (int b = 0; b < p.blocks; ++b)
-        s += (double)p.partials[((size_t)b * kGradTiles + t) * kGradTileElems + rc];
-    *dst = (float)s;
+    if (dst != nullptr) *dst = (float)tot;
 }
 
 }  // namespace
@@ -635,8 +643,7 @@ hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s) {
         hipLaunchKernelGGL((k_uf_backward<16>), dim3((unsigned)p.blocks), dim3(kBlock), 0, s, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_wgrad, dim3((kGradTiles * kGradTileElems + kBlock - 1) / kBlock),
-                       dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_reduce_wgrad, dim3(kGradTiles * kGradTileElems / 16), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
