@@ -446,19 +446,26 @@ __device__ inline float result_pixel_sum(float v) {
     return v;
 }
 
-__device__ inline float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// Reciprocal square root, logistic and tanh from the hardware's
+// one-instruction approximations (as recip above; about 1 ulp, far inside the
+// float32 form's budget): the IEEE-exact sequences take ten to thirty
+// instructions each and sit on the per-layer-pixel path.
+__device__ inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float sigmoidf_(float x) { return recip(1.0f + __expf(-x)); }
+// tanh x = 1 - 2 / (1 + e^{2x}) (absolute error a few 1e-8; saturates to +-1)
+__device__ inline float tanhf_(float x) { return 1.0f - 2.0f * recip(1.0f + __expf(2.0f * x)); }
 
 __device__ inline void lds_write4(float *dst, const float *f) {
     *reinterpret_cast<float4 *>(dst) = make_float4(f[0], f[1], f[2], f[3]);
 }
 
-// Register budget per instance: the waves per SIMD each form reaches without
-// spilling (float32 forms keep the compiler's default).
+// Register budget per instance: the waves per SIMD each form reaches
+// (float32 forms keep the compiler's default).  At four waves (128 VGPRs)
+// the C = 16 standard form parks three values in scratch outside the view
+// loop; the extra wave is worth more (levels 1-2: -7 %).
 template <int C, bool BF16, bool FOLD>
 struct Occupancy {
-    static constexpr int waves = !BF16 ? 1
-                               : (C > 32) ? 2
-                               : ((FOLD && !Shape<C>::TAPK) ? 4 : 3);
+    static constexpr int waves = !BF16 ? 1 : (C > 32) ? 2 : 4;
 };
 
 // FOLD = false: standard cross-attention (per-sample key and value
@@ -661,7 +668,7 @@ k_update_fuse(const UFParams p) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) ss = fmaf(fa[kc][i], fa[kc][i], ss);
         ss = operand_pixel_sum<C>(ss);
-        const float inv = 1.0f / sqrtf(ss * (1.0f / (float)C) + 1e-6f);
+        const float inv = rsqrt_(ss * (1.0f / (float)C) + 1e-6f);
         f32x4 Q[NT];
         {
             MA Xn[KC];
@@ -830,7 +837,7 @@ k_update_fuse(const UFParams p) {
             // o = acc / Z: result layout -> LDS -> operand layout
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const float iz = vscale / Z[(G == 1) ? 0 : t];
+                const float iz = vscale * recip(Z[(G == 1) ? 0 : t]);
                 float o4[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) o4[i] = acc[t][i] * iz;
@@ -901,7 +908,7 @@ k_update_fuse(const UFParams p) {
                 if (m + 1 < p.V) view_step(tb);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const float iz = 1.0f / Zs;
+            const float iz = recip(Zs);
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float t8[8];
@@ -958,14 +965,15 @@ k_update_fuse(const UFParams p) {
                 float an, dn;
                 if (p.mode == 0) {
                     const float a = fminf(fmaxf(a_in, 1e-6f), 1.0f - 1e-6f);
-                    an = sigmoidf_(logf(a / (1.0f - a)) + xs);
-                    float disp = 1.0f / de + half_l * band * tanhf(xd);
+                    // sigma(logit(a) + xs) = 1 / (1 + (1 - a) / a e^{-xs})
+                    an = recip(fmaf((1.0f - a) * recip(a), __expf(-xs), 1.0f));
+                    float disp = recip(de) + half_l * band * tanhf_(xd);
                     disp = fminf(fmaxf(disp, p.inv_far), p.inv_near);
-                    dn = 1.0f / disp;
+                    dn = recip(disp);
                 } else {
                     an = sigmoidf_(xs);
                     const float delta = ((float)(p.L - li) - 0.5f) / (float)p.L;
-                    dn = 1.0f / (fmaf(delta + half_l * tanhf(xd), band, p.inv_far));
+                    dn = recip(fmaf(delta + half_l * tanhf_(xd), band, p.inv_far));
                 }
                 p.depth_out[pe] = dn;
                 p.alpha_out[pe] = an;
