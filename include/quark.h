@@ -162,7 +162,8 @@ QK_API qk_status qk_context_destroy(qk_context *ctx);
  *               (ldm_out may alias ldm_in: each layer-pixel is read before
  *               it is written, by the same wave)
  * Supported by the kernels: heads == 1, C == C_feat == head_dim in
- * {8, 16, 32, 64}; otherwise QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
+ * {8, 16, 32, 64}, each feature map under 1 GiB; otherwise
+ * QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
  * QK_F32, QK_PREC_BF16 and QK_PREC_BF16_FP8PROJ need QK_BF16 (else
  * QK_EDTYPE). */
 QK_API qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V,

@@ -207,8 +207,12 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
             return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
         if (feats[m].H < 1 || feats[m].W < 1)
             return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
-        if ((int64_t)feats[m].H * feats[m].W * w->C_feat >= (int64_t)1 << 31)
-            return fail(QK_EUNSUPPORTED, "feature map %d exceeds 2^31 elements", m);
+        // the gather addresses a map as one buffer with 32-bit byte offsets
+        const int64_t fbytes = (int64_t)feats[m].H * feats[m].W * w->C_feat *
+                               (precision == QK_PREC_FP32 ? 4 : 2);
+        if (fbytes >= (int64_t)1 << 30)
+            return fail(QK_EUNSUPPORTED, "feature map %d is %lld bytes; maps must be under 1 GiB", m,
+                        (long long)fbytes);
     }
     if (w->heads != 1 || w->head_dim != in->C || w->C_feat != in->C || !supported_c(in->C))
         return fail(QK_EUNSUPPORTED,

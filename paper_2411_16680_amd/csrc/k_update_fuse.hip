@@ -248,11 +248,24 @@ struct Taps {
     float w[4];
 };
 
+// Feature map m as a buffer resource: a load whose byte offset falls
+// outside [0, bytes) returns zeros (the hardware's range check), so tap
+// addresses need no clamping.  The host keeps every map under 1 GiB, so the
+// offsets below stay in int range.
+template <int C, bool BF16>
+__device__ inline __amdgpu_buffer_rsrc_t feat_rsrc(const UFParams &p, int m) {
+    const int bytes = p.fH[m] * p.fW[m] * C * (int)sizeof(typename Op<BF16>::T);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p.feat[m]), 0, bytes, 0x00020000);
+}
+
 template <bool BF16>
-__device__ inline void raw_load(const typename Op<BF16>::T *ptr, RawTap<BF16> &r) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(ptr);
-    r.v[0] = q[0];
-    if constexpr (!BF16) r.v[1] = q[1];
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t r, int byte_off, RawTap<BF16> &t) {
+    const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    t.v[0] = make_uint4(a[0], a[1], a[2], a[3]);
+    if constexpr (!BF16) {
+        const auto b = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off + 16, 0, 0);
+        t.v[1] = make_uint4(b[0], b[1], b[2], b[3]);
+    }
 }
 
 template <bool BF16>
@@ -278,9 +291,11 @@ __device__ inline void raw_unpack(const RawTap<BF16> &r, float *f) {
 // Back-projection of one layer-pixel into view m (the first half of the
 // bilinear sample): p = A_m (u, v, 1) + b_m / d; a point with p_z <= 1e-6
 // (behind the view) samples zero.  Computes this lane's four tap addresses
-// (half-pixel centres; taps clamped into the map, weight 0 when outside, so
-// the loads are unconditional) and issues the loads of channels
-// ch0 + 32 kc + [0, 8).
+// (half-pixel centres) and issues the loads of channels ch0 + 32 kc + [0, 8).
+// A tap outside the map has weight 0 and its load is unconditional: its
+// offset is either out of the buffer's range (zeros) or lands on a pixel of
+// the neighbouring row.  A sample no tap of which can touch the map takes the
+// tap corner (-4, -4), whose offsets are all negative.
 template <int C, bool BF16>
 __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16>::type uc,
                                   typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
@@ -288,7 +303,7 @@ __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16
     using Coord = typename CoordT<BF16>::type;
     using T = typename Op<BF16>::T;
     constexpr int KC = Shape<C>::KC;
-    const T *fm = reinterpret_cast<const T *>(p.feat[m]);
+    const __amdgpu_buffer_rsrc_t fr = feat_rsrc<C, BF16>(p, m);
     const int fh = p.fH[m], fw = p.fW[m];
     const Coord pz = fma(cam_entry<BF16>(p, m, 6), uc,
                          fma(cam_entry<BF16>(p, m, 7), vc,
@@ -301,7 +316,8 @@ __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16
                              fma(cam_entry<BF16>(p, m, 10), invdc, cam_entry<BF16>(p, m, 5))));
     const Coord rz = recip(pz);
     const Coord fxc = qx * rz - (Coord)0.5, fyc = qy * rz - (Coord)0.5;
-    const bool ok = a_ok && (pz > (Coord)1e-6) && (fabs(fxc) < (Coord)1e7) && (fabs(fyc) < (Coord)1e7);
+    const bool ok = a_ok && (pz > (Coord)1e-6) && (fxc > (Coord)-2) && (fxc < (Coord)(fw + 1)) &&
+                    (fyc > (Coord)-2) && (fyc < (Coord)(fh + 1));
     const Coord xf = floor(fxc), yf = floor(fyc);
     const float wx = (float)(fxc - xf), wy = (float)(fyc - yf);
     const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
@@ -311,16 +327,15 @@ __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16
     tp.w[1] = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
     tp.w[2] = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
     tp.w[3] = (vx1 && vy1) ? wx * wy : 0.0f;
-    const int cx0 = min(max(ix, 0), fw - 1), cx1 = min(max(ix + 1, 0), fw - 1);
-    const int cy0 = min(max(iy, 0), fh - 1), cy1 = min(max(iy + 1, 0), fh - 1);
-    const int o00 = (cy0 * fw + cx0) * C + ch0, o10 = (cy0 * fw + cx1) * C + ch0;
-    const int o01 = (cy1 * fw + cx0) * C + ch0, o11 = (cy1 * fw + cx1) * C + ch0;
+    constexpr int E = (int)sizeof(T);
+    const int o00 = ((iy * fw + ix) * C + ch0) * E, o10 = o00 + C * E;
+    const int o01 = o00 + fw * C * E, o11 = o01 + C * E;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
-        raw_load<BF16>(fm + o00 + 32 * kc, tp.t[kc][0]);
-        raw_load<BF16>(fm + o10 + 32 * kc, tp.t[kc][1]);
-        raw_load<BF16>(fm + o01 + 32 * kc, tp.t[kc][2]);
-        raw_load<BF16>(fm + o11 + 32 * kc, tp.t[kc][3]);
+        buf_load<BF16>(fr, o00 + 32 * kc * E, tp.t[kc][0]);
+        buf_load<BF16>(fr, o10 + 32 * kc * E, tp.t[kc][1]);
+        buf_load<BF16>(fr, o01 + 32 * kc * E, tp.t[kc][2]);
+        buf_load<BF16>(fr, o11 + 32 * kc * E, tp.t[kc][3]);
     }
 }
 
@@ -358,7 +373,7 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
                                   bool a_ok, int r, int g, int2 *tT, TapsK<BF16> &tp) {
     using Coord = typename CoordT<BF16>::type;
     using T = typename Op<BF16>::T;
-    const T *fm = reinterpret_cast<const T *>(p.feat[m]);
+    const __amdgpu_buffer_rsrc_t fr = feat_rsrc<C, BF16>(p, m);
     const int fh = p.fH[m], fw = p.fW[m];
     const Coord pz = fma(cam_entry<BF16>(p, m, 6), uc,
                          fma(cam_entry<BF16>(p, m, 7), vc,
@@ -371,22 +386,23 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
                              fma(cam_entry<BF16>(p, m, 10), invdc, cam_entry<BF16>(p, m, 5))));
     const Coord rz = recip(pz);
     const Coord fxc = qx * rz - (Coord)0.5, fyc = qy * rz - (Coord)0.5;
-    const bool ok = a_ok && (pz > (Coord)1e-6) && (fabs(fxc) < (Coord)1e7) && (fabs(fyc) < (Coord)1e7);
+    const bool ok = a_ok && (pz > (Coord)1e-6) && (fxc > (Coord)-2) && (fxc < (Coord)(fw + 1)) &&
+                    (fyc > (Coord)-2) && (fyc < (Coord)(fh + 1));
     const Coord xf = floor(fxc), yf = floor(fyc);
     const float wx = (float)(fxc - xf), wy = (float)(fyc - yf);
     const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
     const bool vx0 = (unsigned)ix < (unsigned)fw, vx1 = (unsigned)(ix + 1) < (unsigned)fw;
     const bool vy0 = (unsigned)iy < (unsigned)fh, vy1 = (unsigned)(iy + 1) < (unsigned)fh;
-    const int cx0 = min(max(ix, 0), fw - 1), cx1 = min(max(ix + 1, 0), fw - 1);
-    const int cy0 = min(max(iy, 0), fh - 1), cy1 = min(max(iy + 1, 0), fh - 1);
-    int4 ow0, ow1;       // (offset, weight bits) of taps 00, 10 | 01, 11
-    ow0.x = (cy0 * fw + cx0) * C;
+    // byte offsets as in issue_taps (out-of-map taps: zeros or a neighbour, weight 0)
+    constexpr int E = (int)sizeof(T);
+    int4 ow0, ow1;       // (byte offset, weight bits) of taps 00, 10 | 01, 11
+    ow0.x = (iy * fw + ix) * C * E;
     ow0.y = __float_as_int((vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f);
-    ow0.z = (cy0 * fw + cx1) * C;
+    ow0.z = ow0.x + C * E;
     ow0.w = __float_as_int((vx1 && vy0) ? wx * (1.0f - wy) : 0.0f);
-    ow1.x = (cy1 * fw + cx0) * C;
+    ow1.x = ow0.x + fw * C * E;
     ow1.y = __float_as_int((vx0 && vy1) ? (1.0f - wx) * wy : 0.0f);
-    ow1.z = (cy1 * fw + cx1) * C;
+    ow1.z = ow1.x + C * E;
     ow1.w = __float_as_int((vx1 && vy1) ? wx * wy : 0.0f);
     int4 *slot = reinterpret_cast<int4 *>(&tT[(g * 16 + r) * 4]);
     slot[0] = ow0;
@@ -398,7 +414,7 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
     for (int j = 0; j < 4; ++j) {
         const int2 e = tT[64 * j + lane];
         tp.w[j] = __int_as_float(e.y);
-        raw_load<BF16>(fm + e.x, tp.t[j]);
+        buf_load<BF16>(fr, e.x, tp.t[j]);
     }
 }
 

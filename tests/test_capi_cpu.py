@@ -142,6 +142,14 @@ def test_rejections():
            _FakeT((2, 12, 20), 0x720000))
     assert lib.update_fuse_check(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, ldm,
                                  out) == lib.QK_ESHAPE
+    # a feature map of 1 GiB or more (float32: 4096 x 4096 x 16) is refused,
+    # one just under it passes
+    big = list(feats)
+    big[1] = _FakeT((4096, 4096, 16), feats[1]._addr)
+    assert _check(sc, big, wts, ldm) == lib.QK_EUNSUPPORTED
+    assert "1 GiB" in lib.load().qk_last_error().decode()
+    big[1] = _FakeT((4095, 4096, 16), feats[1]._addr)
+    assert _check(sc, big, wts, ldm) == lib.QK_OK
     # acc without rgb
     assert _check(sc, feats, wts, ldm, acc_out=_FakeT((12, 20))) == lib.QK_EINVAL
     msg = lib.load().qk_last_error().decode()
