@@ -48,6 +48,7 @@ def lib():
         L.or_reproject.restype = ctypes.c_int
         L.or_reproject_T.restype = ctypes.c_int
         L.or_update_fuse.restype = ctypes.c_int
+        L.or_render_ibr.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         for name in ("or_reprojection_matrix", "or_reproject", "or_reproject_T"):
             pass
@@ -156,6 +157,76 @@ def composite(color, alpha, back_to_front: bool = False):
         return rgb.reshape(pix_shape + (3,)), None
     lib().or_composite(L, ctypes.c_long(npix), _d(color), _d(alpha), _d(rgb), _d(acc))
     return rgb.reshape(pix_shape + (3,)), acc.reshape(pix_shape)
+
+
+# --------------------------------------------------------------------------
+# Final render: upsample & activate, blend-weight image-based render
+# --------------------------------------------------------------------------
+
+def upsample_bilinear(src, H: int, W: int) -> np.ndarray:
+    """src [h][w] or [h][w][C] -> [H][W](...) (half-pixel centres, border
+    extended)."""
+    src = _f64(src)
+    squeeze = src.ndim == 2
+    if squeeze:
+        src = src[..., None]
+    h, w, C = src.shape
+    dst = np.zeros((H, W, C))
+    lib().or_upsample_bilinear(_d(src), h, w, C, int(H), int(W), _d(dst))
+    return dst[..., 0] if squeeze else dst
+
+
+def ibr_activate(xd, xs, xb, li, L, near, far):
+    """One layer-pixel's activation: returns (depth, sigma, beta[V])."""
+    xb = _f64(xb)
+    d = ctypes.c_double()
+    sg = ctypes.c_double()
+    beta = np.zeros(xb.shape[0])
+    lib().or_ibr_activate(ctypes.c_double(xd), ctypes.c_double(xs), _d(xb), xb.shape[0],
+                          int(li), int(L), ctypes.c_double(near), ctypes.c_double(far),
+                          ctypes.byref(d), ctypes.byref(sg), _d(beta))
+    return d.value, sg.value, beta
+
+
+def image_rgb(img) -> np.ndarray:
+    """An RGBA8 image [H][W][4] as the RGB values in [0, 1] the render reads."""
+    return np.ascontiguousarray(np.asarray(img)[..., :3], dtype=np.float64) / 255.0
+
+
+def render_ibr(in_cams, images, novel, near, far, depth_logit, sigma_logit, blend_logit,
+               H: int, W: int, *, rows: Optional[Sequence[int]] = None,
+               want_layers: bool = False) -> Dict[str, np.ndarray]:
+    """The final render on the given output rows (default: all).  ``images``
+    are RGBA8 arrays [Hi][Wi][4] (or float RGB [Hi][Wi][3] in [0, 1]); the
+    logits are [L][h][w] (depth, density) and [L][h][w][V] (blend)."""
+    V = len(in_cams)
+    img64 = [image_rgb(im) if np.asarray(im).dtype == np.uint8 else _f64(im) for im in images]
+    dl, sl, bl = _f64(depth_logit), _f64(sigma_logit), _f64(blend_logit)
+    L, h, w = dl.shape
+    rows = np.arange(H, dtype=np.int32) if rows is None else np.asarray(rows, dtype=np.int32)
+    R = int(rows.shape[0])
+    Kin = _f64(np.stack([c.K for c in in_cams]))
+    Ein = _f64(np.stack([c.E for c in in_cams]))
+    cam_wh = np.ascontiguousarray([[c.width, c.height] for c in in_cams], dtype=np.int32)
+    img_hw = np.ascontiguousarray([[im.shape[0], im.shape[1]] for im in img64], dtype=np.int32)
+    iptrs = (_dp * V)(*[_d(im) for im in img64])
+    nov_wh = np.array([novel.width, novel.height], dtype=np.int32)
+    Kn, En = _f64(novel.K), _f64(novel.E)
+    rgb = np.zeros((R, W, 3))
+    acc = np.zeros((R, W))
+    dmap = np.zeros((R, W))
+    lc = np.zeros((L, R, W, 3)) if want_layers else None
+    rc = lib().or_render_ibr(
+        V, _d(Kin), _d(Ein), cam_wh.ctypes.data_as(_ip), iptrs, img_hw.ctypes.data_as(_ip),
+        _d(Kn), _d(En), nov_wh.ctypes.data_as(_ip), ctypes.c_double(near), ctypes.c_double(far),
+        L, h, w, _d(dl), _d(sl), _d(bl), int(H), int(W), rows.ctypes.data_as(_ip), R,
+        _d(rgb), _d(acc), _d(dmap), _d(lc) if lc is not None else ctypes.cast(None, _dp))
+    if rc != 0:
+        raise ValueError("oracle render_ibr failed (singular camera?)")
+    out = {"rgb": rgb, "acc": acc, "depth": dmap, "rows": rows}
+    if lc is not None:
+        out["layer_color"] = lc
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -498,6 +498,148 @@ OR_EXPORT int or_update_fuse(int V, const double *Kin, const double *Ein, const 
     return err;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Final render (Sec. 3.1, Eq. 1; Sec. 3.2.3 "Upsampling & Activation").     */
+/* The final LDM arrives as unactivated attributes at a reduced grid (h, w):  */
+/* depth logits x_d and density logits x_sigma [L][h][w] and blend-weight     */
+/* logits [L][h][w][V] over the V input images.  They are bilinearly          */
+/* upsampled to the output grid (H, W) and only then activated: density      */
+/* sigma = sigmoid(x_sigma), depth through the anchored disparity-band        */
+/* activation (the paper's depth activation, anchor of paper layer           */
+/* l = L - index), blend weights beta = softmax over the views (delayed until */
+/* after the upsampling).  Each input image is carried onto every layer by    */
+/* the back-projection operator through the decoded depth (reprojection and  */
+/* bilinear sampling with zero padding, a point behind a view samples zero),  */
+/* the V images are mixed per layer with beta, and the layers are            */
+/* over-composited with alpha = sigma (front to back, black background).     */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear resampling of src[h][w][C] at output pixel (x, y) of an (H, W)
+ * grid, half-pixel centres: source coordinate (x + 0.5) w / W - 0.5, clamped
+ * below at 0; taps floor and floor + 1, the latter clamped to the last
+ * row/column (the border value extends outward). */
+static void upsample_at(const double *src, int h, int w, int C, int H, int W, int x, int y,
+                        double *out)
+{
+    double sy = (y + 0.5) * (double)h / (double)H - 0.5;
+    double sx = (x + 0.5) * (double)w / (double)W - 0.5;
+    if (sy < 0.0) sy = 0.0;
+    if (sx < 0.0) sx = 0.0;
+    int y0 = (int)floor(sy), x0 = (int)floor(sx);
+    if (y0 > h - 1) y0 = h - 1;
+    if (x0 > w - 1) x0 = w - 1;
+    int y1 = (y0 + 1 < h) ? y0 + 1 : h - 1;
+    int x1 = (x0 + 1 < w) ? x0 + 1 : w - 1;
+    double ly = sy - y0, lx = sx - x0;
+    const double *s00 = src + ((size_t)y0 * w + x0) * C, *s10 = src + ((size_t)y0 * w + x1) * C;
+    const double *s01 = src + ((size_t)y1 * w + x0) * C, *s11 = src + ((size_t)y1 * w + x1) * C;
+    for (int c = 0; c < C; ++c)
+        out[c] = (1.0 - ly) * ((1.0 - lx) * s00[c] + lx * s10[c]) +
+                 ly * ((1.0 - lx) * s01[c] + lx * s11[c]);
+}
+
+OR_EXPORT void or_upsample_bilinear(const double *src, int h, int w, int C, int H, int W,
+                                    double *dst)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) upsample_at(src, h, w, C, H, W, x, y, dst + ((size_t)y * W + x) * C);
+}
+
+/* Activation of one layer-pixel's upsampled logits (layer index li, 0 =
+ * nearest): sigma = sigmoid(xs); depth = 1 / ((delta + (0.5/L) tanh(xd))
+ * (1/near - 1/far) + 1/far) with delta = (l - 0.5)/L, l = L - li; beta =
+ * softmax of xb over the V views (maximum subtracted). */
+OR_EXPORT void or_ibr_activate(double xd, double xs, const double *xb, int V, int li, int L,
+                               double near_, double far_, double *depth, double *sigma,
+                               double *beta)
+{
+    *sigma = sigmoid(xs);
+    double delta = ((L - li) - 0.5) / L;
+    *depth = 1.0 / ((delta + (0.5 / L) * tanh(xd)) * (1.0 / near_ - 1.0 / far_) + 1.0 / far_);
+    double mx = -INFINITY;
+    for (int m = 0; m < V; ++m)
+        if (xb[m] > mx) mx = xb[m];
+    double z = 0.0;
+    for (int m = 0; m < V; ++m) { beta[m] = exp(xb[m] - mx); z += beta[m]; }
+    for (int m = 0; m < V; ++m) beta[m] /= z;
+}
+
+/* The render over the listed output rows.
+ * Inputs (double, row-major):
+ *   V views: Kin[V][9], Ein[V][16], cam_wh[V][2] (grid of Kin),
+ *            images[V] -> [Hi][Wi][3] (RGB in [0, 1]), img_hw[V][2] = (Hi, Wi)
+ *   novel:   Kn[9], En[16], nov_wh[2] (grid of Kn)
+ *   LDM:     L, h, w; depth_logit[L][h][w], sigma_logit[L][h][w],
+ *            blend_logit[L][h][w][V]
+ *   output grid H, W; rows[nrows]
+ * Outputs, packed over the rows: rgb[R][W][3], acc[R][W] (1 - prod(1 - sigma)),
+ * depth_map[R][W] (the decoded depth over-composited the same way), and, if
+ * non-NULL, layer_color[L][R][W][3] (the blended image of each layer). */
+OR_EXPORT int or_render_ibr(int V, const double *Kin, const double *Ein, const int *cam_wh,
+                            const double *const *images, const int *img_hw, const double *Kn,
+                            const double *En, const int *nov_wh, double near_, double far_, int L,
+                            int h, int w, const double *depth_logit, const double *sigma_logit,
+                            const double *blend_logit, int H, int W, const int *rows, int nrows,
+                            double *rgb, double *acc, double *depth_map, double *layer_color)
+{
+    double Kns[9];
+    or_scale_intrinsics(Kn, nov_wh[0], nov_wh[1], W, H, Kns);
+    double *T = malloc(sizeof(double) * 16 * (size_t)V);
+    for (int m = 0; m < V; ++m) {
+        double Kms[9];
+        or_scale_intrinsics(Kin + 9 * m, cam_wh[2 * m], cam_wh[2 * m + 1], img_hw[2 * m + 1],
+                            img_hw[2 * m], Kms);
+        if (or_reprojection_matrix(Kns, En, Kms, Ein + 16 * m, T + 16 * m) != 0) {
+            free(T);
+            return -1;
+        }
+    }
+    long total = (long)nrows * W;
+#pragma omp parallel
+    {
+        double *xb = malloc(sizeof(double) * V);
+        double *beta = malloc(sizeof(double) * V);
+#pragma omp for schedule(dynamic, 64)
+        for (long idx = 0; idx < total; ++idx) {
+            int x = (int)(idx % W);
+            int r = (int)(idx / W);
+            int y = rows[r];
+            double u = x + 0.5, v = y + 0.5;
+            double Tr = 1.0, out[3] = {0.0, 0.0, 0.0}, dm = 0.0;
+            for (int li = 0; li < L; ++li) {
+                double xd, xs, d, sg;
+                upsample_at(depth_logit + (size_t)li * h * w, h, w, 1, H, W, x, y, &xd);
+                upsample_at(sigma_logit + (size_t)li * h * w, h, w, 1, H, W, x, y, &xs);
+                upsample_at(blend_logit + (size_t)li * h * w * V, h, w, V, H, W, x, y, xb);
+                or_ibr_activate(xd, xs, xb, V, li, L, near_, far_, &d, &sg, beta);
+                double c[3] = {0.0, 0.0, 0.0};
+                for (int m = 0; m < V; ++m) {
+                    double uv[2], s[3];
+                    if (or_reproject_T(T + 16 * m, u, v, d, uv) == 1)
+                        or_bilinear(images[m], img_hw[2 * m], img_hw[2 * m + 1], 3, uv[0], uv[1], s);
+                    else
+                        s[0] = s[1] = s[2] = 0.0;
+                    for (int j = 0; j < 3; ++j) c[j] += beta[m] * s[j];
+                }
+                if (layer_color)
+                    for (int j = 0; j < 3; ++j)
+                        layer_color[(((size_t)li * nrows + r) * W + x) * 3 + j] = c[j];
+                for (int j = 0; j < 3; ++j) out[j] += Tr * sg * c[j];
+                dm += Tr * sg * d;
+                Tr *= (1.0 - sg);
+            }
+            size_t o = (size_t)r * W + x;
+            for (int j = 0; j < 3; ++j) rgb[o * 3 + j] = out[j];
+            if (acc) acc[o] = 1.0 - Tr;
+            if (depth_map) depth_map[o] = dm;
+        }
+        free(xb);
+        free(beta);
+    }
+    free(T);
+    return 0;
+}
+
 OR_EXPORT int or_num_threads(void)
 {
 #ifdef _OPENMP

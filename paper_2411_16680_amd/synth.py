@@ -353,6 +353,60 @@ def make_custom(*, V: int, H: int, W: int, C: int, L: int, heads: int = 1,
                  [lvl], steps=steps, target=target)
 
 
+# ----------------------------------------------------------------------------
+# Final render workload: unactivated LDM attributes at a reduced grid plus
+# the full-resolution input images
+# ----------------------------------------------------------------------------
+
+@dataclass
+class RenderScene:
+    in_cams: List[Camera]
+    images: List[np.ndarray]           # V arrays [Hi][Wi][4] uint8 (RGBA8, alpha 255)
+    novel: Camera
+    near: float
+    far: float
+    depth_logit: np.ndarray            # [L][h][w] float32
+    sigma_logit: np.ndarray            # [L][h][w] float32
+    blend_logit: np.ndarray            # [L][h][w][V] float32
+    H: int                             # output grid
+    W: int
+
+    @property
+    def V(self) -> int:
+        return len(self.in_cams)
+
+    @property
+    def logits(self):
+        return self.depth_logit, self.sigma_logit, self.blend_logit
+
+
+def make_render(*, V: int = 8, W: int = 1920, H: int = 1080, s: int = 2, L: int = 4,
+                lowres_hw: Optional[tuple] = None, img_hw: Optional[tuple] = None,
+                seed: int = 1006, arc: float = 0.5, radius: float = 1.5, hfov: float = 60.0,
+                near: float = 0.5, far: float = 20.0, sigma_std: float = 1.5) -> RenderScene:
+    """The final render's inputs: V RGBA8 input images (uniform random
+    bytes, alpha 255) of ``img_hw`` (default the output grid) on an arc rig
+    (the multi-scale workload's rig by default: 0.5 m arc of a 1.5 m ring, 60
+    degree field of view, novel camera jittered 5 cm in radius), and the
+    final LDM's logits on a grid ``s`` times coarser than the output (or
+    ``lowres_hw``): depth and blend logits N(0, 1), density logits
+    N(0, sigma_std).  Draw order: cameras, images (view-major), depth,
+    density, blend logits."""
+    rng = np.random.default_rng(seed)
+    Hi, Wi = (H, W) if img_hw is None else img_hw
+    h, w = (H // s, W // s) if lowres_hw is None else lowres_hw
+    in_cams, novel = _arc_rig(rng, V, arc, radius, Wi, Hi, hfov, novel_radius_jitter=0.05)
+    images = []
+    for _ in range(V):
+        im = rng.integers(0, 256, size=(Hi, Wi, 4), dtype=np.uint8)
+        im[..., 3] = 255
+        images.append(im)
+    dlog = _normal(rng, (L, h, w))
+    slog = _normal(rng, (L, h, w), std=sigma_std)
+    blog = _normal(rng, (L, h, w, V))
+    return RenderScene(in_cams, images, novel, near, far, dlog, slog, blog, H, W)
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""
