@@ -33,6 +33,7 @@ METRIC = "1080p frames/s + p50/p99 ms, Update&Fuse+render, V=8, BF16 vs FP32, sa
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense bf16
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_16680_amd", "csrc", "k_update_fuse.hip")
+RENDER_SRC = os.path.join(ROOT, "paper_2411_16680_amd", "csrc", "k_render.hip")
 
 
 def log(*a):
@@ -122,7 +123,7 @@ def per_level_ms(ctx, scene, dls, attn: str = "standard", precision: str = None,
     return out
 
 
-def traffic_from_profiles(kernel_name: str, launches_key: str):
+def traffic_from_profiles(kernel_name: str, launches_key: str, src: str = KERNEL_SRC):
     """HBM bytes per launch measured with rocprofv3 PMC counters, if the
     committed measurement was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -130,7 +131,7 @@ def traffic_from_profiles(kernel_name: str, launches_key: str):
         return None
     try:
         rec = json.load(open(path))
-        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         ent = rec.get(launches_key)
         if not ent or ent.get("kernel_src_sha256_16") != src_hash:
             return None
@@ -185,7 +186,7 @@ def profile_run(ctx, steps: int, depth_mode: str):
     counter collection (FETCH_SIZE / WRITE_SIZE are scaled by what they read
     for the copy)."""
     import torch
-    from paper_2411_16680_amd import runner, synth
+    from paper_2411_16680_amd import lib, runner, synth
     sc = synth.to_bf16(synth.make_inputs(3, depth_mode=depth_mode))
     dls = runner.scene_to_device(sc)
     for dl in dls:
@@ -195,6 +196,13 @@ def profile_run(ctx, steps: int, depth_mode: str):
         runner.run_scene(ctx, sc, dls)
         torch.cuda.synchronize()
         log(f"profile frame {s + 1}/{steps}")
+    del dls
+    rs, args = render_inputs()
+    for s in range(steps):
+        lib.render_ibr(ctx, *args)
+        torch.cuda.synchronize()
+        log(f"profile render {s + 1}/{steps}")
+    del args
     n = 128 * 1024 * 1024                          # 512 MiB of float32
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -206,6 +214,93 @@ def profile_run(ctx, steps: int, depth_mode: str):
 # ---------------------------------------------------------------------------
 # Training step (forward + adjoint) and serving
 # ---------------------------------------------------------------------------
+
+RENDER_WORKLOAD = ("final render: 1920x1080 output from a 960x540 LDM of 4 layers (upsample "
+                   "& activate, blend-weight image-based render, composite), V=8 RGBA8 input "
+                   "images of 1920x1080")
+
+
+def render_inputs():
+    """The final render's benchmark inputs on the device; returns the scene
+    and the positional arguments of lib.render_ibr after ctx."""
+    import torch
+    from paper_2411_16680_amd import synth
+    rs = synth.make_render()
+    imgs = [torch.from_numpy(im).cuda() for im in rs.images]
+    lg = tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+               for a in rs.logits)
+    rgb = torch.empty((rs.H, rs.W, 3), device="cuda")
+    torch.cuda.synchronize()
+    return rs, (rs.in_cams, imgs, rs.novel, rs.near, rs.far, lg, rgb)
+
+
+def render_bytes(rs) -> int:
+    """Compulsory HBM bytes of one render: the input images once, the logits
+    once, the RGB written once."""
+    L, h, w = rs.depth_logit.shape
+    img = sum(im.shape[0] * im.shape[1] * 4 for im in rs.images)
+    return img + L * h * w * (2 + rs.V) * 4 + rs.H * rs.W * 12
+
+
+def time_render(ctx, reps: int = 50):
+    """The final render at 1080p: average launch time with HIP events on its
+    stream, frames/s, layer-pixel-views/s and the HBM roofline."""
+    import torch
+    from paper_2411_16680_amd import lib
+    rs, args = render_inputs()
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lib.render_ibr(ctx, *args, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lib.render_ibr(ctx, *args, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    L = rs.depth_logit.shape[0]
+    nbytes = render_bytes(rs)
+    gbs = nbytes / (ms / 1000.0) / 1e9
+    return {"workload": RENDER_WORKLOAD, "avg_launch_ms": ms, "frames_per_s": 1000.0 / ms,
+            "layer_pixel_views_per_s": rs.H * rs.W * L * rs.V / (ms / 1000.0),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes,
+                         "traffic": traffic_from_profiles("k_render_ibr", "k_render_ibr_1080p",
+                                                          RENDER_SRC)},
+            "context": "paper: its inference renderer takes about 1.3 ms per 1080p frame on "
+                       "an NVIDIA A100 (not the same inputs)"}
+
+
+def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
+    """The standalone front-to-back composite (qk_composite) over a 1080p LDM
+    of L layers: its average launch time with HIP events on its stream and
+    its HBM roofline (colour and alpha read once, RGB and accumulated alpha
+    written once)."""
+    import torch
+    from paper_2411_16680_amd import lib
+    g = torch.Generator(device="cuda").manual_seed(5)
+    color = torch.rand((L, H, W, 3), device="cuda", generator=g)
+    alpha = torch.rand((L, H, W), device="cuda", generator=g)
+    rgb = torch.empty((H, W, 3), device="cuda")
+    acc = torch.empty((H, W), device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lib.composite(ctx, color, alpha, rgb, acc, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lib.composite(ctx, color, alpha, rgb, acc, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = H * W * (L * 16 + 16)
+    gbs = nbytes / (ms / 1000.0) / 1e9
+    return {"kernel": f"k_composite ({W}x{H}, L={L}, float32)", "avg_launch_ms": ms,
+            "algorithmic_bytes_per_launch": nbytes, "bound": "hbm", "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
 
 def time_training_step(ctx, steps: int = 50, warmup: int = 5):
     """The 960x540 backward workload (V=4, C=16, L=8): float32 forward with
@@ -394,6 +489,16 @@ def main():
     frame_bytes = sum(level_bytes(l, V, 2, i == len(sc16.levels) - 1)
                       for i, l in enumerate(sc16.levels))
 
+    render = time_render(ctx)
+    log(f"final render: {render['avg_launch_ms'] * 1000:.1f} us per 1080p frame, "
+        f"{render['roofline']['achieved']:.0f} GB/s of compulsory bytes")
+    torch.cuda.empty_cache()
+
+    composite = time_composite(ctx)
+    log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
+        f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
+    torch.cuda.empty_cache()
+
     train = None
     if not args.no_train:
         log("timing the forward + adjoint training step (960x540, V=4, C=16, L=8)")
@@ -459,6 +564,8 @@ def main():
         "frame_compulsory_bytes": frame_bytes,
         "frame_hbm_frac": frame_bytes / (ms_per_step / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roof,
+        "composite_roofline": composite,
+        "final_render": render,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,

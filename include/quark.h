@@ -262,6 +262,69 @@ QK_API qk_status qk_update_fuse_backward_check(int32_t V, const qk_camera *in_ca
                                         float *const *d_feats,
                                         const qk_weight_grads *d_weights);
 
+/* ---- Final render: Upsample & Activate, blend-weight image-based render ----
+ * (Sec. 3.1, Eq. 1; Sec. 3.2.3 "Upsampling & Activation".)  The final LDM is
+ * given as unactivated attributes on its own reduced grid (L, h, w); the
+ * render produces the output image on an (H, W) grid, usually h = H/s,
+ * w = W/s for the paper's scale factor s of 2 to 4.  For each layer l (0 =
+ * nearest) and output pixel:
+ *   1. bilinear upsampling of the depth logit x_d, the density logit x_s and
+ *      the V blend-weight logits (half-pixel centres: output pixel x reads
+ *      source coordinate (x + 0.5) w / W - 0.5, clamped below at 0; the tap
+ *      x0 + 1 is clamped to the last column, i.e. the border extends);
+ *   2. activation after the upsampling: alpha = sigmoid(x_s); disparity
+ *      ((l_p - 0.5)/L + (0.5/L) tanh(x_d)) (1/near - 1/far) + 1/far with
+ *      l_p = L - l (the paper's depth activation, its layer 1 the farthest),
+ *      depth = 1/disparity; beta = softmax of the V blend logits;
+ *   3. the back-projection of each input image onto the layer through that
+ *      depth: the pixel centre is reprojected into image m (as in
+ *      qk_update_fuse, cameras composed in double) and the image sampled
+ *      bilinearly with zero padding; a point behind image m samples zero;
+ *   4. layer colour c = sum_m beta_m sample_m;
+ *   5. front-to-back over composite: rgb += T alpha c, depth_out += T alpha
+ *      depth, T *= 1 - alpha; acc_out = 1 - T (black background).
+ * All arithmetic is float32 except the reprojection (double: absolute
+ * coordinates on 1080p images need more than a float's 24 bits).
+ *
+ *   V          number of input images, 1..16
+ *   in_cams    host [V]; images device [V], RGBA8 [Hi][Wi][4] (alpha byte
+ *              ignored, value v reads as v/255), rows packed, 4-byte aligned,
+ *              each under 1 GiB
+ *   novel      host; its K is rescaled to the output grid (H, W)
+ *   near_, far_ the frustum planes of the depth activation, 0 < near_ < far_
+ *   logits     device float32: depth_logit and sigma_logit [L][h][w],
+ *              blend_logit [L][h][w][V] (V == the call's V)
+ *   rgb_out    device [H][W][3] float32; acc_out and depth_out device
+ *              [H][W] float32 or NULL
+ * Errors (nothing enqueued): QK_EINVAL (NULL or misaligned buffer, bad
+ * camera, near/far), QK_ESHAPE (non-positive dims, logits.V != V, V out of
+ * range), QK_EUNSUPPORTED (an image of 1 GiB or more, an output or logit
+ * volume of 2^31 elements or more). */
+typedef struct {
+    const void *data;     /* device RGBA8 [H][W][4] */
+    int32_t H, W;
+} qk_image;
+
+typedef struct {
+    const float *depth_logit;   /* device [L][H][W] */
+    const float *sigma_logit;   /* device [L][H][W] */
+    const float *blend_logit;   /* device [L][H][W][V] */
+    int32_t L, H, W, V;
+} qk_ldm_logits;
+
+QK_API qk_status qk_render_ibr(qk_context *ctx, void *hip_stream, int32_t V,
+                               const qk_camera *in_cams, const qk_image *images,
+                               const qk_camera *novel, float near_, float far_,
+                               const qk_ldm_logits *logits, int32_t H, int32_t W, float *rgb_out,
+                               float *acc_out, float *depth_out);
+
+/* Dry run of qk_render_ibr's argument checks (no device use). */
+QK_API qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const qk_image *images,
+                                     const qk_camera *novel, float near_, float far_,
+                                     const qk_ldm_logits *logits, int32_t H, int32_t W,
+                                     const float *rgb_out, const float *acc_out,
+                                     const float *depth_out);
+
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);
 

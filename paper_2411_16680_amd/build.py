@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libquark.so")
-SOURCES = ["k_update_fuse.hip", "k_backward.hip", "k_init.hip", "k_fp8.hip", "capi.cpp"]
+SOURCES = ["k_update_fuse.hip", "k_backward.hip", "k_init.hip", "k_fp8.hip", "k_render.hip",
+           "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

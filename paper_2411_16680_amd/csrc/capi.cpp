@@ -21,6 +21,7 @@ hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
 hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
 hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
+hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -318,6 +319,45 @@ qk_status grow(float **buf, size_t *have, size_t need, hipStream_t stream) {
         return fail(QK_ENOMEM, "workspace of %zu floats", need);
     }
     *have = need;
+    return QK_OK;
+}
+
+qk_status check_render(int32_t V, const qk_camera *in_cams, const qk_image *images,
+                       const qk_camera *novel, float near_, float far_, const qk_ldm_logits *lg,
+                       int32_t H, int32_t W, const float *rgb_out, const float *acc_out,
+                       const float *depth_out) {
+    if (!in_cams || !images || !novel || !lg) return fail(QK_EINVAL, "NULL argument");
+    if (V < 1 || V > qk::kMaxViews)
+        return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (lg->L < 1 || lg->H < 1 || lg->W < 1 || H < 1 || W < 1)
+        return fail(QK_ESHAPE, "dims must be positive (L=%d h=%d w=%d H=%d W=%d)", lg->L, lg->H,
+                    lg->W, H, W);
+    if (lg->V != V) return fail(QK_ESHAPE, "blend logits have %d views, V = %d", lg->V, V);
+    if ((int64_t)lg->L * lg->H * lg->W * V >= ((int64_t)1 << 31) ||
+        (int64_t)H * W * 3 >= ((int64_t)1 << 31))
+        return fail(QK_EUNSUPPORTED, "logit volume or output of 2^31 elements or more");
+    if (!lg->depth_logit || !lg->sigma_logit || !lg->blend_logit || !rgb_out)
+        return fail(QK_EINVAL, "NULL buffer");
+    if (!aligned4(lg->depth_logit) || !aligned4(lg->sigma_logit) || !aligned4(lg->blend_logit) ||
+        !aligned4(rgb_out) || (acc_out && !aligned4(acc_out)) ||
+        (depth_out && !aligned4(depth_out)))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    for (int m = 0; m < V; ++m) {
+        char what[32];
+        snprintf(what, sizeof(what), "camera %d", m);
+        st = check_camera(&in_cams[m], what);
+        if (st != QK_OK) return st;
+        if (!images[m].data) return fail(QK_EINVAL, "image %d is NULL", m);
+        if (!aligned4(images[m].data)) return fail(QK_EINVAL, "image %d must be 4-byte aligned", m);
+        if (images[m].H < 1 || images[m].W < 1)
+            return fail(QK_ESHAPE, "image %d has grid %dx%d", m, images[m].W, images[m].H);
+        if ((int64_t)images[m].H * images[m].W * 4 >= ((int64_t)1 << 30))
+            return fail(QK_EUNSUPPORTED, "image %d is 1 GiB or more", m);
+    }
     return QK_OK;
 }
 
@@ -648,6 +688,55 @@ qk_status qk_ldm_init(qk_context *ctx, void *hip_stream, const float *f0, float 
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipError_t e = qk::launch_ldm_init(p, ldm->dtype == QK_BF16, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "ldm_init launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const qk_image *images,
+                              const qk_camera *novel, float near_, float far_,
+                              const qk_ldm_logits *logits, int32_t H, int32_t W,
+                              const float *rgb_out, const float *acc_out, const float *depth_out) {
+    return check_render(V, in_cams, images, novel, near_, far_, logits, H, W, rgb_out, acc_out,
+                        depth_out);
+}
+
+qk_status qk_render_ibr(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                        const qk_image *images, const qk_camera *novel, float near_, float far_,
+                        const qk_ldm_logits *lg, int32_t H, int32_t W, float *rgb_out,
+                        float *acc_out, float *depth_out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_render(V, in_cams, images, novel, near_, far_, lg, H, W, rgb_out,
+                                acc_out, depth_out);
+    if (st != QK_OK) return st;
+    qk::RenderParams p;
+    std::memset(&p, 0, sizeof(p));
+    for (int m = 0; m < V; ++m) {
+        p.img[m] = images[m].data;
+        p.iH[m] = images[m].H;
+        p.iW[m] = images[m].W;
+        compose_table(novel, W, H, &in_cams[m], images[m].W, images[m].H, p.cam[m]);
+    }
+    p.depth_logit = lg->depth_logit;
+    p.sigma_logit = lg->sigma_logit;
+    p.blend_logit = lg->blend_logit;
+    p.rgb = rgb_out;
+    p.acc = acc_out;
+    p.depth = depth_out;
+    p.V = V;
+    p.L = lg->L;
+    p.h = lg->H;
+    p.w = lg->W;
+    p.H = H;
+    p.W = W;
+    p.rx = (double)lg->W / (double)W;
+    p.ry = (double)lg->H / (double)H;
+    p.band = 1.0 / (double)near_ - 1.0 / (double)far_;
+    p.inv_far = 1.0 / (double)far_;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipError_t e = qk::launch_render_ibr(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "render launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

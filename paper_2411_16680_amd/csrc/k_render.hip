@@ -1,0 +1,153 @@
+// k_render.hip -- the final render of an LDM (Sec. 3.1, Eq. 1, and
+// Sec. 3.2.3 "Upsampling & Activation"): bilinear upsampling of the
+// unactivated depth, density and blend-weight logits to the output grid,
+// activation after the upsampling, back-projection of every input image onto
+// every layer through the decoded depth, blending of the images with the
+// blend weights and the front-to-back over composite.
+//
+// One thread per output pixel, 16 x 16 pixel tiles (a wave covers 16 x 4), so
+// the neighbouring threads that share low-resolution logit taps and, at
+// similar depths, image taps sit in the same wave.  The per-view softmax of
+// the blend logits runs online (running maximum, rescaled sums), so neither
+// the weights nor the per-view samples are stored.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "uf_params.h"
+
+namespace qk {
+namespace {
+
+// RGBA8 image m as a buffer resource: a load at a byte offset outside the
+// image reads zero.  A tap outside the image is sent to kTapOOB, far past
+// the end (images are under 1 GiB), never to a negative offset: the compiler
+// may merge the loads of neighbouring taps or fold a constant into the
+// instruction's immediate offset, and a negative register offset would then
+// take a valid tap out of range with it.
+constexpr int kTapOOB = 0x40000000;
+
+__device__ inline __amdgpu_buffer_rsrc_t image_rsrc(const RenderParams &p, int m) {
+    const int bytes = p.iH[m] * p.iW[m] * 4;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p.img[m]), 0, bytes, 0x00020000);
+}
+
+__device__ inline unsigned load_texel(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
+
+// Byte c of a packed texel as a float 0..255.
+__device__ inline float chan(unsigned t, int c) {
+    return (float)((t >> (8 * c)) & 0xffu);
+}
+
+__device__ inline float sigmoid_(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
+__global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
+    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (x >= p.W || y >= p.H) return;              // no barriers below
+
+    // upsampling taps: source coordinate (x + 0.5) w / W - 0.5, clamped
+    // below at 0; the second tap clamped to the last column / row
+    double sx = ((double)x + 0.5) * p.rx - 0.5, sy = ((double)y + 0.5) * p.ry - 0.5;
+    sx = sx < 0.0 ? 0.0 : sx;
+    sy = sy < 0.0 ? 0.0 : sy;
+    int x0 = (int)sx, y0 = (int)sy;                 // sx, sy >= 0: truncation is floor
+    x0 = x0 < p.w - 1 ? x0 : p.w - 1;
+    y0 = y0 < p.h - 1 ? y0 : p.h - 1;
+    const int x1 = x0 + 1 < p.w ? x0 + 1 : p.w - 1, y1 = y0 + 1 < p.h ? y0 + 1 : p.h - 1;
+    const double lxd = sx - x0, lyd = sy - y0;
+    const float lx = (float)lxd, ly = (float)lyd;
+    const int64_t hw = (int64_t)p.h * p.w;
+    const int64_t t00 = (int64_t)y0 * p.w + x0, t10 = (int64_t)y0 * p.w + x1;
+    const int64_t t01 = (int64_t)y1 * p.w + x0, t11 = (int64_t)y1 * p.w + x1;
+    auto lerp_f = [&](float a00, float a10, float a01, float a11) {
+        return (1.0f - ly) * ((1.0f - lx) * a00 + lx * a10) + ly * ((1.0f - lx) * a01 + lx * a11);
+    };
+
+    const double u = (double)x + 0.5, v = (double)y + 0.5;
+    const int V = p.V, L = p.L;
+    float Tr = 1.0f, out0 = 0.0f, out1 = 0.0f, out2 = 0.0f, dmap = 0.0f;
+
+    for (int li = 0; li < L; ++li) {
+        // depth: the logit is interpolated in double, since an error in it is
+        // magnified by the parallax (up to ~1e3 px per unit of disparity)
+        const float *D = p.depth_logit + li * hw;
+        const double xd = (1.0 - lyd) * ((1.0 - lxd) * (double)D[t00] + lxd * (double)D[t10]) +
+                          lyd * ((1.0 - lxd) * (double)D[t01] + lxd * (double)D[t11]);
+        const double delta = ((double)(L - li) - 0.5) / (double)L;
+        const double disp = (delta + (0.5 / (double)L) * (double)tanhf((float)xd)) * p.band + p.inv_far;
+        const float depth = (float)(1.0 / disp);
+        const float *S = p.sigma_logit + li * hw;
+        const float alpha = sigmoid_(lerp_f(S[t00], S[t10], S[t01], S[t11]));
+
+        // blend: online softmax over the views of the upsampled logits
+        const float *B = p.blend_logit + li * hw * V;
+        float mx = -3.0e38f, z = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        for (int m = 0; m < V; ++m) {
+            const float xb = lerp_f(B[t00 * V + m], B[t10 * V + m], B[t01 * V + m], B[t11 * V + m]);
+            if (xb > mx) {                           // move the reference
+                const float r = __expf(mx - xb);
+                z *= r; c0 *= r; c1 *= r; c2 *= r;
+                mx = xb;
+            }
+            const float e = __expf(xb - mx);
+
+            // back-projection of image m through this depth
+            const double *A = p.cam[m];
+            const double pz = fma(A[6], u, fma(A[7], v, fma(A[11], disp, A[8])));
+            const double qx = fma(A[0], u, fma(A[1], v, fma(A[9], disp, A[2])));
+            const double qy = fma(A[3], u, fma(A[4], v, fma(A[10], disp, A[5])));
+            const int iw = p.iW[m], ih = p.iH[m];
+            const double rz = 1.0 / pz;
+            const double fxc = qx * rz - 0.5, fyc = qy * rz - 0.5;
+            const bool ok = (pz > 1e-6) && (fxc > -2.0) && (fxc < (double)(iw + 1)) &&
+                            (fyc > -2.0) && (fyc < (double)(ih + 1));
+            const double xf = floor(fxc), yf = floor(fyc);
+            const float wx = (float)(fxc - xf), wy = (float)(fyc - yf);
+            const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
+            const bool vx0 = (unsigned)ix < (unsigned)iw, vx1 = (unsigned)(ix + 1) < (unsigned)iw;
+            const bool vy0 = (unsigned)iy < (unsigned)ih, vy1 = (unsigned)(iy + 1) < (unsigned)ih;
+            const float w00 = (vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f;
+            const float w10 = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
+            const float w01 = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
+            const float w11 = (vx1 && vy1) ? wx * wy : 0.0f;
+            const __amdgpu_buffer_rsrc_t rs = image_rsrc(p, m);
+            const int o = (iy * iw + ix) * 4;
+            const unsigned a00 = load_texel(rs, (vx0 && vy0) ? o : kTapOOB);
+            const unsigned a10 = load_texel(rs, (vx1 && vy0) ? o + 4 : kTapOOB);
+            const unsigned a01 = load_texel(rs, (vx0 && vy1) ? o + 4 * iw : kTapOOB);
+            const unsigned a11 = load_texel(rs, (vx1 && vy1) ? o + 4 * iw + 4 : kTapOOB);
+            const float s0 = w00 * chan(a00, 0) + w10 * chan(a10, 0) + w01 * chan(a01, 0) + w11 * chan(a11, 0);
+            const float s1 = w00 * chan(a00, 1) + w10 * chan(a10, 1) + w01 * chan(a01, 1) + w11 * chan(a11, 1);
+            const float s2 = w00 * chan(a00, 2) + w10 * chan(a10, 2) + w01 * chan(a01, 2) + w11 * chan(a11, 2);
+            z += e;
+            c0 = fmaf(e, s0, c0);
+            c1 = fmaf(e, s1, c1);
+            c2 = fmaf(e, s2, c2);
+        }
+        const float k = Tr * alpha * (1.0f / 255.0f) / z;   // beta = e / z; texels v / 255
+        out0 = fmaf(k, c0, out0);
+        out1 = fmaf(k, c1, out1);
+        out2 = fmaf(k, c2, out2);
+        dmap = fmaf(Tr * alpha, depth, dmap);
+        Tr *= 1.0f - alpha;
+    }
+    const int64_t q = (int64_t)y * p.W + x;
+    p.rgb[q * 3 + 0] = out0;
+    p.rgb[q * 3 + 1] = out1;
+    p.rgb[q * 3 + 2] = out2;
+    if (p.acc != nullptr) p.acc[q] = 1.0f - Tr;
+    if (p.depth != nullptr) p.depth[q] = dmap;
+}
+
+}  // namespace
+
+hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s) {
+    const dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
+    hipLaunchKernelGGL(k_render_ibr, grid, dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace qk

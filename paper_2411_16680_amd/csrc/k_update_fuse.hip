@@ -250,8 +250,13 @@ struct Taps {
 
 // Feature map m as a buffer resource: a load whose byte offset falls
 // outside [0, bytes) returns zeros (the hardware's range check), so tap
-// addresses need no clamping.  The host keeps every map under 1 GiB, so the
-// offsets below stay in int range.
+// addresses need no clamping.  A tap outside the map is sent to kTapOOB, far
+// past the end (the host keeps every map under 1 GiB), never to a negative
+// offset: the compiler may fold a constant part of an offset into the
+// instruction's immediate field or merge neighbouring loads, and a negative
+// register offset then takes a valid tap out of range with it.
+constexpr int kTapOOB = 0x40000000;
+
 template <int C, bool BF16>
 __device__ inline __amdgpu_buffer_rsrc_t feat_rsrc(const UFParams &p, int m) {
     const int bytes = p.fH[m] * p.fW[m] * C * (int)sizeof(typename Op<BF16>::T);
@@ -292,10 +297,8 @@ __device__ inline void raw_unpack(const RawTap<BF16> &r, float *f) {
 // bilinear sample): p = A_m (u, v, 1) + b_m / d; a point with p_z <= 1e-6
 // (behind the view) samples zero.  Computes this lane's four tap addresses
 // (half-pixel centres) and issues the loads of channels ch0 + 32 kc + [0, 8).
-// A tap outside the map has weight 0 and its load is unconditional: its
-// offset is either out of the buffer's range (zeros) or lands on a pixel of
-// the neighbouring row.  A sample no tap of which can touch the map takes the
-// tap corner (-4, -4), whose offsets are all negative.
+// A tap outside the map has weight 0 and its load is unconditional, at the
+// out-of-range offset kTapOOB (it reads zeros).
 template <int C, bool BF16>
 __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16>::type uc,
                                   typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
@@ -328,8 +331,11 @@ __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16
     tp.w[2] = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
     tp.w[3] = (vx1 && vy1) ? wx * wy : 0.0f;
     constexpr int E = (int)sizeof(T);
-    const int o00 = ((iy * fw + ix) * C + ch0) * E, o10 = o00 + C * E;
-    const int o01 = o00 + fw * C * E, o11 = o01 + C * E;
+    const int o = ((iy * fw + ix) * C + ch0) * E;
+    const int o00 = (vx0 && vy0) ? o : kTapOOB;
+    const int o10 = (vx1 && vy0) ? o + C * E : kTapOOB;
+    const int o01 = (vx0 && vy1) ? o + fw * C * E : kTapOOB;
+    const int o11 = (vx1 && vy1) ? o + (fw + 1) * C * E : kTapOOB;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
         buf_load<BF16>(fr, o00 + 32 * kc * E, tp.t[kc][0]);
@@ -393,16 +399,17 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
     const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
     const bool vx0 = (unsigned)ix < (unsigned)fw, vx1 = (unsigned)(ix + 1) < (unsigned)fw;
     const bool vy0 = (unsigned)iy < (unsigned)fh, vy1 = (unsigned)(iy + 1) < (unsigned)fh;
-    // byte offsets as in issue_taps (out-of-map taps: zeros or a neighbour, weight 0)
+    // byte offsets as in issue_taps (an out-of-map tap reads zeros at kTapOOB)
     constexpr int E = (int)sizeof(T);
+    const int o = (iy * fw + ix) * C * E;
     int4 ow0, ow1;       // (byte offset, weight bits) of taps 00, 10 | 01, 11
-    ow0.x = (iy * fw + ix) * C * E;
+    ow0.x = (vx0 && vy0) ? o : kTapOOB;
     ow0.y = __float_as_int((vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f);
-    ow0.z = ow0.x + C * E;
+    ow0.z = (vx1 && vy0) ? o + C * E : kTapOOB;
     ow0.w = __float_as_int((vx1 && vy0) ? wx * (1.0f - wy) : 0.0f);
-    ow1.x = ow0.x + fw * C * E;
+    ow1.x = (vx0 && vy1) ? o + fw * C * E : kTapOOB;
     ow1.y = __float_as_int((vx0 && vy1) ? (1.0f - wx) * wy : 0.0f);
-    ow1.z = ow1.x + C * E;
+    ow1.z = (vx1 && vy1) ? o + (fw + 1) * C * E : kTapOOB;
     ow1.w = __float_as_int((vx1 && vy1) ? wx * wy : 0.0f);
     int4 *slot = reinterpret_cast<int4 *>(&tT[(g * 16 + r) * 4]);
     slot[0] = ow0;

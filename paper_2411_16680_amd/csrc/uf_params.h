@@ -121,3 +121,23 @@ struct F8Params {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Final render (upsample & activate, blend-weight image-based render).
+struct RenderParams {
+    const void *img[kMaxViews];     // RGBA8 [iH][iW][4]
+    int32_t iH[kMaxViews], iW[kMaxViews];
+    double cam[kMaxViews][12];      // output grid -> image m: A (9), b (3)
+    const float *depth_logit;       // [L][h][w]
+    const float *sigma_logit;       // [L][h][w]
+    const float *blend_logit;       // [L][h][w][V]
+    float *rgb;                     // [H][W][3]
+    float *acc;                     // [H][W] or NULL
+    float *depth;                   // [H][W] or NULL
+    int32_t V, L, h, w, H, W;
+    double rx, ry;                  // w / W, h / H (source step per output pixel)
+    double band, inv_far;           // 1/near - 1/far, 1/far
+};
+
+}  // namespace qk

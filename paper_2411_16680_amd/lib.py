@@ -28,7 +28,7 @@ MODE = {"residual": 0, "paper": 1}
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
-           "qk_composite",
+           "qk_composite", "qk_render_ibr", "qk_render_ibr_check",
            "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
@@ -45,6 +45,16 @@ class qk_camera(ctypes.Structure):
 
 class qk_feature_map(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class qk_image(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class qk_ldm_logits(ctypes.Structure):
+    _fields_ = [("depth_logit", ctypes.c_void_p), ("sigma_logit", ctypes.c_void_p),
+                ("blend_logit", ctypes.c_void_p), ("L", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("V", ctypes.c_int32)]
 
 
 class qk_ldm(ctypes.Structure):
@@ -100,10 +110,15 @@ def load() -> ctypes.CDLL:
                                ctypes.c_void_p]
     L.qk_camera_tables.argtypes = [ctypes.c_int32, P(qk_camera), P(ctypes.c_int32), P(qk_camera),
                                    ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
+    render_args = [ctypes.c_int32, P(qk_camera), P(qk_image), P(qk_camera), ctypes.c_float,
+                   ctypes.c_float, P(qk_ldm_logits), ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.qk_render_ibr.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + render_args
+    L.qk_render_ibr_check.argtypes = render_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
-                 "qk_camera_tables"):
+                 "qk_render_ibr", "qk_render_ibr_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -310,6 +325,41 @@ def composite(ctx: Context, color, alpha, rgb_out, acc_out=None, stream=None):
     L, H, W = (int(s) for s in alpha.shape)
     _check(ctx._lib.qk_composite(ctx.handle, _stream_handle(stream), L, H, W, _ptr(color),
                                  _ptr(alpha), _ptr(rgb_out), _ptr(acc_out)))
+
+
+def _render_args(in_cams, images, novel, near, far, logits, H, W, rgb_out, acc_out, depth_out):
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    imgs = (qk_image * V)(*[qk_image(_ptr(im), int(im.shape[0]), int(im.shape[1]))
+                            for im in images])
+    dl, sl, bl = logits
+    L, h, w = (int(s) for s in dl.shape)
+    lg = qk_ldm_logits(_ptr(dl), _ptr(sl), _ptr(bl), L, h, w,
+                       int(bl.shape[3]) if len(bl.shape) == 4 else -1)
+    nov = make_camera(novel)
+    args = (V, cams, imgs, ctypes.byref(nov), ctypes.c_float(near), ctypes.c_float(far),
+            ctypes.byref(lg), int(H), int(W), _ptr(rgb_out), _ptr(acc_out), _ptr(depth_out))
+    return args, (cams, imgs, lg, nov)
+
+
+def render_ibr(ctx: Context, in_cams, images, novel, near, far, logits, rgb_out, *,
+               acc_out=None, depth_out=None, stream=None):
+    """qk_render_ibr: images are RGBA8 device tensors [Hi][Wi][4] (uint8);
+    logits = (depth_logit [L][h][w], sigma_logit [L][h][w],
+    blend_logit [L][h][w][V]) float32; rgb_out [H][W][3] float32 sets the
+    output grid."""
+    H, W = int(rgb_out.shape[0]), int(rgb_out.shape[1])
+    args, keep = _render_args(in_cams, images, novel, near, far, logits, H, W, rgb_out, acc_out,
+                              depth_out)
+    _check(ctx._lib.qk_render_ibr(ctx.handle, _stream_handle(stream), *args))
+
+
+def render_ibr_check(in_cams, images, novel, near, far, logits, H, W, rgb_out, *, acc_out=None,
+                     depth_out=None) -> int:
+    """qk_render_ibr_check: the status qk_render_ibr would return (no device use)."""
+    args, keep = _render_args(in_cams, images, novel, near, far, logits, H, W, rgb_out, acc_out,
+                              depth_out)
+    return int(load().qk_render_ibr_check(*args))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

@@ -233,3 +233,59 @@ def test_backward_null_context_rejected():
     args, keep = lib._bwd_args(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, "residual", ldm,
                                ldm, None, None, d_in, dfe, dw)
     assert lib.load().qk_update_fuse_backward(None, None, *args) == lib.QK_EINVAL
+
+
+def _render_args(V=3, L=2, h=6, w=10, H=12, W=20, Hi=14, Wi=22):
+    import torch
+    rs = synth.make_render(V=V, W=W, H=H, L=L, lowres_hw=(h, w), img_hw=(Hi, Wi), seed=2)
+    imgs = [_FakeT((Hi, Wi, 4), 0x200000 + 0x10000 * i, torch.uint8) for i in range(V)]
+    lg = (_FakeT((L, h, w), 0x300000), _FakeT((L, h, w), 0x310000),
+          _FakeT((L, h, w, V), 0x320000))
+    rgb = _FakeT((H, W, 3), 0x400000)
+    return rs, imgs, lg, rgb
+
+
+def _rcheck(rs, imgs, lg, rgb, near=None, far=None, **kw):
+    return lib.render_ibr_check(rs.in_cams, imgs, rs.novel, rs.near if near is None else near,
+                                rs.far if far is None else far, lg, rgb.shape[0], rgb.shape[1],
+                                rgb, **kw)
+
+
+def test_render_valid_arguments_pass():
+    rs, imgs, lg, rgb = _render_args()
+    assert _rcheck(rs, imgs, lg, rgb) == lib.QK_OK
+    assert _rcheck(rs, imgs, lg, rgb, acc_out=_FakeT((12, 20), 0x500000),
+                   depth_out=_FakeT((12, 20), 0x510000)) == lib.QK_OK
+
+
+def test_render_rejections():
+    rs, imgs, lg, rgb = _render_args()
+    # blend logits for another number of views
+    bad = (lg[0], lg[1], _FakeT((2, 6, 10, 4), 0x320000))
+    assert _rcheck(rs, imgs, bad, rgb) == lib.QK_ESHAPE
+    # misaligned image, NULL logit, misaligned output
+    im2 = list(imgs)
+    im2[1] = _FakeT(imgs[1].shape, imgs[1]._addr + 2, imgs[1].dtype)
+    assert _rcheck(rs, im2, lg, rgb) == lib.QK_EINVAL
+    assert "aligned" in lib.load().qk_last_error().decode()
+    assert _rcheck(rs, imgs, (lg[0], None, lg[2]), rgb) == lib.QK_EINVAL
+    assert _rcheck(rs, imgs, lg, _FakeT((12, 20, 3), 0x400002)) == lib.QK_EINVAL
+    # near >= far
+    assert _rcheck(rs, imgs, lg, rgb, near=3.0, far=3.0) == lib.QK_EINVAL
+    # an image of 1 GiB (16384 x 16384 RGBA8) is refused
+    im3 = list(imgs)
+    im3[0] = _FakeT((16384, 16384, 4), imgs[0]._addr)
+    assert _rcheck(rs, im3, lg, rgb) == lib.QK_EUNSUPPORTED
+    # non-positive output grid
+    assert lib.render_ibr_check(rs.in_cams, imgs, rs.novel, rs.near, rs.far, lg, 0, 20,
+                                rgb) == lib.QK_ESHAPE
+    # more than 16 views
+    rs17, imgs17, lg17, rgb17 = _render_args(V=17)
+    assert _rcheck(rs17, imgs17, lg17, rgb17) == lib.QK_ESHAPE
+
+
+def test_render_null_context_rejected_before_device_use():
+    rs, imgs, lg, rgb = _render_args()
+    args, keep = lib._render_args(rs.in_cams, imgs, rs.novel, rs.near, rs.far, lg, 12, 20, rgb,
+                                  None, None)
+    assert lib.load().qk_render_ibr(None, None, *args) == lib.QK_EINVAL

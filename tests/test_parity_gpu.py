@@ -211,6 +211,27 @@ def test_edge_cases(ctx, name, kw, form, attn):
 
 @pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
+@pytest.mark.parametrize("C", [8, 16, 32, 64])
+def test_corner_cells(ctx, C, form, attn):
+    """Views that are the novel camera itself, with feature maps one pixel
+    smaller than the LDM grid: row 0 and column 0 of every layer sample cells
+    whose first tap row / column lies outside the map, and pixel (0, 0) the
+    corner cell whose only inside tap, (0, 0), carries ~95 % of the weight."""
+    _say("corner cells", C, form, attn)
+    H, W = 6, 40
+    sc = synth.make_custom(V=3, H=H, W=W, C=C, L=3, feat_hw=(H - 1, W - 1), seed=40 + C)
+    nov = sc.novel
+    sc.in_cams = [synth.Camera(nov.K.copy(), nov.E.copy(), nov.width, nov.height)
+                  for _ in range(3)]
+    if form == "bf16":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn)
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"corner-cells C{C} {attn}")
+
+
+@pytest.mark.parametrize("attn", ATTN)
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
 def test_paper_decode_mode(ctx, form, attn):
     _say("paper decode", form, attn)
     sc = synth.make_custom(V=4, H=7, W=45, C=32, L=6, seed=31)

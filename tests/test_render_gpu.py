@@ -1,0 +1,128 @@
+"""Parity of the final render (qk_render_ibr: upsample & activate, blend-weight
+image-based render, composite) against the FP64 oracle, through the C-ABI.
+
+Bar (float32 arithmetic, reprojection and the depth logit's interpolation in
+double): RGB max-abs <= 1e-4, accumulated alpha <= 1e-5, composited depth
+relative <= 1e-5 -- the float rounding left (tanh, softmax, sigmoid, the
+blend) moves a sample by well under 1e-4 px even at the rig's largest
+parallax (~1e3 px per unit of disparity), and an image's values change by at
+most 1 per px."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_16680_amd import lib, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"rgb": 1e-4, "acc": 1e-5, "depth_rel": 1e-5}
+
+
+def _say(*a):
+    print("[render]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib.Context(0)
+
+
+def _device(rs):
+    imgs = [torch.from_numpy(im).cuda() for im in rs.images]
+    lg = tuple(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+               for a in rs.logits)
+    return imgs, lg
+
+
+def _gpu_render(ctx, rs, cams=None):
+    imgs, lg = _device(rs)
+    rgb = torch.full((rs.H, rs.W, 3), float("nan"), device="cuda")
+    acc = torch.full((rs.H, rs.W), float("nan"), device="cuda")
+    dep = torch.full((rs.H, rs.W), float("nan"), device="cuda")
+    lib.render_ibr(ctx, rs.in_cams if cams is None else cams, imgs, rs.novel, rs.near, rs.far,
+                   lg, rgb, acc_out=acc, depth_out=dep)
+    torch.cuda.synchronize()
+    return {"rgb": rgb.cpu().numpy(), "acc": acc.cpu().numpy(), "depth": dep.cpu().numpy()}
+
+
+def _compare(name, got, ref, rows=None):
+    g = {k: (v if rows is None else v[rows]) for k, v in got.items()}
+    e_rgb = float(np.max(np.abs(g["rgb"] - ref["rgb"])))
+    e_acc = float(np.max(np.abs(g["acc"] - ref["acc"])))
+    e_dep = float(np.max(np.abs(g["depth"] - ref["depth"]) / np.maximum(np.abs(ref["depth"]), 1e-30)))
+    _say(name, f"rgb {e_rgb:.3g} acc {e_acc:.3g} depth_rel {e_dep:.3g}")
+    assert np.all(np.isfinite(g["rgb"]))
+    assert e_rgb <= TOL["rgb"], (name, e_rgb)
+    assert e_acc <= TOL["acc"], (name, e_acc)
+    assert e_dep <= TOL["depth_rel"], (name, e_dep)
+
+
+def _oracle(rs, cams=None, rows=None):
+    return oracle.render_ibr(rs.in_cams if cams is None else cams, rs.images, rs.novel, rs.near,
+                             rs.far, *rs.logits, rs.H, rs.W, rows=rows)
+
+
+CASES = {
+    "small-V3-s2": dict(V=3, W=40, H=24, s=2, L=3, img_hw=(30, 50), seed=11),
+    "ragged-53x37-V5-L4": dict(V=5, W=53, H=37, L=4, lowres_hw=(13, 18), img_hw=(41, 61), seed=3),
+    "s3-V4": dict(V=4, W=96, H=54, s=3, L=2, seed=5),
+    "s1-identity-upsample": dict(V=2, W=35, H=20, s=1, L=3, seed=6),
+    "lowres-1x1": dict(V=3, W=33, H=18, L=2, lowres_hw=(1, 1), seed=7),
+    "one-layer": dict(V=2, W=48, H=32, s=2, L=1, seed=8),
+    "one-view": dict(V=1, W=48, H=32, s=2, L=3, seed=9),
+    "max-views-V16": dict(V=16, W=40, H=24, s=2, L=2, seed=10),
+    "wide-fov-behind": dict(V=6, W=64, H=36, s=2, L=3, arc=4.0, radius=1.5, hfov=140.0, seed=12),
+    "images-larger-than-output": dict(V=3, W=40, H=24, s=4, L=3, img_hw=(96, 160), seed=13),
+    "single-pixel-output": dict(V=2, W=1, H=1, L=2, lowres_hw=(1, 1), img_hw=(9, 7), seed=14),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_render_parity(ctx, name):
+    rs = synth.make_render(**CASES[name])
+    _say("case", name, f"V={rs.V} out {rs.W}x{rs.H} logits {rs.depth_logit.shape}")
+    _compare(name, _gpu_render(ctx, rs), _oracle(rs))
+
+
+def test_identity_camera_reproduces_the_image(ctx):
+    rs = synth.make_render(V=1, W=40, H=24, s=2, L=3, seed=15)
+    cam = synth.Camera(rs.novel.K.copy(), rs.novel.E.copy(), rs.novel.width, rs.novel.height)
+    got = _gpu_render(ctx, rs, cams=[cam])
+    ref = _oracle(rs, cams=[cam])
+    _compare("identity-camera", got, ref)
+    img = oracle.image_rgb(rs.images[0])
+    assert np.max(np.abs(got["rgb"] - img * got["acc"][..., None])) <= 1e-4
+
+
+def test_corner_cells(ctx):
+    """Input cameras equal to the novel camera with images one pixel smaller
+    than the output grid: the first row and column sample cells whose first
+    tap row / column is outside the image, pixel (0, 0) the corner cell."""
+    rs = synth.make_render(V=2, W=40, H=24, s=2, L=3, img_hw=(23, 39), seed=17)
+    nov = rs.novel
+    cams = [synth.Camera(nov.K.copy(), nov.E.copy(), nov.width, nov.height) for _ in range(2)]
+    _compare("corner-cells", _gpu_render(ctx, rs, cams=cams), _oracle(rs, cams=cams))
+
+
+def test_render_full_size_sampled_rows(ctx):
+    """The benchmark's configuration (1920x1080 output from a 960x540 LDM of
+    4 layers, 8 RGBA8 input images of 1920x1080), checked on sampled rows."""
+    rs = synth.make_render()
+    got = _gpu_render(ctx, rs)
+    rows = np.array([0, 1, 15, 16, 538, 539, 540, 901, 1078, 1079], dtype=np.int32)
+    _compare("1080p-sampled-rows", got, _oracle(rs, rows=rows), rows=rows)
+
+
+def test_render_is_deterministic_and_stream_ordered(ctx):
+    rs = synth.make_render(V=4, W=70, H=40, s=2, L=3, seed=16)
+    a = _gpu_render(ctx, rs)
+    b = _gpu_render(ctx, rs)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
