@@ -44,8 +44,20 @@ __device__ inline float chan(unsigned t, int c) {
 __device__ inline float sigmoid_(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
 __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    // XCD-aware tile order: workgroups are dispatched round-robin over the
+    // 8 XCDs, so workgroup i is given tile (i % 8) * per + i / 8 and each XCD
+    // walks one contiguous band of 16-row tiles; with horizontal-ish
+    // baselines the band's samples fall in a band of image rows that stays
+    // in the XCD's L2
+    const int tiles_x = (p.W + 15) >> 4;
+    const int n = tiles_x * ((p.H + 15) >> 4);
+    int tile;
+    {
+        const int i = blockIdx.x, xcd = i & 7, loc = i >> 3, q = n >> 3, rem = n & 7;
+        tile = (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+    }
+    const int x = (tile % tiles_x) * 16 + (threadIdx.x & 15);
+    const int y = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
     if (x >= p.W || y >= p.H) return;              // no barriers below
 
     // upsampling taps: source coordinate (x + 0.5) w / W - 0.5, clamped
@@ -100,7 +112,10 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
             const double qx = fma(A[0], u, fma(A[1], v, fma(A[9], disp, A[2])));
             const double qy = fma(A[3], u, fma(A[4], v, fma(A[10], disp, A[5])));
             const int iw = p.iW[m], ih = p.iH[m];
-            const double rz = 1.0 / pz;
+            // 1/pz: the hardware reciprocal refined by one Newton step (the
+            // relative error squares, far below what the coordinates need)
+            double rz = __builtin_amdgcn_rcp(pz);
+            rz = fma(rz, fma(-pz, rz, 1.0), rz);
             const double fxc = qx * rz - 0.5, fyc = qy * rz - 0.5;
             const bool ok = (pz > 1e-6) && (fxc > -2.0) && (fxc < (double)(iw + 1)) &&
                             (fyc > -2.0) && (fyc < (double)(ih + 1));
@@ -145,8 +160,8 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
 }  // namespace
 
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s) {
-    const dim3 grid((p.W + 15) / 16, (p.H + 15) / 16);
-    hipLaunchKernelGGL(k_render_ibr, grid, dim3(256), 0, s, p);
+    const int tiles = ((p.W + 15) / 16) * ((p.H + 15) / 16);
+    hipLaunchKernelGGL(k_render_ibr, dim3(tiles), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
