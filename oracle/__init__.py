@@ -49,6 +49,7 @@ def lib():
         L.or_reproject_T.restype = ctypes.c_int
         L.or_update_fuse.restype = ctypes.c_int
         L.or_render_ibr.restype = ctypes.c_int
+        L.or_render_to_views.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         for name in ("or_reprojection_matrix", "or_reproject", "or_reproject_T"):
             pass
@@ -227,6 +228,48 @@ def render_ibr(in_cams, images, novel, near, far, depth_logit, sigma_logit, blen
     if lc is not None:
         out["layer_color"] = lc
     return out
+
+
+# --------------------------------------------------------------------------
+# Render to input views (projection operator P_theta and per-view composite)
+# --------------------------------------------------------------------------
+
+def splat_layer(T, depth, val, Hm: int, Wm: int) -> np.ndarray:
+    """P_theta of one layer: val [H][W] or [H][W][C] at depth [H][W] (novel
+    grid) into an (Hm, Wm) view grid through the 4x4 chain T."""
+    T, depth, val = _f64(T), _f64(depth), _f64(val)
+    squeeze = val.ndim == 2
+    if squeeze:
+        val = val[..., None]
+    H, W, C = val.shape
+    out = np.zeros((Hm, Wm, C))
+    lib().or_splat_layer(_d(T), H, W, _d(depth), _d(val), C, int(Hm), int(Wm), _d(out))
+    return out[..., 0] if squeeze else out
+
+
+def render_to_views(in_cams, novel, depth, alpha, color, view_hw) -> Dict[str, list]:
+    """Eq. 2 for every view: depth, alpha [L][H][W], color [L][H][W][3]
+    (novel grid); view_hw [V] of (Hm, Wm).  Returns {"img": [V] [Hm][Wm][3],
+    "acc": [V] [Hm][Wm]}."""
+    V = len(in_cams)
+    depth, alpha, color = _f64(depth), _f64(alpha), _f64(color)
+    L, H, W = depth.shape
+    Kin = _f64(np.stack([c.K for c in in_cams]))
+    Ein = _f64(np.stack([c.E for c in in_cams]))
+    cam_wh = np.ascontiguousarray([[c.width, c.height] for c in in_cams], dtype=np.int32)
+    vhw = np.ascontiguousarray(view_hw, dtype=np.int32).reshape(V, 2)
+    imgs = [np.zeros((int(h), int(w), 3)) for h, w in vhw]
+    accs = [np.zeros((int(h), int(w))) for h, w in vhw]
+    iptr = (_dp * V)(*[_d(a) for a in imgs])
+    aptr = (_dp * V)(*[_d(a) for a in accs])
+    nov_wh = np.array([novel.width, novel.height], dtype=np.int32)
+    rc = lib().or_render_to_views(V, _d(Kin), _d(Ein), cam_wh.ctypes.data_as(_ip),
+                                  vhw.ctypes.data_as(_ip), _d(_f64(novel.K)), _d(_f64(novel.E)),
+                                  nov_wh.ctypes.data_as(_ip), L, H, W, _d(depth), _d(alpha),
+                                  _d(color), iptr, aptr)
+    if rc != 0:
+        raise ValueError("oracle render_to_views failed (singular camera?)")
+    return {"img": imgs, "acc": accs}
 
 
 # --------------------------------------------------------------------------

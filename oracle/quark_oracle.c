@@ -640,6 +640,95 @@ OR_EXPORT int or_render_ibr(int V, const double *Kin, const double *Ein, const i
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Render to input views (Sec. 3.2.2 "Decoding and rendering the            */
+/* intermediate LDM", Eq. 2): the decoded intermediate LDM -- per layer-     */
+/* pixel depth d, density sigma and appearance a (RGB) -- is carried into    */
+/* each input view by the projection operator P_theta and over-composited    */
+/* there.  P_theta is the operator whose adjoint is the back-projection      */
+/* P^T_theta used for sampling (Sec. 3.1): a layer-pixel reprojected through */
+/* its depth to view m's continuous coordinate adds its value to the four   */
+/* view pixels around that point, with the bilinear weights that sampling    */
+/* at that point would give them (taps outside the view grid dropped, a      */
+/* point behind the view adds nothing; no normalisation).  Each layer is     */
+/* projected separately; the projected layers are composited front to back  */
+/* (layer 0 nearest the novel camera) with the projected density as alpha.  */
+/* ------------------------------------------------------------------------ */
+
+/* Project one layer's values val[H][W][C] (novel grid, depth[H][W]) into a
+ * view grid (Hm, Wm) through the 4x4 chain T (as for sampling), adding into
+ * out[Hm][Wm][C]. */
+OR_EXPORT void or_splat_layer(const double *T, int H, int W, const double *depth,
+                              const double *val, int C, int Hm, int Wm, double *out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double uv[2];
+            size_t q = (size_t)y * W + x;
+            if (or_reproject_T(T, x + 0.5, y + 0.5, depth[q], uv) != 1) continue;
+            double fx_ = uv[0] - 0.5, fy_ = uv[1] - 0.5;
+            if (!(fabs(fx_) < 1e9 && fabs(fy_) < 1e9)) continue;
+            double xf = floor(fx_), yf = floor(fy_);
+            double fx = fx_ - xf, fy = fy_ - yf;
+            long x0 = (long)xf, y0 = (long)yf;
+            const long tx[4] = {x0, x0 + 1, x0, x0 + 1};
+            const long ty[4] = {y0, y0, y0 + 1, y0 + 1};
+            const double w[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+            for (int t = 0; t < 4; ++t) {
+                if (tx[t] < 0 || tx[t] >= Wm || ty[t] < 0 || ty[t] >= Hm) continue;
+                double *o = out + ((size_t)ty[t] * Wm + (size_t)tx[t]) * C;
+                for (int c = 0; c < C; ++c) o[c] += w[t] * val[q * C + c];
+            }
+        }
+}
+
+/* The whole render to the V views.
+ * Inputs: Kin[V][9], Ein[V][16], cam_wh[V][2] (grid of Kin), view_hw[V][2]
+ * (Hm, Wm: the grid each view is rendered on); novel Kn[9], En[16],
+ * nov_wh[2]; LDM L, H, W with depth, alpha [L][H][W] and color [L][H][W][3].
+ * Outputs: img[V] -> [Hm][Wm][3], acc[V] -> [Hm][Wm] (1 - prod(1 - alpha))
+ * or NULL. */
+OR_EXPORT int or_render_to_views(int V, const double *Kin, const double *Ein, const int *cam_wh,
+                                 const int *view_hw, const double *Kn, const double *En,
+                                 const int *nov_wh, int L, int H, int W, const double *depth,
+                                 const double *alpha, const double *color, double *const *img,
+                                 double *const *acc)
+{
+    double Kns[9];
+    or_scale_intrinsics(Kn, nov_wh[0], nov_wh[1], W, H, Kns);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int m = 0; m < V; ++m) {
+        int Hm = view_hw[2 * m], Wm = view_hw[2 * m + 1];
+        double Kms[9], T[16];
+        or_scale_intrinsics(Kin + 9 * m, cam_wh[2 * m], cam_wh[2 * m + 1], Wm, Hm, Kms);
+        if (or_reprojection_matrix(Kns, En, Kms, Ein + 16 * m, T) != 0) { err = -1; continue; }
+        size_t np = (size_t)Hm * Wm;
+        double *pc = calloc(np * 3, sizeof(double));   /* P(a) of one layer     */
+        double *ps = calloc(np, sizeof(double));       /* P(sigma) of one layer */
+        double *Tr = malloc(np * sizeof(double));
+        for (size_t p = 0; p < np; ++p) Tr[p] = 1.0;
+        for (size_t p = 0; p < np * 3; ++p) img[m][p] = 0.0;
+        for (int l = 0; l < L; ++l) {
+            memset(pc, 0, np * 3 * sizeof(double));
+            memset(ps, 0, np * sizeof(double));
+            size_t off = (size_t)l * H * W;
+            or_splat_layer(T, H, W, depth + off, color + off * 3, 3, Hm, Wm, pc);
+            or_splat_layer(T, H, W, depth + off, alpha + off, 1, Hm, Wm, ps);
+            for (size_t p = 0; p < np; ++p) {
+                for (int j = 0; j < 3; ++j) img[m][p * 3 + j] += Tr[p] * ps[p] * pc[p * 3 + j];
+                Tr[p] *= (1.0 - ps[p]);
+            }
+        }
+        if (acc && acc[m])
+            for (size_t p = 0; p < np; ++p) acc[m][p] = 1.0 - Tr[p];
+        free(pc);
+        free(ps);
+        free(Tr);
+    }
+    return err;
+}
+
 OR_EXPORT int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -407,6 +407,46 @@ def make_render(*, V: int = 8, W: int = 1920, H: int = 1080, s: int = 2, L: int 
     return RenderScene(in_cams, images, novel, near, far, dlog, slog, blog, H, W)
 
 
+# ----------------------------------------------------------------------------
+# Render-to-input-views workload: a decoded intermediate LDM and the views
+# it is projected into
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ViewsScene:
+    in_cams: List[Camera]
+    novel: Camera
+    near: float
+    far: float
+    depth: np.ndarray                  # [L][H][W] float32, sorted near to far per pixel
+    alpha: np.ndarray                  # [L][H][W] float32
+    color: np.ndarray                  # [L][H][W][3] float32 in [0, 1]
+    view_hw: List[tuple]               # per view (Hm, Wm): the grid it is rendered on
+
+    @property
+    def V(self) -> int:
+        return len(self.in_cams)
+
+
+def make_views(*, V: int = 8, W: int = 1920, H: int = 1080, L: int = 4,
+               view_hw: Optional[tuple] = None, seed: int = 1007, arc: float = 0.5,
+               radius: float = 1.5, hfov: float = 60.0, near: float = 0.5, far: float = 20.0,
+               depth_mode: str = "iid") -> ViewsScene:
+    """An intermediate LDM to render into the input views: the multi-scale
+    workload's rig by default (V = 8, 60 degree field of view, 0.5 m arc of a
+    1.5 m ring, novel radius jittered 5 cm), depths log-uniform in
+    [near, far] sorted per pixel (i.i.d. or smooth), alpha Beta(1/2, 1/2),
+    colours uniform in [0, 1]; every view rendered on ``view_hw`` (default
+    the LDM grid).  Draw order: cameras, depth, alpha, colour."""
+    rng = np.random.default_rng(seed)
+    in_cams, novel = _arc_rig(rng, V, arc, radius, W, H, hfov, novel_radius_jitter=0.05)
+    depth = _sorted_depths(rng, L, H, W, near, far, "log", depth_mode)
+    alpha = _alpha(rng, (L, H, W), "beta")
+    color = rng.uniform(0.0, 1.0, size=(L, H, W, 3)).astype(np.float32)
+    vhw = [(H, W) if view_hw is None else tuple(view_hw)] * V
+    return ViewsScene(in_cams, novel, near, far, depth, alpha, color, vhw)
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""
