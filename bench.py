@@ -203,6 +203,15 @@ def profile_run(ctx, steps: int, depth_mode: str):
         torch.cuda.synchronize()
         log(f"profile render {s + 1}/{steps}")
     del args
+    vs = synth.make_views()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    d, a, c = dev(vs.depth), dev(vs.alpha), dev(vs.color)
+    rgbs = [torch.empty((h, w, 3), device="cuda") for h, w in vs.view_hw]
+    for s in range(steps):
+        lib.render_to_views(ctx, vs.in_cams, vs.novel, d, a, c, rgbs)
+        torch.cuda.synchronize()
+        log(f"profile render to views {s + 1}/{steps}")
+    del d, a, c, rgbs
     n = 128 * 1024 * 1024                          # 512 MiB of float32
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -270,6 +279,43 @@ def time_render(ctx, reps: int = 50):
                                                           RENDER_SRC)},
             "context": "paper: its inference renderer takes about 1.3 ms per 1080p frame on "
                        "an NVIDIA A100 (not the same inputs)"}
+
+
+VIEWS_WORKLOAD = ("render to input views: a decoded 1920x1080 LDM of 4 layers (depth, density, "
+                  "colour) splatted into 8 views of 1920x1080 and composited per view")
+
+
+def time_views(ctx, reps: int = 20):
+    """The render to input views at the multi-scale workload's finest level:
+    average call time (zero fill, splat, per-view composite) with HIP events
+    on its stream, and the HBM roofline of its compulsory bytes (the LDM
+    read once, the projected planes written once and read once, the view
+    images written)."""
+    import torch
+    from paper_2411_16680_amd import lib, synth
+    vs = synth.make_views()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    d, a, c = dev(vs.depth), dev(vs.alpha), dev(vs.color)
+    rgbs = [torch.empty((h, w, 3), device="cuda") for h, w in vs.view_hw]
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lib.render_to_views(ctx, vs.in_cams, vs.novel, d, a, c, rgbs, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        lib.render_to_views(ctx, vs.in_cams, vs.novel, d, a, c, rgbs, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    L, H, W = vs.depth.shape
+    planes = sum(L * h * w * 16 for h, w in vs.view_hw)
+    nbytes = L * H * W * 20 + 2 * planes + sum(h * w * 12 for h, w in vs.view_hw)
+    gbs = nbytes / (ms / 1000.0) / 1e9
+    return {"workload": VIEWS_WORKLOAD, "avg_call_ms": ms,
+            "layer_pixel_views_per_s": L * H * W * vs.V / (ms / 1000.0),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_call": nbytes}}
 
 
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
@@ -494,6 +540,11 @@ def main():
         f"{render['roofline']['achieved']:.0f} GB/s of compulsory bytes")
     torch.cuda.empty_cache()
 
+    views = time_views(ctx)
+    log(f"render to input views: {views['avg_call_ms']:.3f} ms per call "
+        f"({views['roofline']['achieved']:.0f} GB/s of compulsory bytes)")
+    torch.cuda.empty_cache()
+
     composite = time_composite(ctx)
     log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
         f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
@@ -566,6 +617,7 @@ def main():
         "roofline": roof,
         "composite_roofline": composite,
         "final_render": render,
+        "render_to_views": views,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,

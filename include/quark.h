@@ -134,9 +134,10 @@ typedef struct qk_context qk_context;
 /* Create a context bound to HIP device `device`.  The context owns device
  * workspaces that grow on demand and live until qk_context_destroy: the
  * folded weights of the one-to-many form (2 C C_feat floats), the e4m3
- * scales (8 floats) and the
+ * scales (8 floats), the
  * backward pass's scratch (16 bytes per layer-pixel when d_rgb is given,
- * plus 5 KiB per backward workgroup).  Growing one synchronises the
+ * plus 5 KiB per backward workgroup) and the projected planes of the render
+ * to input views (16 bytes per layer and view pixel).  Growing one synchronises the
  * caller's stream and allocates.  A context may be used from one host
  * thread at a time; calls that share it on different streams race on its
  * workspaces.  Errors: QK_EINVAL (out == NULL), QK_EHIP. */
@@ -324,6 +325,59 @@ QK_API qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const 
                                      const qk_ldm_logits *logits, int32_t H, int32_t W,
                                      const float *rgb_out, const float *acc_out,
                                      const float *depth_out);
+
+/* ---- Render to input views (Sec. 3.2.2 "Decoding and rendering the
+ * intermediate LDM", Eq. 2) ----
+ * The decoded intermediate LDM -- per layer-pixel depth d, density sigma and
+ * appearance a (RGB, already activated) on the LDM grid (L, H, W) -- is
+ * rendered into each input view m on that view's grid (Hm, Wm):
+ *   1. projection P_theta, the transpose of the bilinear back-projection of
+ *      qk_update_fuse: each layer-pixel, reprojected through its depth to
+ *      view m's continuous coordinate (cameras composed in double, the
+ *      novel K rescaled to (W, H), view m's K to (Wm, Hm)), adds
+ *      w * (a, sigma) to the four view pixels around that point with the
+ *      bilinear weights w sampling there would use (half-pixel centres;
+ *      taps outside the view are dropped, a point behind it adds nothing;
+ *      no normalisation), each layer into its own plane;
+ *   2. over composite of the projected planes, front to back (layer 0
+ *      nearest the novel camera): rgb += T P(sigma) P(a),
+ *      T *= 1 - P(sigma); acc = 1 - T.
+ * Float32 arithmetic (reprojection in double); the splat uses float atomics,
+ * so the order of the additions into a view pixel, and its last bits, vary
+ * from run to run.
+ *
+ *   V          number of views, 1..16; in_cams host [V]
+ *   novel      host; its K is rescaled to the LDM grid
+ *   ldm        device float32 depth, alpha [L][H][W], color [L][H][W][3];
+ *              depth > 0
+ *   views      host [V]: device rgb [Hm][Wm][3] float32 and acc [Hm][Wm]
+ *              float32 or NULL, with the view's grid
+ * Workspace: the projected planes, sum over views of L Hm Wm 4 floats, in
+ * the context (grown on demand like the others).
+ * Errors (nothing enqueued): QK_EINVAL (NULL or misaligned buffer, bad
+ * camera), QK_ESHAPE (non-positive dims, V out of range), QK_EUNSUPPORTED
+ * (an LDM or a workspace of 2^31 elements or more). */
+typedef struct {
+    const float *depth;   /* device [L][H][W] */
+    const float *alpha;   /* device [L][H][W] */
+    const float *color;   /* device [L][H][W][3] */
+    int32_t L, H, W;
+} qk_ldm_decoded;
+
+typedef struct {
+    float *rgb;           /* device [H][W][3] */
+    float *acc;           /* device [H][W] or NULL */
+    int32_t H, W;
+} qk_view_image;
+
+QK_API qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
+                                    const qk_camera *in_cams, const qk_camera *novel,
+                                    const qk_ldm_decoded *ldm, const qk_view_image *views);
+
+/* Dry run of qk_render_to_views's argument checks (no device use). */
+QK_API qk_status qk_render_to_views_check(int32_t V, const qk_camera *in_cams,
+                                          const qk_camera *novel, const qk_ldm_decoded *ldm,
+                                          const qk_view_image *views);
 
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);

@@ -22,6 +22,7 @@ hipError_t launch_composite(const CompParams &p, hipStream_t s);
 hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
 hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
+hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -33,6 +34,8 @@ struct qk_context {
     size_t bws_elems = 0;
     float *f8 = nullptr;         // e4m3 scales [7] + running maximum [1]
     size_t f8_elems = 0;
+    float *vws = nullptr;        // projected planes of the render to input views
+    size_t vws_elems = 0;
 };
 
 namespace {
@@ -361,6 +364,40 @@ qk_status check_render(int32_t V, const qk_camera *in_cams, const qk_image *imag
     return QK_OK;
 }
 
+qk_status check_views(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
+                      const qk_ldm_decoded *ldm, const qk_view_image *views, int64_t *ws_floats) {
+    if (!in_cams || !novel || !ldm || !views) return fail(QK_EINVAL, "NULL argument");
+    if (V < 1 || V > qk::kMaxViews)
+        return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (ldm->L < 1 || ldm->H < 1 || ldm->W < 1)
+        return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d)", ldm->L, ldm->H,
+                    ldm->W);
+    if ((int64_t)ldm->L * ldm->H * ldm->W * 3 >= ((int64_t)1 << 31))
+        return fail(QK_EUNSUPPORTED, "LDM of 2^31 elements or more");
+    if (!ldm->depth || !ldm->alpha || !ldm->color) return fail(QK_EINVAL, "NULL LDM buffer");
+    if (!aligned4(ldm->depth) || !aligned4(ldm->alpha) || !aligned4(ldm->color))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    int64_t total = 0;
+    for (int m = 0; m < V; ++m) {
+        char what[32];
+        snprintf(what, sizeof(what), "camera %d", m);
+        st = check_camera(&in_cams[m], what);
+        if (st != QK_OK) return st;
+        if (views[m].H < 1 || views[m].W < 1)
+            return fail(QK_ESHAPE, "view %d has grid %dx%d", m, views[m].W, views[m].H);
+        if (!views[m].rgb) return fail(QK_EINVAL, "view %d rgb is NULL", m);
+        if (!aligned4(views[m].rgb) || (views[m].acc && !aligned4(views[m].acc)))
+            return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+        total += (int64_t)ldm->L * views[m].H * views[m].W * 4;
+        if (total >= ((int64_t)1 << 31))
+            return fail(QK_EUNSUPPORTED, "projected planes of 2^31 floats or more");
+    }
+    if (ws_floats) *ws_floats = total;
+    return QK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -386,12 +423,13 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && (ctx->wfold || ctx->bws || ctx->f8)) {
+    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
         if (ctx->bws) (void)hipFree(ctx->bws);
         if (ctx->f8) (void)hipFree(ctx->f8);
+        if (ctx->vws) (void)hipFree(ctx->vws);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -737,6 +775,55 @@ qk_status qk_render_ibr(qk_context *ctx, void *hip_stream, int32_t V, const qk_c
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipError_t e = qk::launch_render_ibr(p, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "render launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_render_to_views_check(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
+                                   const qk_ldm_decoded *ldm, const qk_view_image *views) {
+    return check_views(V, in_cams, novel, ldm, views, nullptr);
+}
+
+qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
+                             const qk_camera *in_cams, const qk_camera *novel,
+                             const qk_ldm_decoded *ldm, const qk_view_image *views) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    int64_t total = 0;
+    qk_status st = check_views(V, in_cams, novel, ldm, views, &total);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    st = grow(&ctx->vws, &ctx->vws_elems, (size_t)total, stream);
+    if (st != QK_OK) return st;
+    qk::ViewsParams p;
+    std::memset(&p, 0, sizeof(p));
+    int64_t base = 0, maxpix = 0;
+    for (int m = 0; m < V; ++m) {
+        compose_table(novel, ldm->W, ldm->H, &in_cams[m], views[m].W, views[m].H, p.cam[m]);
+        p.vH[m] = views[m].H;
+        p.vW[m] = views[m].W;
+        p.sbase[m] = base;
+        p.rgb[m] = views[m].rgb;
+        p.acc[m] = views[m].acc;
+        const int64_t np = (int64_t)views[m].H * views[m].W;
+        base += (int64_t)ldm->L * np * 4;
+        maxpix = std::max(maxpix, np);
+    }
+    p.ws = ctx->vws;
+    p.ws_floats = total;
+    p.depth = ldm->depth;
+    p.alpha = ldm->alpha;
+    p.color = ldm->color;
+    p.V = V;
+    p.L = ldm->L;
+    p.H = ldm->H;
+    p.W = ldm->W;
+    p.N = (int64_t)ldm->L * ldm->H * ldm->W;
+    p.max_view_pixels = maxpix;
+    hipError_t e = qk::launch_render_to_views(p, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "render to views launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -141,3 +141,23 @@ struct RenderParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Render of a decoded intermediate LDM into the input views.
+struct ViewsParams {
+    double cam[kMaxViews][12];      // LDM grid -> view m's grid: A (9), b (3)
+    int32_t vH[kMaxViews], vW[kMaxViews];
+    int64_t sbase[kMaxViews];       // float offset of view m's [L][Hm][Wm][4] block in ws
+    float *rgb[kMaxViews];          // [Hm][Wm][3]
+    float *acc[kMaxViews];          // [Hm][Wm] or NULL
+    float *ws;                      // projected layers, all views
+    int64_t ws_floats;
+    const float *depth, *alpha;     // [L][H][W]
+    const float *color;             // [L][H][W][3]
+    int32_t V, L, H, W;
+    int64_t N;                      // L * H * W
+    int64_t max_view_pixels;
+};
+
+}  // namespace qk

@@ -28,7 +28,8 @@ MODE = {"residual": 0, "paper": 1}
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
-           "qk_composite", "qk_render_ibr", "qk_render_ibr_check",
+           "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
+           "qk_render_to_views_check",
            "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
@@ -55,6 +56,16 @@ class qk_ldm_logits(ctypes.Structure):
     _fields_ = [("depth_logit", ctypes.c_void_p), ("sigma_logit", ctypes.c_void_p),
                 ("blend_logit", ctypes.c_void_p), ("L", ctypes.c_int32), ("H", ctypes.c_int32),
                 ("W", ctypes.c_int32), ("V", ctypes.c_int32)]
+
+
+class qk_ldm_decoded(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("color", ctypes.c_void_p),
+                ("L", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class qk_view_image(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32)]
 
 
 class qk_ldm(ctypes.Structure):
@@ -115,10 +126,14 @@ def load() -> ctypes.CDLL:
                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.qk_render_ibr.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + render_args
     L.qk_render_ibr_check.argtypes = render_args
+    views_args = [ctypes.c_int32, P(qk_camera), P(qk_camera), P(qk_ldm_decoded), P(qk_view_image)]
+    L.qk_render_to_views.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + views_args
+    L.qk_render_to_views_check.argtypes = views_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
-                 "qk_render_ibr", "qk_render_ibr_check", "qk_camera_tables"):
+                 "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
+                 "qk_render_to_views_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -360,6 +375,33 @@ def render_ibr_check(in_cams, images, novel, near, far, logits, H, W, rgb_out, *
     args, keep = _render_args(in_cams, images, novel, near, far, logits, H, W, rgb_out, acc_out,
                               depth_out)
     return int(load().qk_render_ibr_check(*args))
+
+
+def _views_args(in_cams, novel, depth, alpha, color, rgb_outs, acc_outs):
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    L, H, W = (int(s) for s in depth.shape)
+    ld = qk_ldm_decoded(_ptr(depth), _ptr(alpha), _ptr(color), L, H, W)
+    accs = [None] * V if acc_outs is None else list(acc_outs)
+    views = (qk_view_image * V)(*[qk_view_image(_ptr(r), _ptr(a), int(r.shape[0]), int(r.shape[1]))
+                                  for r, a in zip(rgb_outs, accs)])
+    nov = make_camera(novel)
+    return (V, cams, ctypes.byref(nov), ctypes.byref(ld), views), (cams, ld, views, nov)
+
+
+def render_to_views(ctx: Context, in_cams, novel, depth, alpha, color, rgb_outs, acc_outs=None,
+                    stream=None):
+    """qk_render_to_views: depth, alpha [L][H][W], color [L][H][W][3] float32
+    device tensors; rgb_outs[m] [Hm][Wm][3] (sets view m's grid), acc_outs[m]
+    [Hm][Wm] or None."""
+    args, keep = _views_args(in_cams, novel, depth, alpha, color, rgb_outs, acc_outs)
+    _check(ctx._lib.qk_render_to_views(ctx.handle, _stream_handle(stream), *args))
+
+
+def render_to_views_check(in_cams, novel, depth, alpha, color, rgb_outs, acc_outs=None) -> int:
+    """qk_render_to_views_check: the status qk_render_to_views would return."""
+    args, keep = _views_args(in_cams, novel, depth, alpha, color, rgb_outs, acc_outs)
+    return int(load().qk_render_to_views_check(*args))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

@@ -289,3 +289,47 @@ def test_render_null_context_rejected_before_device_use():
     args, keep = lib._render_args(rs.in_cams, imgs, rs.novel, rs.near, rs.far, lg, 12, 20, rgb,
                                   None, None)
     assert lib.load().qk_render_ibr(None, None, *args) == lib.QK_EINVAL
+
+
+def _views_args(V=3, L=2, H=12, W=20, Hm=14, Wm=22):
+    vs = synth.make_views(V=V, W=W, H=H, L=L, view_hw=(Hm, Wm), seed=2)
+    d, a = _FakeT((L, H, W), 0x300000), _FakeT((L, H, W), 0x310000)
+    c = _FakeT((L, H, W, 3), 0x320000)
+    rgbs = [_FakeT((Hm, Wm, 3), 0x400000 + 0x10000 * m) for m in range(V)]
+    return vs, d, a, c, rgbs
+
+
+def test_views_valid_arguments_pass():
+    vs, d, a, c, rgbs = _views_args()
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, d, a, c, rgbs) == lib.QK_OK
+    accs = [_FakeT((14, 22), 0x500000 + 0x10000 * m) for m in range(3)]
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, d, a, c, rgbs, accs) == lib.QK_OK
+
+
+def test_views_rejections():
+    vs, d, a, c, rgbs = _views_args()
+    # misaligned LDM buffer, NULL colour, misaligned output
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, _FakeT(d.shape, d._addr + 2), a, c,
+                                     rgbs) == lib.QK_EINVAL
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, d, a, None, rgbs) == lib.QK_EINVAL
+    bad = list(rgbs)
+    bad[2] = _FakeT(rgbs[2].shape, rgbs[2]._addr + 1)
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, d, a, c, bad) == lib.QK_EINVAL
+    # empty view grid
+    bad[2] = _FakeT((0, 22, 3), rgbs[2]._addr)
+    assert lib.render_to_views_check(vs.in_cams, vs.novel, d, a, c, bad) == lib.QK_ESHAPE
+    # projected planes of 2^31 floats: 8 layers x 8192 x 8192 x 4
+    vs8, d8, a8, c8, _ = _views_args(V=1, L=8)
+    huge = [_FakeT((8192, 8192, 3), 0x400000)]
+    assert lib.render_to_views_check(vs8.in_cams[:1], vs8.novel, d8, a8, c8,
+                                     huge) == lib.QK_EUNSUPPORTED
+    # 17 views
+    vs17, d17, a17, c17, r17 = _views_args(V=17)
+    assert lib.render_to_views_check(vs17.in_cams, vs17.novel, d17, a17, c17,
+                                     r17) == lib.QK_ESHAPE
+
+
+def test_views_null_context_rejected_before_device_use():
+    vs, d, a, c, rgbs = _views_args()
+    args, keep = lib._views_args(vs.in_cams, vs.novel, d, a, c, rgbs, None)
+    assert lib.load().qk_render_to_views(None, None, *args) == lib.QK_EINVAL

@@ -1,0 +1,131 @@
+"""Parity of the render to input views (qk_render_to_views: projection of a
+decoded intermediate LDM into every view by a bilinear splat, per-view
+composite) against the FP64 oracle, through the C-ABI.
+
+Bar, per view pixel: |error| <= 1e-4 + 1e-5 M, M = sum over layers of
+|T_l| |P(sigma_l)| max|P(a_l)| (for the accumulated alpha: |T_l| |P(sigma_l)|)
+-- the magnitudes the composite adds up.  The splat is unnormalised, so
+where several layer-pixels crowd into one view pixel P(sigma) exceeds 1, T
+changes sign and grows, and the float32 rounding of the weights, payloads
+and atomic sums (each ~1e-7 relative, a few dozen per pixel) scales with M
+rather than with the result; positions are computed in double."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_16680_amd import lib, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _say(*a):
+    print("[views]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib.Context(0)
+
+
+def _gpu(ctx, vs, cams=None):
+    cams = vs.in_cams if cams is None else cams
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    d, a, c = dev(vs.depth), dev(vs.alpha), dev(vs.color)
+    rgbs = [torch.full((h, w, 3), float("nan"), device="cuda") for h, w in vs.view_hw]
+    accs = [torch.full((h, w), float("nan"), device="cuda") for h, w in vs.view_hw]
+    lib.render_to_views(ctx, cams, vs.novel, d, a, c, rgbs, accs)
+    torch.cuda.synchronize()
+    return [r.cpu().numpy() for r in rgbs], [x.cpu().numpy() for x in accs]
+
+
+def _magnitudes(vs, cams, m):
+    """Per view pixel: the sums of |terms| of the colour and alpha composites."""
+    L, H, W = vs.depth.shape
+    Hm, Wm = vs.view_hw[m]
+    nov, cam = vs.novel, cams[m]
+    Kn = oracle.scale_intrinsics(nov.K, nov.width, nov.height, W, H)
+    Km = oracle.scale_intrinsics(cam.K, cam.width, cam.height, Wm, Hm)
+    T = oracle.reprojection_matrix(Kn, nov.E, Km, cam.E)
+    Tr = np.ones((Hm, Wm))
+    Mc, Ma = np.zeros((Hm, Wm)), np.zeros((Hm, Wm))
+    for l in range(L):
+        pc = oracle.splat_layer(T, vs.depth[l], vs.color[l], Hm, Wm)
+        ps = oracle.splat_layer(T, vs.depth[l], vs.alpha[l], Hm, Wm)
+        Mc += np.abs(Tr) * np.abs(ps) * np.abs(pc).max(axis=-1)
+        Ma += np.abs(Tr) * np.maximum(np.abs(ps), 1.0)
+        Tr = Tr * (1 - ps)
+    return Mc, Ma
+
+
+def _compare(name, ctx, vs, cams=None):
+    cams = vs.in_cams if cams is None else cams
+    rgbs, accs = _gpu(ctx, vs, cams)
+    ref = oracle.render_to_views(cams, vs.novel, vs.depth, vs.alpha, vs.color, vs.view_hw)
+    worst_rgb = worst_acc = 0.0
+    for m in range(vs.V):
+        Mc, Ma = _magnitudes(vs, cams, m)
+        e_rgb = np.abs(rgbs[m] - ref["img"][m]).max(axis=-1)
+        e_acc = np.abs(accs[m] - ref["acc"][m])
+        worst_rgb = max(worst_rgb, float(np.max(e_rgb / (TOL + 1e-5 * Mc))))
+        worst_acc = max(worst_acc, float(np.max(e_acc / (TOL + 1e-5 * Ma))))
+    e_max = max(float(np.max(np.abs(g - r))) for g, r in zip(rgbs, ref["img"]))
+    _say(name, f"rgb max-abs {e_max:.3g}; error / bound: rgb {worst_rgb:.3g} acc {worst_acc:.3g}")
+    assert all(np.all(np.isfinite(g)) for g in rgbs)
+    assert worst_rgb <= 1.0 and worst_acc <= 1.0, (name, worst_rgb, worst_acc)
+    return rgbs, ref
+
+
+CASES = {
+    "small-V3": dict(V=3, W=36, H=20, L=3, seed=21),
+    "ragged-53x37-V5-L4": dict(V=5, W=53, H=37, L=4, view_hw=(41, 61), seed=3),
+    "coarser-views": dict(V=4, W=64, H=36, L=3, view_hw=(15, 27), seed=4),
+    "finer-views": dict(V=2, W=30, H=17, L=2, view_hw=(51, 90), seed=5),
+    "wide-fov-behind": dict(V=6, W=64, H=36, L=3, arc=4.0, hfov=140.0, seed=9),
+    "max-views-V16": dict(V=16, W=40, H=24, L=2, seed=10),
+    "one-layer": dict(V=2, W=48, H=32, L=1, seed=11),
+    "one-view": dict(V=1, W=48, H=32, L=3, seed=12),
+    "single-pixel-ldm": dict(V=3, W=1, H=1, L=2, view_hw=(7, 9), seed=13),
+    "smooth-depth": dict(V=4, W=96, H=54, L=4, depth_mode="smooth", seed=14),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_views_parity(ctx, name):
+    vs = synth.make_views(**CASES[name])
+    _say("case", name, f"V={vs.V} ldm {vs.depth.shape} views {vs.view_hw[0]}")
+    _compare(name, ctx, vs)
+
+
+def test_identity_camera_is_the_composite(ctx):
+    vs = synth.make_views(V=1, W=40, H=24, L=3, seed=15)
+    nov = vs.novel
+    cam = synth.Camera(nov.K.copy(), nov.E.copy(), nov.width, nov.height)
+    rgbs, _ = _compare("identity-camera", ctx, vs, cams=[cam])
+    rgb, _ = oracle.composite(vs.color, vs.alpha)
+    assert np.max(np.abs(rgbs[0] - rgb)) <= TOL
+
+
+def test_views_full_size(ctx):
+    """The benchmark's configuration: a 1920x1080 LDM of 4 layers rendered
+    into 8 views of 1920x1080."""
+    vs = synth.make_views()
+    _compare("1080p-L4-V8", ctx, vs)
+
+
+def test_workspace_reuse_smaller_then_larger(ctx):
+    """The context's workspace is grown on demand and cleared per call: a
+    large call, a smaller one, then the large one again."""
+    big = synth.make_views(V=3, W=64, H=40, L=3, seed=16)
+    small = synth.make_views(V=2, W=20, H=12, L=2, seed=17)
+    _compare("reuse-big", ctx, big)
+    _compare("reuse-small", ctx, small)
+    _compare("reuse-big-again", ctx, big)
