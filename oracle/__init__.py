@@ -273,6 +273,21 @@ def render_to_views(in_cams, novel, depth, alpha, color, view_hw) -> Dict[str, l
 
 
 # --------------------------------------------------------------------------
+# Residual CNN block of a fusion block
+# --------------------------------------------------------------------------
+
+def residual_conv(F, W1, W2) -> np.ndarray:
+    """V' = V + W2 * relu(W1 * V) per layer: F [L][H][W][C] (float32, or
+    bfloat16 bit patterns), W1, W2 [3][3][C][C]."""
+    F = _as_f64_array(F)
+    W1, W2 = _f64(W1), _f64(W2)
+    L, H, W, C = F.shape
+    out = np.zeros_like(F)
+    lib().or_residual_conv(L, H, W, C, _d(F), _d(W1), _d(W2), _d(out))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Whole step over a scene level
 # --------------------------------------------------------------------------
 

@@ -729,6 +729,53 @@ OR_EXPORT int or_render_to_views(int V, const double *Kin, const double *Ein, co
     return err;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Residual CNN block of a fusion block (Sec. 3.2.2 "Iterative Updates": each */
+/* fusion block follows its attention with one or more residual CNNs that    */
+/* update the encoded LDM; the network tables of the appendix list them).   */
+/* Per LDM layer, over the layer's (H, W) grid: two 3x3 convolutions C -> C  */
+/* with zero padding and a ReLU between them, added to the input:            */
+/*   V' = V + W2 * relu(W1 * V),                                             */
+/* out(y, x)[co] = sum_{ky, kx, ci} in(y + ky - 1, x + kx - 1)[ci] W[ky][kx][ci][co]. */
+/* No biases, no normalisation.                                              */
+/* ------------------------------------------------------------------------ */
+
+static void conv3x3(const double *in, int H, int W, int C, const double *Wt, double *out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double *o = out + ((size_t)y * W + x) * C;
+            for (int co = 0; co < C; ++co) o[co] = 0.0;
+            for (int ky = 0; ky < 3; ++ky)
+                for (int kx = 0; kx < 3; ++kx) {
+                    int yy = y + ky - 1, xx = x + kx - 1;
+                    if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;   /* zero padding */
+                    const double *i = in + ((size_t)yy * W + xx) * C;
+                    const double *w = Wt + (size_t)(ky * 3 + kx) * C * C;
+                    for (int ci = 0; ci < C; ++ci)
+                        for (int co = 0; co < C; ++co) o[co] += i[ci] * w[(size_t)ci * C + co];
+                }
+        }
+}
+
+/* F, out [L][H][W][C]; W1, W2 [3][3][C][C]. */
+OR_EXPORT void or_residual_conv(int L, int H, int W, int C, const double *F, const double *W1,
+                                const double *W2, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int l = 0; l < L; ++l) {
+        size_t n = (size_t)H * W * C, off = (size_t)l * n;
+        double *h = malloc(sizeof(double) * n);
+        double *g = malloc(sizeof(double) * n);
+        conv3x3(F + off, H, W, C, W1, h);
+        for (size_t i = 0; i < n; ++i) h[i] = h[i] > 0.0 ? h[i] : 0.0;
+        conv3x3(h, H, W, C, W2, g);
+        for (size_t i = 0; i < n; ++i) out[off + i] = F[off + i] + g[i];
+        free(h);
+        free(g);
+    }
+}
+
 OR_EXPORT int or_num_threads(void)
 {
 #ifdef _OPENMP

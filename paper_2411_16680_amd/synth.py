@@ -447,6 +447,23 @@ def make_views(*, V: int = 8, W: int = 1920, H: int = 1080, L: int = 4,
     return ViewsScene(in_cams, novel, near, far, depth, alpha, color, vhw)
 
 
+# ----------------------------------------------------------------------------
+# Residual CNN block workload: a feature volume and two 3x3 kernels
+# ----------------------------------------------------------------------------
+
+def make_conv_block(*, L: int = 16, H: int = 270, W: int = 480, C: int = 32, seed: int = 1008,
+                    dtype: str = "bf16"):
+    """A feature volume [L][H][W][C] N(0, 1) (bfloat16 bits or float32) and
+    two kernels [3][3][C][C] N(0, 1/sqrt(9 C)) (std = 1/sqrt(fan_in)).
+    Returns (F, W1, W2).  Draw order: F, W1, W2."""
+    rng = np.random.default_rng(seed)
+    F = _cast(_normal(rng, (L, H, W, C)), dtype)
+    std = 1.0 / math.sqrt(9.0 * C)
+    W1 = _normal(rng, (3, 3, C, C), std)
+    W2 = _normal(rng, (3, 3, C, C), std)
+    return F, W1, W2
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""
