@@ -318,6 +318,49 @@ def time_views(ctx, reps: int = 20):
                          "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_call": nbytes}}
 
 
+CONV_WORKLOAD = ("residual CNN block of a fusion block: two 3x3 convolutions 32 -> 32 with a "
+                 "ReLU, per layer, on a bfloat16 feature volume of 16 layers of 480x270")
+
+
+def time_conv(ctx, reps: int = 50):
+    """The residual CNN block on the multi-scale workload's 480x270 level
+    (16 layers, C = 32): average launch time with HIP events on its stream,
+    and its roofline against whichever bound its intensity selects."""
+    import torch
+    from paper_2411_16680_amd import lib, synth
+    F, W1, W2 = synth.make_conv_block()
+    Fd = torch.from_numpy(F.view(np.int16)).cuda().view(torch.bfloat16)
+    out = torch.empty_like(Fd)
+    w1, w2 = torch.from_numpy(W1).cuda(), torch.from_numpy(W2).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lib.residual_conv(ctx, Fd, w1, w2, out, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lib.residual_conv(ctx, Fd, w1, w2, out, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    L, H, W, C = F.shape
+    px = L * H * W
+    flops = px * 2 * (2 * 9 * C * C)
+    nbytes = px * C * 2 * 2
+    s_ = ms / 1000.0
+    intensity = flops / nbytes
+    ridge = MFMA_BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": nbytes / s_ / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": flops / s_ / 1e12, "peak": MFMA_BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"algorithmic_bytes_per_launch": nbytes, "algorithmic_flops_per_launch": flops,
+                 "mfma_tflops": flops / s_ / 1e12})
+    return {"workload": CONV_WORKLOAD, "avg_launch_ms": ms, "roofline": roof}
+
+
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
     """The standalone front-to-back composite (qk_composite) over a 1080p LDM
     of L layers: its average launch time with HIP events on its stream and
@@ -545,6 +588,11 @@ def main():
         f"({views['roofline']['achieved']:.0f} GB/s of compulsory bytes)")
     torch.cuda.empty_cache()
 
+    conv = time_conv(ctx)
+    log(f"residual CNN block: {conv['avg_launch_ms'] * 1000:.1f} us, "
+        f"{conv['roofline']['mfma_tflops']:.0f} TFLOP/s")
+    torch.cuda.empty_cache()
+
     composite = time_composite(ctx)
     log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
         f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
@@ -618,6 +666,7 @@ def main():
         "composite_roofline": composite,
         "final_render": render,
         "render_to_views": views,
+        "residual_conv": conv,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,

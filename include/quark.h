@@ -379,6 +379,29 @@ QK_API qk_status qk_render_to_views_check(int32_t V, const qk_camera *in_cams,
                                           const qk_camera *novel, const qk_ldm_decoded *ldm,
                                           const qk_view_image *views);
 
+/* ---- Residual CNN block of a fusion block (Sec. 3.2.2, "Iterative
+ * Updates": each fusion block follows its attention with residual CNNs
+ * that update the encoded LDM) ----
+ * Per layer l, over the layer's (H, W) grid, with zero padding:
+ *   F_out = F + W2 * relu(W1 * F),
+ *   (W * X)(y, x)[co] = sum_{ky, kx, ci} X(y + ky - 1, x + kx - 1)[ci] W[ky][kx][ci][co].
+ * bfloat16 feature volumes, MFMA bfloat16 operands with float32
+ * accumulation; the ReLU output is rounded to bfloat16 as the second
+ * convolution's operand; the sum is rounded to bfloat16 once.
+ *   ldm_in, ldm_out  F [L][H][W][32] bfloat16 (depth, alpha unused; may be
+ *                    NULL); ldm_out must not overlap ldm_in
+ *   W1, W2           device float32 [3][3][32][32]
+ * Workspace: the kernels' bfloat16 fragments (36 KiB) in the context.
+ * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned or overlapping
+ * buffers), QK_ESHAPE (dims), QK_EDTYPE (not bfloat16), QK_EUNSUPPORTED
+ * (C != 32). */
+QK_API qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *ldm_in,
+                                  const float *W1, const float *W2, const qk_ldm *ldm_out);
+
+/* Dry run of qk_residual_conv's argument checks (no device use). */
+QK_API qk_status qk_residual_conv_check(const qk_ldm *ldm_in, const float *W1, const float *W2,
+                                        const qk_ldm *ldm_out);
+
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);
 

@@ -23,6 +23,7 @@ hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
 hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
 hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
+hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -36,6 +37,8 @@ struct qk_context {
     size_t f8_elems = 0;
     float *vws = nullptr;        // projected planes of the render to input views
     size_t vws_elems = 0;
+    float *cfrag = nullptr;      // bfloat16 fragments of the residual block's kernels
+    size_t cfrag_elems = 0;
 };
 
 namespace {
@@ -398,6 +401,28 @@ qk_status check_views(int32_t V, const qk_camera *in_cams, const qk_camera *nove
     return QK_OK;
 }
 
+qk_status check_conv(const qk_ldm *in, const float *W1, const float *W2, const qk_ldm *out) {
+    if (!in || !out || !W1 || !W2) return fail(QK_EINVAL, "NULL argument");
+    if (in->L < 1 || in->H < 1 || in->W < 1)
+        return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d)", in->L, in->H, in->W);
+    if (in->C != 32) return fail(QK_EUNSUPPORTED, "the residual block supports C = 32 (got %d)", in->C);
+    if (in->dtype != QK_BF16 || out->dtype != QK_BF16)
+        return fail(QK_EDTYPE, "the residual block takes bfloat16 feature volumes");
+    if (out->L != in->L || out->H != in->H || out->W != in->W || out->C != in->C)
+        return fail(QK_ESHAPE, "ldm_out dims differ from ldm_in");
+    if (!in->F || !out->F) return fail(QK_EINVAL, "NULL feature volume");
+    if (!aligned16(in->F) || !aligned16(out->F))
+        return fail(QK_EINVAL, "feature volumes must be 16-byte aligned");
+    if (!aligned4(W1) || !aligned4(W2)) return fail(QK_EINVAL, "weights must be 4-byte aligned");
+    const int64_t elems = (int64_t)in->L * in->H * in->W * in->C;
+    if (elems >= ((int64_t)1 << 40)) return fail(QK_EUNSUPPORTED, "feature volume too large");
+    const char *a = static_cast<const char *>(in->F), *b = static_cast<const char *>(out->F);
+    const int64_t bytes = elems * 2;
+    if (a < b + bytes && b < a + bytes)
+        return fail(QK_EINVAL, "ldm_out must not overlap ldm_in (tiles read their neighbours)");
+    return QK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -423,13 +448,14 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws)) {
+    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
         if (ctx->bws) (void)hipFree(ctx->bws);
         if (ctx->f8) (void)hipFree(ctx->f8);
         if (ctx->vws) (void)hipFree(ctx->vws);
+        if (ctx->cfrag) (void)hipFree(ctx->cfrag);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -824,6 +850,41 @@ qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
     p.max_view_pixels = maxpix;
     hipError_t e = qk::launch_render_to_views(p, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "render to views launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_residual_conv_check(const qk_ldm *ldm_in, const float *W1, const float *W2,
+                                 const qk_ldm *ldm_out) {
+    return check_conv(ldm_in, W1, W2, ldm_out);
+}
+
+qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *in, const float *W1,
+                           const float *W2, const qk_ldm *out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_conv(in, W1, W2, out);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    st = grow(&ctx->cfrag, &ctx->cfrag_elems, 2 * 9 * 2 * 64 * 4, stream);
+    if (st != QK_OK) return st;
+    qk::ConvParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.F = static_cast<const uint16_t *>(in->F);
+    p.F_out = static_cast<uint16_t *>(out->F);
+    p.W1 = W1;
+    p.W2 = W2;
+    p.frag = reinterpret_cast<uint4 *>(ctx->cfrag);
+    p.L = in->L;
+    p.H = in->H;
+    p.W = in->W;
+    p.tiles_x = (in->W + 15) / 16;
+    p.tiles_y = (in->H + 7) / 8;
+    p.n_tiles = (int64_t)in->L * p.tiles_x * p.tiles_y;
+    hipError_t e = qk::launch_residual_conv(p, ctx->num_cu, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "residual block launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -1,0 +1,157 @@
+// k_conv.hip -- residual CNN block of a fusion block (Sec. 3.2.2: each fusion
+// block follows its attention with residual CNNs that update the encoded
+// LDM): per layer, F_out = F + W2 * relu(W1 * F) with 3x3 kernels and zero
+// padding, C = 32 channels, bfloat16 storage and MFMA operands, float32
+// accumulation.
+//
+// An implicit GEMM on v_mfma_f32_16x16x32_bf16: for each of the 9 taps, the
+// A operand is the tap's W^T (16 output channels x 32 input channels, one
+// fragment per half of the outputs) and the B operand 16 pixels x 32 input
+// channels -- one 16-byte LDS read per lane, since pixels are channel-last.
+// A persistent workgroup keeps both kernels' fragments in LDS and walks
+// 16 x 8 output tiles: it stages the 20 x 12 input region (2-pixel halo,
+// zeros outside the image), computes the first convolution on the 18 x 10
+// region the second one needs (ReLU, zeros outside the image -- the second
+// convolution pads with zeros too -- rounded to bfloat16 as its operand),
+// then the second convolution, adds the input and stores bfloat16.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "uf_params.h"
+
+namespace qk {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 32, TX = 16, TY = 8;
+constexpr int IX = TX + 4, IY = TY + 4;          // staged input region
+constexpr int MX = TX + 2, MY = TY + 2;          // first convolution's region
+constexpr int NMID = MX * MY;                    // 180 pixels
+constexpr int MID_TILES = (NMID + 15) / 16;      // 12 pixel tiles of 16
+constexpr int NFRAG = 2 * 9 * 2 * 64;            // [conv][tap][half of C_out][lane]
+
+__device__ inline f32x4 mma(const uint4 &a, const uint4 &b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// Weight fragments: lane (c, g) of fragment (conv, tap, half) holds
+// W[tap][8g .. 8g+7][16 half + c] (input channels along K).
+__global__ void __launch_bounds__(256) k_conv_frag(const ConvParams p) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= NFRAG) return;
+    const int lane = i & 63, half = (i >> 6) & 1, tap = (i >> 7) % 9, conv = (i >> 7) / 9;
+    const float *Wm = conv ? p.W2 : p.W1;
+    const int c = lane & 15, g = lane >> 4;
+    bf16x8 v;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (__bf16)Wm[(tap * kC + 8 * g + k) * kC + 16 * half + c];
+    p.frag[i] = __builtin_bit_cast(uint4, v);
+}
+
+__global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
+    __shared__ uint4 s_w[NFRAG];                 // 36 KiB
+    __shared__ uint4 s_in[IY * IX * 4];          // 15 KiB: [row][col][4 x 8 channels]
+    __shared__ uint4 s_mid[NMID * 4];            // 11.25 KiB
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    for (int i = tid; i < NFRAG; i += 256) s_w[i] = p.frag[i];
+    const int64_t per_layer = (int64_t)p.tiles_x * p.tiles_y;
+    uint16_t *mid16 = reinterpret_cast<uint16_t *>(s_mid);
+    const uint16_t *in16 = reinterpret_cast<const uint16_t *>(s_in);
+
+    for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
+        const int l = (int)(t / per_layer);
+        const int rem = (int)(t - (int64_t)l * per_layer);
+        const int ty = rem / p.tiles_x, tx = rem - ty * p.tiles_x;
+        const int x0 = tx * TX, y0 = ty * TY;
+        const uint16_t *Fl = p.F + (int64_t)l * p.H * p.W * kC;
+        __syncthreads();                         // weights in; the previous tile is done
+
+        for (int i = tid; i < IY * IX * 4; i += 256) {
+            const int pix = i >> 2, q = i & 3;
+            const int r = pix / IX, c = pix - r * IX;
+            const int y = y0 - 2 + r, x = x0 - 2 + c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < p.H && x >= 0 && x < p.W)
+                v = *reinterpret_cast<const uint4 *>(Fl + ((int64_t)y * p.W + x) * kC + 8 * q);
+            s_in[i] = v;
+        }
+        __syncthreads();
+
+        // first convolution on the 18 x 10 region, 16 pixels per MFMA column block
+        for (int mt = wave; mt < MID_TILES; mt += 4) {
+            const int pm = 16 * mt + n;
+            const int pmc = pm < NMID ? pm : 0;
+            const int mr = pmc / MX, mc = pmc - mr * MX;
+            f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+                const uint4 b = s_in[((mr + dy) * IX + (mc + dx)) * 4 + g];
+                a0 = mma(s_w[(tap * 2 + 0) * 64 + lane], b, a0);
+                a1 = mma(s_w[(tap * 2 + 1) * 64 + lane], b, a1);
+            }
+            if (pm < NMID) {
+                const int y = y0 - 1 + mr, x = x0 - 1 + mc;
+                const bool inside = y >= 0 && y < p.H && x >= 0 && x < p.W;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    mid16[pm * kC + 4 * g + i] = inside ? f2bf(fmaxf(a0[i], 0.0f)) : (uint16_t)0;
+                    mid16[pm * kC + 16 + 4 * g + i] = inside ? f2bf(fmaxf(a1[i], 0.0f)) : (uint16_t)0;
+                }
+            }
+        }
+        __syncthreads();
+
+        // second convolution, residual, store: output rows 2 wave, 2 wave + 1
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int r = 2 * wave + rr;
+            f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+                const uint4 b = s_mid[((r + dy) * MX + (n + dx)) * 4 + g];
+                a0 = mma(s_w[((9 + tap) * 2 + 0) * 64 + lane], b, a0);
+                a1 = mma(s_w[((9 + tap) * 2 + 1) * 64 + lane], b, a1);
+            }
+            const int y = y0 + r, x = x0 + n;
+            if (y < p.H && x < p.W) {
+                const uint16_t *res = in16 + ((r + 2) * IX + n + 2) * kC;
+                uint16_t o0[4], o1[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    o0[i] = f2bf(a0[i] + bf2f(res[4 * g + i]));
+                    o1[i] = f2bf(a1[i] + bf2f(res[16 + 4 * g + i]));
+                }
+                uint16_t *dst = p.F_out + (((int64_t)l * p.H + y) * p.W + x) * kC;
+                *reinterpret_cast<uint2 *>(dst + 4 * g) =
+                    make_uint2(o0[0] | ((unsigned)o0[1] << 16), o0[2] | ((unsigned)o0[3] << 16));
+                *reinterpret_cast<uint2 *>(dst + 16 + 4 * g) =
+                    make_uint2(o1[0] | ((unsigned)o1[1] << 16), o1[2] | ((unsigned)o1[3] << 16));
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_frag, dim3((NFRAG + 255) / 256), dim3(256), 0, s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t blocks = 2 * (int64_t)(num_cu > 0 ? num_cu : 256);
+    if (blocks > p.n_tiles) blocks = p.n_tiles;
+    hipLaunchKernelGGL(k_residual_conv, dim3((unsigned)blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace qk

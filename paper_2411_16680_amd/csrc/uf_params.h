@@ -161,3 +161,19 @@ struct ViewsParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Residual CNN block of a fusion block: F_out = F + W2 * relu(W1 * F), 3x3
+// kernels, per layer, bfloat16 storage, C = 32.
+struct ConvParams {
+    const uint16_t *F;              // [L][H][W][32] bfloat16
+    uint16_t *F_out;                // [L][H][W][32] bfloat16
+    const float *W1, *W2;           // [3][3][32][32] float32 masters
+    uint4 *frag;                    // workspace: bf16 weight fragments [2][9][2][64]
+    int32_t L, H, W;
+    int32_t tiles_x, tiles_y;       // 16 x 8 output tiles per layer
+    int64_t n_tiles;
+};
+
+}  // namespace qk

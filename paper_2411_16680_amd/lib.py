@@ -29,7 +29,7 @@ MODE = {"residual": 0, "paper": 1}
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
-           "qk_render_to_views_check",
+           "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
            "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
@@ -129,11 +129,15 @@ def load() -> ctypes.CDLL:
     views_args = [ctypes.c_int32, P(qk_camera), P(qk_camera), P(qk_ldm_decoded), P(qk_view_image)]
     L.qk_render_to_views.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + views_args
     L.qk_render_to_views_check.argtypes = views_args
+    conv_args = [P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, P(qk_ldm)]
+    L.qk_residual_conv.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + conv_args
+    L.qk_residual_conv_check.argtypes = conv_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
-                 "qk_render_to_views_check", "qk_camera_tables"):
+                 "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
+                 "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -402,6 +406,25 @@ def render_to_views_check(in_cams, novel, depth, alpha, color, rgb_outs, acc_out
     """qk_render_to_views_check: the status qk_render_to_views would return."""
     args, keep = _views_args(in_cams, novel, depth, alpha, color, rgb_outs, acc_outs)
     return int(load().qk_render_to_views_check(*args))
+
+
+def _volume(F) -> qk_ldm:
+    L, H, W, C = (int(s) for s in F.shape)
+    return qk_ldm(_ptr(F), None, None, L, H, W, C, _dtype_code(F))
+
+
+def residual_conv(ctx: Context, F_in, W1, W2, F_out, stream=None):
+    """qk_residual_conv: F_out = F_in + W2 * relu(W1 * F_in) per layer;
+    F_in, F_out [L][H][W][32] bfloat16 device tensors, W1, W2 [3][3][32][32]
+    float32."""
+    a, b = _volume(F_in), _volume(F_out)
+    _check(ctx._lib.qk_residual_conv(ctx.handle, _stream_handle(stream), ctypes.byref(a),
+                                     _ptr(W1), _ptr(W2), ctypes.byref(b)))
+
+
+def residual_conv_check(F_in, W1, W2, F_out) -> int:
+    a, b = _volume(F_in), _volume(F_out)
+    return int(load().qk_residual_conv_check(ctypes.byref(a), _ptr(W1), _ptr(W2), ctypes.byref(b)))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

@@ -333,3 +333,24 @@ def test_views_null_context_rejected_before_device_use():
     vs, d, a, c, rgbs = _views_args()
     args, keep = lib._views_args(vs.in_cams, vs.novel, d, a, c, rgbs, None)
     assert lib.load().qk_render_to_views(None, None, *args) == lib.QK_EINVAL
+
+
+def test_residual_conv_checks():
+    import torch
+    F = _FakeT((2, 9, 13, 32), 0x300000, torch.bfloat16)
+    out = _FakeT((2, 9, 13, 32), 0x900000, torch.bfloat16)
+    W1, W2 = _FakeT((3, 3, 32, 32), 0x600000), _FakeT((3, 3, 32, 32), 0x610000)
+    assert lib.residual_conv_check(F, W1, W2, out) == lib.QK_OK
+    # C other than 32, float32 volume, differing dims, overlap, misalignment, NULL
+    assert lib.residual_conv_check(_FakeT((2, 9, 13, 16), 0x300000, torch.bfloat16), W1, W2,
+                                   _FakeT((2, 9, 13, 16), 0x900000, torch.bfloat16)) == lib.QK_EUNSUPPORTED
+    assert lib.residual_conv_check(_FakeT((2, 9, 13, 32), 0x300000), W1, W2,
+                                   _FakeT((2, 9, 13, 32), 0x900000)) == lib.QK_EDTYPE
+    assert lib.residual_conv_check(F, W1, W2, _FakeT((2, 9, 12, 32), 0x900000,
+                                                     torch.bfloat16)) == lib.QK_ESHAPE
+    assert lib.residual_conv_check(F, W1, W2, _FakeT((2, 9, 13, 32), 0x300000 + 64,
+                                                     torch.bfloat16)) == lib.QK_EINVAL
+    assert "overlap" in lib.load().qk_last_error().decode()
+    assert lib.residual_conv_check(_FakeT((2, 9, 13, 32), 0x300008, torch.bfloat16), W1, W2,
+                                   out) == lib.QK_EINVAL
+    assert lib.residual_conv_check(F, None, W2, out) == lib.QK_EINVAL
