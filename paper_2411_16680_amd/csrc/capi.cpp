@@ -880,9 +880,6 @@ qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *in, 
     p.L = in->L;
     p.H = in->H;
     p.W = in->W;
-    p.tiles_x = (in->W + 15) / 16;
-    p.tiles_y = (in->H + 7) / 8;
-    p.n_tiles = (int64_t)in->L * p.tiles_x * p.tiles_y;
     hipError_t e = qk::launch_residual_conv(p, ctx->num_cu, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "residual block launch: %s", hipGetErrorString(e));
     return QK_OK;

@@ -58,8 +58,10 @@ __global__ void __launch_bounds__(256) k_conv_frag(const ConvParams p) {
 
 __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
     __shared__ uint4 s_w[NFRAG];                 // 36 KiB
-    __shared__ uint4 s_in[IY * IX * 4];          // 15 KiB: [row][col][4 x 8 channels]
-    __shared__ uint4 s_mid[NMID * 4];            // 11.25 KiB
+    // pixels are 5 16-byte chunks apart (4 used): a stride of 80 bytes
+    // spreads a column block's 16-byte operand reads over the LDS banks
+    __shared__ uint4 s_in[IY * IX * 5];          // 18.75 KiB: [row][col][8-channel chunk]
+    __shared__ uint4 s_mid[NMID * 5];            // 14 KiB
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
     for (int i = tid; i < NFRAG; i += 256) s_w[i] = p.frag[i];
@@ -82,7 +84,7 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (y >= 0 && y < p.H && x >= 0 && x < p.W)
                 v = *reinterpret_cast<const uint4 *>(Fl + ((int64_t)y * p.W + x) * kC + 8 * q);
-            s_in[i] = v;
+            s_in[pix * 5 + q] = v;
         }
         __syncthreads();
 
@@ -95,7 +97,7 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-                const uint4 b = s_in[((mr + dy) * IX + (mc + dx)) * 4 + g];
+                const uint4 b = s_in[((mr + dy) * IX + (mc + dx)) * 5 + g];
                 a0 = mma(s_w[(tap * 2 + 0) * 64 + lane], b, a0);
                 a1 = mma(s_w[(tap * 2 + 1) * 64 + lane], b, a1);
             }
@@ -104,8 +106,8 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
                 const bool inside = y >= 0 && y < p.H && x >= 0 && x < p.W;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    mid16[pm * kC + 4 * g + i] = inside ? f2bf(fmaxf(a0[i], 0.0f)) : (uint16_t)0;
-                    mid16[pm * kC + 16 + 4 * g + i] = inside ? f2bf(fmaxf(a1[i], 0.0f)) : (uint16_t)0;
+                    mid16[pm * 40 + 4 * g + i] = inside ? f2bf(fmaxf(a0[i], 0.0f)) : (uint16_t)0;
+                    mid16[pm * 40 + 16 + 4 * g + i] = inside ? f2bf(fmaxf(a1[i], 0.0f)) : (uint16_t)0;
                 }
             }
         }
@@ -119,13 +121,13 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-                const uint4 b = s_mid[((r + dy) * MX + (n + dx)) * 4 + g];
+                const uint4 b = s_mid[((r + dy) * MX + (n + dx)) * 5 + g];
                 a0 = mma(s_w[((9 + tap) * 2 + 0) * 64 + lane], b, a0);
                 a1 = mma(s_w[((9 + tap) * 2 + 1) * 64 + lane], b, a1);
             }
             const int y = y0 + r, x = x0 + n;
             if (y < p.H && x < p.W) {
-                const uint16_t *res = in16 + ((r + 2) * IX + n + 2) * kC;
+                const uint16_t *res = in16 + ((r + 2) * IX + n + 2) * 40;
                 uint16_t o0[4], o1[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -144,7 +146,11 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
 
 }  // namespace
 
-hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s) {
+hipError_t launch_residual_conv(const ConvParams &pin, int num_cu, hipStream_t s) {
+    ConvParams p = pin;
+    p.tiles_x = (p.W + TX - 1) / TX;
+    p.tiles_y = (p.H + TY - 1) / TY;
+    p.n_tiles = (int64_t)p.L * p.tiles_x * p.tiles_y;
     hipLaunchKernelGGL(k_conv_frag, dim3((NFRAG + 255) / 256), dim3(256), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -172,7 +172,7 @@ struct ConvParams {
     const float *W1, *W2;           // [3][3][32][32] float32 masters
     uint4 *frag;                    // workspace: bf16 weight fragments [2][9][2][64]
     int32_t L, H, W;
-    int32_t tiles_x, tiles_y;       // 16 x 8 output tiles per layer
+    int32_t tiles_x, tiles_y;       // output tiles per layer (set by the launcher)
     int64_t n_tiles;
 };
 
