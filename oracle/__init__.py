@@ -287,6 +287,17 @@ def residual_conv(F, W1, W2) -> np.ndarray:
     return out
 
 
+def layer_collapse(F, W1, W2) -> np.ndarray:
+    """out[j] = (F[2j] + F[2j+1]) / 2 + relu([F[2j], F[2j+1]] W1) W2: F
+    [L][H][W][C] (L even; float32 or bfloat16 bits), W1 [2C][C], W2 [C][C]."""
+    F = _as_f64_array(F)
+    W1, W2 = _f64(W1), _f64(W2)
+    L, H, W, C = F.shape
+    out = np.zeros((L // 2, H, W, C))
+    lib().or_layer_collapse(L, H, W, C, _d(F), _d(W1), _d(W2), _d(out))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Whole step over a scene level
 # --------------------------------------------------------------------------

@@ -776,6 +776,47 @@ OR_EXPORT void or_residual_conv(int L, int H, int W, int C, const double *F, con
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Layer collapse (Sec. 3.2.2, "Layer Collapse"; the Lc blocks of the        */
+/* network tables): before the last two update steps the number of layers   */
+/* halves; each new layer is the mean of a pair of adjacent layers plus a    */
+/* residual MLP of their concatenation:                                      */
+/*   out[j] = (F[2j] + F[2j+1]) / 2 + relu([F[2j], F[2j+1]] W1) W2,          */
+/* W1 [2C][C], W2 [C][C], per pixel, no biases.                              */
+/* ------------------------------------------------------------------------ */
+
+/* F [L][H][W][C] with L even -> out [L/2][H][W][C]. */
+OR_EXPORT void or_layer_collapse(int L, int H, int W, int C, const double *F, const double *W1,
+                                 const double *W2, double *out)
+{
+    long npix = (long)H * W;
+#pragma omp parallel
+    {
+        double *x = malloc(sizeof(double) * 2 * C);
+        double *h = malloc(sizeof(double) * C);
+#pragma omp for schedule(static)
+        for (long idx = 0; idx < (long)(L / 2) * npix; ++idx) {
+            long j = idx / npix, p = idx % npix;
+            const double *a = F + ((size_t)(2 * j) * npix + p) * C;
+            const double *b = F + ((size_t)(2 * j + 1) * npix + p) * C;
+            for (int c = 0; c < C; ++c) { x[c] = a[c]; x[C + c] = b[c]; }
+            for (int o = 0; o < C; ++o) {
+                double s = 0.0;
+                for (int i = 0; i < 2 * C; ++i) s += x[i] * W1[(size_t)i * C + o];
+                h[o] = s > 0.0 ? s : 0.0;
+            }
+            double *y = out + ((size_t)j * npix + p) * C;
+            for (int o = 0; o < C; ++o) {
+                double s = 0.0;
+                for (int i = 0; i < C; ++i) s += h[i] * W2[(size_t)i * C + o];
+                y[o] = 0.5 * (a[o] + b[o]) + s;
+            }
+        }
+        free(x);
+        free(h);
+    }
+}
+
 OR_EXPORT int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -464,6 +464,18 @@ def make_conv_block(*, L: int = 16, H: int = 270, W: int = 480, C: int = 32, see
     return F, W1, W2
 
 
+def make_collapse(*, L: int = 16, H: int = 270, W: int = 480, C: int = 32, seed: int = 1009,
+                  dtype: str = "bf16"):
+    """A feature volume [L][H][W][C] N(0, 1) and the layer collapse's MLP
+    weights W1 [2C][C] N(0, 1/sqrt(2C)), W2 [C][C] N(0, 1/sqrt(C)).  Returns
+    (F, W1, W2).  Draw order: F, W1, W2."""
+    rng = np.random.default_rng(seed)
+    F = _cast(_normal(rng, (L, H, W, C)), dtype)
+    W1 = _normal(rng, (2 * C, C), 1.0 / math.sqrt(2 * C))
+    W2 = _normal(rng, (C, C), 1.0 / math.sqrt(C))
+    return F, W1, W2
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""
