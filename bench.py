@@ -361,6 +361,39 @@ def time_conv(ctx, reps: int = 50):
     return {"workload": CONV_WORKLOAD, "avg_launch_ms": ms, "roofline": roof}
 
 
+COLLAPSE_WORKLOAD = ("layer collapse: 16 -> 8 layers of 480x270, C = 32, bfloat16 (mean of "
+                     "adjacent layers plus a residual ReLU MLP of their concatenation)")
+
+
+def time_collapse(ctx, reps: int = 50):
+    """The layer collapse on the 480x270 C = 32 level: average launch time
+    with HIP events on its stream and its HBM roofline (the input read once,
+    the halved volume written once)."""
+    import torch
+    from paper_2411_16680_amd import lib, synth
+    F, W1, W2 = synth.make_collapse()
+    Fd = torch.from_numpy(F.view(np.int16)).cuda().view(torch.bfloat16)
+    L, H, W, C = F.shape
+    out = torch.empty((L // 2, H, W, C), device="cuda", dtype=torch.bfloat16)
+    w1, w2 = torch.from_numpy(W1).cuda(), torch.from_numpy(W2).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lib.layer_collapse(ctx, Fd, w1, w2, out, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lib.layer_collapse(ctx, Fd, w1, w2, out, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = L * H * W * C * 2 + (L // 2) * H * W * C * 2
+    gbs = nbytes / (ms / 1000.0) / 1e9
+    return {"workload": COLLAPSE_WORKLOAD, "avg_launch_ms": ms,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+
+
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
     """The standalone front-to-back composite (qk_composite) over a 1080p LDM
     of L layers: its average launch time with HIP events on its stream and
@@ -593,6 +626,11 @@ def main():
         f"{conv['roofline']['mfma_tflops']:.0f} TFLOP/s")
     torch.cuda.empty_cache()
 
+    collapse = time_collapse(ctx)
+    log(f"layer collapse: {collapse['avg_launch_ms'] * 1000:.1f} us, "
+        f"{collapse['roofline']['achieved']:.0f} GB/s")
+    torch.cuda.empty_cache()
+
     composite = time_composite(ctx)
     log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
         f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
@@ -667,6 +705,7 @@ def main():
         "final_render": render,
         "render_to_views": views,
         "residual_conv": conv,
+        "layer_collapse": collapse,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,

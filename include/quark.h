@@ -402,6 +402,28 @@ QK_API qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ld
 QK_API qk_status qk_residual_conv_check(const qk_ldm *ldm_in, const float *W1, const float *W2,
                                         const qk_ldm *ldm_out);
 
+/* ---- Layer collapse (Sec. 3.2.2, "Layer Collapse"; the Lc blocks of the
+ * network tables) ----
+ * Halves the number of layers: for j = 0 .. L/2 - 1 and every pixel,
+ *   out[j] = (F[2j] + F[2j+1]) / 2 + relu([F[2j], F[2j+1]] W1) W2,
+ * [a, b] the 2C-channel concatenation, no biases.  bfloat16 volumes, MFMA
+ * bfloat16 operands, float32 accumulation; the ReLU output is rounded to
+ * bfloat16 as the second product's operand, the result once at the store.
+ * Only the encoded features are collapsed: depth and alpha are decoded from
+ * them afresh by the next step (QK_UPDATE_PAPER_DECODE).
+ *   ldm_in   F [L][H][W][32] bfloat16, L even
+ *   ldm_out  F [L/2][H][W][32] bfloat16, not overlapping ldm_in
+ *   W1, W2   device float32 [64][32], [32][32]
+ * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned or overlapping),
+ * QK_ESHAPE (odd L, dims), QK_EDTYPE (not bfloat16), QK_EUNSUPPORTED
+ * (C != 32). */
+QK_API qk_status qk_layer_collapse(qk_context *ctx, void *hip_stream, const qk_ldm *ldm_in,
+                                   const float *W1, const float *W2, const qk_ldm *ldm_out);
+
+/* Dry run of qk_layer_collapse's argument checks (no device use). */
+QK_API qk_status qk_layer_collapse_check(const qk_ldm *ldm_in, const float *W1, const float *W2,
+                                         const qk_ldm *ldm_out);
+
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);
 

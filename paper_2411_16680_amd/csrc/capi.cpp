@@ -24,6 +24,7 @@ hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
 hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
 hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s);
+hipError_t launch_layer_collapse(const CollapseParams &p, int num_cu, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -420,6 +421,27 @@ qk_status check_conv(const qk_ldm *in, const float *W1, const float *W2, const q
     const int64_t bytes = elems * 2;
     if (a < b + bytes && b < a + bytes)
         return fail(QK_EINVAL, "ldm_out must not overlap ldm_in (tiles read their neighbours)");
+    return QK_OK;
+}
+
+qk_status check_collapse(const qk_ldm *in, const float *W1, const float *W2, const qk_ldm *out) {
+    if (!in || !out || !W1 || !W2) return fail(QK_EINVAL, "NULL argument");
+    if (in->L < 2 || in->H < 1 || in->W < 1)
+        return fail(QK_ESHAPE, "need L >= 2 and positive H, W (L=%d H=%d W=%d)", in->L, in->H, in->W);
+    if (in->L % 2 != 0) return fail(QK_ESHAPE, "layer collapse needs an even L (got %d)", in->L);
+    if (in->C != 32) return fail(QK_EUNSUPPORTED, "layer collapse supports C = 32 (got %d)", in->C);
+    if (in->dtype != QK_BF16 || out->dtype != QK_BF16)
+        return fail(QK_EDTYPE, "layer collapse takes bfloat16 feature volumes");
+    if (out->L != in->L / 2 || out->H != in->H || out->W != in->W || out->C != in->C)
+        return fail(QK_ESHAPE, "ldm_out must be [L/2][H][W][C] of ldm_in");
+    if (!in->F || !out->F) return fail(QK_EINVAL, "NULL feature volume");
+    if (!aligned16(in->F) || !aligned16(out->F))
+        return fail(QK_EINVAL, "feature volumes must be 16-byte aligned");
+    if (!aligned4(W1) || !aligned4(W2)) return fail(QK_EINVAL, "weights must be 4-byte aligned");
+    const int64_t bin = (int64_t)in->L * in->H * in->W * in->C * 2;
+    const char *a = static_cast<const char *>(in->F), *b = static_cast<const char *>(out->F);
+    if (a < b + bin / 2 && b < a + bin)
+        return fail(QK_EINVAL, "ldm_out must not overlap ldm_in");
     return QK_OK;
 }
 
@@ -882,6 +904,34 @@ qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *in, 
     p.W = in->W;
     hipError_t e = qk::launch_residual_conv(p, ctx->num_cu, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "residual block launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_layer_collapse_check(const qk_ldm *ldm_in, const float *W1, const float *W2,
+                                  const qk_ldm *ldm_out) {
+    return check_collapse(ldm_in, W1, W2, ldm_out);
+}
+
+qk_status qk_layer_collapse(qk_context *ctx, void *hip_stream, const qk_ldm *in, const float *W1,
+                            const float *W2, const qk_ldm *out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_collapse(in, W1, W2, out);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk::CollapseParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.F = static_cast<const uint16_t *>(in->F);
+    p.F_out = static_cast<uint16_t *>(out->F);
+    p.W1 = W1;
+    p.W2 = W2;
+    p.L = in->L;
+    p.npix = (int64_t)in->H * in->W;
+    p.n_blocks = (int64_t)(in->L / 2) * ((p.npix + 15) / 16);
+    hipError_t e = qk::launch_layer_collapse(p, ctx->num_cu, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "layer collapse launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -177,3 +177,18 @@ struct ConvParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Layer collapse: out[j] = (F[2j] + F[2j+1]) / 2 + relu([F[2j], F[2j+1]] W1) W2,
+// bfloat16 storage, C = 32.
+struct CollapseParams {
+    const uint16_t *F;              // [L][H][W][32]
+    uint16_t *F_out;                // [L/2][H][W][32]
+    const float *W1, *W2;           // [64][32], [32][32] float32 masters
+    int32_t L;
+    int64_t npix;                   // H * W
+    int64_t n_blocks;               // 16-pixel blocks of the output
+};
+
+}  // namespace qk

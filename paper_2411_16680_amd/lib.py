@@ -30,6 +30,7 @@ EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_upda
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
            "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
+           "qk_layer_collapse", "qk_layer_collapse_check",
            "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
@@ -132,12 +133,14 @@ def load() -> ctypes.CDLL:
     conv_args = [P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, P(qk_ldm)]
     L.qk_residual_conv.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + conv_args
     L.qk_residual_conv_check.argtypes = conv_args
+    L.qk_layer_collapse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + conv_args
+    L.qk_layer_collapse_check.argtypes = conv_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
                  "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
-                 "qk_camera_tables"):
+                 "qk_layer_collapse", "qk_layer_collapse_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -425,6 +428,21 @@ def residual_conv(ctx: Context, F_in, W1, W2, F_out, stream=None):
 def residual_conv_check(F_in, W1, W2, F_out) -> int:
     a, b = _volume(F_in), _volume(F_out)
     return int(load().qk_residual_conv_check(ctypes.byref(a), _ptr(W1), _ptr(W2), ctypes.byref(b)))
+
+
+def layer_collapse(ctx: Context, F_in, W1, W2, F_out, stream=None):
+    """qk_layer_collapse: F_out[j] = (F_in[2j] + F_in[2j+1]) / 2 +
+    relu([F_in[2j], F_in[2j+1]] W1) W2; bfloat16 device tensors
+    [L][H][W][32] -> [L/2][H][W][32], W1 [64][32], W2 [32][32] float32."""
+    a, b = _volume(F_in), _volume(F_out)
+    _check(ctx._lib.qk_layer_collapse(ctx.handle, _stream_handle(stream), ctypes.byref(a),
+                                      _ptr(W1), _ptr(W2), ctypes.byref(b)))
+
+
+def layer_collapse_check(F_in, W1, W2, F_out) -> int:
+    a, b = _volume(F_in), _volume(F_out)
+    return int(load().qk_layer_collapse_check(ctypes.byref(a), _ptr(W1), _ptr(W2),
+                                              ctypes.byref(b)))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

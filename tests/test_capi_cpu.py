@@ -354,3 +354,21 @@ def test_residual_conv_checks():
     assert lib.residual_conv_check(_FakeT((2, 9, 13, 32), 0x300008, torch.bfloat16), W1, W2,
                                    out) == lib.QK_EINVAL
     assert lib.residual_conv_check(F, None, W2, out) == lib.QK_EINVAL
+
+
+def test_layer_collapse_checks():
+    import torch
+    F = _FakeT((4, 9, 13, 32), 0x300000, torch.bfloat16)
+    out = _FakeT((2, 9, 13, 32), 0x900000, torch.bfloat16)
+    W1, W2 = _FakeT((64, 32), 0x600000), _FakeT((32, 32), 0x610000)
+    assert lib.layer_collapse_check(F, W1, W2, out) == lib.QK_OK
+    assert lib.layer_collapse_check(_FakeT((3, 9, 13, 32), 0x300000, torch.bfloat16), W1, W2,
+                                    out) == lib.QK_ESHAPE
+    assert "even" in lib.load().qk_last_error().decode()
+    assert lib.layer_collapse_check(F, W1, W2, _FakeT((4, 9, 13, 32), 0x900000,
+                                                      torch.bfloat16)) == lib.QK_ESHAPE
+    assert lib.layer_collapse_check(_FakeT((4, 9, 13, 16), 0x300000, torch.bfloat16), W1, W2,
+                                    _FakeT((2, 9, 13, 16), 0x900000, torch.bfloat16)) == lib.QK_EUNSUPPORTED
+    assert lib.layer_collapse_check(F, W1, W2, _FakeT((2, 9, 13, 32), 0x300000 + 4096,
+                                                      torch.bfloat16)) == lib.QK_EINVAL
+    assert lib.layer_collapse_check(F, None, W2, out) == lib.QK_EINVAL
