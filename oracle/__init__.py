@@ -50,6 +50,7 @@ def lib():
         L.or_update_fuse.restype = ctypes.c_int
         L.or_render_ibr.restype = ctypes.c_int
         L.or_render_to_views.restype = ctypes.c_int
+        L.or_ray_encoding.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         for name in ("or_reprojection_matrix", "or_reproject", "or_reproject_T"):
             pass
@@ -296,6 +297,25 @@ def layer_collapse(F, W1, W2) -> np.ndarray:
     out = np.zeros((L // 2, H, W, C))
     lib().or_layer_collapse(L, H, W, C, _d(F), _d(W1), _d(W2), _d(out))
     return out
+
+
+def ray_encoding(cam, novel, near, far, Wr, Hf: int, Wf: int, want_delta: bool = False):
+    """The ray-direction encoding of ``cam``'s pixels on an (Hf, Wf) grid:
+    returns out [Hf][Wf][C] (and the NDC difference [Hf][Wf][2])."""
+    Wr = _f64(Wr)
+    C = Wr.shape[1]
+    out = np.zeros((Hf, Wf, C))
+    dl = np.zeros((Hf, Wf, 2)) if want_delta else None
+    cwh = np.array([cam.width, cam.height], dtype=np.int32)
+    nwh = np.array([novel.width, novel.height], dtype=np.int32)
+    rc = lib().or_ray_encoding(_d(_f64(cam.K)), _d(_f64(cam.E)), cwh.ctypes.data_as(_ip), int(Hf),
+                               int(Wf), _d(_f64(novel.K)), _d(_f64(novel.E)),
+                               nwh.ctypes.data_as(_ip), ctypes.c_double(near),
+                               ctypes.c_double(far), _d(Wr), C, _d(out),
+                               _d(dl) if dl is not None else ctypes.cast(None, _dp))
+    if rc != 0:
+        raise ValueError("oracle ray_encoding failed (singular camera?)")
+    return (out, dl) if want_delta else out
 
 
 # --------------------------------------------------------------------------

@@ -38,6 +38,9 @@
  */
 
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -815,6 +818,79 @@ OR_EXPORT void or_layer_collapse(int L, int H, int W, int C, const double *F, co
         free(x);
         free(h);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray-direction encoding of an input view's pixels (Sec. 3.2.2, "Encode     */
+/* Input Images"): the ray of pixel (x, y) of view m is intersected with the */
+/* planes z = near and z = far of the novel camera's frustum (its own frame),*/
+/* both points are projected by the novel camera, and the difference (far    */
+/* minus near) is taken in normalised device coordinates (2 u / W_n,         */
+/* 2 v / H_n of the novel grid); it is squashed by tanh, encoded with 8      */
+/* octaves of sinusoids -- e[4k + 0..3] = sin(2^k pi t_x), cos(2^k pi t_x),  */
+/* sin(2^k pi t_y), cos(2^k pi t_y) -- and projected by W [32][C].          */
+/* ------------------------------------------------------------------------ */
+
+static void mat3_of_4x4(const double *E, double *R) {
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = E[4 * r + c];
+}
+
+/* Km, Em, cam_wh: view m's camera on its own grid; the view is encoded on
+ * an (Hf, Wf) grid.  out [Hf][Wf][C]; delta_out [Hf][Wf][2] (the NDC
+ * difference, before tanh) if non-NULL. */
+OR_EXPORT int or_ray_encoding(const double *Km, const double *Em, const int *cam_wh, int Hf,
+                              int Wf, const double *Kn, const double *En, const int *nov_wh,
+                              double near_, double far_, const double *Wr, int C, double *out,
+                              double *delta_out)
+{
+    double Ks[9], Ksi[16], Ks4[16], Emi[16];
+    or_scale_intrinsics(Km, cam_wh[0], cam_wh[1], Wf, Hf, Ks);
+    k_to_4x4(Ks, Ks4);
+    if (inv4(Ks4, Ksi) != 0 || inv4(Em, Emi) != 0) return -1;
+    double Rn[9];
+    mat3_of_4x4(En, Rn);
+    /* camera m's centre in the novel frame: En * inv(Em) * (0, 0, 0, 1) */
+    double cw[4] = {Emi[3], Emi[7], Emi[11], Emi[15]}, o[3];
+    for (int r = 0; r < 3; ++r)
+        o[r] = En[4 * r] * cw[0] + En[4 * r + 1] * cw[1] + En[4 * r + 2] * cw[2] + En[4 * r + 3] * cw[3];
+    for (int y = 0; y < Hf; ++y)
+        for (int x = 0; x < Wf; ++x) {
+            double pc[3] = {x + 0.5, y + 0.5, 1.0}, dc[3], dw[3], dn[3];
+            for (int r = 0; r < 3; ++r)            /* ray in camera m: K^-1 (u, v, 1) */
+                dc[r] = Ksi[4 * r] * pc[0] + Ksi[4 * r + 1] * pc[1] + Ksi[4 * r + 2] * pc[2];
+            for (int r = 0; r < 3; ++r)            /* to world: inverse rotation of Em */
+                dw[r] = Emi[4 * r] * dc[0] + Emi[4 * r + 1] * dc[1] + Emi[4 * r + 2] * dc[2];
+            for (int r = 0; r < 3; ++r)            /* to the novel frame */
+                dn[r] = Rn[3 * r] * dw[0] + Rn[3 * r + 1] * dw[1] + Rn[3 * r + 2] * dw[2];
+            double ndc[2][2];
+            const double planes[2] = {near_, far_};
+            for (int k = 0; k < 2; ++k) {
+                double sp = (planes[k] - o[2]) / dn[2];
+                double P[3] = {o[0] + sp * dn[0], o[1] + sp * dn[1], o[2] + sp * dn[2]};
+                double u = (Kn[0] * P[0] + Kn[1] * P[1] + Kn[2] * P[2]) / P[2];
+                double v = (Kn[3] * P[0] + Kn[4] * P[1] + Kn[5] * P[2]) / P[2];
+                ndc[k][0] = 2.0 * u / nov_wh[0];
+                ndc[k][1] = 2.0 * v / nov_wh[1];
+            }
+            double dlt[2] = {ndc[1][0] - ndc[0][0], ndc[1][1] - ndc[0][1]};
+            size_t q = (size_t)y * Wf + x;
+            if (delta_out) { delta_out[2 * q] = dlt[0]; delta_out[2 * q + 1] = dlt[1]; }
+            double t[2] = {tanh(dlt[0]), tanh(dlt[1])}, e[32];
+            for (int k = 0; k < 8; ++k) {
+                double f = M_PI * (double)(1 << k);
+                e[4 * k + 0] = sin(f * t[0]);
+                e[4 * k + 1] = cos(f * t[0]);
+                e[4 * k + 2] = sin(f * t[1]);
+                e[4 * k + 3] = cos(f * t[1]);
+            }
+            for (int c = 0; c < C; ++c) {
+                double sacc = 0.0;
+                for (int i = 0; i < 32; ++i) sacc += e[i] * Wr[(size_t)i * C + c];
+                out[q * C + c] = sacc;
+            }
+        }
+    return 0;
 }
 
 OR_EXPORT int or_num_threads(void)
