@@ -25,6 +25,7 @@ hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
 hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
 hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s);
 hipError_t launch_layer_collapse(const CollapseParams &p, int num_cu, hipStream_t s);
+hipError_t launch_ray_encoding(const RayParams &p, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -421,6 +422,47 @@ qk_status check_conv(const qk_ldm *in, const float *W1, const float *W2, const q
     const int64_t bytes = elems * 2;
     if (a < b + bytes && b < a + bytes)
         return fail(QK_EINVAL, "ldm_out must not overlap ldm_in (tiles read their neighbours)");
+    return QK_OK;
+}
+
+qk_status check_ray(int32_t V, const qk_camera *in_cams, const qk_camera *novel, float near_,
+                    float far_, const float *Wr, int32_t C, qk_dtype dtype,
+                    const qk_feature_map_inout *feats) {
+    if (!in_cams || !novel || !Wr || !feats) return fail(QK_EINVAL, "NULL argument");
+    if (V < 1 || V > qk::kMaxViews)
+        return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (!supported_c(C)) return fail(QK_EUNSUPPORTED, "C = %d not in {8, 16, 32, 64}", C);
+    if (dtype != QK_F32 && dtype != QK_BF16) return fail(QK_EDTYPE, "unknown dtype %d", (int)dtype);
+    if (!aligned16(Wr)) return fail(QK_EINVAL, "Wr must be 16-byte aligned");
+    qk_status st = check_camera(novel, "novel camera");
+    if (st != QK_OK) return st;
+    const int64_t esize = dtype == QK_BF16 ? 2 : 4;
+    for (int m = 0; m < V; ++m) {
+        char what[32];
+        snprintf(what, sizeof(what), "camera %d", m);
+        st = check_camera(&in_cams[m], what);
+        if (st != QK_OK) return st;
+        if (feats[m].H < 1 || feats[m].W < 1)
+            return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
+        if (!feats[m].data) return fail(QK_EINVAL, "feature map %d is NULL", m);
+        if (!aligned16(feats[m].data))
+            return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
+        if ((int64_t)feats[m].H * feats[m].W * C >= ((int64_t)1 << 40))
+            return fail(QK_EUNSUPPORTED, "feature map %d too large", m);
+    }
+    // each map is read and written in place by its own threads: two views
+    // sharing memory would race
+    for (int a = 0; a < V; ++a)
+        for (int b = a + 1; b < V; ++b) {
+            const char *pa = static_cast<const char *>(feats[a].data);
+            const char *pb = static_cast<const char *>(feats[b].data);
+            const int64_t na = (int64_t)feats[a].H * feats[a].W * C * esize;
+            const int64_t nb = (int64_t)feats[b].H * feats[b].W * C * esize;
+            if (pa < pb + nb && pb < pa + na)
+                return fail(QK_EINVAL, "feature maps %d and %d overlap", a, b);
+        }
     return QK_OK;
 }
 
@@ -932,6 +974,70 @@ qk_status qk_layer_collapse(qk_context *ctx, void *hip_stream, const qk_ldm *in,
     p.n_blocks = (int64_t)(in->L / 2) * ((p.npix + 15) / 16);
     hipError_t e = qk::launch_layer_collapse(p, ctx->num_cu, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "layer collapse launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_ray_encoding_check(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
+                                float near_, float far_, const float *Wr, int32_t C,
+                                qk_dtype dtype, const qk_feature_map_inout *feats) {
+    return check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, feats);
+}
+
+qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                          const qk_camera *novel, float near_, float far_, const float *Wr,
+                          int32_t C, qk_dtype dtype, const qk_feature_map_inout *feats) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, feats);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk::RayParams p;
+    std::memset(&p, 0, sizeof(p));
+    double Mn[9], tn[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) Mn[3 * r + c] = novel->E[4 * r + c];
+        tn[r] = novel->E[4 * r + 3];
+    }
+    int64_t maxpix = 0;
+    for (int m = 0; m < V; ++m) {
+        // ray direction in the novel frame: M_n M_m^-1 K_m^-1 (u, v, 1), K_m
+        // rescaled to the feature map's grid; view m's centre there:
+        // M_n (-M_m^-1 t_m) + t_n
+        const qk_camera *cam = &in_cams[m];
+        double Ks[9], Ksi[9], Mm[9], Mmi[9], R[9], tm[3];
+        scaled_K(cam, feats[m].W, feats[m].H, Ks);
+        mat3_inv(Ks, Ksi);
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) Mm[3 * r + c] = cam->E[4 * r + c];
+            tm[r] = cam->E[4 * r + 3];
+        }
+        mat3_inv(Mm, Mmi);
+        mat3_mul(Mn, Mmi, R);
+        mat3_mul(R, Ksi, p.D[m]);
+        for (int r = 0; r < 3; ++r) {
+            double s = tn[r];
+            for (int k = 0; k < 3; ++k) s -= R[3 * r + k] * tm[k];
+            p.o[m][r] = s;
+        }
+        p.feat[m] = feats[m].data;
+        p.fH[m] = feats[m].H;
+        p.fW[m] = feats[m].W;
+        maxpix = std::max(maxpix, (int64_t)feats[m].H * feats[m].W);
+    }
+    p.kx0 = 2.0 * novel->K[0] / novel->width;
+    p.kx1 = 2.0 * novel->K[1] / novel->width;
+    p.ky0 = 2.0 * novel->K[3] / novel->height;
+    p.ky1 = 2.0 * novel->K[4] / novel->height;
+    p.inv_band = 1.0 / (double)far_ - 1.0 / (double)near_;
+    p.Wr = Wr;
+    p.V = V;
+    p.C = C;
+    p.bf16 = dtype == QK_BF16;
+    p.max_pixels = maxpix;
+    hipError_t e = qk::launch_ray_encoding(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "ray encoding launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -192,3 +192,20 @@ struct CollapseParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Ray-direction encoding added to the input views' feature maps.
+struct RayParams {
+    double D[kMaxViews][9];         // (u, v, 1) on view m's grid -> ray direction, novel frame
+    double o[kMaxViews][3];         // view m's centre in the novel frame
+    void *feat[kMaxViews];          // [Hf][Wf][C], float32 or bfloat16, in place
+    int32_t fH[kMaxViews], fW[kMaxViews];
+    double kx0, kx1, ky0, ky1;      // (2/W_n) K_n[0][0..1], (2/H_n) K_n[1][0..1]
+    double inv_band;                // 1/far - 1/near
+    const float *Wr;                // [32][C]
+    int32_t V, C, bf16;
+    int64_t max_pixels;
+};
+
+}  // namespace qk

@@ -30,8 +30,8 @@ EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_upda
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
            "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
-           "qk_layer_collapse", "qk_layer_collapse_check",
-           "qk_camera_tables", "qk_last_error", "qk_version"]
+           "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
+           "qk_ray_encoding_check", "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
 class QuarkError(RuntimeError):
@@ -46,6 +46,10 @@ class qk_camera(ctypes.Structure):
 
 
 class qk_feature_map(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class qk_feature_map_inout(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
 
 
@@ -135,12 +139,17 @@ def load() -> ctypes.CDLL:
     L.qk_residual_conv_check.argtypes = conv_args
     L.qk_layer_collapse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + conv_args
     L.qk_layer_collapse_check.argtypes = conv_args
+    ray_args = [ctypes.c_int32, P(qk_camera), P(qk_camera), ctypes.c_float, ctypes.c_float,
+                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, P(qk_feature_map_inout)]
+    L.qk_ray_encoding.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + ray_args
+    L.qk_ray_encoding_check.argtypes = ray_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
                  "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
-                 "qk_layer_collapse", "qk_layer_collapse_check", "qk_camera_tables"):
+                 "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
+                 "qk_ray_encoding_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -443,6 +452,31 @@ def layer_collapse_check(F_in, W1, W2, F_out) -> int:
     a, b = _volume(F_in), _volume(F_out)
     return int(load().qk_layer_collapse_check(ctypes.byref(a), _ptr(W1), _ptr(W2),
                                               ctypes.byref(b)))
+
+
+def _ray_args(in_cams, novel, near, far, Wr, feats):
+    V = len(in_cams)
+    cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    maps = (qk_feature_map_inout * V)(*[qk_feature_map_inout(_ptr(f), int(f.shape[0]),
+                                                             int(f.shape[1])) for f in feats])
+    nov = make_camera(novel)
+    C = int(Wr.shape[1]) if Wr is not None else 0
+    return ((V, cams, ctypes.byref(nov), float(near), float(far), _ptr(Wr), C,
+             _dtype_code(feats[0]), maps), (cams, maps, nov))
+
+
+def ray_encoding(ctx: Context, in_cams, novel, near: float, far: float, Wr, feats, stream=None):
+    """qk_ray_encoding: adds each view's ray-direction encoding to its
+    feature map in place; Wr [32][C] float32, feats[m] [Hf][Wf][C] float32
+    or bfloat16 device tensors (one dtype)."""
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats)
+    _check(ctx._lib.qk_ray_encoding(ctx.handle, _stream_handle(stream), *args))
+
+
+def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats) -> int:
+    """qk_ray_encoding_check: the status qk_ray_encoding would return."""
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats)
+    return int(load().qk_ray_encoding_check(*args))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

@@ -476,6 +476,37 @@ def make_collapse(*, L: int = 16, H: int = 270, W: int = 480, C: int = 32, seed:
     return F, W1, W2
 
 
+# ----------------------------------------------------------------------------
+# Ray-direction encoding workload: an input rig, a novel camera and the
+# projection weights of every pyramid level (the feature maps themselves are
+# drawn by the caller, on the host or the device)
+# ----------------------------------------------------------------------------
+
+RAY_LEVELS = ((8, 64), (4, 32), (2, 16), (1, 8))   # (k, C): grid (H/k, W/k)
+
+
+@dataclass
+class RayScene:
+    in_cams: List[Camera]          # on the (W, H) input grid
+    novel: Camera
+    near: float
+    far: float
+    feat_hw: List[tuple]           # per level (Hf, Wf)
+    Wr: List[np.ndarray]           # per level [32][C] float32
+
+
+def make_ray(*, V: int = 8, W: int = 1920, H: int = 1080, levels=RAY_LEVELS, arc: float = 0.5,
+             radius: float = 1.5, hfov: float = 60.0, near: float = 0.5, far: float = 20.0,
+             seed: int = 1010) -> RayScene:
+    """V cameras on an arc facing a centre (the 1080p, V = 8 rig by default),
+    a novel camera inside the arc, and per level a projection Wr [32][C]
+    N(0, 1/sqrt(32)).  Draw order: cameras, then Wr level by level."""
+    rng = np.random.default_rng(seed)
+    in_cams, novel = _arc_rig(rng, V, arc, radius, W, H, hfov, novel_radius_jitter=0.05)
+    Wr = [_normal(rng, (32, C), 1.0 / math.sqrt(32.0)) for _, C in levels]
+    return RayScene(in_cams, novel, near, far, [(H // k, W // k) for k, _ in levels], Wr)
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""

@@ -372,3 +372,32 @@ def test_layer_collapse_checks():
     assert lib.layer_collapse_check(F, W1, W2, _FakeT((2, 9, 13, 32), 0x300000 + 4096,
                                                       torch.bfloat16)) == lib.QK_EINVAL
     assert lib.layer_collapse_check(F, None, W2, out) == lib.QK_EINVAL
+
+
+def test_ray_encoding_checks():
+    import torch
+    sc = synth.make_custom(V=3, H=12, W=20, C=16, L=2, seed=4)
+    cams, nov = sc.in_cams, sc.novel
+    Wr = _FakeT((32, 16), 0x600000)
+    feats = [_FakeT((9, 13, 16), 0x100000 * (m + 1)) for m in range(3)]
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats) == lib.QK_OK
+    bf = [_FakeT((9, 13, 16), 0x100000 * (m + 1), torch.bfloat16) for m in range(3)]
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, bf) == lib.QK_OK
+    assert lib.ray_encoding_check(cams, nov, 0.5, 0.5, Wr, feats) == lib.QK_EINVAL
+    assert lib.ray_encoding_check(cams, nov, 0.0, 20.0, Wr, feats) == lib.QK_EINVAL
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, _FakeT((32, 12), 0x600000),
+                                  feats) == lib.QK_EUNSUPPORTED
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, _FakeT((32, 16), 0x600004),
+                                  feats) == lib.QK_EINVAL
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr,
+                                  [_FakeT((9, 13, 16), 0x100000, torch.float16)] * 3) == lib.QK_EDTYPE
+    # overlapping maps race (each is written in place)
+    ov = [feats[0], _FakeT((9, 13, 16), 0x100000 + 64), feats[2]]
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, ov) == lib.QK_EINVAL
+    assert "overlap" in lib.load().qk_last_error().decode()
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr,
+                                  [feats[0], _FakeT((0, 13, 16), 0x200000), feats[2]]) == lib.QK_ESHAPE
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr,
+                                  [feats[0], _FakeT((9, 13, 16), 0x200008), feats[2]]) == lib.QK_EINVAL
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, None, feats) == lib.QK_EINVAL
+    assert lib.ray_encoding_check(cams * 6, nov, 0.5, 20.0, Wr, feats * 6) == lib.QK_ESHAPE

@@ -1,0 +1,159 @@
+"""Parity of the ray-direction encoding (qk_ray_encoding) against the FP64
+oracle, through the C-ABI: each view's feature map receives, in place, the
+encoding of its pixels' ray directions.
+
+Bar, float32 maps: with S = |f| + sum_i |Wr[i][c]| (a bound on every
+partial sum of the 32-term projection accumulated on top of the feature f),
+|out_gpu - out_oracle| <= 1e-6 + 4e-6 S: 33 float32 roundings of at most
+2^-24 S each, the sinusoids' own error (about one ulp) and the float
+rounding of their reduced argument (2^-23 times pi) weighted by |Wr|.
+bfloat16 maps add the final rounding, half an ulp: 2^-8 of the value."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_16680_amd import lib, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[ray]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib.Context(0)
+
+
+def _to_device(f, dtype):
+    if dtype == "bf16":
+        bits = synth.f32_to_bf16_bits(f)
+        return (torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16),
+                synth.bf16_bits_to_f32(bits).astype(np.float64))
+    return torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).cuda(), f.astype(np.float64)
+
+
+def _bound(f, Wr, ref, dtype):
+    S = np.abs(f) + np.sum(np.abs(Wr.astype(np.float64)), axis=0)
+    d = 1e-6 + 4e-6 * S
+    if dtype == "bf16":
+        d = d + 2.0 ** -8 * (np.abs(ref) + d)
+    return d
+
+
+def _check(ctx, cams, novel, near, far, Wr, maps, dtype, label):
+    C = Wr.shape[1]
+    dev, exact = zip(*[_to_device(f, dtype) for f in maps])
+    dev = list(dev)
+    w = torch.from_numpy(Wr).cuda()
+    _say(label, f"V={len(cams)} C={C} {dtype} maps={[tuple(f.shape[:2]) for f in maps]}")
+    lib.ray_encoding(ctx, cams, novel, near, far, w, dev)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, (d, f) in enumerate(zip(dev, exact)):
+        got = d.float().cpu().numpy().astype(np.float64)
+        Hf, Wf = f.shape[:2]
+        ref = f + oracle.ray_encoding(cams[m], novel, near, far, Wr, Hf, Wf)
+        ratio = float(np.max(np.abs(got - ref) / _bound(f, Wr, ref, dtype)))
+        worst = max(worst, ratio)
+        assert np.all(np.isfinite(got)), (label, m)
+        assert ratio <= 1.0, (label, m, ratio)
+    _say(label, f"error / bound {worst:.3g}")
+
+
+CASES = [
+    ("small-f32-C16", dict(V=3, W=64, H=36), [(18, 32)], 16, "f32"),
+    ("C8-bf16", dict(V=4, W=96, H=54), [(27, 48)], 8, "bf16"),
+    ("C32-f32", dict(V=2, W=32, H=18), [(9, 16)], 32, "f32"),
+    ("C64-bf16-ragged", dict(V=3, W=94, H=66), [(33, 47)], 64, "bf16"),
+    ("C64-f32", dict(V=2, W=40, H=30), [(15, 20)], 64, "f32"),
+    ("ragged-maps", dict(V=4, W=64, H=36), [(1, 1), (7, 13), (33, 47), (2, 300)], 16, "f32"),
+    ("max-views-V16", dict(V=16, W=48, H=27), [(5, 9)], 8, "f32"),
+    ("wide-arc", dict(V=5, W=64, H=48, arc=4.0, radius=1.5, hfov=120.0), [(24, 32)], 32, "f32"),
+    ("near-far-close", dict(V=3, W=64, H=36, near=1.0, far=1.25), [(18, 32)], 8, "bf16"),
+]
+
+
+@pytest.mark.parametrize("label,kw,hw,C,dtype", CASES, ids=[c[0] for c in CASES])
+def test_ray_parity(ctx, label, kw, hw, C, dtype):
+    V = kw["V"]
+    rs = synth.make_ray(levels=((1, C),), seed=len(label) * 13 + C, **kw)
+    rng = np.random.default_rng(C + V)
+    hws = hw * V if len(hw) == 1 else hw
+    maps = [rng.standard_normal((h, w, C)).astype(np.float32) for h, w in hws]
+    _check(ctx, rs.in_cams, rs.novel, rs.near, rs.far, rs.Wr[0], maps, dtype, label)
+
+
+def test_aligned_view_adds_a_constant(ctx):
+    """A view that is the novel camera itself: zero difference everywhere,
+    so every pixel receives sum_k (Wr[4k+1] + Wr[4k+3])."""
+    rs = synth.make_ray(V=2, W=64, H=36, levels=((1, 16),), seed=4)
+    nov = rs.novel
+    Wr = rs.Wr[0]
+    f = np.zeros((36, 64, 16), dtype=np.float32)
+    d = torch.from_numpy(f).cuda()
+    lib.ray_encoding(ctx, [nov], nov, rs.near, rs.far, torch.from_numpy(Wr).cuda(), [d])
+    got = d.cpu().numpy().astype(np.float64)
+    const = (np.tile([0.0, 1.0, 0.0, 1.0], 8) @ Wr.astype(np.float64))
+    assert np.max(np.abs(got - const)) <= 1e-6 + 4e-6 * np.sum(np.abs(Wr))
+
+
+def test_in_place_twice_and_nothing_else_written(ctx):
+    """Two calls add the encoding twice; the bytes after each map stay as
+    they were."""
+    rs = synth.make_ray(V=3, W=64, H=36, levels=((1, 32),), seed=6)
+    Wr = rs.Wr[0]
+    rng = np.random.default_rng(3)
+    hws = [(17, 31), (9, 64), (1, 3)]
+    bufs, maps = [], []
+    for h, w in hws:
+        b = torch.full((h * w * 32 + 64,), 7.25, device="cuda")
+        f = rng.standard_normal((h, w, 32)).astype(np.float32)
+        b[: h * w * 32] = torch.from_numpy(f.reshape(-1)).cuda()
+        bufs.append(b)
+        maps.append(f)
+    views = [b[: h * w * 32].view(h, w, 32) for b, (h, w) in zip(bufs, hws)]
+    w = torch.from_numpy(Wr).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, views, stream=s)
+        lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, views, stream=s)
+    s.synchronize()
+    for m, ((h, wd), b, f) in enumerate(zip(hws, bufs, maps)):
+        enc = oracle.ray_encoding(rs.in_cams[m], rs.novel, rs.near, rs.far, Wr, h, wd)
+        ref = f.astype(np.float64) + 2.0 * enc
+        got = b[: h * wd * 32].cpu().numpy().reshape(h, wd, 32).astype(np.float64)
+        S = np.abs(f) + 2.0 * np.sum(np.abs(Wr.astype(np.float64)), axis=0)
+        assert np.max(np.abs(got - ref) / (2e-6 + 4e-6 * S)) <= 1.0
+        assert torch.all(b[h * wd * 32:] == 7.25).item()
+
+
+def test_full_size_pyramid(ctx):
+    """The 1080p, V = 8 rig: all four pyramid levels (C = 64, 32, 16, 8 on
+    grids 1/8 .. 1/1), bfloat16 maps drawn on the device, one call per level
+    as timed; views 0, 3 and 7 compared with the oracle in full."""
+    rs = synth.make_ray()
+    g = torch.Generator(device="cuda").manual_seed(11)
+    for li, ((Hf, Wf), Wr) in enumerate(zip(rs.feat_hw, rs.Wr)):
+        C = Wr.shape[1]
+        maps = [torch.randn((Hf, Wf, C), generator=g, device="cuda").to(torch.bfloat16)
+                for _ in rs.in_cams]
+        before = {m: maps[m].float().cpu().numpy().astype(np.float64) for m in (0, 3, 7)}
+        _say(f"level {li}: {len(maps)} maps {Hf}x{Wf}x{C} bf16")
+        lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, torch.from_numpy(Wr).cuda(),
+                         maps)
+        torch.cuda.synchronize()
+        for m, f in before.items():
+            ref = f + oracle.ray_encoding(rs.in_cams[m], rs.novel, rs.near, rs.far, Wr, Hf, Wf)
+            got = maps[m].float().cpu().numpy().astype(np.float64)
+            ratio = float(np.max(np.abs(got - ref) / _bound(f, Wr, ref, "bf16")))
+            _say(f"level {li} view {m}: error / bound {ratio:.3g}")
+            assert ratio <= 1.0
