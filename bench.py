@@ -397,49 +397,59 @@ def time_collapse(ctx, reps: int = 50):
 RAY_WORKLOAD = ("ray-direction encoding added in place to the four-level feature pyramid of "
                 "V = 8 1080p views (240x135 C64, 480x270 C32, 960x540 C16, 1920x1080 C8), "
                 "bfloat16 maps, one call per level")
+RAY_LOW_HW = (135, 240)       # the paper's form: evaluated on the coarsest level's grid
 
 
 def time_ray(ctx, reps: int = 20):
-    """The ray-direction encoding over the 1080p V = 8 pyramid: average launch
-    time of each level's call with HIP events on its stream, and the HBM
-    roofline of the largest level (its maps read and written once)."""
+    """The ray-direction encoding over the 1080p V = 8 pyramid, in the
+    paper's form (evaluated on the coarsest grid, bilinearly upsampled: two
+    launches per call) and per pixel: average call time of each level with
+    HIP events on its stream, and the HBM roofline of the largest level (its
+    maps read and written once) in the paper's form."""
     import torch
     from paper_2411_16680_amd import lib, synth
     rs = synth.make_ray()
     g = torch.Generator(device="cuda").manual_seed(11)
     stream = torch.cuda.current_stream()
-    per_level, total_ms, total_bytes = [], 0.0, 0
-    for (Hf, Wf), Wr in zip(rs.feat_hw, rs.Wr):
-        C = Wr.shape[1]
-        maps = [torch.randn((Hf, Wf, C), generator=g, device="cuda").to(torch.bfloat16)
-                for _ in rs.in_cams]
-        w = torch.from_numpy(Wr).cuda()
-        for _ in range(3):
-            lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, maps, stream=stream)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, maps, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / reps
-        nbytes = len(maps) * Hf * Wf * C * 2 * 2
-        per_level.append({"grid": f"{Wf}x{Hf}", "C": C, "avg_launch_ms": ms,
-                          "algorithmic_bytes_per_launch": nbytes,
-                          "GB_s": nbytes / (ms / 1000.0) / 1e9})
-        total_ms += ms
-        total_bytes += nbytes
-        del maps
-    big = max(per_level, key=lambda r: r["algorithmic_bytes_per_launch"])
-    roof = {"bound": "hbm", "achieved": big["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": big["GB_s"] / HBM_PEAK_GBS,
-            "kernel": f"k_ray_encoding<C={big['C']},bf16> ({big['grid']}, V=8)",
-            "algorithmic_bytes_per_launch": big["algorithmic_bytes_per_launch"],
-            "avg_launch_ms": big["avg_launch_ms"]}
-    return {"workload": RAY_WORKLOAD, "pyramid_ms": total_ms,
-            "pyramid_GB_s": total_bytes / (total_ms / 1000.0) / 1e9, "per_level": per_level,
-            "roofline": roof}
+    out = {"workload": RAY_WORKLOAD}
+    for form, low in (("lowres", RAY_LOW_HW), ("per_pixel", None)):
+        per_level, total_ms, total_bytes = [], 0.0, 0
+        for (Hf, Wf), Wr in zip(rs.feat_hw, rs.Wr):
+            C = Wr.shape[1]
+            maps = [torch.randn((Hf, Wf, C), generator=g, device="cuda").to(torch.bfloat16)
+                    for _ in rs.in_cams]
+            w = torch.from_numpy(Wr).cuda()
+            for _ in range(3):
+                lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, maps, low_hw=low,
+                                 stream=stream)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, maps, low_hw=low,
+                                 stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            nbytes = len(maps) * Hf * Wf * C * 2 * 2
+            per_level.append({"grid": f"{Wf}x{Hf}", "C": C, "avg_call_ms": ms,
+                              "algorithmic_bytes_per_call": nbytes,
+                              "GB_s": nbytes / (ms / 1000.0) / 1e9})
+            total_ms += ms
+            total_bytes += nbytes
+            del maps
+        out[form] = {"low_res_grid": None if low is None else f"{low[1]}x{low[0]}",
+                     "pyramid_ms": total_ms,
+                     "pyramid_GB_s": total_bytes / (total_ms / 1000.0) / 1e9,
+                     "per_level": per_level}
+    big = max(out["lowres"]["per_level"], key=lambda r: r["algorithmic_bytes_per_call"])
+    out["roofline"] = {"bound": "hbm", "achieved": big["GB_s"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": big["GB_s"] / HBM_PEAK_GBS,
+                       "kernel": f"k_ray_lowres<{big['C']}> + k_ray_upsample_add<{big['C']},bf16> "
+                                 f"({big['grid']}, V=8, one call)",
+                       "algorithmic_bytes_per_call": big["algorithmic_bytes_per_call"],
+                       "avg_call_ms": big["avg_call_ms"]}
+    return out
 
 
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
@@ -680,8 +690,10 @@ def main():
     torch.cuda.empty_cache()
 
     ray = time_ray(ctx)
-    lv = ", ".join(f"{r['avg_launch_ms'] * 1000:.1f}" for r in ray["per_level"])
-    log(f"ray-direction encoding: {ray['pyramid_ms'] * 1000:.1f} us per pyramid (levels {lv} us)")
+    for form in ("lowres", "per_pixel"):
+        lv = ", ".join(f"{r['avg_call_ms'] * 1000:.1f}" for r in ray[form]["per_level"])
+        log(f"ray-direction encoding ({form}): {ray[form]['pyramid_ms'] * 1000:.1f} us per "
+            f"pyramid (levels {lv} us)")
     torch.cuda.empty_cache()
 
     composite = time_composite(ctx)

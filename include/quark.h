@@ -428,30 +428,40 @@ QK_API qk_status qk_layer_collapse_check(const qk_ldm *ldm_in, const float *W1, 
  * input features of every pyramid level receive an encoding of their
  * pixels' ray directions; its form, "Encode Input Images" of Sec. 3.2.2)
  * ----
- * For every pixel (u, v) (half-pixel centres) of view m's feature map, the
- * ray through it (view m's K rescaled to the map's grid) is cut by the
- * planes z = near and z = far of the novel camera; both points are
- * projected by the novel camera (its K on its own grid, NDC
- * = 2 (u, v) / (width, height)) and their difference, far minus near,
- * delta = (dx, dy), is encoded as
+ * For a pixel (u, v) (half-pixel centres) of view m on a grid, the ray
+ * through it (view m's K rescaled to the grid) is cut by the planes
+ * z = near and z = far of the novel camera; both points are projected by
+ * the novel camera (its K on its own grid, NDC = 2 (u, v) / (width,
+ * height)) and their difference, far minus near, delta = (dx, dy), is
+ * encoded as
  *   t = tanh(delta),
  *   e[4k + 0..3] = sin(2^k pi t_x), cos(2^k pi t_x), sin(2^k pi t_y), cos(2^k pi t_y),
- *   k = 0..7, and ADDED to the feature: I[v][u][:] += e Wr.
- * The geometry and tanh in double, sin and cos in float of the argument
- * reduced modulo 2 in double, the projection in float32 onto the feature,
- * which is rounded once to its dtype.  A ray parallel to the novel image
- * plane (d_z = 0 in the novel frame) gives non-finite values.
+ *   k = 0..7, and e Wr is ADDED to the feature map in place.
+ * Two forms, by (low_H, low_W):
+ *   (0, 0)   per pixel: every pixel of the map evaluates its own encoding;
+ *   (h, w)   the paper's: the encoding is evaluated on the (h, w) grid and
+ *            bilinearly upsampled to each map's grid (half-pixel centres,
+ *            border extended) before it is added; one low-resolution grid
+ *            serves every level (each with its own Wr).
+ * The geometry and tanh in double, the sinusoids in double from one
+ * quarter-period series and the double-angle identities, rounded to float;
+ * the projection and the upsampling in float32 onto the feature, which is
+ * rounded once to its dtype.  A ray parallel to the novel image plane
+ * (d_z = 0 in the novel frame) gives non-finite values.
  *   V        number of views, 1..16; in_cams host [V]
  *   novel    host camera
  *   near, far  0 < near < far, in the novel frame's depth units
  *   Wr       device float32 [32][C], 16-byte aligned
  *   C        8, 16, 32 or 64
  *   dtype    of the feature maps (QK_F32 or QK_BF16)
+ *   low_H, low_W  the low-resolution grid, or both 0
  *   feats    host [V]: device [H][W][C] maps, 16-byte aligned, read and
  *            written in place; no two may overlap
+ * Workspace (low-resolution form): V h w C floats in the context.
  * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned or overlapping
- * buffers, bad camera, near/far), QK_ESHAPE (dims, V out of range),
- * QK_EDTYPE (dtype), QK_EUNSUPPORTED (C, a map of 2^40 elements or
+ * buffers, bad camera, near/far), QK_ESHAPE (dims, V out of range, a
+ * low-resolution grid with one side 0), QK_EDTYPE (dtype), QK_EUNSUPPORTED
+ * (C, a map of 2^40 elements or more, a workspace of 2^31 floats or
  * more). */
 typedef struct {
     void *data;           /* device [H][W][C], read and written */
@@ -461,12 +471,14 @@ typedef struct {
 QK_API qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V,
                                  const qk_camera *in_cams, const qk_camera *novel, float near_,
                                  float far_, const float *Wr, int32_t C, qk_dtype dtype,
+                                 int32_t low_H, int32_t low_W,
                                  const qk_feature_map_inout *feats);
 
 /* Dry run of qk_ray_encoding's argument checks (no device use). */
 QK_API qk_status qk_ray_encoding_check(int32_t V, const qk_camera *in_cams,
                                        const qk_camera *novel, float near_, float far_,
                                        const float *Wr, int32_t C, qk_dtype dtype,
+                                       int32_t low_H, int32_t low_W,
                                        const qk_feature_map_inout *feats);
 
 QK_API const char *qk_last_error(void);

@@ -318,6 +318,16 @@ def ray_encoding(cam, novel, near, far, Wr, Hf: int, Wf: int, want_delta: bool =
     return (out, dl) if want_delta else out
 
 
+def ray_encoding_lowres(cam, novel, near, far, Wr, low_hw, Hf: int, Wf: int):
+    """The paper's form of the ray-direction encoding (Sec. 3.2.2, "Encode
+    Input Images"): the 8-octave sinusoids evaluated once on the
+    low-resolution grid ``low_hw`` = (h, w), bilinearly upsampled to the
+    (Hf, Wf) map grid, then projected by Wr: returns [Hf][Wf][C]."""
+    h, w = int(low_hw[0]), int(low_hw[1])
+    e = ray_encoding(cam, novel, near, far, np.eye(32), h, w)
+    return upsample_bilinear(e, Hf, Wf) @ _f64(Wr)
+
+
 # --------------------------------------------------------------------------
 # Whole step over a scene level
 # --------------------------------------------------------------------------

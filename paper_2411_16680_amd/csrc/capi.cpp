@@ -41,6 +41,8 @@ struct qk_context {
     size_t vws_elems = 0;
     float *cfrag = nullptr;      // bfloat16 fragments of the residual block's kernels
     size_t cfrag_elems = 0;
+    float *rws = nullptr;        // low-resolution projected ray encodings
+    size_t rws_elems = 0;
 };
 
 namespace {
@@ -426,8 +428,8 @@ qk_status check_conv(const qk_ldm *in, const float *W1, const float *W2, const q
 }
 
 qk_status check_ray(int32_t V, const qk_camera *in_cams, const qk_camera *novel, float near_,
-                    float far_, const float *Wr, int32_t C, qk_dtype dtype,
-                    const qk_feature_map_inout *feats) {
+                    float far_, const float *Wr, int32_t C, qk_dtype dtype, int32_t low_H,
+                    int32_t low_W, const qk_feature_map_inout *feats) {
     if (!in_cams || !novel || !Wr || !feats) return fail(QK_EINVAL, "NULL argument");
     if (V < 1 || V > qk::kMaxViews)
         return fail(QK_ESHAPE, "V = %d outside 1..%d", V, qk::kMaxViews);
@@ -436,6 +438,10 @@ qk_status check_ray(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
     if (!supported_c(C)) return fail(QK_EUNSUPPORTED, "C = %d not in {8, 16, 32, 64}", C);
     if (dtype != QK_F32 && dtype != QK_BF16) return fail(QK_EDTYPE, "unknown dtype %d", (int)dtype);
     if (!aligned16(Wr)) return fail(QK_EINVAL, "Wr must be 16-byte aligned");
+    if (low_H < 0 || low_W < 0 || (low_H == 0) != (low_W == 0))
+        return fail(QK_ESHAPE, "low-resolution grid %dx%d: both positive, or both 0", low_W, low_H);
+    if ((int64_t)V * low_H * low_W * C >= ((int64_t)1 << 31))
+        return fail(QK_EUNSUPPORTED, "low-resolution encodings of 2^31 floats or more");
     qk_status st = check_camera(novel, "novel camera");
     if (st != QK_OK) return st;
     const int64_t esize = dtype == QK_BF16 ? 2 : 4;
@@ -512,7 +518,7 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag)) {
+    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag || ctx->rws)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
@@ -520,6 +526,7 @@ qk_status qk_context_destroy(qk_context *ctx) {
         if (ctx->f8) (void)hipFree(ctx->f8);
         if (ctx->vws) (void)hipFree(ctx->vws);
         if (ctx->cfrag) (void)hipFree(ctx->cfrag);
+        if (ctx->rws) (void)hipFree(ctx->rws);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -979,20 +986,27 @@ qk_status qk_layer_collapse(qk_context *ctx, void *hip_stream, const qk_ldm *in,
 
 qk_status qk_ray_encoding_check(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
                                 float near_, float far_, const float *Wr, int32_t C,
-                                qk_dtype dtype, const qk_feature_map_inout *feats) {
-    return check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, feats);
+                                qk_dtype dtype, int32_t low_H, int32_t low_W,
+                                const qk_feature_map_inout *feats) {
+    return check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, low_H, low_W, feats);
 }
 
 qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
                           const qk_camera *novel, float near_, float far_, const float *Wr,
-                          int32_t C, qk_dtype dtype, const qk_feature_map_inout *feats) {
+                          int32_t C, qk_dtype dtype, int32_t low_H, int32_t low_W,
+                          const qk_feature_map_inout *feats) {
     if (!ctx) return fail(QK_EINVAL, "context is NULL");
-    qk_status st = check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, feats);
+    qk_status st = check_ray(V, in_cams, novel, near_, far_, Wr, C, dtype, low_H, low_W, feats);
     if (st != QK_OK) return st;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
     if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (low_H > 0) {
+        st = grow(&ctx->rws, &ctx->rws_elems, (size_t)V * low_H * low_W * C, stream);
+        if (st != QK_OK) return st;
+    }
     qk::RayParams p;
     std::memset(&p, 0, sizeof(p));
     double Mn[9], tn[3];
@@ -1003,11 +1017,14 @@ qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk
     int64_t maxpix = 0;
     for (int m = 0; m < V; ++m) {
         // ray direction in the novel frame: M_n M_m^-1 K_m^-1 (u, v, 1), K_m
-        // rescaled to the feature map's grid; view m's centre there:
-        // M_n (-M_m^-1 t_m) + t_n
+        // rescaled to the grid the encoding is evaluated on (the map's, or
+        // the low-resolution one); view m's centre there: M_n (-M_m^-1 t_m) + t_n
         const qk_camera *cam = &in_cams[m];
         double Ks[9], Ksi[9], Mm[9], Mmi[9], R[9], tm[3];
-        scaled_K(cam, feats[m].W, feats[m].H, Ks);
+        if (low_H > 0)
+            scaled_K(cam, low_W, low_H, Ks);
+        else
+            scaled_K(cam, feats[m].W, feats[m].H, Ks);
         mat3_inv(Ks, Ksi);
         for (int r = 0; r < 3; ++r) {
             for (int c = 0; c < 3; ++c) Mm[3 * r + c] = cam->E[4 * r + c];
@@ -1032,11 +1049,14 @@ qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk
     p.ky1 = 2.0 * novel->K[4] / novel->height;
     p.inv_band = 1.0 / (double)far_ - 1.0 / (double)near_;
     p.Wr = Wr;
+    p.P = low_H > 0 ? ctx->rws : nullptr;
+    p.lH = low_H;
+    p.lW = low_W;
     p.V = V;
     p.C = C;
     p.bf16 = dtype == QK_BF16;
     p.max_pixels = maxpix;
-    hipError_t e = qk::launch_ray_encoding(p, reinterpret_cast<hipStream_t>(hip_stream));
+    hipError_t e = qk::launch_ray_encoding(p, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "ray encoding launch: %s", hipGetErrorString(e));
     return QK_OK;
 }

@@ -204,6 +204,8 @@ struct RayParams {
     double kx0, kx1, ky0, ky1;      // (2/W_n) K_n[0][0..1], (2/H_n) K_n[1][0..1]
     double inv_band;                // 1/far - 1/near
     const float *Wr;                // [32][C]
+    float *P;                       // low-resolution form: [V][lH][lW][C] workspace
+    int32_t lH, lW;                 // low-resolution grid, 0 = per-pixel form
     int32_t V, C, bf16;
     int64_t max_pixels;
 };

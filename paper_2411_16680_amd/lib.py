@@ -140,7 +140,8 @@ def load() -> ctypes.CDLL:
     L.qk_layer_collapse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + conv_args
     L.qk_layer_collapse_check.argtypes = conv_args
     ray_args = [ctypes.c_int32, P(qk_camera), P(qk_camera), ctypes.c_float, ctypes.c_float,
-                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, P(qk_feature_map_inout)]
+                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                P(qk_feature_map_inout)]
     L.qk_ray_encoding.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + ray_args
     L.qk_ray_encoding_check.argtypes = ray_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
@@ -454,28 +455,32 @@ def layer_collapse_check(F_in, W1, W2, F_out) -> int:
                                               ctypes.byref(b)))
 
 
-def _ray_args(in_cams, novel, near, far, Wr, feats):
+def _ray_args(in_cams, novel, near, far, Wr, feats, low_hw):
     V = len(in_cams)
     cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
     maps = (qk_feature_map_inout * V)(*[qk_feature_map_inout(_ptr(f), int(f.shape[0]),
                                                              int(f.shape[1])) for f in feats])
     nov = make_camera(novel)
     C = int(Wr.shape[1]) if Wr is not None else 0
+    lh, lw = (0, 0) if low_hw is None else (int(low_hw[0]), int(low_hw[1]))
     return ((V, cams, ctypes.byref(nov), float(near), float(far), _ptr(Wr), C,
-             _dtype_code(feats[0]), maps), (cams, maps, nov))
+             _dtype_code(feats[0]), lh, lw, maps), (cams, maps, nov))
 
 
-def ray_encoding(ctx: Context, in_cams, novel, near: float, far: float, Wr, feats, stream=None):
+def ray_encoding(ctx: Context, in_cams, novel, near: float, far: float, Wr, feats, low_hw=None,
+                 stream=None):
     """qk_ray_encoding: adds each view's ray-direction encoding to its
     feature map in place; Wr [32][C] float32, feats[m] [Hf][Wf][C] float32
-    or bfloat16 device tensors (one dtype)."""
-    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats)
+    or bfloat16 device tensors (one dtype); low_hw = (h, w) evaluates the
+    encoding on that grid and upsamples it (the paper's form), None per
+    pixel."""
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw)
     _check(ctx._lib.qk_ray_encoding(ctx.handle, _stream_handle(stream), *args))
 
 
-def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats) -> int:
+def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats, low_hw=None) -> int:
     """qk_ray_encoding_check: the status qk_ray_encoding would return."""
-    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats)
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw)
     return int(load().qk_ray_encoding_check(*args))
 
 

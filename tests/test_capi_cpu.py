@@ -401,3 +401,9 @@ def test_ray_encoding_checks():
                                   [feats[0], _FakeT((9, 13, 16), 0x200008), feats[2]]) == lib.QK_EINVAL
     assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, None, feats) == lib.QK_EINVAL
     assert lib.ray_encoding_check(cams * 6, nov, 0.5, 20.0, Wr, feats * 6) == lib.QK_ESHAPE
+    # the low-resolution form: both sides positive, or both 0
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, low_hw=(5, 7)) == lib.QK_OK
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, low_hw=(0, 7)) == lib.QK_ESHAPE
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, low_hw=(-1, -1)) == lib.QK_ESHAPE
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
+                                  low_hw=(1 << 14, 1 << 14)) == lib.QK_EUNSUPPORTED

@@ -80,3 +80,39 @@ def test_octaves_at_one_half():
         e[4 * k + 2] = 0.0
         e[4 * k + 3] = 1.0
     assert np.max(np.abs(out - e)) < 1e-12
+
+
+def test_lowres_form_on_the_map_grid_is_the_per_pixel_form():
+    """Upsampling from a grid to itself is the identity, so the paper's
+    low-resolution form on the map's own grid is the per-pixel encoding."""
+    sc = synth.make_ray(V=3, W=64, H=36, levels=((1, 16),), seed=2)
+    for cam in sc.in_cams:
+        a = oracle.ray_encoding(cam, sc.novel, NEAR, FAR, sc.Wr[0], 18, 32)
+        b = oracle.ray_encoding_lowres(cam, sc.novel, NEAR, FAR, sc.Wr[0], (18, 32), 18, 32)
+        assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_lowres_form_of_a_constant_difference_is_that_constant():
+    """A sideways translation gives one difference vector everywhere; its
+    upsampled encoding is the per-pixel one at any grid."""
+    nov = _rig()
+    cam = _moved(nov, (0.05, 0.0, 0.0))
+    Wr = np.random.default_rng(3).standard_normal((32, 8))
+    a = oracle.ray_encoding(cam, nov, NEAR, FAR, Wr, 27, 48)
+    b = oracle.ray_encoding_lowres(cam, nov, NEAR, FAR, Wr, (4, 7), 27, 48)
+    assert np.max(np.abs(a - b)) < 1e-12
+    assert np.max(np.abs(a - a[0, 0])) < 1e-12
+
+
+def test_lowres_form_interpolates_between_low_res_centres():
+    """At a map pixel whose centre falls midway between two low-res centres
+    (an exact 2x upsampling: the map's second pixel sits at low-res
+    coordinate 0.25, its third at 0.75) the result is the bilinear mix of
+    the per-pixel encodings evaluated at those low-res centres."""
+    sc = synth.make_ray(V=2, W=64, H=36, levels=((1, 8),), seed=8)
+    cam, Wr = sc.in_cams[1], sc.Wr[0]
+    lo = oracle.ray_encoding(cam, sc.novel, NEAR, FAR, Wr, 9, 16)
+    up = oracle.ray_encoding_lowres(cam, sc.novel, NEAR, FAR, Wr, (9, 16), 18, 32)
+    # map pixel (y=3, x=5) sits at low-res (1.25, 2.25) -> weights 3/4, 1/4
+    ref = (0.75 * (0.75 * lo[1, 2] + 0.25 * lo[1, 3]) + 0.25 * (0.75 * lo[2, 2] + 0.25 * lo[2, 3]))
+    assert np.max(np.abs(up[3, 5] - ref)) < 1e-12

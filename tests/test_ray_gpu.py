@@ -49,19 +49,26 @@ def _bound(f, Wr, ref, dtype):
     return d
 
 
-def _check(ctx, cams, novel, near, far, Wr, maps, dtype, label):
+def _encoding(cam, novel, near, far, Wr, Hf, Wf, low_hw):
+    if low_hw is None:
+        return oracle.ray_encoding(cam, novel, near, far, Wr, Hf, Wf)
+    return oracle.ray_encoding_lowres(cam, novel, near, far, Wr, low_hw, Hf, Wf)
+
+
+def _check(ctx, cams, novel, near, far, Wr, maps, dtype, label, low_hw=None):
     C = Wr.shape[1]
     dev, exact = zip(*[_to_device(f, dtype) for f in maps])
     dev = list(dev)
     w = torch.from_numpy(Wr).cuda()
-    _say(label, f"V={len(cams)} C={C} {dtype} maps={[tuple(f.shape[:2]) for f in maps]}")
-    lib.ray_encoding(ctx, cams, novel, near, far, w, dev)
+    _say(label, f"V={len(cams)} C={C} {dtype} low={low_hw} "
+                f"maps={[tuple(f.shape[:2]) for f in maps]}")
+    lib.ray_encoding(ctx, cams, novel, near, far, w, dev, low_hw=low_hw)
     torch.cuda.synchronize()
     worst = 0.0
     for m, (d, f) in enumerate(zip(dev, exact)):
         got = d.float().cpu().numpy().astype(np.float64)
         Hf, Wf = f.shape[:2]
-        ref = f + oracle.ray_encoding(cams[m], novel, near, far, Wr, Hf, Wf)
+        ref = f + _encoding(cams[m], novel, near, far, Wr, Hf, Wf, low_hw)
         ratio = float(np.max(np.abs(got - ref) / _bound(f, Wr, ref, dtype)))
         worst = max(worst, ratio)
         assert np.all(np.isfinite(got)), (label, m)
@@ -90,6 +97,31 @@ def test_ray_parity(ctx, label, kw, hw, C, dtype):
     hws = hw * V if len(hw) == 1 else hw
     maps = [rng.standard_normal((h, w, C)).astype(np.float32) for h, w in hws]
     _check(ctx, rs.in_cams, rs.novel, rs.near, rs.far, rs.Wr[0], maps, dtype, label)
+
+
+LOW_CASES = [
+    ("low-4x7-to-27x48-f32", dict(V=3, W=96, H=54), (4, 7), [(27, 48)], 8, "f32"),
+    ("low-ragged-maps-bf16", dict(V=4, W=64, H=36), (5, 9),
+     [(1, 1), (7, 13), (33, 47), (2, 300)], 16, "bf16"),
+    ("low-C64-f32", dict(V=2, W=64, H=36), (9, 16), [(18, 32)], 64, "f32"),
+    ("low-C32-bf16-wide", dict(V=5, W=64, H=48, arc=4.0, radius=1.5, hfov=120.0), (6, 8),
+     [(24, 32)], 32, "bf16"),
+    ("low-equal-to-map", dict(V=3, W=64, H=36), (18, 32), [(18, 32)], 16, "f32"),
+    ("low-finer-than-map", dict(V=2, W=64, H=36), (20, 30), [(9, 16)], 8, "f32"),
+    ("low-1x1", dict(V=3, W=64, H=36), (1, 1), [(5, 6)], 8, "f32"),
+]
+
+
+@pytest.mark.parametrize("label,kw,low,hw,C,dtype", LOW_CASES, ids=[c[0] for c in LOW_CASES])
+def test_ray_lowres_parity(ctx, label, kw, low, hw, C, dtype):
+    """The paper's form: the encoding on a low-resolution grid, bilinearly
+    upsampled to every map."""
+    V = kw["V"]
+    rs = synth.make_ray(levels=((1, C),), seed=len(label) * 7 + C, **kw)
+    rng = np.random.default_rng(C + 2 * V)
+    hws = hw * V if len(hw) == 1 else hw
+    maps = [rng.standard_normal((h, w, C)).astype(np.float32) for h, w in hws]
+    _check(ctx, rs.in_cams, rs.novel, rs.near, rs.far, rs.Wr[0], maps, dtype, label, low_hw=low)
 
 
 def test_aligned_view_adds_a_constant(ctx):
@@ -136,10 +168,12 @@ def test_in_place_twice_and_nothing_else_written(ctx):
         assert torch.all(b[h * wd * 32:] == 7.25).item()
 
 
-def test_full_size_pyramid(ctx):
+@pytest.mark.parametrize("low_hw", [None, (135, 240)], ids=["per-pixel", "low-135x240"])
+def test_full_size_pyramid(ctx, low_hw):
     """The 1080p, V = 8 rig: all four pyramid levels (C = 64, 32, 16, 8 on
     grids 1/8 .. 1/1), bfloat16 maps drawn on the device, one call per level
-    as timed; views 0, 3 and 7 compared with the oracle in full."""
+    as timed, per pixel and in the paper's form from the coarsest level's
+    grid; views 0, 3 and 7 compared with the oracle in full."""
     rs = synth.make_ray()
     g = torch.Generator(device="cuda").manual_seed(11)
     for li, ((Hf, Wf), Wr) in enumerate(zip(rs.feat_hw, rs.Wr)):
@@ -149,10 +183,10 @@ def test_full_size_pyramid(ctx):
         before = {m: maps[m].float().cpu().numpy().astype(np.float64) for m in (0, 3, 7)}
         _say(f"level {li}: {len(maps)} maps {Hf}x{Wf}x{C} bf16")
         lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, torch.from_numpy(Wr).cuda(),
-                         maps)
+                         maps, low_hw=low_hw)
         torch.cuda.synchronize()
         for m, f in before.items():
-            ref = f + oracle.ray_encoding(rs.in_cams[m], rs.novel, rs.near, rs.far, Wr, Hf, Wf)
+            ref = f + _encoding(rs.in_cams[m], rs.novel, rs.near, rs.far, Wr, Hf, Wf, low_hw)
             got = maps[m].float().cpu().numpy().astype(np.float64)
             ratio = float(np.max(np.abs(got - ref) / _bound(f, Wr, ref, "bf16")))
             _say(f"level {li} view {m}: error / bound {ratio:.3g}")
