@@ -162,8 +162,15 @@ QK_API qk_status qk_context_destroy(qk_context *ctx);
  *   ldm_in      current state; ldm_out receives F', depth', alpha'
  *               (ldm_out may alias ldm_in: each layer-pixel is read before
  *               it is written, by the same wave)
- * Supported by the kernels: heads == 1, C == C_feat == head_dim in
- * {8, 16, 32, 64}, each feature map under 1 GiB; otherwise
+ * Attention has `heads` heads of `head_dim` channels (Sec. 3.3, the
+ * MultiHead equation): head h takes channels h head_dim .. (h + 1)
+ * head_dim - 1 of the Q, K and V projections, its own softmax over the
+ * views with logits scaled by 1/sqrt(head_dim), and the heads' outputs,
+ * concatenated, go through Wo.
+ * Supported by the kernels: C == C_feat in {8, 16, 32, 64}, each feature
+ * map under 1 GiB, and one head of C channels, or for C >= 32 in the
+ * standard form heads x head_dim == C with head_dim 16 or 32 (or 8 at
+ * C = 32: the paper's four heads of its 32 channels); otherwise
  * QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
  * QK_F32, QK_PREC_BF16 and QK_PREC_BF16_FP8PROJ need QK_BF16 (else
  * QK_EDTYPE). */

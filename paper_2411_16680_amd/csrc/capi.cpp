@@ -15,7 +15,7 @@
 #include "uf_params.h"
 
 namespace qk {
-hipError_t launch_update_fuse(const UFParams &p, int C, int prec, bool fold, hipStream_t s);
+hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool fold, hipStream_t s);
 hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s);
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
@@ -225,11 +225,23 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
             return fail(QK_EUNSUPPORTED, "feature map %d is %lld bytes; maps must be under 1 GiB", m,
                         (long long)fbytes);
     }
-    if (w->heads != 1 || w->head_dim != in->C || w->C_feat != in->C || !supported_c(in->C))
-        return fail(QK_EUNSUPPORTED,
-                    "kernels support heads == 1 and C == C_feat == head_dim in {8,16,32,64} "
-                    "(got heads=%d head_dim=%d C=%d C_feat=%d)",
-                    w->heads, w->head_dim, in->C, w->C_feat);
+    if (w->C_feat != in->C || !supported_c(in->C))
+        return fail(QK_EUNSUPPORTED, "kernels support C == C_feat in {8,16,32,64} (got C=%d C_feat=%d)",
+                    in->C, w->C_feat);
+    if (w->heads != 1 || w->head_dim != in->C) {
+        // several heads: the standard form, C >= 32, heads x head_dim == C,
+        // head_dim 8 (C = 32) or 16 or 32
+        const bool ok = attn_form == QK_ATTN_STANDARD && in->C >= 32 &&
+                        w->heads * w->head_dim == in->C &&
+                        ((w->head_dim == 8 && in->C == 32) || w->head_dim == 16 || w->head_dim == 32);
+        if (!ok)
+            return fail(QK_EUNSUPPORTED,
+                        "kernels support one head of C channels, or for C >= 32 in the standard "
+                        "form heads x head_dim == C with head_dim 16, 32 (or 8 at C = 32) "
+                        "(got heads=%d head_dim=%d C=%d, %s form)",
+                        w->heads, w->head_dim, in->C,
+                        attn_form == QK_ATTN_FOLDED ? "folded" : "standard");
+    }
     return QK_OK;
 }
 
@@ -676,7 +688,7 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         if (e8 != hipSuccess) return fail(QK_EHIP, "fp8 scale launch: %s", hipGetErrorString(e8));
         p.f8_scales = ctx->f8;
     }
-    hipError_t e = qk::launch_update_fuse(p, in->C, (int)precision, fold, stream);
+    hipError_t e = qk::launch_update_fuse(p, in->C, w->head_dim, (int)precision, fold, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "update_fuse launch: %s", hipGetErrorString(e));
     return QK_OK;
 }

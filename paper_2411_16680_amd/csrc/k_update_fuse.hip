@@ -492,16 +492,22 @@ struct Occupancy {
 };
 
 // FOLD = false: standard cross-attention (per-sample key and value
-// projections on MFMA).  FOLD = true: one-to-many attention -- the key
+// projections on MFMA), with C / HD heads of HD channels each (C >= 32):
+// head h owns output channels h HD .. (h + 1) HD - 1 of Q, K and V, which
+// are whole 16-row output tiles for HD >= 16 and, for HD = 8, the upper or
+// lower two lanes of a pixel's four in one tile; each lane keeps one softmax
+// state per head it holds channels of.  FOLD = true: one-to-many attention -- the key
 // projection folded into the query (q~ = N(F) W_q W_k^T / sqrt(d)) and the
 // value projection into the output (W_v W_o); the per-view work is a dot
 // product and a weighted sum on the samples themselves (for C = 8 the same
 // MFMA loop, with the blended sample standing in for keys and values).
-template <int C, bool BF16, bool FOLD, bool F8>
+template <int C, bool BF16, bool FOLD, bool F8, int HD>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(Occupancy<C, BF16, FOLD>::waves)))
 k_update_fuse(const UFParams p) {
     static_assert(!F8 || BF16, "e4m3 projections take bfloat16 storage");
+    static_assert(HD == C || (C >= 32 && !FOLD && (HD == 8 || (HD >= 16 && C % HD == 0))),
+                  "several heads: standard form, C >= 32, head width 8 or a multiple of 16");
     using SH = Shape<C>;
     using OP = Op<BF16>;
     using AF = typename OP::A;
@@ -512,7 +518,12 @@ k_update_fuse(const UFParams p) {
     constexpr int G = SH::G, KC = SH::KC, NT = SH::NT, ND = SH::ND, PIX = SH::PIX, P = SH::P;
     constexpr bool TAPK = SH::TAPK;
     constexpr bool STDLOOP = !FOLD || TAPK;     // the MFMA view loop
-    constexpr int NS = (G == 1) ? 1 : NT;       // softmax states per lane
+    // softmax states per lane: one per 16-pixel sub-tile (G > 1), else one
+    // per head whose channels the lane holds (TPH output tiles per head)
+    constexpr int TPH = (HD >= 16) ? HD / 16 : 1;
+    constexpr int NS = (G == 1) ? ((HD >= 16) ? NT / TPH : NT) : NT;
+    // the state of output tile t
+    auto st_of = [](int t) constexpr { return (G == 1 && HD >= 16) ? t / TPH : t; };
     using FR = Frags<C, STDLOOP>;
     static_assert(!TAPK || 64 * sizeof(MA) <= PIX * P * sizeof(float),
                   "tap staging must fit the o tile it shares");
@@ -656,7 +667,7 @@ k_update_fuse(const UFParams p) {
     const T *Fin = reinterpret_cast<const T *>(p.F_in);
     T *Fout = reinterpret_cast<T *>(p.F_out);
     const bool do_comp = p.rgb != nullptr;
-    const float scale = FOLD ? 1.0f : 1.0f / sqrtf((float)C);   // folded: W_qk carries it
+    const float scale = FOLD ? 1.0f : 1.0f / sqrtf((float)HD);  // folded: W_qk carries it
     const Coord uc = (Coord)(a_ok ? xa : 0) + (Coord)0.5, vc = (Coord)y + (Coord)0.5;
     const Coord uc_ld = (Coord)(ld_ok ? x_ld : 0) + (Coord)0.5;
     const float band = p.inv_near - p.inv_far;
@@ -780,13 +791,27 @@ k_update_fuse(const UFParams p) {
                     }
                 }
                 float lg[NS];
-                if constexpr (G == 1) {
-                    float part = 0.0f;
+                if constexpr (G == 1 && HD >= 16) {
+                    // a head's channels: TPH whole tiles, all four lanes
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
+                    for (int s = 0; s < NS; ++s) {
+                        float part = 0.0f;
+#pragma unroll
+                        for (int t = s * TPH; t < (s + 1) * TPH; ++t)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
+                        lg[s] = result_pixel_sum<C>(part) * (scale * kscale);
+                    }
+                } else if constexpr (G == 1) {
+                    // HD = 8: the lane's four rows of tile t and its row-pair
+                    // partner's are one head
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        float part = 0.0f;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) part = fmaf(Q[t][i], Kt[t][i], part);
-                    lg[0] = result_pixel_sum<C>(part) * (scale * kscale);
+                        lg[t] = rows_pair_sum16(part) * (scale * kscale);
+                    }
                 } else {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
@@ -809,7 +834,7 @@ k_update_fuse(const UFParams p) {
                         Z[s] *= r;
 #pragma unroll
                         for (int t = 0; t < NT; ++t)
-                            if (G == 1 || t == s)
+                            if (st_of(t) == s)
 #pragma unroll
                                 for (int i = 0; i < 4; ++i) acc[t][i] *= r;
                         M[s] = lg[s];
@@ -831,7 +856,7 @@ k_update_fuse(const UFParams p) {
 #pragma unroll
                         for (int kc = 0; kc < KC; ++kc) Vt = MM::mma(Bv[kc][t], Sb[kc], Vt);
                     }
-                    const int s = (G == 1) ? 0 : t;
+                    const int s = st_of(t);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(pw[s], Vt[i], acc[t][i]);
                 }
@@ -860,7 +885,7 @@ k_update_fuse(const UFParams p) {
             // o = acc / Z: result layout -> LDS -> operand layout
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const float iz = vscale * recip(Z[(G == 1) ? 0 : t]);
+                const float iz = vscale * recip(Z[st_of(t)]);
                 float o4[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) o4[i] = acc[t][i] * iz;
@@ -1050,26 +1075,38 @@ __global__ void __launch_bounds__(256) k_composite(const CompParams p) {
 // ---------------------------------------------------------------------------
 // Launchers (host side of this translation unit)
 // ---------------------------------------------------------------------------
-template <int C, bool BF16, bool FOLD, bool F8>
+template <int C, bool BF16, bool FOLD, bool F8, int HD>
 static hipError_t launch_uf(const UFParams &p, hipStream_t s) {
-    hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8>), dim3(p.n_tiles), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8, HD>), dim3(p.n_tiles), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
 // prec: 0 float32, 1 bfloat16, 2 bfloat16 storage with e4m3 projections
-template <int C>
+template <int C, int HD>
 static hipError_t launch_c(const UFParams &p, int prec, bool fold, hipStream_t s) {
-    if (prec == 2) return fold ? launch_uf<C, true, true, true>(p, s) : launch_uf<C, true, false, true>(p, s);
-    if (prec == 1) return fold ? launch_uf<C, true, true, false>(p, s) : launch_uf<C, true, false, false>(p, s);
-    return fold ? launch_uf<C, false, true, false>(p, s) : launch_uf<C, false, false, false>(p, s);
+    if constexpr (HD != C) {                     // several heads: standard form only
+        if (fold) return hipErrorInvalidValue;
+        if (prec == 2) return launch_uf<C, true, false, true, HD>(p, s);
+        if (prec == 1) return launch_uf<C, true, false, false, HD>(p, s);
+        return launch_uf<C, false, false, false, HD>(p, s);
+    } else {
+        if (prec == 2) return fold ? launch_uf<C, true, true, true, C>(p, s) : launch_uf<C, true, false, true, C>(p, s);
+        if (prec == 1) return fold ? launch_uf<C, true, true, false, C>(p, s) : launch_uf<C, true, false, false, C>(p, s);
+        return fold ? launch_uf<C, false, true, false, C>(p, s) : launch_uf<C, false, false, false, C>(p, s);
+    }
 }
 
-hipError_t launch_update_fuse(const UFParams &p, int C, int prec, bool fold, hipStream_t s) {
-    switch (C) {
-        case 8: return launch_c<8>(p, prec, fold, s);
-        case 16: return launch_c<16>(p, prec, fold, s);
-        case 32: return launch_c<32>(p, prec, fold, s);
-        case 64: return launch_c<64>(p, prec, fold, s);
+// hd: the width of one head (C for a single head)
+hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool fold, hipStream_t s) {
+    switch (C * 1000 + hd) {
+        case 8008: return launch_c<8, 8>(p, prec, fold, s);
+        case 16016: return launch_c<16, 16>(p, prec, fold, s);
+        case 32032: return launch_c<32, 32>(p, prec, fold, s);
+        case 32016: return launch_c<32, 16>(p, prec, fold, s);
+        case 32008: return launch_c<32, 8>(p, prec, fold, s);
+        case 64064: return launch_c<64, 64>(p, prec, fold, s);
+        case 64032: return launch_c<64, 32>(p, prec, fold, s);
+        case 64016: return launch_c<64, 16>(p, prec, fold, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -36,6 +36,7 @@ class DeviceLevel:
     rgb: Optional[object] = None
     acc: Optional[object] = None
     composite: bool = True
+    heads: int = 1                     # attention heads (head width C / heads)
     extra: dict = field(default_factory=dict)
 
 
@@ -50,7 +51,7 @@ def level_to_device(level, device="cuda", composite: Optional[bool] = None) -> D
          for k, v in level.weights.items()}
     dl = DeviceLevel(level.L, level.H, level.W, level.C, feats, F, depth, alpha, w,
                      torch.empty_like(F), torch.empty_like(depth), torch.empty_like(alpha),
-                     composite=comp)
+                     composite=comp, heads=int(getattr(level, "heads", 1)))
     if comp:
         dl.rgb = torch.empty((level.H, level.W, 3), dtype=torch.float32, device=device)
         dl.acc = torch.empty((level.H, level.W), dtype=torch.float32, device=device)
@@ -69,11 +70,14 @@ def run_level(ctx: lib.Context, scene, dl: DeviceLevel, *, steps: Optional[int] 
     when the level composites."""
     steps = scene.steps if steps is None else steps
     precision = precision or ("bf16" if scene.dtype == "bf16" else "fp32")
+    wts = dl.extra.get("qk_weights")
+    if wts is None:                    # built once (the tensors stay in dl.weights)
+        wts = dl.extra["qk_weights"] = lib.make_weights(dl.weights, heads=dl.heads)
     for s in range(steps):
         src = (dl.F, dl.depth, dl.alpha) if s == 0 else (dl.F_out, dl.depth_out, dl.alpha_out)
         last = s == steps - 1
         lib.update_fuse(ctx, scene.in_cams, dl.feats, scene.novel, scene.near, scene.far,
-                        dl.weights, src, (dl.F_out, dl.depth_out, dl.alpha_out),
+                        wts, src, (dl.F_out, dl.depth_out, dl.alpha_out),
                         precision=precision, attn_form=attn_form, mode=mode,
                         rgb_out=dl.rgb if (last and dl.composite) else None,
                         acc_out=dl.acc if (last and dl.composite) else None, stream=stream)

@@ -122,6 +122,7 @@ def test_rejections():
     assert _check(sc2, f2, w2, l2) == lib.QK_EUNSUPPORTED
     sc2, f2, w2, l2 = _args(C=16, heads=2, head_dim=8)
     assert _check(sc2, f2, w2, l2) == lib.QK_EUNSUPPORTED
+
     # misaligned feature buffer
     F, d, a = ldm
     bad = (_FakeT(F.shape, F._addr + 4), d, a)
@@ -154,6 +155,24 @@ def test_rejections():
     assert _check(sc, feats, wts, ldm, acc_out=_FakeT((12, 20))) == lib.QK_EINVAL
     msg = lib.load().qk_last_error().decode()
     assert "rgb" in msg
+
+
+
+def test_heads():
+    """Several heads: the standard form at C >= 32 with heads x head_dim == C
+    and head_dim 16, 32 (or 8 at C = 32); not the folded form."""
+    for C, heads, hd in ((32, 4, 8), (32, 2, 16), (64, 4, 16), (64, 2, 32), (32, 1, 32)):
+        sc, f, w, l = _args(C=C, heads=heads, head_dim=hd)
+        assert _check(sc, f, w, l) == lib.QK_OK, (C, heads, hd)
+        sc, f, w, l = _args(C=C, heads=heads, head_dim=hd, dtype="bf16")
+        assert _check(sc, f, w, l, precision="bf16") == lib.QK_OK
+        assert _check(sc, f, w, l, precision="bf16_fp8proj") == lib.QK_OK
+    for C, heads, hd in ((64, 8, 8), (32, 4, 16), (32, 2, 8), (16, 2, 8), (8, 2, 4)):
+        sc, f, w, l = _args(C=C, heads=heads, head_dim=hd)
+        assert _check(sc, f, w, l) == lib.QK_EUNSUPPORTED, (C, heads, hd)
+    sc, f, w, l = _args(C=32, heads=4, head_dim=8)
+    assert _check(sc, f, w, l, attn_form="folded") == lib.QK_EUNSUPPORTED
+    assert "folded" in lib.load().qk_last_error().decode()
 
 
 def test_null_context_rejected_before_device_use():

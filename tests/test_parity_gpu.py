@@ -242,6 +242,45 @@ def test_paper_decode_mode(ctx, form, attn):
     compare(gpu, ref, form, sc, sc.levels[0], label=f"paper-decode {attn}")
 
 
+HEADS = [
+    # (name, kwargs for make_custom): the paper's four and two heads of its
+    # 32 channels, and four / two heads at C = 64
+    ("C32-h4-hd8-ragged", dict(V=4, H=6, W=37, C=32, L=3, heads=4, head_dim=8)),
+    ("C32-h2-hd16", dict(V=3, H=5, W=40, C=32, L=3, heads=2, head_dim=16)),
+    ("C64-h4-hd16", dict(V=5, H=4, W=33, C=64, L=2, heads=4, head_dim=16)),
+    ("C64-h2-hd32", dict(V=3, H=5, W=20, C=64, L=2, heads=2, head_dim=32)),
+    ("C32-h4-V16", dict(V=16, H=3, W=24, C=32, L=2, heads=4, head_dim=8, arc=0.6)),
+    ("C32-h4-one-view", dict(V=1, H=4, W=18, C=32, L=2, heads=4, head_dim=8)),
+]
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("name,kw", HEADS, ids=[e[0] for e in HEADS])
+def test_several_heads(ctx, name, kw, form):
+    """Multi-head cross-attention (standard form): per-head softmax over the
+    views, heads concatenated into the output projection."""
+    _say("heads", name, form)
+    sc = synth.make_custom(dtype="f32", seed=zlib.crc32(name.encode()) % 1000, **kw)
+    if form != "fp32":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0])
+    gpu, _ = run_gpu_level(ctx, sc, attn_form="standard",
+                           precision=PREC["fp8"] if form == "fp8" else None)
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"{name} standard")
+
+
+def test_heads_differ_from_one_head(ctx):
+    """The same weights read as four heads and as one head give different
+    updates (the per-head softmax is not the one-head softmax)."""
+    sc = synth.make_custom(dtype="f32", seed=77, V=4, H=4, W=20, C=32, L=2, heads=4, head_dim=8)
+    g4, _ = run_gpu_level(ctx, sc, attn_form="standard")
+    sc.levels[0].heads, sc.levels[0].head_dim = 1, 32
+    g1, _ = run_gpu_level(ctx, sc, attn_form="standard")
+    ref1 = oracle.run_level(sc, sc.levels[0])
+    compare(g1, ref1, "fp32", sc, sc.levels[0], label="C32 same weights one head")
+    assert float(np.max(np.abs(g4["F"] - g1["F"]))) > 1e-3
+
+
 def test_in_place_and_optional_outputs(ctx):
     _say("in-place / no F' / no acc")
     sc = synth.make_custom(V=3, H=6, W=50, C=16, L=4, seed=5)
