@@ -639,6 +639,19 @@ def main():
         del dls
         torch.cuda.empty_cache()
 
+    # several heads: the 480x270 C = 32 level (the paper's width) with its
+    # weights read as 1, 2 and 4 heads (standard form, bfloat16)
+    heads_ms = {}
+    dl1 = runner.level_to_device(sc16.levels[1], composite=False)
+    for h in (1, 2, 4):
+        dl1.heads = h
+        dl1.extra.pop("qk_weights", None)
+        heads_ms[str(h)] = per_level_ms(ctx, sc16, [dl1], "standard", "bf16")[0]
+    log(f"heads on the 480x270 C32 level: " +
+        ", ".join(f"{h}: {v * 1000:.1f} us" for h, v in heads_ms.items()))
+    del dl1
+    torch.cuda.empty_cache()
+
     bf = results["bf16"]
     ms_per_step = bf["total_ms"] / bf["steps"]
     S = sum(l.L * l.H * l.W for l in sc16.levels) * V
@@ -762,6 +775,8 @@ def main():
                    "per_level_ms": results["bf16_folded"]["per_level_ms"],
                    "note": "one-to-many (folded) attention, bf16: the paper's optimized form"},
         "per_level_ms": bf["per_level_ms"],
+        "heads_level1_ms": {"level": "480x270 L16 C32 V8, standard attention, bf16",
+                            "ms_by_heads": heads_ms},
         "layer_pixel_views_per_s": S / (ms_per_step / 1000.0),
         "frame_compulsory_bytes": frame_bytes,
         "frame_hbm_frac": frame_bytes / (ms_per_step / 1000.0) / (HBM_PEAK_GBS * 1e9),
