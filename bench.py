@@ -182,9 +182,11 @@ def cpu_baseline(scene, target_s: float = 25.0):
 # ---------------------------------------------------------------------------
 
 def profile_run(ctx, steps: int, depth_mode: str):
-    """Frames of the bf16 standard form, then a plain copy of known size, for
-    counter collection (FETCH_SIZE / WRITE_SIZE are scaled by what they read
-    for the copy)."""
+    """Frames of the bf16 standard form, final renders, renders to the input
+    views, the ray-direction encoding of the pyramid, the residual CNN block
+    and the layer collapse, then a plain copy of known size, for counter
+    collection (FETCH_SIZE / WRITE_SIZE are scaled by what they read for the
+    copy)."""
     import torch
     from paper_2411_16680_amd import lib, runner, synth
     sc = synth.to_bf16(synth.make_inputs(3, depth_mode=depth_mode))
@@ -212,6 +214,33 @@ def profile_run(ctx, steps: int, depth_mode: str):
         torch.cuda.synchronize()
         log(f"profile render to views {s + 1}/{steps}")
     del d, a, c, rgbs
+    # the ray-direction encoding in the paper's form, all four levels
+    rsr = synth.make_ray()
+    g = torch.Generator(device="cuda").manual_seed(11)
+    for (Hf, Wf), Wr in zip(rsr.feat_hw, rsr.Wr):
+        maps = [torch.randn((Hf, Wf, Wr.shape[1]), generator=g, device="cuda").to(torch.bfloat16)
+                for _ in rsr.in_cams]
+        w = torch.from_numpy(Wr).cuda()
+        for s in range(steps):
+            lib.ray_encoding(ctx, rsr.in_cams, rsr.novel, rsr.near, rsr.far, w, maps,
+                             low_hw=RAY_LOW_HW)
+            torch.cuda.synchronize()
+        log(f"profile ray encoding {Wf}x{Hf} C{Wr.shape[1]}")
+        del maps
+    # the residual CNN block and the layer collapse on the 480x270 C = 32 level
+    for name, make, call, out_layers in (
+            ("residual block", synth.make_conv_block, lib.residual_conv, lambda L: L),
+            ("layer collapse", synth.make_collapse, lib.layer_collapse, lambda L: L // 2)):
+        F, W1, W2 = make()
+        Fd = torch.from_numpy(F.view(np.int16)).cuda().view(torch.bfloat16)
+        L, H, W, C = F.shape
+        out = torch.empty((out_layers(L), H, W, C), device="cuda", dtype=torch.bfloat16)
+        w1, w2 = torch.from_numpy(W1).cuda(), torch.from_numpy(W2).cuda()
+        for s in range(steps):
+            call(ctx, Fd, w1, w2, out)
+            torch.cuda.synchronize()
+        log(f"profile {name}")
+        del Fd, out
     n = 128 * 1024 * 1024                          # 512 MiB of float32
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -398,6 +427,7 @@ RAY_WORKLOAD = ("ray-direction encoding added in place to the four-level feature
                 "V = 8 1080p views (240x135 C64, 480x270 C32, 960x540 C16, 1920x1080 C8), "
                 "bfloat16 maps, one call per level")
 RAY_LOW_HW = (135, 240)       # the paper's form: evaluated on the coarsest level's grid
+RAY_SRC = os.path.join(ROOT, "paper_2411_16680_amd", "csrc", "k_ray.hip")
 
 
 def time_ray(ctx, reps: int = 20):
@@ -448,7 +478,9 @@ def time_ray(ctx, reps: int = 20):
                        "kernel": f"k_ray_lowres<{big['C']}> + k_ray_upsample_add<{big['C']},bf16> "
                                  f"({big['grid']}, V=8, one call)",
                        "algorithmic_bytes_per_call": big["algorithmic_bytes_per_call"],
-                       "avg_call_ms": big["avg_call_ms"]}
+                       "avg_call_ms": big["avg_call_ms"],
+                       # both launches of the call, from the committed counters
+                       "traffic": traffic_from_profiles("k_ray", "k_ray_lowres_form_1080p", RAY_SRC)}
     return out
 
 
