@@ -488,6 +488,50 @@ QK_API qk_status qk_ray_encoding_check(int32_t V, const qk_camera *in_cams,
                                        int32_t low_H, int32_t low_W,
                                        const qk_feature_map_inout *feats);
 
+/* ---- Resolution transition (Sec. 3.2.2: the steps that grow the LDM
+ * upsample the feature volume and the rendered views by two in each
+ * spatial dimension; the appendix network tables give the grids) ----
+ * Bilinear upsampling by exactly two, half-pixel centres, border extended:
+ * dst[n][Y][X] samples src[n] at ((X + 0.5)/2 - 0.5, (Y + 0.5)/2 - 0.5),
+ * i.e. blends of two rows and two columns with weights 1/4 and 3/4.
+ * Float32 arithmetic, one rounding to the dtype at the store.
+ *   src   device [N][H][W][C], dst device [N][2H][2W][C], one dtype
+ *         (QK_F32 or QK_BF16), not overlapping; 16-byte aligned when C is
+ *         a multiple of 8, else aligned to the element
+ * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned or overlapping),
+ * QK_ESHAPE (dims), QK_EDTYPE, QK_EUNSUPPORTED (2^38 elements or more). */
+QK_API qk_status qk_upsample2x(qk_context *ctx, void *hip_stream, const void *src, void *dst,
+                               int32_t N, int32_t H, int32_t W, int32_t C, qk_dtype dtype);
+
+/* Dry run of qk_upsample2x's argument checks (no device use). */
+QK_API qk_status qk_upsample2x_check(const void *src, void *dst, int32_t N, int32_t H,
+                                     int32_t W, int32_t C, qk_dtype dtype);
+
+/* ---- Decode of an encoded LDM (Sec. 3.2.2: each step first decodes the
+ * feature volume into an LDM; the absolute decode with the depth anchors
+ * of Sec. 3.2.3, as QK_UPDATE_PAPER_DECODE) ----
+ * For layer l (0 nearest) of L and every pixel, with F the C-channel
+ * feature:
+ *   alpha = sigmoid(F . w_sigma),  colour = sigmoid(F W_color),
+ *   depth = 1 / ((delta_l + (0.5/L) tanh(F . w_depth)) (1/near - 1/far) + 1/far),
+ *   delta_l = (L - l - 0.5) / L.
+ * Float32 arithmetic.
+ *   ldm        F [L][H][W][C] (QK_F32 or QK_BF16, C in {8, 16, 32, 64})
+ *              read; depth, alpha [L][H][W] written
+ *   w_sigma, w_depth  device float32 [C];  W_color device float32 [C][3]
+ *   color_out  device float32 [L][H][W][3] or NULL
+ * Errors (nothing enqueued): QK_EINVAL (NULL or misaligned, near/far),
+ * QK_ESHAPE, QK_EDTYPE, QK_EUNSUPPORTED (C, 2^38 elements or more). */
+QK_API qk_status qk_ldm_decode(qk_context *ctx, void *hip_stream, const qk_ldm *ldm,
+                               const float *w_sigma, const float *w_depth,
+                               const float *W_color, float near_, float far_,
+                               float *color_out);
+
+/* Dry run of qk_ldm_decode's argument checks (no device use). */
+QK_API qk_status qk_ldm_decode_check(const qk_ldm *ldm, const float *w_sigma,
+                                     const float *w_depth, const float *W_color, float near_,
+                                     float far_, const float *color_out);
+
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);
 

@@ -318,6 +318,28 @@ def ray_encoding(cam, novel, near, far, Wr, Hf: int, Wf: int, want_delta: bool =
     return (out, dl) if want_delta else out
 
 
+def upsample2x(src):
+    """Bilinear upsampling by two of src [N][H][W][C] (half-pixel centres,
+    border extended): the general resampling at (2H, 2W), per n."""
+    src = _f64(src)
+    return np.stack([upsample_bilinear(s, 2 * s.shape[0], 2 * s.shape[1]) for s in src])
+
+
+def decode_volume(F, w_sigma, w_depth, W_color, near, far):
+    """The absolute decode (Sec. 3.2.2-3.2.3, the paper's depth anchors) of
+    every layer-pixel of F [L][H][W][C]: returns (depth, alpha, color)."""
+    F = _as_f64_array(F)
+    L, H, W, _ = F.shape
+    depth, alpha, color = np.zeros((L, H, W)), np.zeros((L, H, W)), np.zeros((L, H, W, 3))
+    for li in range(L):
+        for y in range(H):
+            for x in range(W):
+                a, d, c = decode(F[li, y, x], w_sigma, w_depth, W_color, 0.5, 1.0, li, L, near,
+                                 far, mode=1)
+                depth[li, y, x], alpha[li, y, x], color[li, y, x] = d, a, c
+    return depth, alpha, color
+
+
 def ray_encoding_lowres(cam, novel, near, far, Wr, low_hw, Hf: int, Wf: int):
     """The paper's form of the ray-direction encoding (Sec. 3.2.2, "Encode
     Input Images"): the 8-octave sinusoids evaluated once on the

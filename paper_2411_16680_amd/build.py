@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libquark.so")
 SOURCES = ["k_update_fuse.hip", "k_backward.hip", "k_init.hip", "k_fp8.hip", "k_render.hip",
            "k_views.hip", "k_conv.hip",
-           "k_collapse.hip", "k_ray.hip", "capi.cpp"]
+           "k_collapse.hip", "k_ray.hip", "k_resample.hip", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -26,6 +26,8 @@ hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
 hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s);
 hipError_t launch_layer_collapse(const CollapseParams &p, int num_cu, hipStream_t s);
 hipError_t launch_ray_encoding(const RayParams &p, hipStream_t s);
+hipError_t launch_upsample2x(const Up2Params &p, hipStream_t s);
+hipError_t launch_ldm_decode(const DecodeParams &p, hipStream_t s);
 }  // namespace qk
 
 struct qk_context {
@@ -481,6 +483,44 @@ qk_status check_ray(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
             if (pa < pb + nb && pb < pa + na)
                 return fail(QK_EINVAL, "feature maps %d and %d overlap", a, b);
         }
+    return QK_OK;
+}
+
+qk_status check_upsample2x(const void *src, void *dst, int32_t N, int32_t H, int32_t W, int32_t C,
+                           qk_dtype dtype) {
+    if (!src || !dst) return fail(QK_EINVAL, "NULL argument");
+    if (N < 1 || H < 1 || W < 1 || C < 1)
+        return fail(QK_ESHAPE, "dims must be positive (N=%d H=%d W=%d C=%d)", N, H, W, C);
+    if (dtype != QK_F32 && dtype != QK_BF16) return fail(QK_EDTYPE, "unknown dtype %d", (int)dtype);
+    const int64_t e = dtype == QK_BF16 ? 2 : 4;
+    const int64_t n_in = (int64_t)N * H * W * C;
+    if (n_in >= ((int64_t)1 << 38)) return fail(QK_EUNSUPPORTED, "volume too large");
+    const uintptr_t need = C % 8 == 0 ? 16 : (uintptr_t)e;
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & (need - 1))
+        return fail(QK_EINVAL, "buffers must be %d-byte aligned", (int)need);
+    const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+    if (a < b + 4 * n_in * e && b < a + n_in * e)
+        return fail(QK_EINVAL, "dst must not overlap src");
+    return QK_OK;
+}
+
+qk_status check_decode(const qk_ldm *ldm, const float *w_sigma, const float *w_depth,
+                       const float *W_color, float near_, float far_, const float *color_out) {
+    if (!ldm || !w_sigma || !w_depth || !W_color) return fail(QK_EINVAL, "NULL argument");
+    if (ldm->L < 1 || ldm->H < 1 || ldm->W < 1)
+        return fail(QK_ESHAPE, "LDM dims must be positive (L=%d H=%d W=%d)", ldm->L, ldm->H, ldm->W);
+    if (!supported_c(ldm->C)) return fail(QK_EUNSUPPORTED, "C = %d not in {8, 16, 32, 64}", ldm->C);
+    if (ldm->dtype != QK_F32 && ldm->dtype != QK_BF16)
+        return fail(QK_EDTYPE, "unknown dtype %d", (int)ldm->dtype);
+    if (!(near_ > 0.0f) || !(far_ > near_) || !std::isfinite(far_))
+        return fail(QK_EINVAL, "need 0 < near < far (got %g, %g)", near_, far_);
+    if (!ldm->F || !ldm->depth || !ldm->alpha) return fail(QK_EINVAL, "NULL LDM buffer");
+    if (!aligned16(ldm->F)) return fail(QK_EINVAL, "the feature volume must be 16-byte aligned");
+    if (!aligned4(ldm->depth) || !aligned4(ldm->alpha) || (color_out && !aligned4(color_out)) ||
+        !aligned4(w_sigma) || !aligned4(w_depth) || !aligned4(W_color))
+        return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    if ((int64_t)ldm->L * ldm->H * ldm->W * ldm->C >= ((int64_t)1 << 38))
+        return fail(QK_EUNSUPPORTED, "LDM too large");
     return QK_OK;
 }
 
@@ -1070,6 +1110,50 @@ qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk
     p.max_pixels = maxpix;
     hipError_t e = qk::launch_ray_encoding(p, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "ray encoding launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_upsample2x_check(const void *src, void *dst, int32_t N, int32_t H, int32_t W,
+                              int32_t C, qk_dtype dtype) {
+    return check_upsample2x(src, dst, N, H, W, C, dtype);
+}
+
+qk_status qk_upsample2x(qk_context *ctx, void *hip_stream, const void *src, void *dst, int32_t N,
+                        int32_t H, int32_t W, int32_t C, qk_dtype dtype) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_upsample2x(src, dst, N, H, W, C, dtype);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk::Up2Params p{src, dst, N, H, W, C, dtype == QK_BF16 ? 1 : 0};
+    hipError_t e = qk::launch_upsample2x(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "upsample launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_ldm_decode_check(const qk_ldm *ldm, const float *w_sigma, const float *w_depth,
+                              const float *W_color, float near_, float far_,
+                              const float *color_out) {
+    return check_decode(ldm, w_sigma, w_depth, W_color, near_, far_, color_out);
+}
+
+qk_status qk_ldm_decode(qk_context *ctx, void *hip_stream, const qk_ldm *ldm,
+                        const float *w_sigma, const float *w_depth, const float *W_color,
+                        float near_, float far_, float *color_out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_decode(ldm, w_sigma, w_depth, W_color, near_, far_, color_out);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk::DecodeParams p{ldm->F, w_sigma, w_depth, W_color, ldm->depth, ldm->alpha, color_out,
+                       ldm->L, ldm->H, ldm->W, ldm->C, ldm->dtype == QK_BF16 ? 1 : 0,
+                       (float)(1.0 / (double)near_), (float)(1.0 / (double)far_)};
+    hipError_t e = qk::launch_ldm_decode(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "decode launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

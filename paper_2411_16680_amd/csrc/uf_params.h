@@ -211,3 +211,23 @@ struct RayParams {
 };
 
 }  // namespace qk
+
+namespace qk {
+
+// Exact 2x bilinear upsampling of channel-last volumes [N][H][W][C].
+struct Up2Params {
+    const void *src;                // [N][H][W][C]
+    void *dst;                      // [N][2H][2W][C]
+    int32_t N, H, W, C, bf16;
+};
+
+// Decode of an encoded LDM (the paper's absolute decode).
+struct DecodeParams {
+    const void *F;                  // [L][H][W][C]
+    const float *w_sigma, *w_depth, *W_color;   // [C], [C], [C][3]
+    float *depth, *alpha, *color;   // [L][H][W], [L][H][W], [L][H][W][3] or null
+    int32_t L, H, W, C, bf16;
+    float inv_near, inv_far;
+};
+
+}  // namespace qk

@@ -31,7 +31,8 @@ EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_upda
            "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
            "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
            "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
-           "qk_ray_encoding_check", "qk_camera_tables", "qk_last_error", "qk_version"]
+           "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check", "qk_ldm_decode",
+           "qk_ldm_decode_check", "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
 class QuarkError(RuntimeError):
@@ -144,13 +145,22 @@ def load() -> ctypes.CDLL:
                 P(qk_feature_map_inout)]
     L.qk_ray_encoding.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + ray_args
     L.qk_ray_encoding_check.argtypes = ray_args
+    up_args = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+               ctypes.c_int32, ctypes.c_int]
+    L.qk_upsample2x.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + up_args
+    L.qk_upsample2x_check.argtypes = up_args
+    dec_args = [P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                ctypes.c_float, ctypes.c_void_p]
+    L.qk_ldm_decode.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + dec_args
+    L.qk_ldm_decode_check.argtypes = dec_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
                  "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
                  "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
-                 "qk_ray_encoding_check", "qk_camera_tables"):
+                 "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check",
+                 "qk_ldm_decode", "qk_ldm_decode_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -482,6 +492,42 @@ def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats, low_h
     """qk_ray_encoding_check: the status qk_ray_encoding would return."""
     args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw)
     return int(load().qk_ray_encoding_check(*args))
+
+
+def _up_args(src, dst):
+    shape = tuple(int(d) for d in src.shape)
+    N, H, W, C = shape if len(shape) == 4 else (1,) + shape
+    return (_ptr(src), _ptr(dst), N, H, W, C, _dtype_code(src))
+
+
+def upsample2x(ctx: Context, src, dst, stream=None):
+    """qk_upsample2x: src [N][H][W][C] (or [H][W][C]) -> dst [N][2H][2W][C],
+    float32 or bfloat16 device tensors."""
+    _check(ctx._lib.qk_upsample2x(ctx.handle, _stream_handle(stream), *_up_args(src, dst)))
+
+
+def upsample2x_check(src, dst) -> int:
+    return int(load().qk_upsample2x_check(*_up_args(src, dst)))
+
+
+def _dec_args(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out):
+    L, H, W, C = (int(d) for d in F.shape)
+    ldm = qk_ldm(_ptr(F), _ptr(depth), _ptr(alpha), L, H, W, C, _dtype_code(F))
+    return (ctypes.byref(ldm), _ptr(w_sigma), _ptr(w_depth), _ptr(W_color), float(near),
+            float(far), _ptr(color_out)), ldm
+
+
+def ldm_decode(ctx: Context, F, depth, alpha, w_sigma, w_depth, W_color, near: float, far: float,
+               color_out=None, stream=None):
+    """qk_ldm_decode: F [L][H][W][C] float32 / bfloat16 -> depth, alpha
+    [L][H][W] (and color_out [L][H][W][3] if given), the absolute decode."""
+    args, keep = _dec_args(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out)
+    _check(ctx._lib.qk_ldm_decode(ctx.handle, _stream_handle(stream), *args))
+
+
+def ldm_decode_check(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out=None) -> int:
+    args, keep = _dec_args(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out)
+    return int(load().qk_ldm_decode_check(*args))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

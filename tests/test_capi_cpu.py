@@ -426,3 +426,25 @@ def test_ray_encoding_checks():
     assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, low_hw=(-1, -1)) == lib.QK_ESHAPE
     assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
                                   low_hw=(1 << 14, 1 << 14)) == lib.QK_EUNSUPPORTED
+
+
+def test_upsample2x_and_decode_checks():
+    import torch
+    src = _FakeT((2, 5, 7, 8), 0x100000)
+    dst = _FakeT((2, 10, 14, 8), 0x200000)
+    assert lib.upsample2x_check(src, dst) == lib.QK_OK
+    assert lib.upsample2x_check(_FakeT((2, 5, 7, 3), 0x100004), _FakeT((2, 10, 14, 3), 0x200000)) == lib.QK_OK
+    assert lib.upsample2x_check(_FakeT((2, 5, 7, 8), 0x100004), dst) == lib.QK_EINVAL
+    assert lib.upsample2x_check(src, _FakeT((2, 10, 14, 8), 0x100000 + 64)) == lib.QK_EINVAL
+    assert "overlap" in lib.load().qk_last_error().decode()
+    assert lib.upsample2x_check(_FakeT((0, 5, 7, 8), 0x100000), dst) == lib.QK_ESHAPE
+    assert lib.upsample2x_check(_FakeT((2, 5, 7, 8), 0x100000, torch.float16), dst) == lib.QK_EDTYPE
+    F = _FakeT((4, 5, 6, 32), 0x300000, torch.bfloat16)
+    d, a = _FakeT((4, 5, 6), 0x400000), _FakeT((4, 5, 6), 0x410000)
+    ws, wd, wc = _FakeT((32,), 0x500000), _FakeT((32,), 0x510000), _FakeT((32, 3), 0x520000)
+    assert lib.ldm_decode_check(F, d, a, ws, wd, wc, 0.5, 20.0) == lib.QK_OK
+    assert lib.ldm_decode_check(F, d, a, ws, wd, wc, 0.5, 20.0, color_out=_FakeT((4, 5, 6, 3), 0x600000)) == lib.QK_OK
+    assert lib.ldm_decode_check(_FakeT((4, 5, 6, 24), 0x300000), d, a, ws, wd, wc, 0.5, 20.0) == lib.QK_EUNSUPPORTED
+    assert lib.ldm_decode_check(F, d, a, ws, wd, wc, 2.0, 1.0) == lib.QK_EINVAL
+    assert lib.ldm_decode_check(F, None, a, ws, wd, wc, 0.5, 20.0) == lib.QK_EINVAL
+    assert lib.ldm_decode_check(_FakeT((4, 5, 6, 32), 0x300008), d, a, ws, wd, wc, 0.5, 20.0) == lib.QK_EINVAL
