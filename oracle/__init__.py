@@ -437,6 +437,32 @@ def run_level(scene, level, *, steps: Optional[int] = None, rows=None, mode: int
     return out
 
 
+def run_chain(ch, attn_form: int = 0):
+    """The chained steps of a ``synth.ChainScene`` (Sec. 3.2.2 iterative
+    updates): step i > 0 takes step i - 1's updated features, collapses their
+    layers and / or upsamples them by two as its transition asks; every step
+    decodes its input features (the absolute decode), runs Update & Fuse with
+    the absolute decode, and the last one composites.  Returns the per-step
+    outputs and the final rgb / acc."""
+    F = _as_f64_array(ch.F0)
+    outs = []
+    for i, st in enumerate(ch.steps):
+        if i > 0:
+            F = outs[-1]["F"]
+            if st.collapse:
+                F = layer_collapse(F, *ch.collapse_w[i])
+            if st.upsample:
+                F = upsample2x(F)
+        w = ch.weights[i]
+        d, a, _ = decode_volume(F, w["w_sigma"], w["w_depth"], w["W_color"], ch.near, ch.far)
+        out = update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F, depth=d,
+                          alpha=a, mode=1, attn_form=attn_form)
+        out["F_in"], out["depth_in"], out["alpha_in"] = F, d, a
+        outs.append(out)
+    rgb, acc = composite(outs[-1]["color"], outs[-1]["alpha"])
+    return outs, rgb, acc
+
+
 def run_scene(scene, *, rows_per_level=None, mode: int = 0, attn_form: int = 0):
     """All levels of a scene.  ``rows_per_level`` is a list (one entry per
     level, None = all rows)."""

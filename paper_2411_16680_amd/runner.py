@@ -98,3 +98,93 @@ def level_outputs_numpy(dl: DeviceLevel) -> Dict[str, np.ndarray]:
         out["rgb"] = dl.rgb.cpu().numpy().astype(np.float64)
         out["acc"] = dl.acc.cpu().numpy().astype(np.float64)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Chained multi-scale updates (the paper's iterative Update & Fuse schedule)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DeviceChain:
+    feats: List[List]                  # per pyramid level, V device maps
+    F0: object
+    weights: List[Dict]                # per step, device tensors
+    qkw: List[object]                  # per step, qk_weights
+    collapse_w: List[Optional[tuple]]
+    F_in: List[Optional[object]]       # per step: upsampled / collapsed input (or None)
+    tmp: List[Optional[object]]        # per step: collapsed, before upsampling
+    depth: List[object]
+    alpha: List[object]
+    F_out: List[object]
+    depth_out: List[object]
+    alpha_out: List[object]
+    rgb: object
+    acc: Optional[object] = None
+
+
+def chain_to_device(ch, device="cuda") -> DeviceChain:
+    import torch
+    tdt = torch.bfloat16 if ch.dtype == "bf16" else torch.float32
+    feats = [[_to_dev(f, device) for f in lvl] for lvl in ch.feats]
+    ws = [{k: _to_dev(np.ascontiguousarray(v, dtype=np.float32), device) for k, v in w.items()}
+          for w in ch.weights]
+    qkw = [lib.make_weights(w, heads=st.heads) for w, st in zip(ws, ch.steps)]
+    cw = [None if c is None else tuple(_to_dev(np.ascontiguousarray(a, dtype=np.float32), device)
+                                       for a in c) for c in ch.collapse_w]
+    C = ch.C
+    F_in, tmp, depth, alpha, F_out, d_out, a_out = [], [], [], [], [], [], []
+    prev = None
+    for i, st in enumerate(ch.steps):
+        shp = (st.L, st.H, st.W)
+        if i > 0:                      # the transition must produce this step's grid
+            want = (prev[0] // 2 if st.collapse else prev[0],
+                    2 * prev[1] if st.upsample else prev[1], 2 * prev[2] if st.upsample else prev[2])
+            if shp != want or (st.collapse and prev[0] % 2):
+                raise ValueError(f"step {i}: grid {shp} does not follow {prev} by its transition")
+        if i > 0 and st.collapse:
+            tmp.append(torch.empty((st.L,) + prev[1:] + (C,), dtype=tdt, device=device))
+        else:
+            tmp.append(None)
+        F_in.append(torch.empty(shp + (C,), dtype=tdt, device=device)
+                    if i > 0 and st.upsample else None)
+        depth.append(torch.empty(shp, dtype=torch.float32, device=device))
+        alpha.append(torch.empty(shp, dtype=torch.float32, device=device))
+        F_out.append(torch.empty(shp + (C,), dtype=tdt, device=device))
+        d_out.append(torch.empty(shp, dtype=torch.float32, device=device))
+        a_out.append(torch.empty(shp, dtype=torch.float32, device=device))
+        prev = shp
+    last = ch.steps[-1]
+    rgb = torch.empty((last.H, last.W, 3), dtype=torch.float32, device=device)
+    return DeviceChain(feats, _to_dev(ch.F0, device), ws, qkw, cw, F_in, tmp, depth, alpha, F_out,
+                       d_out, a_out, rgb)
+
+
+def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard", stream=None):
+    """The steps in order.  Step i > 0 takes step i - 1's updated features,
+    collapses their layers (qk_layer_collapse) and / or doubles their grid
+    (qk_upsample2x) as its transition asks; every step decodes its input
+    features into depth and alpha (qk_ldm_decode), then runs Update & Fuse
+    with the absolute decode (qk_update_fuse); the last one composites."""
+    prec = "bf16" if ch.dtype == "bf16" else "fp32"
+    F = dc.F0
+    n = len(ch.steps)
+    for i, st in enumerate(ch.steps):
+        if i > 0:
+            F = dc.F_out[i - 1]
+            if st.collapse:
+                W1, W2 = dc.collapse_w[i]
+                lib.layer_collapse(ctx, F, W1, W2, dc.tmp[i], stream=stream)
+                F = dc.tmp[i]
+            if st.upsample:
+                lib.upsample2x(ctx, F, dc.F_in[i], stream=stream)
+                F = dc.F_in[i]
+        w = dc.weights[i]
+        lib.ldm_decode(ctx, F, dc.depth[i], dc.alpha[i], w["w_sigma"], w["w_depth"], w["W_color"],
+                       ch.near, ch.far, stream=stream)
+        last = i == n - 1
+        lib.update_fuse(ctx, ch.in_cams, dc.feats[st.level], ch.novel, ch.near, ch.far, dc.qkw[i],
+                        (F, dc.depth[i], dc.alpha[i]),
+                        (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
+                        precision=prec, attn_form=attn_form, mode="paper",
+                        rgb_out=dc.rgb if last else None, acc_out=dc.acc if last else None,
+                        stream=stream)

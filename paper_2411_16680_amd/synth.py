@@ -507,6 +507,81 @@ def make_ray(*, V: int = 8, W: int = 1920, H: int = 1080, levels=RAY_LEVELS, arc
     return RayScene(in_cams, novel, near, far, [(H // k, W // k) for k, _ in levels], Wr)
 
 
+# ----------------------------------------------------------------------------
+# Chained multi-scale updates: the Update & Fuse steps of the paper's network
+# table (LDM grid, layers, heads, transitions), random weights
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ChainStep:
+    L: int
+    H: int
+    W: int
+    level: int                     # pyramid level of its feature maps
+    heads: int
+    collapse: bool                 # halve the layers first (layer collapse)
+    upsample: bool                 # then double the grid (2x upsampling)
+
+
+# Quark's five Update & Fuse steps (appendix table, 1080p inputs): LDM grid
+# and layers after each step's transition, image-feature level (36x60,
+# 72x120, 144x240, 288x480), attention heads
+QUARK_STEPS = (ChainStep(24, 36, 64, 0, 4, False, False),
+               ChainStep(24, 72, 128, 1, 4, False, True),
+               ChainStep(24, 72, 128, 1, 4, False, False),
+               ChainStep(12, 144, 256, 2, 2, True, True),
+               ChainStep(6, 288, 512, 3, 1, True, True))
+QUARK_FEAT_HW = ((36, 60), (72, 120), (144, 240), (288, 480))
+
+
+@dataclass
+class ChainScene:
+    in_cams: List[Camera]
+    novel: Camera
+    near: float
+    far: float
+    C: int
+    steps: List[ChainStep]
+    feats: List[List[np.ndarray]]  # per pyramid level, V maps [Hf][Wf][C]
+    F0: np.ndarray                 # the first step's encoded LDM [L][H][W][C]
+    weights: List[Dict[str, np.ndarray]]          # per step (heads of C / heads)
+    collapse_w: List[Optional[tuple]]             # per step: (W1, W2) or None
+    dtype: str = "bf16"
+
+    @property
+    def V(self) -> int:
+        return len(self.in_cams)
+
+    def level(self, i: int) -> "Level":
+        """Step i as a Level (its state arrays are produced by the chain)."""
+        st = self.steps[i]
+        return Level(st.L, st.H, st.W, self.C, self.C, st.heads, self.C // st.heads,
+                     self.feats[st.level], None, None, None, self.weights[i],
+                     composite=(i == len(self.steps) - 1))
+
+
+def make_chain(*, V: int = 8, steps=QUARK_STEPS, feat_hw=QUARK_FEAT_HW, C: int = 32,
+               input_hw=(1080, 1920), arc: float = 0.5, radius: float = 1.5, hfov: float = 60.0,
+               dtype: str = "bf16", seed: int = 1011) -> ChainScene:
+    """The rig of the multi-scale workload, one feature map per view and
+    pyramid level N(0, 1), the first step's LDM features N(0, 1), and per step
+    the attention / decode weights (std 1/sqrt(fan_in)) and, where it halves
+    the layers, the collapse MLP.  Draw order: cameras, features (level-major,
+    then view), F0, then per step its weights and collapse weights."""
+    rng = np.random.default_rng(seed)
+    FH, FW = input_hw
+    in_cams, novel = _arc_rig(rng, V, arc, radius, FW, FH, hfov, novel_radius_jitter=0.05)
+    feats = [[_cast(_normal(rng, (h, w, C)), dtype) for _ in range(V)] for h, w in feat_hw]
+    s0 = steps[0]
+    F0 = _cast(_normal(rng, (s0.L, s0.H, s0.W, C)), dtype)
+    weights, cw = [], []
+    for st in steps:
+        weights.append(_weights(rng, C, C, st.heads, C // st.heads))
+        cw.append((_normal(rng, (2 * C, C), 1.0 / math.sqrt(2 * C)),
+                   _normal(rng, (C, C), 1.0 / math.sqrt(C))) if st.collapse else None)
+    return ChainScene(in_cams, novel, 0.5, 20.0, C, list(steps), feats, F0, weights, cw, dtype)
+
+
 def to_bf16(scene: Scene) -> Scene:
     """The same draws stored in bfloat16 (features and LDM features are
     rounded to nearest-even; everything else is unchanged)."""
