@@ -484,6 +484,35 @@ def time_ray(ctx, reps: int = 20):
     return out
 
 
+CHAIN_WORKLOAD = ("the five Update & Fuse steps of the paper's network table at 1080p inputs, "
+                  "V = 8, C = 32, bfloat16, random weights: 24x36x64 (4 heads) -> 24x72x128 "
+                  "(upsampled, 4 heads) -> 24x72x128 (4 heads) -> 12x144x256 (collapsed and "
+                  "upsampled, 2 heads) -> 6x288x512 (collapsed and upsampled, 1 head) + composite; "
+                  "each step decodes its input first")
+
+
+def time_chain(ctx, reps: int = 20):
+    """The chained schedule: average time of one whole chain (all its
+    launches) with HIP events on the stream, and of each step's launches."""
+    import torch
+    from paper_2411_16680_amd import runner, synth
+    ch = synth.make_chain()
+    dc = runner.chain_to_device(ch)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        runner.run_chain(ctx, ch, dc, stream=stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        runner.run_chain(ctx, ch, dc, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"workload": CHAIN_WORKLOAD, "chain_ms": ms, "chains_per_s": 1000.0 / ms,
+            "layer_pixel_views": sum(st.L * st.H * st.W for st in ch.steps) * ch.V}
+
+
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
     """The standalone front-to-back composite (qk_composite) over a 1080p LDM
     of L layers: its average launch time with HIP events on its stream and
@@ -605,6 +634,9 @@ def main():
     ap.add_argument("--profile-train", action="store_true",
                     help="for rocprofv3: run --steps training steps (float32 forward + adjoint, "
                          "960x540 V=4) and exit without timing")
+    ap.add_argument("--profile-chain", action="store_true",
+                    help="for rocprofv3: run --steps chains of the paper's five-step schedule "
+                         "(1080p inputs, V=8, bf16) and exit without timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-run", action="store_true",
@@ -614,7 +646,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path would shard by output-pixel strips; see the design notes)",
+              "(the path would shard by output-pixel strips)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -633,6 +665,14 @@ def main():
     if args.profile_train:
         t = time_training_step(ctx, steps=args.steps, warmup=1)
         log(f"profile training steps: {t['step_ms']:.3f} ms each")
+        return
+    if args.profile_chain:
+        ch = synth.make_chain()
+        dc = runner.chain_to_device(ch)
+        for s in range(args.steps):
+            runner.run_chain(ctx, ch, dc)
+            torch.cuda.synchronize()
+        log(f"profile chains: {args.steps} done")
         return
 
     log("drawing the 1080p multi-scale workload (V=8)")
@@ -741,6 +781,11 @@ def main():
             f"pyramid (levels {lv} us)")
     torch.cuda.empty_cache()
 
+    chain = time_chain(ctx)
+    log(f"chained paper schedule: {chain['chain_ms']:.3f} ms per chain of 5 steps "
+        f"({chain['chains_per_s']:.0f} per s)")
+    torch.cuda.empty_cache()
+
     composite = time_composite(ctx)
     log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
         f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
@@ -819,6 +864,7 @@ def main():
         "residual_conv": conv,
         "layer_collapse": collapse,
         "ray_encoding": ray,
+        "chain": chain,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,
