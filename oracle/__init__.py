@@ -439,16 +439,18 @@ def run_level(scene, level, *, steps: Optional[int] = None, rows=None, mode: int
 
 def run_chain(ch, attn_form: int = 0):
     """The chained steps of a ``synth.ChainScene`` (Sec. 3.2.2 iterative
-    updates): step i > 0 takes step i - 1's updated features, collapses their
+    updates): step i > 0 takes step i - 1's output features, collapses their
     layers and / or upsamples them by two as its transition asks; every step
     decodes its input features (the absolute decode), runs Update & Fuse with
-    the absolute decode, and the last one composites.  Returns the per-step
-    outputs and the final rgb / acc."""
+    the absolute decode and, if it has one, its residual CNN block; the last
+    step's output LDM (decoded after the block) is composited.  Returns the
+    per-step outputs and the final rgb / acc."""
     F = _as_f64_array(ch.F0)
     outs = []
+    n = len(ch.steps)
     for i, st in enumerate(ch.steps):
         if i > 0:
-            F = outs[-1]["F"]
+            F = outs[-1]["F_next"]
             if st.collapse:
                 F = layer_collapse(F, *ch.collapse_w[i])
             if st.upsample:
@@ -458,6 +460,13 @@ def run_chain(ch, attn_form: int = 0):
         out = update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F, depth=d,
                           alpha=a, mode=1, attn_form=attn_form)
         out["F_in"], out["depth_in"], out["alpha_in"] = F, d, a
+        out["F_next"] = out["F"]
+        if st.conv:
+            out["F_conv"] = residual_conv(out["F"], *ch.conv_w[i])
+            out["F_next"] = out["F_conv"]
+            if i == n - 1:
+                out["depth"], out["alpha"], out["color"] = decode_volume(
+                    out["F_conv"], w["w_sigma"], w["w_depth"], w["W_color"], ch.near, ch.far)
         outs.append(out)
     rgb, acc = composite(outs[-1]["color"], outs[-1]["alpha"])
     return outs, rgb, acc

@@ -111,7 +111,9 @@ class DeviceChain:
     weights: List[Dict]                # per step, device tensors
     qkw: List[object]                  # per step, qk_weights
     collapse_w: List[Optional[tuple]]
+    conv_w: List[Optional[tuple]]
     F_in: List[Optional[object]]       # per step: upsampled / collapsed input (or None)
+    F_conv: List[Optional[object]]     # per step: after the residual CNN block (or None)
     tmp: List[Optional[object]]        # per step: collapsed, before upsampling
     depth: List[object]
     alpha: List[object]
@@ -119,6 +121,7 @@ class DeviceChain:
     depth_out: List[object]
     alpha_out: List[object]
     rgb: object
+    color: Optional[object] = None     # last step with a CNN block: decoded colour
     acc: Optional[object] = None
 
 
@@ -131,8 +134,10 @@ def chain_to_device(ch, device="cuda") -> DeviceChain:
     qkw = [lib.make_weights(w, heads=st.heads) for w, st in zip(ws, ch.steps)]
     cw = [None if c is None else tuple(_to_dev(np.ascontiguousarray(a, dtype=np.float32), device)
                                        for a in c) for c in ch.collapse_w]
+    kw = [None if c is None else tuple(_to_dev(np.ascontiguousarray(a, dtype=np.float32), device)
+                                       for a in c) for c in ch.conv_w]
     C = ch.C
-    F_in, tmp, depth, alpha, F_out, d_out, a_out = [], [], [], [], [], [], []
+    F_in, tmp, depth, alpha, F_out, d_out, a_out, F_conv = [], [], [], [], [], [], [], []
     prev = None
     for i, st in enumerate(ch.steps):
         shp = (st.L, st.H, st.W)
@@ -150,27 +155,34 @@ def chain_to_device(ch, device="cuda") -> DeviceChain:
         depth.append(torch.empty(shp, dtype=torch.float32, device=device))
         alpha.append(torch.empty(shp, dtype=torch.float32, device=device))
         F_out.append(torch.empty(shp + (C,), dtype=tdt, device=device))
+        F_conv.append(torch.empty(shp + (C,), dtype=tdt, device=device) if st.conv else None)
         d_out.append(torch.empty(shp, dtype=torch.float32, device=device))
         a_out.append(torch.empty(shp, dtype=torch.float32, device=device))
         prev = shp
     last = ch.steps[-1]
     rgb = torch.empty((last.H, last.W, 3), dtype=torch.float32, device=device)
-    return DeviceChain(feats, _to_dev(ch.F0, device), ws, qkw, cw, F_in, tmp, depth, alpha, F_out,
-                       d_out, a_out, rgb)
+    color = (torch.empty((last.L, last.H, last.W, 3), dtype=torch.float32, device=device)
+             if last.conv else None)
+    return DeviceChain(feats, _to_dev(ch.F0, device), ws, qkw, cw, kw, F_in, F_conv, tmp, depth,
+                       alpha, F_out, d_out, a_out, rgb, color)
 
 
 def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard", stream=None):
-    """The steps in order.  Step i > 0 takes step i - 1's updated features,
+    """The steps in order.  Step i > 0 takes step i - 1's output features,
     collapses their layers (qk_layer_collapse) and / or doubles their grid
     (qk_upsample2x) as its transition asks; every step decodes its input
-    features into depth and alpha (qk_ldm_decode), then runs Update & Fuse
-    with the absolute decode (qk_update_fuse); the last one composites."""
+    features into depth and alpha (qk_ldm_decode), runs Update & Fuse with
+    the absolute decode (qk_update_fuse) and, if it has one, its residual CNN
+    block (qk_residual_conv).  The last step composites its output: inside
+    Update & Fuse, or after its CNN block by decoding the block's output
+    (qk_ldm_decode) and compositing it (qk_composite)."""
     prec = "bf16" if ch.dtype == "bf16" else "fp32"
     F = dc.F0
     n = len(ch.steps)
     for i, st in enumerate(ch.steps):
         if i > 0:
-            F = dc.F_out[i - 1]
+            prev = ch.steps[i - 1]
+            F = dc.F_conv[i - 1] if prev.conv else dc.F_out[i - 1]
             if st.collapse:
                 W1, W2 = dc.collapse_w[i]
                 lib.layer_collapse(ctx, F, W1, W2, dc.tmp[i], stream=stream)
@@ -181,10 +193,19 @@ def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard"
         w = dc.weights[i]
         lib.ldm_decode(ctx, F, dc.depth[i], dc.alpha[i], w["w_sigma"], w["w_depth"], w["W_color"],
                        ch.near, ch.far, stream=stream)
-        last = i == n - 1
+        comp = i == n - 1 and not st.conv
         lib.update_fuse(ctx, ch.in_cams, dc.feats[st.level], ch.novel, ch.near, ch.far, dc.qkw[i],
                         (F, dc.depth[i], dc.alpha[i]),
                         (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
                         precision=prec, attn_form=attn_form, mode="paper",
-                        rgb_out=dc.rgb if last else None, acc_out=dc.acc if last else None,
+                        rgb_out=dc.rgb if comp else None, acc_out=dc.acc if comp else None,
                         stream=stream)
+        if st.conv:
+            K1, K2 = dc.conv_w[i]
+            lib.residual_conv(ctx, dc.F_out[i], K1, K2, dc.F_conv[i], stream=stream)
+            if i == n - 1:
+                # the output LDM: decode of the block's output, then composite
+                lib.ldm_decode(ctx, dc.F_conv[i], dc.depth_out[i], dc.alpha_out[i], w["w_sigma"],
+                               w["w_depth"], w["W_color"], ch.near, ch.far, color_out=dc.color,
+                               stream=stream)
+                lib.composite(ctx, dc.color, dc.alpha_out[i], dc.rgb, dc.acc, stream=stream)

@@ -521,16 +521,18 @@ class ChainStep:
     heads: int
     collapse: bool                 # halve the layers first (layer collapse)
     upsample: bool                 # then double the grid (2x upsampling)
+    conv: bool = False             # a residual CNN block after the attention
 
 
 # Quark's five Update & Fuse steps (appendix table, 1080p inputs): LDM grid
 # and layers after each step's transition, image-feature level (36x60,
-# 72x120, 144x240, 288x480), attention heads
-QUARK_STEPS = (ChainStep(24, 36, 64, 0, 4, False, False),
-               ChainStep(24, 72, 128, 1, 4, False, True),
-               ChainStep(24, 72, 128, 1, 4, False, False),
-               ChainStep(12, 144, 256, 2, 2, True, True),
-               ChainStep(6, 288, 512, 3, 1, True, True))
+# 72x120, 144x240, 288x480), attention heads, one residual CNN block after
+# the attention
+QUARK_STEPS = (ChainStep(24, 36, 64, 0, 4, False, False, True),
+               ChainStep(24, 72, 128, 1, 4, False, True, True),
+               ChainStep(24, 72, 128, 1, 4, False, False, True),
+               ChainStep(12, 144, 256, 2, 2, True, True, True),
+               ChainStep(6, 288, 512, 3, 1, True, True, True))
 QUARK_FEAT_HW = ((36, 60), (72, 120), (144, 240), (288, 480))
 
 
@@ -546,6 +548,7 @@ class ChainScene:
     F0: np.ndarray                 # the first step's encoded LDM [L][H][W][C]
     weights: List[Dict[str, np.ndarray]]          # per step (heads of C / heads)
     collapse_w: List[Optional[tuple]]             # per step: (W1, W2) or None
+    conv_w: List[Optional[tuple]]                 # per step: (W1, W2) 3x3 kernels or None
     dtype: str = "bf16"
 
     @property
@@ -565,21 +568,24 @@ def make_chain(*, V: int = 8, steps=QUARK_STEPS, feat_hw=QUARK_FEAT_HW, C: int =
                dtype: str = "bf16", seed: int = 1011) -> ChainScene:
     """The rig of the multi-scale workload, one feature map per view and
     pyramid level N(0, 1), the first step's LDM features N(0, 1), and per step
-    the attention / decode weights (std 1/sqrt(fan_in)) and, where it halves
-    the layers, the collapse MLP.  Draw order: cameras, features (level-major,
-    then view), F0, then per step its weights and collapse weights."""
+    the attention / decode weights (std 1/sqrt(fan_in)), where it halves the
+    layers the collapse MLP, and where it has one the residual CNN block's
+    kernels.  Draw order: cameras, features (level-major, then view), F0,
+    then per step its weights, collapse and conv weights."""
     rng = np.random.default_rng(seed)
     FH, FW = input_hw
     in_cams, novel = _arc_rig(rng, V, arc, radius, FW, FH, hfov, novel_radius_jitter=0.05)
     feats = [[_cast(_normal(rng, (h, w, C)), dtype) for _ in range(V)] for h, w in feat_hw]
     s0 = steps[0]
     F0 = _cast(_normal(rng, (s0.L, s0.H, s0.W, C)), dtype)
-    weights, cw = [], []
+    weights, cw, kw = [], [], []
     for st in steps:
         weights.append(_weights(rng, C, C, st.heads, C // st.heads))
         cw.append((_normal(rng, (2 * C, C), 1.0 / math.sqrt(2 * C)),
                    _normal(rng, (C, C), 1.0 / math.sqrt(C))) if st.collapse else None)
-    return ChainScene(in_cams, novel, 0.5, 20.0, C, list(steps), feats, F0, weights, cw, dtype)
+        kw.append((_normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C)),
+                   _normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C))) if st.conv else None)
+    return ChainScene(in_cams, novel, 0.5, 20.0, C, list(steps), feats, F0, weights, cw, kw, dtype)
 
 
 def to_bf16(scene: Scene) -> Scene:

@@ -5,9 +5,9 @@ step after step) against the FP64 oracle's chain, through the C-ABI.
 Bars.  One step's bounds are the Update & Fuse parity bounds of its form
 (float32: F' within 2e-4 + 2e-4|F'|, alpha 1e-4, disparity 1e-3 of one
 step's update; bfloat16: 4e-2 + 1.6e-2|F'|, 2e-2, 0.1); a step whose input
-came through a layer collapse adds the collapse's own bound (bfloat16:
-2e-2 + 1e-2|out| on its input, propagated through the same projections),
-so its bounds double.  In a chain compared end to end each step samples at
+came through a layer collapse or a residual CNN block adds that block's own
+bound (bfloat16: 2e-2 + 1e-2|out| on its input, propagated through the same
+projections), so its bounds double.  In a chain compared end to end each step samples at
 positions moved by the previous steps' depth errors, so step i's bounds
 scale by 2.5 (i + 1) as for the multi-step parity runs; F' is then held at
 the 99.9th percentile with the maximum within twice the bound.  The full
@@ -48,12 +48,14 @@ def _np(t):
 
 
 def _check_step(label, got_F, got_d, got_a, ref, L, near, far, tol, k, percentile):
+    """F' against ref["F"]; depth' and alpha' (if given) against ref's."""
     band = (0.5 / L) * (1.0 / near - 1.0 / far)
     excess = np.abs(got_F - ref["F"]) - tol["F_rel"] * k * np.abs(ref["F"])
     e_F = float(np.percentile(excess, 99.9)) if percentile else float(np.max(excess))
     e_Fmax = float(np.max(excess))
-    e_a = float(np.max(np.abs(got_a - ref["alpha"])))
-    e_d = float(np.max(np.abs(1.0 / got_d - 1.0 / ref["depth"]))) / band
+    e_a = float(np.max(np.abs(got_a - ref["alpha"]))) if got_a is not None else 0.0
+    e_d = (float(np.max(np.abs(1.0 / got_d - 1.0 / ref["depth"]))) / band
+           if got_d is not None else 0.0)
     _say(label, f"k={k:g} F excess {e_F:.3g} (max {e_Fmax:.3g}) alpha {e_a:.3g} disp {e_d:.3g}")
     assert e_F <= tol["F_abs"] * k, (label, "F")
     assert e_Fmax <= 2.0 * tol["F_abs"] * k, (label, "F max")
@@ -63,11 +65,12 @@ def _check_step(label, got_F, got_d, got_a, ref, L, near, far, tol, k, percentil
 
 SMALL = {
     # three steps: the paper's four, two and one heads, an upsampling, then a
-    # collapse with an upsampling (bfloat16: the collapse takes bfloat16)
-    "bf16": (synth.ChainStep(4, 6, 10, 0, 4, False, False),
-             synth.ChainStep(4, 12, 20, 1, 2, False, True),
-             synth.ChainStep(2, 24, 40, 2, 1, True, True)),
-    # float32: no collapse
+    # collapse with an upsampling, a residual CNN block after each attention
+    # (bfloat16: the collapse and the CNN block take bfloat16)
+    "bf16": (synth.ChainStep(4, 6, 10, 0, 4, False, False, True),
+             synth.ChainStep(4, 12, 20, 1, 2, False, True, True),
+             synth.ChainStep(2, 24, 40, 2, 1, True, True, True)),
+    # float32: no collapse, no CNN block
     "fp32": (synth.ChainStep(4, 6, 10, 0, 4, False, False),
              synth.ChainStep(4, 12, 20, 1, 2, False, True),
              synth.ChainStep(4, 12, 20, 1, 1, False, False)),
@@ -85,10 +88,12 @@ def test_small_chain_end_to_end(ctx, form):
     outs, rgb, acc = oracle.run_chain(ch)
     tol = TOL[form]
     for i, (st, ref) in enumerate(zip(steps, outs)):
-        k = 1.0 if i == 0 else 2.5 * (i + 1) * (2.0 if (form == "bf16" and st.collapse) else 1.0)
+        # inputs through a bfloat16 collapse or CNN block double the bounds
+        through = st.collapse or (i > 0 and steps[i - 1].conv)
+        k = 1.0 if i == 0 else 2.5 * (i + 1) * (2.0 if (form == "bf16" and through) else 1.0)
         _check_step(f"{form} step {i}", _np(dc.F_out[i]), _np(dc.depth_out[i]), _np(dc.alpha_out[i]),
                     ref, st.L, ch.near, ch.far, tol, k, percentile=i > 0)
-    k = 2.5 * len(steps)
+    k = 2.5 * len(steps) * (2.0 if steps[-1].conv else 1.0)
     e_rgb = float(np.max(np.abs(_np(dc.rgb) - rgb)))
     _say(form, f"rgb max-abs {e_rgb:.3g} (bound {tol['rgb'] * k:.3g})")
     assert e_rgb <= tol["rgb"] * k
@@ -101,8 +106,12 @@ def test_quark_schedule_step_by_step(ctx):
     checked kernel by kernel on sampled rows, each from the GPU's own input:
     the transition (collapse: 2e-2 + 1e-2|ref|, upsampling: 2^-8|ref| +
     1e-6 max|src|, from the GPU's previous output), the decode (1e-5 in
-    alpha and in disparity over the band) and the update (the single-step
-    bfloat16 bounds, from the GPU's decoded input)."""
+    alpha and in disparity over the band), the update (the single-step
+    bfloat16 bounds, from the GPU's decoded input), the residual CNN block
+    (2e-2 s + 1e-2|ref| with s the RMS of its input, at least 1: the bound
+    of the block's own parity test, made for unit-variance inputs, on row
+    slabs around the sampled rows, from the GPU's update output) and the output LDM (decode of the block's output 1e-5,
+    its composite 1e-4)."""
     ch = synth.make_chain()
     dc = runner.chain_to_device(ch)
     runner.run_chain(ctx, ch, dc)
@@ -116,7 +125,7 @@ def test_quark_schedule_step_by_step(ctx):
             F_in = _np(dc.F0)
         else:
             # the transition, from the GPU's previous output
-            src = _np(dc.F_out[i - 1])
+            src = _np(dc.F_conv[i - 1] if ch.steps[i - 1].conv else dc.F_out[i - 1])
             ref_in, bound = src, 0.0
             if st.collapse:
                 ref_in = oracle.layer_collapse(src, *ch.collapse_w[i])
@@ -125,7 +134,7 @@ def test_quark_schedule_step_by_step(ctx):
                 carried = oracle.upsample2x(bound) if st.collapse else 0.0
                 ref_in = oracle.upsample2x(ref_in)
                 bound = carried + 2.0 ** -8 * np.abs(ref_in) + 1e-6 * np.max(np.abs(src))
-            F_in = _np(dc.F_in[i] if st.upsample else (dc.tmp[i] if st.collapse else dc.F_out[i - 1]))
+            F_in = (_np(dc.F_in[i]) if st.upsample else _np(dc.tmp[i]) if st.collapse else src)
             if st.collapse or st.upsample:
                 b = bound[:, rows] if np.ndim(bound) else bound
                 r = float(np.max(np.abs(F_in[:, rows] - ref_in[:, rows]) / b))
@@ -140,14 +149,46 @@ def test_quark_schedule_step_by_step(ctx):
         e_da = float(np.max(np.abs(a_in[:, rows] - ar)))
         _say(label, f"decode disp/band {e_dd:.3g} alpha {e_da:.3g}")
         assert e_dd <= 1e-5 and e_da <= 1e-5, (label, "decode")
-        # the update, from the GPU's decoded input
+        # the update, from the GPU's decoded input (the last step's depth'
+        # and alpha' are the decode of its CNN block's output, checked below)
+        last = i == len(ch.steps) - 1
         ref = oracle.update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F_in,
                                  depth=d_in, alpha=a_in, rows=rows, mode=1)
-        _check_step(label, _np(dc.F_out[i])[:, rows], _np(dc.depth_out[i])[:, rows],
-                    _np(dc.alpha_out[i])[:, rows], ref, st.L, ch.near, ch.far, tol, 1.0,
-                    percentile=False)
-        if i == len(ch.steps) - 1:
-            rgb, _ = oracle.composite(ref["color"], ref["alpha"])
-            e_rgb = float(np.max(np.abs(_np(dc.rgb)[rows] - rgb)))
-            _say(f"quark rgb max-abs on sampled rows {e_rgb:.3g}")
-            assert e_rgb <= tol["rgb"]
+        skip = last and st.conv
+        _check_step(label, _np(dc.F_out[i])[:, rows],
+                    None if skip else _np(dc.depth_out[i])[:, rows],
+                    None if skip else _np(dc.alpha_out[i])[:, rows], ref, st.L, ch.near, ch.far,
+                    tol, 1.0, percentile=False)
+        if st.conv:
+            # the CNN block on slabs of rows around each sampled row, from the
+            # GPU's update output (rows beyond the slab cannot reach its centre)
+            # (the block's bound holds for unit-variance inputs; its two inner
+            # sums, and so their rounding, scale with the input's magnitude)
+            Fo, Fc = _np(dc.F_out[i]), _np(dc.F_conv[i])
+            scale = max(1.0, float(np.sqrt(np.mean(Fo ** 2))))
+            worst = 0.0
+            for r in rows:
+                lo, hi = max(0, r - 2), min(st.H, r + 3)
+                ref_c = oracle.residual_conv(Fo[:, lo:hi], *ch.conv_w[i])[:, r - lo]
+                worst = max(worst, float(np.max(np.abs(Fc[:, r] - ref_c) /
+                                                (2e-2 * scale + 1e-2 * np.abs(ref_c)))))
+            _say(label, f"residual block error / bound {worst:.3g} (input rms {scale:.3g})")
+            assert worst <= 1.0, (label, "conv")
+        if last:
+            if st.conv:
+                # the output LDM: decode of the block's output, composited
+                dr, ar, cr = oracle.decode_volume(_np(dc.F_conv[i])[:, rows], w["w_sigma"],
+                                                  w["w_depth"], w["W_color"], ch.near, ch.far)
+                e_dd = float(np.max(np.abs(1 / _np(dc.depth_out[i])[:, rows] - 1 / dr))) / band
+                e_da = float(np.max(np.abs(_np(dc.alpha_out[i])[:, rows] - ar)))
+                _say(label, f"output decode disp/band {e_dd:.3g} alpha {e_da:.3g}")
+                assert e_dd <= 1e-5 and e_da <= 1e-5, (label, "output decode")
+                rgb, _ = oracle.composite(cr, ar)
+                e_rgb = float(np.max(np.abs(_np(dc.rgb)[rows] - rgb)))
+                _say(f"quark rgb max-abs on sampled rows {e_rgb:.3g} (decode + composite)")
+                assert e_rgb <= 1e-4
+            else:
+                rgb, _ = oracle.composite(ref["color"], ref["alpha"])
+                e_rgb = float(np.max(np.abs(_np(dc.rgb)[rows] - rgb)))
+                _say(f"quark rgb max-abs on sampled rows {e_rgb:.3g}")
+                assert e_rgb <= tol["rgb"]
