@@ -347,8 +347,9 @@ def time_views(ctx, reps: int = 20):
                          "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_call": nbytes}}
 
 
-CONV_WORKLOAD = ("residual CNN block of a fusion block: two 3x3 convolutions 32 -> 32 with a "
-                 "ReLU, per layer, on a bfloat16 feature volume of 16 layers of 480x270")
+CONV_WORKLOAD = ("residual CNN block of a fusion block: RMS normalisation, two 3x3 convolutions "
+                 "32 -> 32 with a GELU between, per layer, on a bfloat16 feature volume of 16 "
+                 "layers of 480x270")
 
 
 def time_conv(ctx, reps: int = 50):

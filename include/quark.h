@@ -386,15 +386,17 @@ QK_API qk_status qk_render_to_views_check(int32_t V, const qk_camera *in_cams,
                                           const qk_camera *novel, const qk_ldm_decoded *ldm,
                                           const qk_view_image *views);
 
-/* ---- Residual CNN block of a fusion block (Sec. 3.2.2, "Iterative
- * Updates": each fusion block follows its attention with residual CNNs
- * that update the encoded LDM) ----
+/* ---- Residual CNN block of a fusion block (Sec. 3.3: the one-to-many
+ * attention is interleaved with residual 3x3 convolutional blocks; each
+ * fusion block of Sec. 3.2.2 is attention plus such blocks) ----
  * Per layer l, over the layer's (H, W) grid, with zero padding:
- *   F_out = F + W2 * relu(W1 * F),
+ *   F_out = F + W2 * gelu(W1 * N(F)),
+ *   N(F) = F / sqrt(mean_c F^2 + 1e-6) per pixel (the attention's pre-norm),
+ *   gelu(x) = x Phi(x) (the exact form),
  *   (W * X)(y, x)[co] = sum_{ky, kx, ci} X(y + ky - 1, x + kx - 1)[ci] W[ky][kx][ci][co].
  * bfloat16 feature volumes, MFMA bfloat16 operands with float32
- * accumulation; the ReLU output is rounded to bfloat16 as the second
- * convolution's operand; the sum is rounded to bfloat16 once.
+ * accumulation; the normalised input and the GELU output are rounded to
+ * bfloat16 as the convolutions' operands; the sum is rounded once.
  *   ldm_in, ldm_out  F [L][H][W][32] bfloat16 (depth, alpha unused; may be
  *                    NULL); ldm_out must not overlap ldm_in
  *   W1, W2           device float32 [3][3][32][32]

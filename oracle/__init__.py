@@ -278,8 +278,9 @@ def render_to_views(in_cams, novel, depth, alpha, color, view_hw) -> Dict[str, l
 # --------------------------------------------------------------------------
 
 def residual_conv(F, W1, W2) -> np.ndarray:
-    """V' = V + W2 * relu(W1 * V) per layer: F [L][H][W][C] (float32, or
-    bfloat16 bit patterns), W1, W2 [3][3][C][C]."""
+    """V' = V + W2 * gelu(W1 * N(V)) per layer (N the per-pixel RMS
+    normalisation): F [L][H][W][C] (float32, or bfloat16 bit patterns), W1,
+    W2 [3][3][C][C]."""
     F = _as_f64_array(F)
     W1, W2 = _f64(W1), _f64(W2)
     L, H, W, C = F.shape

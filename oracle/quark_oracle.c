@@ -733,14 +733,16 @@ OR_EXPORT int or_render_to_views(int V, const double *Kin, const double *Ein, co
 }
 
 /* ------------------------------------------------------------------------ */
-/* Residual CNN block of a fusion block (Sec. 3.2.2 "Iterative Updates": each */
-/* fusion block follows its attention with one or more residual CNNs that    */
-/* update the encoded LDM; the network tables of the appendix list them).   */
-/* Per LDM layer, over the layer's (H, W) grid: two 3x3 convolutions C -> C  */
-/* with zero padding and a ReLU between them, added to the input:            */
-/*   V' = V + W2 * relu(W1 * V),                                             */
+/* Residual CNN block of a fusion block (Sec. 3.3: the one-to-many attention */
+/* is interleaved with residual 3x3 convolutional blocks, mirroring a        */
+/* Transformer's MLP block; the network tables of the appendix list them).  */
+/* Per LDM layer, over the layer's (H, W) grid: the RMS normalisation N of  */
+/* the attention's pre-norm, per pixel over the channels, then two 3x3       */
+/* convolutions C -> C with zero padding and a GELU between them, added to   */
+/* the input:                                                                */
+/*   V' = V + W2 * gelu(W1 * N(V)),  gelu(x) = x Phi(x) = x (1 + erf(x/sqrt 2))/2, */
 /* out(y, x)[co] = sum_{ky, kx, ci} in(y + ky - 1, x + kx - 1)[ci] W[ky][kx][ci][co]. */
-/* No biases, no normalisation.                                              */
+/* No biases.                                                                */
 /* ------------------------------------------------------------------------ */
 
 static void conv3x3(const double *in, int H, int W, int C, const double *Wt, double *out)
@@ -770,8 +772,9 @@ OR_EXPORT void or_residual_conv(int L, int H, int W, int C, const double *F, con
         size_t n = (size_t)H * W * C, off = (size_t)l * n;
         double *h = malloc(sizeof(double) * n);
         double *g = malloc(sizeof(double) * n);
-        conv3x3(F + off, H, W, C, W1, h);
-        for (size_t i = 0; i < n; ++i) h[i] = h[i] > 0.0 ? h[i] : 0.0;
+        for (size_t p = 0; p < (size_t)H * W; ++p) or_rmsnorm(F + off + p * C, C, g + p * C);
+        conv3x3(g, H, W, C, W1, h);
+        for (size_t i = 0; i < n; ++i) h[i] = 0.5 * h[i] * (1.0 + erf(h[i] / sqrt(2.0)));
         conv3x3(h, H, W, C, W2, g);
         for (size_t i = 0; i < n; ++i) out[off + i] = F[off + i] + g[i];
         free(h);

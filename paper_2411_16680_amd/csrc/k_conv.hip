@@ -1,19 +1,24 @@
-// k_conv.hip -- residual CNN block of a fusion block (Sec. 3.2.2: each fusion
-// block follows its attention with residual CNNs that update the encoded
-// LDM): per layer, F_out = F + W2 * relu(W1 * F) with 3x3 kernels and zero
-// padding, C = 32 channels, bfloat16 storage and MFMA operands, float32
-// accumulation.
+// k_conv.hip -- residual CNN block of a fusion block (Sec. 3.3: the
+// one-to-many attention is interleaved with residual 3x3 convolutional
+// blocks, mirroring a Transformer's MLP block): per layer,
+// F_out = F + W2 * gelu(W1 * N(F)) with N the per-pixel RMS normalisation
+// over the channels (unit gain, eps 1e-6, as the attention's pre-norm),
+// 3x3 kernels and zero padding, gelu(x) = x Phi(x), C = 32 channels,
+// bfloat16 storage and MFMA operands, float32 accumulation.
 //
 // An implicit GEMM on v_mfma_f32_16x16x32_bf16: for each of the 9 taps, the
 // A operand is the tap's W^T (16 output channels x 32 input channels, one
 // fragment per half of the outputs) and the B operand 16 pixels x 32 input
 // channels -- one 16-byte LDS read per lane, since pixels are channel-last.
 // A persistent workgroup keeps both kernels' fragments in LDS and walks
-// 16 x 8 output tiles: it stages the 20 x 12 input region (2-pixel halo,
-// zeros outside the image), computes the first convolution on the 18 x 10
-// region the second one needs (ReLU, zeros outside the image -- the second
-// convolution pads with zeros too -- rounded to bfloat16 as its operand),
-// then the second convolution, adds the input and stores bfloat16.
+// 16 x 8 output tiles: it stages the 20 x 12 input region normalised (2-pixel
+// halo, zeros outside the image; a quad of lanes holds one pixel's four
+// 8-channel chunks and sums its squares with two lane exchanges), computes
+// the first convolution on the 18 x 10 region the second one needs (GELU,
+// zeros outside the image -- the second convolution pads with zeros too --
+// rounded to bfloat16 as its operand), then the second convolution, adds
+// the un-normalised input (read again from memory, where the staging just
+// brought it into the cache) and stores bfloat16.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -42,6 +47,8 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float((unsigned)h <<
 
 __device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
 // Weight fragments: lane (c, g) of fragment (conv, tap, half) holds
 // W[tap][8g .. 8g+7][16 half + c] (input channels along K).
 __global__ void __launch_bounds__(256) k_conv_frag(const ConvParams p) {
@@ -67,7 +74,6 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
     for (int i = tid; i < NFRAG; i += 256) s_w[i] = p.frag[i];
     const int64_t per_layer = (int64_t)p.tiles_x * p.tiles_y;
     uint16_t *mid16 = reinterpret_cast<uint16_t *>(s_mid);
-    const uint16_t *in16 = reinterpret_cast<const uint16_t *>(s_in);
 
     for (int64_t t = blockIdx.x; t < p.n_tiles; t += gridDim.x) {
         const int l = (int)(t / per_layer);
@@ -77,6 +83,8 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
         const uint16_t *Fl = p.F + (int64_t)l * p.H * p.W * kC;
         __syncthreads();                         // weights in; the previous tile is done
 
+        // the 4 lanes of a quad hold one pixel (256 and the trip count's
+        // last cut, 192, are multiples of 4, so quads stay whole)
         for (int i = tid; i < IY * IX * 4; i += 256) {
             const int pix = i >> 2, q = i & 3;
             const int r = pix / IX, c = pix - r * IX;
@@ -84,7 +92,24 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (y >= 0 && y < p.H && x >= 0 && x < p.W)
                 v = *reinterpret_cast<const uint4 *>(Fl + ((int64_t)y * p.W + x) * kC + 8 * q);
-            s_in[pix * 5 + q] = v;
+            const unsigned wd[4] = {v.x, v.y, v.z, v.w};
+            float f[8], ss = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                f[2 * j] = bf2f((uint16_t)(wd[j] & 0xffffu));
+                f[2 * j + 1] = bf2f((uint16_t)(wd[j] >> 16));
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ss = fmaf(f[j], f[j], ss);
+            ss += __shfl_xor(ss, 1);
+            ss += __shfl_xor(ss, 2);
+            const float rn = rsqrtf(ss * (1.0f / kC) + 1e-6f);   // outside: 0 * rn = 0
+            uint4 o;
+            o.x = f2bf(f[0] * rn) | ((unsigned)f2bf(f[1] * rn) << 16);
+            o.y = f2bf(f[2] * rn) | ((unsigned)f2bf(f[3] * rn) << 16);
+            o.z = f2bf(f[4] * rn) | ((unsigned)f2bf(f[5] * rn) << 16);
+            o.w = f2bf(f[6] * rn) | ((unsigned)f2bf(f[7] * rn) << 16);
+            s_in[pix * 5 + q] = o;
         }
         __syncthreads();
 
@@ -106,8 +131,8 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
                 const bool inside = y >= 0 && y < p.H && x >= 0 && x < p.W;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    mid16[pm * 40 + 4 * g + i] = inside ? f2bf(fmaxf(a0[i], 0.0f)) : (uint16_t)0;
-                    mid16[pm * 40 + 16 + 4 * g + i] = inside ? f2bf(fmaxf(a1[i], 0.0f)) : (uint16_t)0;
+                    mid16[pm * 40 + 4 * g + i] = inside ? f2bf(gelu(a0[i])) : (uint16_t)0;
+                    mid16[pm * 40 + 16 + 4 * g + i] = inside ? f2bf(gelu(a1[i])) : (uint16_t)0;
                 }
             }
         }
@@ -127,7 +152,7 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
             }
             const int y = y0 + r, x = x0 + n;
             if (y < p.H && x < p.W) {
-                const uint16_t *res = in16 + ((r + 2) * IX + n + 2) * 40;
+                const uint16_t *res = Fl + ((int64_t)y * p.W + x) * kC;   // un-normalised input
                 uint16_t o0[4], o1[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {

@@ -437,7 +437,7 @@ def _volume(F) -> qk_ldm:
 
 
 def residual_conv(ctx: Context, F_in, W1, W2, F_out, stream=None):
-    """qk_residual_conv: F_out = F_in + W2 * relu(W1 * F_in) per layer;
+    """qk_residual_conv: F_out = F_in + W2 * gelu(W1 * N(F_in)) per layer;
     F_in, F_out [L][H][W][32] bfloat16 device tensors, W1, W2 [3][3][32][32]
     float32."""
     a, b = _volume(F_in), _volume(F_out)

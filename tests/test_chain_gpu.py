@@ -108,9 +108,8 @@ def test_quark_schedule_step_by_step(ctx):
     1e-6 max|src|, from the GPU's previous output), the decode (1e-5 in
     alpha and in disparity over the band), the update (the single-step
     bfloat16 bounds, from the GPU's decoded input), the residual CNN block
-    (2e-2 s + 1e-2|ref| with s the RMS of its input, at least 1: the bound
-    of the block's own parity test, made for unit-variance inputs, on row
-    slabs around the sampled rows, from the GPU's update output) and the output LDM (decode of the block's output 1e-5,
+    (2e-2 + 1e-2|ref|, its own parity bound, on row slabs around the
+    sampled rows, from the GPU's update output) and the output LDM (decode of the block's output 1e-5,
     its composite 1e-4)."""
     ch = synth.make_chain()
     dc = runner.chain_to_device(ch)
@@ -162,17 +161,17 @@ def test_quark_schedule_step_by_step(ctx):
         if st.conv:
             # the CNN block on slabs of rows around each sampled row, from the
             # GPU's update output (rows beyond the slab cannot reach its centre)
-            # (the block's bound holds for unit-variance inputs; its two inner
-            # sums, and so their rounding, scale with the input's magnitude)
+            # (the block normalises its input, so its inner sums, and their
+            # rounding, do not grow with the input's magnitude)
             Fo, Fc = _np(dc.F_out[i]), _np(dc.F_conv[i])
-            scale = max(1.0, float(np.sqrt(np.mean(Fo ** 2))))
             worst = 0.0
             for r in rows:
                 lo, hi = max(0, r - 2), min(st.H, r + 3)
                 ref_c = oracle.residual_conv(Fo[:, lo:hi], *ch.conv_w[i])[:, r - lo]
                 worst = max(worst, float(np.max(np.abs(Fc[:, r] - ref_c) /
-                                                (2e-2 * scale + 1e-2 * np.abs(ref_c)))))
-            _say(label, f"residual block error / bound {worst:.3g} (input rms {scale:.3g})")
+                                                (2e-2 + 1e-2 * np.abs(ref_c)))))
+            rms = float(np.sqrt(np.mean(Fo ** 2)))
+            _say(label, f"residual block error / bound {worst:.3g} (input rms {rms:.3g})")
             assert worst <= 1.0, (label, "conv")
         if last:
             if st.conv:

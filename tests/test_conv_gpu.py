@@ -1,13 +1,14 @@
-"""Parity of the residual CNN block (qk_residual_conv: F' = F + W2 * relu(W1 *
-F) per layer, 3x3, zero padding) against the FP64 oracle, through the C-ABI.
+"""Parity of the residual CNN block (qk_residual_conv: F' = F + W2 *
+gelu(W1 * N(F)) per layer, N the per-pixel RMS normalisation, 3x3, zero
+padding) against the FP64 oracle, through the C-ABI.
 
 Bar (bfloat16 storage and operands, float32 accumulation):
 |F'_gpu - F'_oracle| <= 2e-2 + 1e-2 |F'|.  The kernels are rounded to
 bfloat16 (2^-9 relative per product, 288 products per output with random
-signs), so is the ReLU output feeding the second convolution, and the sum
-once more at the store (2^-9 |F'|); with unit-variance features and
-1/sqrt(fan_in) weights the two chained sums carry ~5e-3 typical, the bound
-is ~4 of those."""
+signs), so are the normalised input and the GELU output feeding the
+convolutions, and the sum once more at the store (2^-9 |F'|); with
+unit-variance features and 1/sqrt(fan_in) weights the two chained sums
+carry ~5e-3 typical, the bound is ~4 of those."""
 
 import sys
 
@@ -68,13 +69,18 @@ def test_conv_full_size_sampled_layers(ctx):
 
 
 def test_conv_identity_kernels(ctx):
-    """Centre-tap identities: F' = F + relu(F) up to the bf16 rounding of
-    the sum."""
+    """Centre-tap identities: F' = F + gelu(N(F)) up to three bfloat16
+    roundings, each at most 2^-8 of its value: the normalised input (through
+    gelu, whose slope is below 1.13), the GELU output and the sum."""
+    import math
     C = 32
     F, _, _ = synth.make_conv_block(L=2, H=11, W=21, seed=5)
     I = np.zeros((3, 3, C, C), dtype=np.float32)
     I[1, 1] = np.eye(C, dtype=np.float32)
     got = _gpu(ctx, F, I, I)
     Fv = synth.bf16_bits_to_f32(F).astype(np.float64)
-    ref = Fv + np.maximum(Fv, 0)
-    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) <= 2.0 ** -8
+    n = Fv / np.sqrt(np.mean(Fv ** 2, axis=-1, keepdims=True) + 1e-6)
+    g = np.vectorize(lambda v: 0.5 * v * (1.0 + math.erf(v / math.sqrt(2.0))))(n)
+    ref = Fv + g
+    bound = 2.0 ** -8 * (np.abs(ref) + 1.13 * np.abs(n) + np.abs(g)) + 1e-6
+    assert np.max(np.abs(got - ref) / bound) <= 1.0
