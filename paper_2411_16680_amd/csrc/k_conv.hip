@@ -3,7 +3,8 @@
 // blocks, mirroring a Transformer's MLP block): per layer,
 // F_out = F + W2 * gelu(W1 * N(F)) with N the per-pixel RMS normalisation
 // over the channels (unit gain, eps 1e-6, as the attention's pre-norm),
-// 3x3 kernels and zero padding, gelu(x) = x Phi(x), C = 32 channels,
+// 3x3 kernels and zero padding, gelu(x) = x Phi(x) (erf by Hastings'
+// approximation, 1.5e-7), C = 32 channels,
 // bfloat16 storage and MFMA operands, float32 accumulation.
 //
 // An implicit GEMM on v_mfma_f32_16x16x32_bf16: for each of the 9 taps, the
@@ -17,8 +18,9 @@
 // the first convolution on the 18 x 10 region the second one needs (GELU,
 // zeros outside the image -- the second convolution pads with zeros too --
 // rounded to bfloat16 as its operand), then the second convolution, adds
-// the un-normalised input (read again from memory, where the staging just
-// brought it into the cache) and stores bfloat16.
+// the un-normalised input (each lane's two pixels loaded into registers at
+// the start of the tile, so their latency hides behind the convolutions) and
+// stores bfloat16.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -47,7 +49,21 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float((unsigned)h <<
 
 __device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// gelu(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2, with erf from Hastings'
+// rational approximation (Abramowitz and Stegun 7.1.26): for z >= 0,
+// erf z = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-z^2},
+// t = 1 / (1 + p z), |error| <= 1.5e-7 -- far below the bfloat16 rounding the
+// result gets as an operand; odd in z.
+__device__ inline float gelu(float x) {
+    const float z = fabsf(x) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+    float poly = fmaf(1.061405429f, t, -1.453152027f);
+    poly = fmaf(poly, t, 1.421413741f);
+    poly = fmaf(poly, t, -0.284496736f);
+    poly = fmaf(poly, t, 0.254829592f);
+    const float e = 1.0f - poly * t * __expf(-z * z);      // erf |x| / sqrt 2
+    return 0.5f * x * (1.0f + copysignf(e, x));
+}
 
 // Weight fragments: lane (c, g) of fragment (conv, tap, half) holds
 // W[tap][8g .. 8g+7][16 half + c] (input channels along K).
@@ -81,18 +97,41 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
         const int ty = rem / p.tiles_x, tx = rem - ty * p.tiles_x;
         const int x0 = tx * TX, y0 = ty * TY;
         const uint16_t *Fl = p.F + (int64_t)l * p.H * p.W * kC;
+        // the residual (un-normalised input) of this lane's two output
+        // pixels, loaded now so that its latency hides behind the convolutions
+        uint2 resv[2][2];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int y = y0 + 2 * wave + rr, x = x0 + n;
+            resv[rr][0] = resv[rr][1] = make_uint2(0u, 0u);
+            if (y < p.H && x < p.W) {
+                const uint16_t *src = Fl + ((int64_t)y * p.W + x) * kC;
+                resv[rr][0] = *reinterpret_cast<const uint2 *>(src + 4 * g);
+                resv[rr][1] = *reinterpret_cast<const uint2 *>(src + 16 + 4 * g);
+            }
+        }
         __syncthreads();                         // weights in; the previous tile is done
 
-        // the 4 lanes of a quad hold one pixel (256 and the trip count's
-        // last cut, 192, are multiples of 4, so quads stay whole)
-        for (int i = tid; i < IY * IX * 4; i += 256) {
+        // the 4 lanes of a quad hold one pixel (256 and the last pass's cut,
+        // 192, are multiples of 4, so quads stay whole; whole waves skip the
+        // last pass); all loads are issued before the first is used
+        constexpr int NSTAGE = (IY * IX * 4 + 255) / 256;
+        uint4 v[NSTAGE];
+#pragma unroll
+        for (int k = 0; k < NSTAGE; ++k) {
+            const int i = tid + 256 * k;
             const int pix = i >> 2, q = i & 3;
             const int r = pix / IX, c = pix - r * IX;
             const int y = y0 - 2 + r, x = x0 - 2 + c;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y >= 0 && y < p.H && x >= 0 && x < p.W)
-                v = *reinterpret_cast<const uint4 *>(Fl + ((int64_t)y * p.W + x) * kC + 8 * q);
-            const unsigned wd[4] = {v.x, v.y, v.z, v.w};
+            v[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (i < IY * IX * 4 && y >= 0 && y < p.H && x >= 0 && x < p.W)
+                v[k] = *reinterpret_cast<const uint4 *>(Fl + ((int64_t)y * p.W + x) * kC + 8 * q);
+        }
+#pragma unroll
+        for (int k = 0; k < NSTAGE; ++k) {
+            const int i = tid + 256 * k;
+            if (k == NSTAGE - 1 && i >= IY * IX * 4) break;      // wave-uniform
+            const unsigned wd[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
             float f[8], ss = 0.0f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -109,7 +148,7 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
             o.y = f2bf(f[2] * rn) | ((unsigned)f2bf(f[3] * rn) << 16);
             o.z = f2bf(f[4] * rn) | ((unsigned)f2bf(f[5] * rn) << 16);
             o.w = f2bf(f[6] * rn) | ((unsigned)f2bf(f[7] * rn) << 16);
-            s_in[pix * 5 + q] = o;
+            s_in[(i >> 2) * 5 + (i & 3)] = o;
         }
         __syncthreads();
 
@@ -152,12 +191,15 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
             }
             const int y = y0 + r, x = x0 + n;
             if (y < p.H && x < p.W) {
-                const uint16_t *res = Fl + ((int64_t)y * p.W + x) * kC;   // un-normalised input
+                const uint16_t r0[4] = {(uint16_t)(resv[rr][0].x & 0xffffu), (uint16_t)(resv[rr][0].x >> 16),
+                                        (uint16_t)(resv[rr][0].y & 0xffffu), (uint16_t)(resv[rr][0].y >> 16)};
+                const uint16_t r1[4] = {(uint16_t)(resv[rr][1].x & 0xffffu), (uint16_t)(resv[rr][1].x >> 16),
+                                        (uint16_t)(resv[rr][1].y & 0xffffu), (uint16_t)(resv[rr][1].y >> 16)};
                 uint16_t o0[4], o1[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    o0[i] = f2bf(a0[i] + bf2f(res[4 * g + i]));
-                    o1[i] = f2bf(a1[i] + bf2f(res[16 + 4 * g + i]));
+                    o0[i] = f2bf(a0[i] + bf2f(r0[i]));
+                    o1[i] = f2bf(a1[i] + bf2f(r1[i]));
                 }
                 uint16_t *dst = p.F_out + (((int64_t)l * p.H + y) * p.W + x) * kC;
                 *reinterpret_cast<uint2 *>(dst + 4 * g) =
