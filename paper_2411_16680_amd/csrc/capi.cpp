@@ -231,15 +231,17 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
         return fail(QK_EUNSUPPORTED, "kernels support C == C_feat in {8,16,32,64} (got C=%d C_feat=%d)",
                     in->C, w->C_feat);
     if (w->heads != 1 || w->head_dim != in->C) {
-        // several heads: the standard form, C >= 32, heads x head_dim == C,
-        // head_dim 8 (C = 32) or 16 or 32
-        const bool ok = attn_form == QK_ATTN_STANDARD && in->C >= 32 &&
-                        w->heads * w->head_dim == in->C &&
-                        ((w->head_dim == 8 && in->C == 32) || w->head_dim == 16 || w->head_dim == 32);
+        // several heads: C >= 32, heads x head_dim == C, head_dim 8 (C = 32)
+        // or 16 or 32; the folded form not with e4m3 projections
+        const bool ok = in->C >= 32 && w->heads * w->head_dim == in->C &&
+                        ((w->head_dim == 8 && in->C == 32) || w->head_dim == 16 || w->head_dim == 32) &&
+                        !(attn_form == QK_ATTN_FOLDED &&
+                          (precision == QK_PREC_BF16_FP8PROJ || in->C != 32));
         if (!ok)
             return fail(QK_EUNSUPPORTED,
-                        "kernels support one head of C channels, or for C >= 32 in the standard "
-                        "form heads x head_dim == C with head_dim 16, 32 (or 8 at C = 32) "
+                        "kernels support one head of C channels, or for C >= 32 heads x head_dim "
+                        "== C with head_dim 16, 32 (or 8 at C = 32), the folded form of several "
+                        "heads at C = 32 without e4m3 projections "
                         "(got heads=%d head_dim=%d C=%d, %s form)",
                         w->heads, w->head_dim, in->C,
                         attn_form == QK_ATTN_FOLDED ? "folded" : "standard");
@@ -683,7 +685,8 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
     if (fold) {
         // fold W_k into the query and W_v into the output projection, on the
         // caller's stream, into the context's workspace
-        const size_t need = 2 * (size_t)w->C * w->C_feat;
+        const size_t per = (size_t)w->heads * w->C * w->C_feat;     // per folded matrix set
+        const size_t need = 2 * per;
         if (ctx->wfold_elems < need) {
             if (ctx->wfold) {
                 hipError_t se = hipStreamSynchronize(stream);
@@ -696,8 +699,8 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
                 return fail(QK_ENOMEM, "workspace of %zu floats", need);
             ctx->wfold_elems = need;
         }
-        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, ctx->wfold, ctx->wfold + (size_t)w->C * w->C_feat,
-                          w->C, w->C_feat, w->heads * w->head_dim,
+        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, ctx->wfold, ctx->wfold + per,
+                          w->C, w->C_feat, w->head_dim, w->heads,
                           1.0f / std::sqrt((float)w->head_dim)};
         hipError_t fe = qk::launch_fold_weights(fp, stream);
         if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));

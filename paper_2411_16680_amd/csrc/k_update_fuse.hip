@@ -62,14 +62,17 @@ struct Shape {
 
 // Weight-fragment slots in LDS: Q, [K, V,] O, decode.  The K/V slots exist
 // only when the view loop projects per-sample keys and values on MFMA.
-template <int C, bool KV>
+template <int C, bool KV, int HQ = 1>
 struct Frags {
+    // HQ query blocks (the heads of the one-to-many form, 1 otherwise); the
+    // output projection reads their HQ C-channel concatenation
     static constexpr int KC = Shape<C>::KC, NT = Shape<C>::NT, ND = Shape<C>::ND;
+    static constexpr int KCO = HQ * KC;
     static constexpr int OFF_Q = 0;
-    static constexpr int OFF_K = KC * NT;
+    static constexpr int OFF_K = HQ * KC * NT;
     static constexpr int OFF_V = OFF_K + (KV ? KC * NT : 0);
     static constexpr int OFF_O = OFF_V + (KV ? KC * NT : 0);
-    static constexpr int OFF_D = OFF_O + KC * NT;
+    static constexpr int OFF_D = OFF_O + KCO * NT;
     static constexpr int N = OFF_D + KC * ND;
 };
 
@@ -503,11 +506,13 @@ struct Occupancy {
 // MFMA loop, with the blended sample standing in for keys and values).
 template <int C, bool BF16, bool FOLD, bool F8, int HD>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(Occupancy<C, BF16, FOLD>::waves)))
+__attribute__((amdgpu_waves_per_eu((FOLD && HD != C) ? 2 : Occupancy<C, BF16, FOLD>::waves)))
 k_update_fuse(const UFParams p) {
     static_assert(!F8 || BF16, "e4m3 projections take bfloat16 storage");
-    static_assert(HD == C || (C >= 32 && !FOLD && (HD == 8 || (HD >= 16 && C % HD == 0))),
-                  "several heads: standard form, C >= 32, head width 8 or a multiple of 16");
+    static_assert(HD == C || (C >= 32 && (HD == 8 || (HD >= 16 && C % HD == 0))),
+                  "several heads: C >= 32, head width 8 or a multiple of 16");
+    static_assert(!(FOLD && HD != C && (F8 || C != 32)),
+                  "several folded heads: C = 32, bfloat16 or float32 (LDS holds HQ query blocks)");
     using SH = Shape<C>;
     using OP = Op<BF16>;
     using AF = typename OP::A;
@@ -524,7 +529,10 @@ k_update_fuse(const UFParams p) {
     constexpr int NS = (G == 1) ? ((HD >= 16) ? NT / TPH : NT) : NT;
     // the state of output tile t
     auto st_of = [](int t) constexpr { return (G == 1 && HD >= 16) ? t / TPH : t; };
-    using FR = Frags<C, STDLOOP>;
+    // the one-to-many form with several heads keeps one C-channel query, one
+    // softmax state and one running sum of the samples per head
+    constexpr int HQ = FOLD ? C / HD : 1;
+    using FR = Frags<C, STDLOOP, HQ>;
     static_assert(!TAPK || 64 * sizeof(MA) <= PIX * P * sizeof(float),
                   "tap staging must fit the o tile it shares");
     static_assert(TAPK || PIX * (C / 8 + (sizeof(MA) <= 16 ? 1 : 0)) * sizeof(MA) <= PIX * P * sizeof(float),
@@ -554,14 +562,18 @@ k_update_fuse(const UFParams p) {
     for (int e = tid; e < FR::N * 64; e += 256) {
         const int f = e >> 6, ln = e & 63;
         const int nn = ln & 15, gg = ln >> 4;
-        // kinds: 0 Q, 1 K, 2 V, 3 O, 4 decode
-        int kind = (f < FR::OFF_D) ? f / (KC * NT) : 4;
-        if (!STDLOOP && kind == 1) kind = 3;      // no K/V slots: the O slots follow Q
-        const int fi = (f < FR::OFF_D) ? f % (KC * NT) : f - FR::OFF_D;
+        // kinds: 0 Q, 1 K, 2 V, 3 O, 4 decode (no K/V slots in the
+        // one-to-many form: the O slots follow Q)
+        const int kind = f < FR::OFF_K ? 0 : f < FR::OFF_V ? 1 : f < FR::OFF_O ? 2
+                       : f < FR::OFF_D ? 3 : 4;
+        int fi = f - (kind == 0 ? FR::OFF_Q : kind == 1 ? FR::OFF_K : kind == 2 ? FR::OFF_V
+                      : kind == 3 ? FR::OFF_O : FR::OFF_D);
+        int head = 0;                             // query block of a Q fragment
+        if (HQ > 1 && kind == 0) { head = fi / (KC * NT); fi -= head * KC * NT; }
         const int ntile = (kind == 4) ? ND : NT;
         const int kc = fi / ntile, t = fi % ntile;
         const int ng = 16 * t + nn;               // output channel row of this lane
-        const float *Wm = kind == 0 ? (FOLD ? p.Wqk : p.Wq) : kind == 1 ? p.Wk
+        const float *Wm = kind == 0 ? (FOLD ? p.Wqk + (size_t)head * C * C : p.Wq) : kind == 1 ? p.Wk
                         : kind == 2 ? p.Wv : (FOLD ? p.Wvo : p.Wo);
         float vals[8];
 #pragma unroll
@@ -575,6 +587,10 @@ k_update_fuse(const UFParams p) {
                     if (FOLD) w = (kap % 8 == nn % 8) ? 1.0f : 0.0f;     // the blended sample itself
                     else w = Wm[(kap % 8) * C + (nn % 8)];
                 }
+            } else if (HQ > 1 && kind == 3) {
+                // output projection over the heads' concatenation: K slot kap
+                // is channel kap % C of head kap / C
+                w = (Wm + (size_t)(kap / C) * C * C)[(kap % C) * C + ng];
             } else if (kind < 4) {
                 if (kap / C == ng / C) w = Wm[(kap % C) * C + (ng % C)];
             } else {                                // decode heads: sigma, depth, r, g, b
@@ -703,7 +719,7 @@ k_update_fuse(const UFParams p) {
             for (int i = 0; i < 8; ++i) ss = fmaf(fa[kc][i], fa[kc][i], ss);
         ss = operand_pixel_sum<C>(ss);
         const float inv = rsqrt_(ss * (1.0f / (float)C) + 1e-6f);
-        f32x4 Q[NT];
+        f32x4 Q[HQ * NT];
         {
             MA Xn[KC];
 #pragma unroll
@@ -714,19 +730,20 @@ k_update_fuse(const UFParams p) {
                 Xn[kc] = MM::make(t8, f8_inv_x);
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                Q[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int qt = 0; qt < HQ * NT; ++qt) {
+                const int hq = qt / NT, t = qt % NT;
+                Q[qt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc)
-                    Q[t] = MM::mma(pfrag(FR::OFF_Q + kc * NT + t), Xn[kc], Q[t]);
+                    Q[qt] = MM::mma(pfrag(FR::OFF_Q + hq * KC * NT + kc * NT + t), Xn[kc], Q[qt]);
                 if constexpr (F8) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) Q[t][i] *= f8s[2] * f8s[0];
+                    for (int i = 0; i < 4; ++i) Q[qt][i] *= f8s[2] * f8s[0];
                 }
             }
         }
 
-        MA Ob[KC];                                     // o, operand layout
+        MA Ob[HQ * KC];                                // o, operand layout
         const Coord invdc = recip((Coord)d);
         const float d_ld = TAPK ? d : (ld_ok ? p.depth_in[rowbase + x_ld] : 1.0f);
         const Coord invdc_ld = TAPK ? invdc : recip((Coord)d_ld);
@@ -900,47 +917,57 @@ k_update_fuse(const UFParams p) {
         } else {
             // ---- one-to-many attention: q~ (the query with W_k folded in) to
             // the operand layout, then per view a dot product with the FP32
-            // sample and a weighted running sum of the samples themselves
+            // sample and a weighted running sum of the samples themselves --
+            // per head, through the same LDS slice one head after another
+            float qa[HQ][KC][8], ob[HQ][KC][8];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                float q4[4] = {Q[t][0], Q[t][1], Q[t][2], Q[t][3]};
-                lds_write4(&tO[(16 * sd(t) + n) * P + ed(t)], q4);
+            for (int hq = 0; hq < HQ; ++hq) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    float q4[4] = {Q[hq * NT + t][0], Q[hq * NT + t][1], Q[hq * NT + t][2],
+                                   Q[hq * NT + t][3]};
+                    lds_write4(&tO[(16 * sd(t) + n) * P + ed(t)], q4);
+                }
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    lds_read8(&tO[pl_b * P + ch0 + 32 * kc], qa[hq][kc]);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) ob[hq][kc][i] = 0.0f;
+                }
             }
-            float qa[KC][8], ob[KC][8];
+            float Mx[HQ], Zs[HQ];
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                lds_read8(&tO[pl_b * P + ch0 + 32 * kc], qa[kc]);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) ob[kc][i] = 0.0f;
-            }
-            float Mx = -1e30f, Zs = 0.0f;
+            for (int hq = 0; hq < HQ; ++hq) { Mx[hq] = -1e30f; Zs[hq] = 0.0f; }
             auto view_step = [&](const Taps<C, BF16> &cur) {
                 float sv[KC][8];
                 blend_taps<C, BF16>(cur, sv);
                 stage_sample<C>(tO, pl_ld, ch_ld, pl_b, ch0, sv);
-                float part = 0.0f;
 #pragma unroll
-                for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) part = fmaf(qa[kc][i], sv[kc][i], part);
-                const float a = operand_pixel_sum<C>(part);
-                float diff = a - Mx;
-                if (diff > 8.0f) {                 // lazily moved reference (see above)
-                    const float r = __expf(-diff);
-                    Zs *= r;
+                for (int hq = 0; hq < HQ; ++hq) {
+                    float part = 0.0f;
 #pragma unroll
                     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) ob[kc][i] *= r;
-                    Mx = a;
-                    diff = 0.0f;
+                        for (int i = 0; i < 8; ++i) part = fmaf(qa[hq][kc][i], sv[kc][i], part);
+                    const float a = operand_pixel_sum<C>(part);
+                    float diff = a - Mx[hq];
+                    if (diff > 8.0f) {             // lazily moved reference (see above)
+                        const float r = __expf(-diff);
+                        Zs[hq] *= r;
+#pragma unroll
+                        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                            for (int i = 0; i < 8; ++i) ob[hq][kc][i] *= r;
+                        Mx[hq] = a;
+                        diff = 0.0f;
+                    }
+                    const float pw = __expf(diff);
+                    Zs[hq] += pw;
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) ob[hq][kc][i] = fmaf(pw, sv[kc][i], ob[hq][kc][i]);
                 }
-                const float pw = __expf(diff);
-                Zs += pw;
-#pragma unroll
-                for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) ob[kc][i] = fmaf(pw, sv[kc][i], ob[kc][i]);
             };
             // two tap buffers in turn (see the standard loop)
             Taps<C, BF16> ta, tb;
@@ -956,13 +983,16 @@ k_update_fuse(const UFParams p) {
                 if (m + 1 < p.V) view_step(tb);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const float iz = recip(Zs);
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                float t8[8];
+            for (int hq = 0; hq < HQ; ++hq) {
+                const float iz = recip(Zs[hq]);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) t8[i] = ob[kc][i] * iz;
-                Ob[kc] = MM::make(t8, f8_inv_o);
+                for (int kc = 0; kc < KC; ++kc) {
+                    float t8[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) t8[i] = ob[hq][kc][i] * iz;
+                    Ob[hq * KC + kc] = MM::make(t8, f8_inv_o);
+                }
             }
         }
 
@@ -977,7 +1007,7 @@ k_update_fuse(const UFParams p) {
             f32x4 Fo = F8 ? f32x4{f4.x * ios, f4.y * ios, f4.z * ios, f4.w * ios}
                           : f32x4{f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) Fo = MM::mma(pfrag(FR::OFF_O + kc * NT + t), Ob[kc], Fo);
+            for (int kc = 0; kc < FR::KCO; ++kc) Fo = MM::mma(pfrag(FR::OFF_O + kc * NT + t), Ob[kc], Fo);
             if constexpr (F8) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) Fo[i] *= os;
@@ -1084,11 +1114,15 @@ static hipError_t launch_uf(const UFParams &p, hipStream_t s) {
 // prec: 0 float32, 1 bfloat16, 2 bfloat16 storage with e4m3 projections
 template <int C, int HD>
 static hipError_t launch_c(const UFParams &p, int prec, bool fold, hipStream_t s) {
-    if constexpr (HD != C) {                     // several heads: standard form only
+    if constexpr (HD != C && C != 32) {          // several heads, standard form only
         if (fold) return hipErrorInvalidValue;
         if (prec == 2) return launch_uf<C, true, false, true, HD>(p, s);
         if (prec == 1) return launch_uf<C, true, false, false, HD>(p, s);
         return launch_uf<C, false, false, false, HD>(p, s);
+    } else if constexpr (HD != C) {              // C = 32: also folded (no e4m3 form)
+        if (prec == 2) return fold ? hipErrorInvalidValue : launch_uf<C, true, false, true, HD>(p, s);
+        if (prec == 1) return fold ? launch_uf<C, true, true, false, HD>(p, s) : launch_uf<C, true, false, false, HD>(p, s);
+        return fold ? launch_uf<C, false, true, false, HD>(p, s) : launch_uf<C, false, false, false, HD>(p, s);
     } else {
         if (prec == 2) return fold ? launch_uf<C, true, true, true, C>(p, s) : launch_uf<C, true, false, true, C>(p, s);
         if (prec == 1) return fold ? launch_uf<C, true, true, false, C>(p, s) : launch_uf<C, true, false, false, C>(p, s);
@@ -1111,29 +1145,34 @@ hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool f
     }
 }
 
-// Folded weights of one-to-many attention (one head of width d = hd):
-//   Wqk[a][b] = sum_e Wq[a][e] Wk[b][e] / sqrt(d)   (C x Cf)
-//   Wvo[b][c] = sum_e Wv[b][e] Wo[e][c]             (Cf x C)
+// Folded weights of one-to-many attention, per head h of width d = hd
+// (channels h d .. h d + d - 1 of the Q/K/V projections):
+//   Wqk[h][a][b] = sum_e Wq[a][h d + e] Wk[b][h d + e] / sqrt(d)   (C x Cf)
+//   Wvo[h][b][c] = sum_e Wv[b][h d + e] Wo[h d + e][c]             (Cf x C)
 // One thread per output element.
 __global__ void __launch_bounds__(256) k_fold_weights(const FoldParams f) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nqk = f.C * f.Cf;
+    const int per = f.C * f.Cf, nqk = f.heads * per, stride = f.heads * f.hd;
     if (idx < nqk) {
-        const int a = idx / f.Cf, b = idx % f.Cf;
+        const int h = idx / per, j = idx - h * per;
+        const int a = j / f.Cf, b = j % f.Cf;
         float acc = 0.0f;
-        for (int e = 0; e < f.hd; ++e) acc = fmaf(f.Wq[a * f.hd + e], f.Wk[b * f.hd + e], acc);
+        for (int e = 0; e < f.hd; ++e)
+            acc = fmaf(f.Wq[a * stride + h * f.hd + e], f.Wk[b * stride + h * f.hd + e], acc);
         f.Wqk[idx] = acc * f.scale;
     } else if (idx < 2 * nqk) {
-        const int j = idx - nqk;
+        const int k = idx - nqk;
+        const int h = k / per, j = k - h * per;
         const int b = j / f.C, c = j % f.C;
         float acc = 0.0f;
-        for (int e = 0; e < f.hd; ++e) acc = fmaf(f.Wv[b * f.hd + e], f.Wo[e * f.C + c], acc);
-        f.Wvo[j] = acc;
+        for (int e = 0; e < f.hd; ++e)
+            acc = fmaf(f.Wv[b * stride + h * f.hd + e], f.Wo[(h * f.hd + e) * f.C + c], acc);
+        f.Wvo[k] = acc;
     }
 }
 
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s) {
-    const int n = 2 * f.C * f.Cf;
+    const int n = 2 * f.heads * f.C * f.Cf;
     hipLaunchKernelGGL(k_fold_weights, dim3((n + 255) / 256), dim3(256), 0, s, f);
     return hipGetLastError();
 }

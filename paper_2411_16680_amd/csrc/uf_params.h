@@ -40,9 +40,9 @@ struct UFParams {
 
 struct FoldParams {
     const float *Wq, *Wk, *Wv, *Wo;
-    float *Wqk, *Wvo;
-    int32_t C, Cf, hd;
-    float scale;
+    float *Wqk, *Wvo;              // [heads][C][Cf], [heads][Cf][C]
+    int32_t C, Cf, hd, heads;      // hd: the width of one head
+    float scale;                   // 1 / sqrt(hd)
 };
 
 struct CompParams {

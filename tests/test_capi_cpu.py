@@ -159,8 +159,8 @@ def test_rejections():
 
 
 def test_heads():
-    """Several heads: the standard form at C >= 32 with heads x head_dim == C
-    and head_dim 16, 32 (or 8 at C = 32); not the folded form."""
+    """Several heads at C >= 32 with heads x head_dim == C and head_dim 16,
+    32 (or 8 at C = 32); the folded form at C = 32 without e4m3 projections."""
     for C, heads, hd in ((32, 4, 8), (32, 2, 16), (64, 4, 16), (64, 2, 32), (32, 1, 32)):
         sc, f, w, l = _args(C=C, heads=heads, head_dim=hd)
         assert _check(sc, f, w, l) == lib.QK_OK, (C, heads, hd)
@@ -170,7 +170,13 @@ def test_heads():
     for C, heads, hd in ((64, 8, 8), (32, 4, 16), (32, 2, 8), (16, 2, 8), (8, 2, 4)):
         sc, f, w, l = _args(C=C, heads=heads, head_dim=hd)
         assert _check(sc, f, w, l) == lib.QK_EUNSUPPORTED, (C, heads, hd)
+    # the folded form of several heads: C = 32, not with e4m3 projections
     sc, f, w, l = _args(C=32, heads=4, head_dim=8)
+    assert _check(sc, f, w, l, attn_form="folded") == lib.QK_OK
+    sc, f, w, l = _args(C=32, heads=2, head_dim=16, dtype="bf16")
+    assert _check(sc, f, w, l, attn_form="folded", precision="bf16") == lib.QK_OK
+    assert _check(sc, f, w, l, attn_form="folded", precision="bf16_fp8proj") == lib.QK_EUNSUPPORTED
+    sc, f, w, l = _args(C=64, heads=4, head_dim=16)
     assert _check(sc, f, w, l, attn_form="folded") == lib.QK_EUNSUPPORTED
     assert "folded" in lib.load().qk_last_error().decode()
 

@@ -269,6 +269,25 @@ def test_several_heads(ctx, name, kw, form):
     compare(gpu, ref, form, sc, sc.levels[0], label=f"{name} standard")
 
 
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,kw", [h for h in HEADS if h[1]["C"] == 32],
+                         ids=[h[0] for h in HEADS if h[1]["C"] == 32])
+def test_several_heads_folded(ctx, name, kw, form):
+    """One-to-many attention with several heads (C = 32): per head the query
+    with its W_k folded in, a softmax over the views of its dot products with
+    the samples, a running sum of the samples, and its W_v W_o folded into
+    the output projection over the heads' concatenation.  The oracle runs
+    the folded form too (exactly equal to the standard form in real
+    arithmetic)."""
+    _say("folded heads", name, form)
+    sc = synth.make_custom(dtype="f32", seed=zlib.crc32(name.encode()) % 1000, **kw)
+    if form != "fp32":
+        sc = synth.to_bf16(sc)
+    ref = oracle.run_level(sc, sc.levels[0], attn_form=1)
+    gpu, _ = run_gpu_level(ctx, sc, attn_form="folded")
+    compare(gpu, ref, form, sc, sc.levels[0], label=f"{name} folded")
+
+
 def test_heads_differ_from_one_head(ctx):
     """The same weights read as four heads and as one head give different
     updates (the per-head softmax is not the one-head softmax)."""
