@@ -493,25 +493,29 @@ CHAIN_WORKLOAD = ("the five Update & Fuse steps of the paper's network table at 
 
 
 def time_chain(ctx, reps: int = 20):
-    """The chained schedule: average time of one whole chain (all its
-    launches) with HIP events on the stream, and of each step's launches."""
+    """The chained schedule, in the paper's one-to-many form and in the
+    standard form: average time of one whole chain (all its launches) with
+    HIP events on the stream."""
     import torch
     from paper_2411_16680_amd import runner, synth
     ch = synth.make_chain()
     dc = runner.chain_to_device(ch)
     stream = torch.cuda.current_stream()
-    for _ in range(3):
-        runner.run_chain(ctx, ch, dc, stream=stream)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
-        runner.run_chain(ctx, ch, dc, stream=stream)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    return {"workload": CHAIN_WORKLOAD, "chain_ms": ms, "chains_per_s": 1000.0 / ms,
-            "layer_pixel_views": sum(st.L * st.H * st.W for st in ch.steps) * ch.V}
+    out = {"workload": CHAIN_WORKLOAD,
+           "layer_pixel_views": sum(st.L * st.H * st.W for st in ch.steps) * ch.V}
+    for attn in ("folded", "standard"):
+        for _ in range(3):
+            runner.run_chain(ctx, ch, dc, attn_form=attn, stream=stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            runner.run_chain(ctx, ch, dc, attn_form=attn, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[attn] = {"chain_ms": ms, "chains_per_s": 1000.0 / ms}
+    return out
 
 
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
@@ -637,7 +641,8 @@ def main():
                          "960x540 V=4) and exit without timing")
     ap.add_argument("--profile-chain", action="store_true",
                     help="for rocprofv3: run --steps chains of the paper's five-step schedule "
-                         "(1080p inputs, V=8, bf16) and exit without timing")
+                         "(1080p inputs, V=8, bf16, one-to-many attention) and exit without "
+                         "timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-run", action="store_true",
@@ -671,7 +676,7 @@ def main():
         ch = synth.make_chain()
         dc = runner.chain_to_device(ch)
         for s in range(args.steps):
-            runner.run_chain(ctx, ch, dc)
+            runner.run_chain(ctx, ch, dc, attn_form="folded")
             torch.cuda.synchronize()
         log(f"profile chains: {args.steps} done")
         return
@@ -714,14 +719,15 @@ def main():
 
     # several heads: the 480x270 C = 32 level (the paper's width) with its
     # weights read as 1, 2 and 4 heads (standard form, bfloat16)
-    heads_ms = {}
+    heads_ms = {"standard": {}, "folded": {}}
     dl1 = runner.level_to_device(sc16.levels[1], composite=False)
-    for h in (1, 2, 4):
-        dl1.heads = h
-        dl1.extra.pop("qk_weights", None)
-        heads_ms[str(h)] = per_level_ms(ctx, sc16, [dl1], "standard", "bf16")[0]
-    log(f"heads on the 480x270 C32 level: " +
-        ", ".join(f"{h}: {v * 1000:.1f} us" for h, v in heads_ms.items()))
+    for attn in ("standard", "folded"):
+        for h in (1, 2, 4):
+            dl1.heads = h
+            dl1.extra.pop("qk_weights", None)
+            heads_ms[attn][str(h)] = per_level_ms(ctx, sc16, [dl1], attn, "bf16")[0]
+        log(f"heads on the 480x270 C32 level, {attn}: " +
+            ", ".join(f"{h}: {v * 1000:.1f} us" for h, v in heads_ms[attn].items()))
     del dl1
     torch.cuda.empty_cache()
 
@@ -783,8 +789,8 @@ def main():
     torch.cuda.empty_cache()
 
     chain = time_chain(ctx)
-    log(f"chained paper schedule: {chain['chain_ms']:.3f} ms per chain of 5 steps "
-        f"({chain['chains_per_s']:.0f} per s)")
+    log(f"chained paper schedule: {chain['folded']['chain_ms']:.3f} ms per chain of 5 steps "
+        f"(one-to-many attention), {chain['standard']['chain_ms']:.3f} ms (standard)")
     torch.cuda.empty_cache()
 
     composite = time_composite(ctx)
@@ -853,8 +859,7 @@ def main():
                    "per_level_ms": results["bf16_folded"]["per_level_ms"],
                    "note": "one-to-many (folded) attention, bf16: the paper's optimized form"},
         "per_level_ms": bf["per_level_ms"],
-        "heads_level1_ms": {"level": "480x270 L16 C32 V8, standard attention, bf16",
-                            "ms_by_heads": heads_ms},
+        "heads_level1_ms": {"level": "480x270 L16 C32 V8, bf16", "ms_by_heads": heads_ms},
         "layer_pixel_views_per_s": S / (ms_per_step / 1000.0),
         "frame_compulsory_bytes": frame_bytes,
         "frame_hbm_frac": frame_bytes / (ms_per_step / 1000.0) / (HBM_PEAK_GBS * 1e9),

@@ -77,15 +77,16 @@ SMALL = {
 }
 
 
+@pytest.mark.parametrize("attn", ["folded", "standard"])
 @pytest.mark.parametrize("form", ["bf16", "fp32"])
-def test_small_chain_end_to_end(ctx, form):
+def test_small_chain_end_to_end(ctx, form, attn):
     steps = SMALL[form]
     ch = synth.make_chain(V=3, steps=steps, feat_hw=((6, 10), (12, 20), (24, 40)),
                           input_hw=(48, 80), dtype="bf16" if form == "bf16" else "f32", seed=21)
     dc = runner.chain_to_device(ch)
-    runner.run_chain(ctx, ch, dc)
+    runner.run_chain(ctx, ch, dc, attn_form=attn)
     torch.cuda.synchronize()
-    outs, rgb, acc = oracle.run_chain(ch)
+    outs, rgb, acc = oracle.run_chain(ch, attn_form=1 if attn == "folded" else 0)
     tol = TOL[form]
     for i, (st, ref) in enumerate(zip(steps, outs)):
         # inputs through a bfloat16 collapse or CNN block double the bounds
@@ -99,7 +100,8 @@ def test_small_chain_end_to_end(ctx, form):
     assert e_rgb <= tol["rgb"] * k
 
 
-def test_quark_schedule_step_by_step(ctx):
+@pytest.mark.parametrize("attn", ["folded", "standard"])
+def test_quark_schedule_step_by_step(ctx, attn):
     """The five Update & Fuse steps of the paper's network table at 1080p
     inputs (V = 8, C = 32, 24 -> 24 -> 24 -> 12 -> 6 layers, 36x64 ->
     288x512, heads 4, 4, 4, 2, 1), bfloat16, run as one chain on the GPU and
@@ -113,13 +115,14 @@ def test_quark_schedule_step_by_step(ctx):
     its composite 1e-4)."""
     ch = synth.make_chain()
     dc = runner.chain_to_device(ch)
-    runner.run_chain(ctx, ch, dc)
+    runner.run_chain(ctx, ch, dc, attn_form=attn)
     torch.cuda.synchronize()
     tol = TOL["bf16"]
     band = 1.0 / ch.near - 1.0 / ch.far
+    af = 1 if attn == "folded" else 0
     for i, st in enumerate(ch.steps):
         rows = sorted({0, st.H // 3, st.H // 2, st.H - 1})
-        label = f"quark step {i} ({st.L}x{st.H}x{st.W}, {st.heads} heads)"
+        label = f"quark {attn} step {i} ({st.L}x{st.H}x{st.W}, {st.heads} heads)"
         if i == 0:
             F_in = _np(dc.F0)
         else:
@@ -152,7 +155,7 @@ def test_quark_schedule_step_by_step(ctx):
         # and alpha' are the decode of its CNN block's output, checked below)
         last = i == len(ch.steps) - 1
         ref = oracle.update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F_in,
-                                 depth=d_in, alpha=a_in, rows=rows, mode=1)
+                                 depth=d_in, alpha=a_in, rows=rows, mode=1, attn_form=af)
         skip = last and st.conv
         _check_step(label, _np(dc.F_out[i])[:, rows],
                     None if skip else _np(dc.depth_out[i])[:, rows],
