@@ -10,8 +10,8 @@ timed region starts.  The headline form is bfloat16 (MFMA projections, float32
 accumulation); the float32 form is timed on the same GPU and reported beside
 it.
 
-Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
-GPU.
+Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on
+one GPU.
 """
 
 from __future__ import annotations
@@ -651,7 +651,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path would shard by output-pixel strips)",
               file=sys.stderr)
         sys.exit(2)

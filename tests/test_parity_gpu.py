@@ -13,8 +13,8 @@ the arithmetic of each form (design notes, "Tolerances"):
     near the far plane, where a small disparity error is a large depth error.
 Multi-step runs compound: the second step samples at positions moved by the
 first step's depth error, so their bounds on the intermediate outputs scale
-with the step count.  Every measured error is written to
-gpurun_out/parity_report.json when that folder exists.
+with the step count.  Every measured error is written to parity_report.json
+in the directory QK_REPORT_DIR names, when it is set.
 """
 
 import math
@@ -113,8 +113,9 @@ def _write_report():
     yield
     import json
     import os
-    if os.path.isdir("gpurun_out") and REPORT:
-        with open(os.path.join("gpurun_out", "parity_report.json"), "w") as f:
+    out = os.environ.get("QK_REPORT_DIR")
+    if out and os.path.isdir(out) and REPORT:
+        with open(os.path.join(out, "parity_report.json"), "w") as f:
             json.dump(REPORT, f, indent=1)
 
 
