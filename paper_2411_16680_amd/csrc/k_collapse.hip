@@ -7,9 +7,11 @@
 // the pair's two 16-byte channel chunks per lane are the B operands of the
 // first product (K = 64 = two K blocks), its ReLU output crosses to the B
 // layout of the second product through the wave's LDS slice (rounded to
-// bfloat16 as the operand), and the mean is added in float32 from the
-// bfloat16 inputs before the single rounding at the store.  The weight
-// fragments are built once per (persistent) workgroup in LDS.
+// bfloat16 as the operand), the second product's output crosses back to the
+// load layout the same way (in float32), and each lane adds the mean of its
+// own two input chunks and stores 16 bytes: a wave writes its 16 pixels as
+// one contiguous 1 KiB.  The weight fragments are built once per
+// (persistent) workgroup in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -23,6 +25,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kC = 32, HS = 40;             // LDS pixel stride of the ReLU output (bf16)
+constexpr int YS = 36;                       // LDS pixel stride of the MLP output (float)
 
 __device__ inline f32x4 mma(const uint4 &a, const uint4 &b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -37,6 +40,7 @@ __global__ void __launch_bounds__(256) k_layer_collapse(const CollapseParams p) 
     // 4..5: W2 output half t.  Lane (c, g) holds W[8g .. 8g+7 of the block][16 t + c].
     __shared__ uint4 s_w[6 * 64];
     __shared__ uint16_t s_h[4][16 * HS];
+    __shared__ float s_y[4][16 * YS];            // the MLP output, to the load layout
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
     for (int i = tid; i < 6 * 64; i += 256) {
@@ -82,26 +86,31 @@ __global__ void __launch_bounds__(256) k_layer_collapse(const CollapseParams p) 
         f32x4 y0 = {0.0f, 0.0f, 0.0f, 0.0f}, y1 = {0.0f, 0.0f, 0.0f, 0.0f};
         y0 = mma(s_w[4 * 64 + lane], hb, y0);
         y1 = mma(s_w[5 * 64 + lane], hb, y1);
-        if (ok) {
-            uint16_t *dst = p.F_out + (j * p.npix + pix) * kC;
-            const uint2 a0 = *reinterpret_cast<const uint2 *>(fa + 4 * g);
-            const uint2 b0 = *reinterpret_cast<const uint2 *>(fb + 4 * g);
-            const uint2 a1 = *reinterpret_cast<const uint2 *>(fa + 16 + 4 * g);
-            const uint2 b1 = *reinterpret_cast<const uint2 *>(fb + 16 + 4 * g);
-            const uint16_t *pa0 = reinterpret_cast<const uint16_t *>(&a0);
-            const uint16_t *pb0 = reinterpret_cast<const uint16_t *>(&b0);
-            const uint16_t *pa1 = reinterpret_cast<const uint16_t *>(&a1);
-            const uint16_t *pb1 = reinterpret_cast<const uint16_t *>(&b1);
-            uint16_t o0[4], o1[4];
+        // the MLP output crosses to the load layout (lane (g, n): channels
+        // 8g .. 8g+7 of pixel n), where the pair's inputs already are, so a
+        // lane adds the mean from its registers and stores 16 whole bytes:
+        // one instruction writes the 16 pixels' 1 KiB contiguously
+        float *ys = s_y[wave];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                o0[i] = f2bf(0.5f * (bf2f(pa0[i]) + bf2f(pb0[i])) + y0[i]);
-                o1[i] = f2bf(0.5f * (bf2f(pa1[i]) + bf2f(pb1[i])) + y1[i]);
+        for (int i = 0; i < 4; ++i) {
+            ys[n * YS + 4 * g + i] = y0[i];
+            ys[n * YS + 16 + 4 * g + i] = y1[i];
+        }
+        __syncthreads();
+        if (ok) {
+            const float4 ya = *reinterpret_cast<const float4 *>(&ys[n * YS + 8 * g]);
+            const float4 yb = *reinterpret_cast<const float4 *>(&ys[n * YS + 8 * g + 4]);
+            const float yv[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+            const unsigned wa[4] = {xa.x, xa.y, xa.z, xa.w}, wb[4] = {xb.x, xb.y, xb.z, xb.w};
+            unsigned o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float lo = 0.5f * (bf2f((uint16_t)(wa[k] & 0xffffu)) + bf2f((uint16_t)(wb[k] & 0xffffu))) + yv[2 * k];
+                const float hi = 0.5f * (bf2f((uint16_t)(wa[k] >> 16)) + bf2f((uint16_t)(wb[k] >> 16))) + yv[2 * k + 1];
+                o[k] = f2bf(lo) | ((unsigned)f2bf(hi) << 16);
             }
-            *reinterpret_cast<uint2 *>(dst + 4 * g) =
-                make_uint2(o0[0] | ((unsigned)o0[1] << 16), o0[2] | ((unsigned)o0[3] << 16));
-            *reinterpret_cast<uint2 *>(dst + 16 + 4 * g) =
-                make_uint2(o1[0] | ((unsigned)o1[1] << 16), o1[2] | ((unsigned)o1[3] << 16));
+            *reinterpret_cast<uint4 *>(p.F_out + (j * p.npix + pix) * kC + 8 * g) =
+                make_uint4(o[0], o[1], o[2], o[3]);
         }
     }
 }
