@@ -9,6 +9,20 @@
  * of L layers x [H, W] in the novel frustum (depth d, alpha sigma, features
  * V), and an output image.
  *
+ * Entry points (each with a dry-run `_check` of its arguments):
+ *   qk_update_fuse           one Update & Fuse step (+ composite), Sec. 3.2.2-3.3
+ *   qk_update_fuse_backward  its adjoint into features, LDM and weights
+ *   qk_ldm_init              learned initialisation of an LDM, Sec. 3.2
+ *   qk_composite             front-to-back over composite, Sec. 3.1
+ *   qk_render_ibr            final render (upsample, activate, blend), Eq. 1
+ *   qk_render_to_views       render of an intermediate LDM into the views, Eq. 2
+ *   qk_residual_conv         residual CNN block of a fusion block, Sec. 3.3
+ *   qk_layer_collapse        layer collapse, Sec. 3.2.2
+ *   qk_ray_encoding          ray-direction encoding of the views, Sec. 3.2.1-3.2.2
+ *   qk_upsample2x            2x resolution transition, Sec. 3.2.2
+ *   qk_ldm_decode            absolute decode of an encoded LDM, Sec. 3.2.2-3.2.3
+ *   qk_camera_tables         the composed reprojection tables (host only)
+ *
  * Conventions for every entry point
  * ---------------------------------
  *  - Every call returns a qk_status; nothing throws across the ABI.  On a
