@@ -9,7 +9,8 @@
  * of L layers x [H, W] in the novel frustum (depth d, alpha sigma, features
  * V), and an output image.
  *
- * Entry points (each with a dry-run `_check` of its arguments):
+ * Entry points (all but qk_ldm_init, qk_composite and qk_camera_tables with
+ * a dry-run `_check` of their arguments):
  *   qk_update_fuse           one Update & Fuse step (+ composite), Sec. 3.2.2-3.3
  *   qk_update_fuse_backward  its adjoint into features, LDM and weights
  *   qk_ldm_init              learned initialisation of an LDM, Sec. 3.2
