@@ -175,8 +175,37 @@ def cpu_baseline(scene, target_s: float = 25.0):
             + ", ".join(f"{n}/{l.H} rows of level {i}" for i, (n, l) in
                         enumerate(zip(sampled, scene.levels)))
             + f"; full-frame time extrapolated per level by H/rows = {total_est:.1f} s")
+    # the same oracle on one thread, two rows per level (a few seconds)
+    oracle.set_num_threads(1)
+    try:
+        one_est = 0.0
+        for lvl in scene.levels:
+            rows = [lvl.H // 3, (2 * lvl.H) // 3]
+            t0 = time.perf_counter()
+            oracle.run_level(scene, lvl, rows=rows)
+            one_est += (time.perf_counter() - t0) * lvl.H / len(rows)
+    finally:
+        oracle.set_num_threads(threads)
     return {"value": fps, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": desc,
-            "s_per_frame": total_est}
+            "s_per_frame": total_est,
+            "one_thread": {"value": 1.0 / one_est, "unit": "frames/s", "s_per_frame": one_est,
+                           "sample": "two LDM rows per level, extrapolated by H/2"},
+            "host": _host_info()}
+
+
+def _host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "usable_cpus": usable, "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 # ---------------------------------------------------------------------------

@@ -52,8 +52,7 @@ def lib():
         L.or_render_to_views.restype = ctypes.c_int
         L.or_ray_encoding.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
-        for name in ("or_reprojection_matrix", "or_reproject", "or_reproject_T"):
-            pass
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -68,6 +67,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later OpenMP regions (n <= 0: unchanged)."""
+    lib().or_set_num_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -905,6 +905,17 @@ OR_EXPORT int or_num_threads(void)
 #endif
 }
 
+/* Thread count of the parallel regions started after this call from the
+   calling thread; n <= 0 leaves it unchanged. */
+OR_EXPORT void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint of one Update & Fuse step and its composite.                      */
 /*                                                                          */

@@ -427,6 +427,23 @@ def test_sampled_rows_equal_full_run_two_steps():
     np.testing.assert_array_equal(part["rgb"], full["rgb"][rows])
 
 
+def test_one_thread_run_equals_threaded_run():
+    # every layer-pixel is computed on its own, so the thread count must not
+    # change a single bit of the result
+    sc = synth.make_custom(V=3, H=12, W=21, C=8, L=3, steps=2, seed=31)
+    n = oracle.num_threads()
+    a = oracle.run_level(sc, sc.levels[0])
+    oracle.set_num_threads(1)
+    try:
+        assert oracle.num_threads() == 1
+        b = oracle.run_level(sc, sc.levels[0])
+    finally:
+        oracle.set_num_threads(n)
+    assert oracle.num_threads() == n
+    for k in ("F", "depth", "alpha", "color", "rgb"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
 def _torch_reimplementation(sc):
     """An independent float64 formulation of the c1 step: world-point chain
     for the reprojection, torch grid_sample for the sampling, torch rms_norm +
