@@ -144,52 +144,73 @@ def traffic_from_profiles(kernel_name: str, launches_key: str, src: str = KERNEL
 # CPU baseline: the FP64 oracle on a bounded sample of the same frame
 # ---------------------------------------------------------------------------
 
+def _level_time(t_small, n_small, t_big, n_big, H):
+    """Time of a whole level from two timed oracle calls on n_small < n_big
+    rows.  A call costs a fixed part (marshalling the level's maps to float64,
+    once per call) plus a part per row (layer-pixels are spread over the
+    threads in small chunks, so that part is linear in the rows); the whole
+    level is one call on H rows."""
+    if n_big > n_small:
+        per_row = max(0.0, (t_big - t_small) / (n_big - n_small))
+        fixed = max(0.0, t_small - per_row * n_small)
+    else:
+        per_row, fixed = t_big / n_big, 0.0
+    return fixed + per_row * H
+
+
+def _timed_level(oracle, scene, lvl, rows):
+    t0 = time.perf_counter()
+    oracle.run_level(scene, lvl, rows=rows)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(scene, target_s: float = 25.0):
     import oracle
     oracle.build(force=False)
     threads = oracle.num_threads()
-    # calibrate on two rows per level, then size the sample to ~target_s
-    est_full = 0.0
-    cal = []
+    # calibrate on 1 and 3 rows per level, then size the sample so that its
+    # per-row part takes about target_s
+    cal, fixed_all, row_all = [], 0.0, 0.0
     for lvl in scene.levels:
-        rows = [lvl.H // 2, lvl.H // 2 + 1]
-        t0 = time.perf_counter()
-        oracle.run_level(scene, lvl, rows=rows)
-        dt = time.perf_counter() - t0
-        cal.append(dt / len(rows))
-        est_full += dt / len(rows) * lvl.H
-    frac = min(1.0, max(0.002, target_s / max(est_full, 1e-9)))
+        r = lvl.H // 2
+        t1 = _timed_level(oracle, scene, lvl, [r])
+        t3 = _timed_level(oracle, scene, lvl, [r - 1, r, r + 1])
+        per_row = max(1e-9, (t3 - t1) / 2)
+        cal.append(t3)
+        fixed_all += max(0.0, t1 - per_row)
+        row_all += per_row * lvl.H
+    frac = min(1.0, max(0.002, target_s / max(row_all, 1e-9)))
     total_est = 0.0
     sampled = []
-    for lvl, per_row in zip(scene.levels, cal):
-        n = max(2, int(round(frac * lvl.H)))
+    for lvl, t_cal in zip(scene.levels, cal):
+        n = max(6, int(round(frac * lvl.H)))
         rows = np.linspace(0, lvl.H - 1, n).round().astype(int)
         rows = sorted(set(rows.tolist()))
-        t0 = time.perf_counter()
-        oracle.run_level(scene, lvl, rows=rows)
-        dt = time.perf_counter() - t0
-        total_est += dt * lvl.H / len(rows)
+        dt = _timed_level(oracle, scene, lvl, rows)
+        total_est += _level_time(t_cal, 3, dt, len(rows), lvl.H)
         sampled.append(len(rows))
     fps = 1.0 / total_est
     desc = ("FP64 oracle (C, OpenMP) on evenly spaced LDM rows of the same 1080p frame: "
             + ", ".join(f"{n}/{l.H} rows of level {i}" for i, (n, l) in
                         enumerate(zip(sampled, scene.levels)))
-            + f"; full-frame time extrapolated per level by H/rows = {total_est:.1f} s")
-    # the same oracle on one thread, two rows per level (a few seconds)
+            + "; each level's time = the per-call part plus the per-row part times H, both "
+              "fitted from this call and a 3-row call"
+            + f"; full frame {total_est:.1f} s")
+    # the same oracle on one thread, 1 and 3 rows per level (a few seconds)
     oracle.set_num_threads(1)
     try:
         one_est = 0.0
         for lvl in scene.levels:
-            rows = [lvl.H // 3, (2 * lvl.H) // 3]
-            t0 = time.perf_counter()
-            oracle.run_level(scene, lvl, rows=rows)
-            one_est += (time.perf_counter() - t0) * lvl.H / len(rows)
+            r = lvl.H // 3
+            t1 = _timed_level(oracle, scene, lvl, [r])
+            t3 = _timed_level(oracle, scene, lvl, [r, r + 1, r + 2])
+            one_est += _level_time(t1, 1, t3, 3, lvl.H)
     finally:
         oracle.set_num_threads(threads)
     return {"value": fps, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": desc,
             "s_per_frame": total_est,
             "one_thread": {"value": 1.0 / one_est, "unit": "frames/s", "s_per_frame": one_est,
-                           "sample": "two LDM rows per level, extrapolated by H/2"},
+                           "sample": "1 and 3 LDM rows per level, fitted the same way"},
             "host": _host_info()}
 
 
