@@ -144,20 +144,6 @@ def traffic_from_profiles(kernel_name: str, launches_key: str, src: str = KERNEL
 # CPU baseline: the FP64 oracle on a bounded sample of the same frame
 # ---------------------------------------------------------------------------
 
-def _level_time(t_small, n_small, t_big, n_big, H):
-    """Time of a whole level from two timed oracle calls on n_small < n_big
-    rows.  A call costs a fixed part (marshalling the level's maps to float64,
-    once per call) plus a part per row (layer-pixels are spread over the
-    threads in small chunks, so that part is linear in the rows); the whole
-    level is one call on H rows."""
-    if n_big > n_small:
-        per_row = max(0.0, (t_big - t_small) / (n_big - n_small))
-        fixed = max(0.0, t_small - per_row * n_small)
-    else:
-        per_row, fixed = t_big / n_big, 0.0
-    return fixed + per_row * H
-
-
 def _timed_level(oracle, scene, lvl, rows):
     t0 = time.perf_counter()
     oracle.run_level(scene, lvl, rows=rows)
@@ -165,52 +151,55 @@ def _timed_level(oracle, scene, lvl, rows):
 
 
 def cpu_baseline(scene, target_s: float = 25.0):
+    """The FP64 oracle on the host's cores, on evenly spaced rows of each
+    level.  A level's time is a per-call part (marshalling its maps to
+    float64) plus a per-row part, fitted to two timed calls and evaluated at
+    H rows; where the sample is the whole level, that is its measured time."""
     import oracle
+    from oracle.timing import fit_rows, fitted_time
     oracle.build(force=False)
     threads = oracle.num_threads()
-    # calibrate on 1 and 3 rows per level, then size the sample so that its
-    # per-row part takes about target_s
-    cal, fixed_all, row_all = [], 0.0, 0.0
+    # calibrate on 1 row and H/16 rows per level, then size the sample so
+    # that its per-row part takes about target_s
+    cal, row_all = [], 0.0
     for lvl in scene.levels:
-        r = lvl.H // 2
-        t1 = _timed_level(oracle, scene, lvl, [r])
-        t3 = _timed_level(oracle, scene, lvl, [r - 1, r, r + 1])
-        per_row = max(1e-9, (t3 - t1) / 2)
-        cal.append(t3)
-        fixed_all += max(0.0, t1 - per_row)
-        row_all += per_row * lvl.H
+        small, big = fit_rows(lvl.H)
+        t_s = _timed_level(oracle, scene, lvl, small)
+        t_b = _timed_level(oracle, scene, lvl, big)
+        cal.append((t_b, len(big)))
+        row_all += max(1e-9, (t_b - t_s) / (len(big) - len(small))) * lvl.H
     frac = min(1.0, max(0.002, target_s / max(row_all, 1e-9)))
     total_est = 0.0
     sampled = []
-    for lvl, t_cal in zip(scene.levels, cal):
-        n = max(6, int(round(frac * lvl.H)))
-        rows = np.linspace(0, lvl.H - 1, n).round().astype(int)
+    for lvl, (t_cal, n_cal) in zip(scene.levels, cal):
+        n = max(2 * n_cal, int(round(frac * lvl.H)))
+        rows = np.linspace(0, lvl.H - 1, min(n, lvl.H)).round().astype(int)
         rows = sorted(set(rows.tolist()))
         dt = _timed_level(oracle, scene, lvl, rows)
-        total_est += _level_time(t_cal, 3, dt, len(rows), lvl.H)
+        total_est += fitted_time(t_cal, n_cal, dt, len(rows), lvl.H)
         sampled.append(len(rows))
     fps = 1.0 / total_est
     desc = ("FP64 oracle (C, OpenMP) on evenly spaced LDM rows of the same 1080p frame: "
             + ", ".join(f"{n}/{l.H} rows of level {i}" for i, (n, l) in
                         enumerate(zip(sampled, scene.levels)))
-            + "; each level's time = the per-call part plus the per-row part times H, both "
-              "fitted from this call and a 3-row call"
-            + f"; full frame {total_est:.1f} s")
-    # the same oracle on one thread, 1 and 3 rows per level (a few seconds)
+            + "; each level's time = a per-call part plus a per-row part times H, fitted "
+              "to this call and an H/16-row call (the measured time where all rows ran)"
+            + f"; full frame {total_est:.2f} s")
+    # the same oracle on one thread, fitted from 1 row and H/16 rows per level
     oracle.set_num_threads(1)
     try:
         one_est = 0.0
         for lvl in scene.levels:
-            r = lvl.H // 3
-            t1 = _timed_level(oracle, scene, lvl, [r])
-            t3 = _timed_level(oracle, scene, lvl, [r, r + 1, r + 2])
-            one_est += _level_time(t1, 1, t3, 3, lvl.H)
+            small, big = fit_rows(lvl.H)
+            t_s = _timed_level(oracle, scene, lvl, small)
+            t_b = _timed_level(oracle, scene, lvl, big)
+            one_est += fitted_time(t_s, len(small), t_b, len(big), lvl.H)
     finally:
         oracle.set_num_threads(threads)
     return {"value": fps, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": desc,
             "s_per_frame": total_est,
             "one_thread": {"value": 1.0 / one_est, "unit": "frames/s", "s_per_frame": one_est,
-                           "sample": "1 and 3 LDM rows per level, fitted the same way"},
+                           "sample": "1 row and H/16 rows per level, fitted the same way"},
             "host": _host_info()}
 
 
