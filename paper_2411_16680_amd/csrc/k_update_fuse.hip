@@ -1149,25 +1149,41 @@ hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool f
 // (channels h d .. h d + d - 1 of the Q/K/V projections):
 //   Wqk[h][a][b] = sum_e Wq[a][h d + e] Wk[b][h d + e] / sqrt(d)   (C x Cf)
 //   Wvo[h][b][c] = sum_e Wv[b][h d + e] Wo[h d + e][c]             (Cf x C)
-// One thread per output element.
+// One thread per output element.  The operands of eight terms are loaded
+// before any of them is used, so a thread waits on memory once per eight
+// terms instead of once per term; the sum is still taken in order of e.
+__device__ __forceinline__ float fold_dot(const float *x, int xs, const float *y, int ys,
+                                          int n) {
+    float acc = 0.0f;
+    int e = 0;
+    for (; e + 8 <= n; e += 8) {
+        float u[8], v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            u[i] = x[(e + i) * xs];
+            v[i] = y[(e + i) * ys];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc = fmaf(u[i], v[i], acc);
+    }
+    for (; e < n; ++e) acc = fmaf(x[e * xs], y[e * ys], acc);
+    return acc;
+}
+
 __global__ void __launch_bounds__(256) k_fold_weights(const FoldParams f) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int per = f.C * f.Cf, nqk = f.heads * per, stride = f.heads * f.hd;
     if (idx < nqk) {
         const int h = idx / per, j = idx - h * per;
         const int a = j / f.Cf, b = j % f.Cf;
-        float acc = 0.0f;
-        for (int e = 0; e < f.hd; ++e)
-            acc = fmaf(f.Wq[a * stride + h * f.hd + e], f.Wk[b * stride + h * f.hd + e], acc);
-        f.Wqk[idx] = acc * f.scale;
+        f.Wqk[idx] = fold_dot(f.Wq + a * stride + h * f.hd, 1,
+                              f.Wk + b * stride + h * f.hd, 1, f.hd) * f.scale;
     } else if (idx < 2 * nqk) {
         const int k = idx - nqk;
         const int h = k / per, j = k - h * per;
         const int b = j / f.C, c = j % f.C;
-        float acc = 0.0f;
-        for (int e = 0; e < f.hd; ++e)
-            acc = fmaf(f.Wv[b * stride + h * f.hd + e], f.Wo[(h * f.hd + e) * f.C + c], acc);
-        f.Wvo[k] = acc;
+        f.Wvo[k] = fold_dot(f.Wv + b * stride + h * f.hd, 1,
+                            f.Wo + h * f.hd * f.C + c, f.C, f.hd);
     }
 }
 
