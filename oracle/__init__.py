@@ -165,6 +165,24 @@ def composite(color, alpha, back_to_front: bool = False):
     return rgb.reshape(pix_shape + (3,)), acc.reshape(pix_shape)
 
 
+def composite_backward(color, alpha, d_rgb, d_acc=None):
+    """Adjoint of ``composite``: (d_color [L][...][3], d_alpha [L][...]) from
+    d_rgb [...][3] and, optionally, d_acc [...] (Sec. 3.1, chain rule)."""
+    color = _f64(color)
+    alpha = _f64(alpha)
+    d_rgb = _f64(d_rgb)
+    L = alpha.shape[0]
+    pix_shape = alpha.shape[1:]
+    npix = int(np.prod(pix_shape)) if pix_shape else 1
+    dc = np.zeros((L, npix, 3))
+    da = np.zeros((L, npix))
+    dA = _f64(d_acc) if d_acc is not None else None
+    lib().or_composite_backward(L, ctypes.c_long(npix), _d(color), _d(alpha), _d(d_rgb),
+                                _d(dA) if dA is not None else ctypes.cast(None, _dp),
+                                _d(dc), _d(da))
+    return dc.reshape((L,) + pix_shape + (3,)), da.reshape((L,) + pix_shape)
+
+
 # --------------------------------------------------------------------------
 # Final render: upsample & activate, blend-weight image-based render
 # --------------------------------------------------------------------------

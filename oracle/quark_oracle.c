@@ -414,6 +414,54 @@ OR_EXPORT void or_composite_back_to_front(int L, long npix, const double *color,
     }
 }
 
+/* Adjoint of the over composite (Sec. 3.1, operator O), by the chain rule   */
+/* through rgb = sum_l T_l alpha_l c_l with T_l = prod_{j<l} (1 - alpha_j)   */
+/* and acc = 1 - T_L.  With B_l the composite of layers l..L-1 on their own  */
+/* (B_L = 0, B_l = alpha_l c_l + (1 - alpha_l) B_{l+1}) and P_l the product  */
+/* of (1 - alpha_j) over j >= l (P_L = 1):                                   */
+/*   d rgb / d c_l     = T_l alpha_l                                         */
+/*   d rgb / d alpha_l = T_l (c_l - B_{l+1})                                 */
+/*   d acc / d alpha_l = T_l P_{l+1}                                         */
+/* Inputs color [L][npix][3], alpha [L][npix], d_rgb [npix][3], d_acc [npix] */
+/* (NULL = 0); outputs d_color [L][npix][3], d_alpha [L][npix].             */
+/* ------------------------------------------------------------------------ */
+
+OR_EXPORT void or_composite_backward(int L, long npix, const double *color, const double *alpha,
+                                     const double *d_rgb, const double *d_acc, double *d_color,
+                                     double *d_alpha)
+{
+    for (long p = 0; p < npix; ++p) {
+        double *T = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+        double *B = (double *)malloc(sizeof(double) * (size_t)(L + 1) * 3);
+        double *P = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+        T[0] = 1.0;
+        for (int l = 0; l < L; ++l) T[l + 1] = T[l] * (1.0 - alpha[(size_t)l * npix + p]);
+        for (int j = 0; j < 3; ++j) B[(size_t)L * 3 + j] = 0.0;
+        P[L] = 1.0;
+        for (int l = L - 1; l >= 0; --l) {
+            double a = alpha[(size_t)l * npix + p];
+            for (int j = 0; j < 3; ++j)
+                B[(size_t)l * 3 + j] = a * color[((size_t)l * npix + p) * 3 + j] +
+                                       (1.0 - a) * B[(size_t)(l + 1) * 3 + j];
+            P[l] = P[l + 1] * (1.0 - a);
+        }
+        double gA = d_acc ? d_acc[p] : 0.0;
+        for (int l = 0; l < L; ++l) {
+            size_t e = (size_t)l * npix + p;
+            double a = alpha[e], da = gA * T[l] * P[l + 1];
+            for (int j = 0; j < 3; ++j) {
+                double g = d_rgb[p * 3 + j];
+                d_color[e * 3 + j] = g * T[l] * a;
+                da += g * T[l] * (color[e * 3 + j] - B[(size_t)(l + 1) * 3 + j]);
+            }
+            d_alpha[e] = da;
+        }
+        free(T);
+        free(B);
+        free(P);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* One Update & Fuse step over a set of LDM rows (every layer of each row).  */
 /* For each layer li, row y in rows[], column x and view m: reproject the    */
