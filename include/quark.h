@@ -15,6 +15,7 @@
  *   qk_update_fuse_backward  its adjoint into features, LDM and weights
  *   qk_ldm_init              learned initialisation of an LDM, Sec. 3.2
  *   qk_composite             front-to-back over composite, Sec. 3.1
+ *   qk_composite_backward    its adjoint, Sec. 3.1
  *   qk_render_ibr            final render (upsample, activate, blend), Eq. 1
  *   qk_render_to_views       render of an intermediate LDM into the views, Eq. 2
  *   qk_residual_conv         residual CNN block of a fusion block, Sec. 3.3
@@ -227,6 +228,33 @@ QK_API qk_status qk_ldm_init(qk_context *ctx, void *hip_stream, const float *f0,
 QK_API qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, int32_t W,
                        const float *color, const float *alpha, float *rgb_out,
                        float *acc_alpha_out);
+
+/* Adjoint of qk_composite (Sec. 3.1, the over operator O, differentiated by
+ * the chain rule; the paper prints no adjoint).  With T_l = prod_{j<l}
+ * (1 - alpha_j), B_{l+1} the composite of layers l+1..L-1 on their own and
+ * P_{l+1} = prod_{j>l} (1 - alpha_j):
+ *   d_color_l = d_rgb T_l alpha_l,
+ *   d_alpha_l = T_l (d_rgb . (color_l - B_{l+1}) + d_acc P_{l+1}).
+ * Float32 arithmetic, one thread per pixel, two passes over its layers.
+ *   color   device [L][H][W][3] float, alpha device [L][H][W] float: the
+ *           composite's inputs
+ *   d_rgb   device [H][W][3] float, dLoss/drgb
+ *   d_acc   device [H][W] float, dLoss/dacc_alpha, or NULL (zero)
+ *   d_color device [L][H][W][3] float, written, or NULL (not computed)
+ *   d_alpha device [L][H][W] float, written (also the pass's scratch)
+ * Errors (nothing enqueued): QK_EINVAL (NULL where not allowed, a buffer
+ * not 4-byte aligned, an output overlapping an input or the other output),
+ * QK_ESHAPE (non-positive dims), QK_EUNSUPPORTED (2^40 elements or more). */
+QK_API qk_status qk_composite_backward(qk_context *ctx, void *hip_stream, int32_t L, int32_t H,
+                                       int32_t W, const float *color, const float *alpha,
+                                       const float *d_rgb, const float *d_acc, float *d_color,
+                                       float *d_alpha);
+
+/* Dry run of qk_composite_backward's argument checks (no device use). */
+QK_API qk_status qk_composite_backward_check(int32_t L, int32_t H, int32_t W, const float *color,
+                                             const float *alpha, const float *d_rgb,
+                                             const float *d_acc, const float *d_color,
+                                             const float *d_alpha);
 
 /* Per-view reprojection tables the kernels use: for view m on the level
  * grid, p = A_m (u, v, 1)^T + b_m / d with A_m = K_m R_m R_n^T K_n^-1 and

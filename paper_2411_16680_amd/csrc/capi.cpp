@@ -19,6 +19,7 @@ hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool f
 hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s);
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
+hipError_t launch_composite_backward(const CompBwdParams &p, hipStream_t s);
 hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
 hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
@@ -752,6 +753,50 @@ qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, 
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipError_t e = qk::launch_composite(p, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "composite launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_composite_backward_check(int32_t L, int32_t H, int32_t W, const float *color,
+                                      const float *alpha, const float *d_rgb, const float *d_acc,
+                                      const float *d_color, const float *d_alpha) {
+    if (!color || !alpha || !d_rgb || !d_alpha) return fail(QK_EINVAL, "NULL buffer");
+    if (L < 1 || H < 1 || W < 1) return fail(QK_ESHAPE, "dims must be positive");
+    const void *bufs[6] = {color, alpha, d_rgb, d_acc, d_color, d_alpha};
+    for (const void *b : bufs)
+        if (b && !aligned4(b)) return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
+    const int64_t npix = (int64_t)H * W;
+    if (npix * L * 3 >= ((int64_t)1 << 40)) return fail(QK_EUNSUPPORTED, "too large");
+    // outputs must not overlap the inputs they are computed from
+    const int64_t n1 = npix * L, n3 = 3 * n1;
+    auto overlap = [](const float *a, int64_t na, const float *b, int64_t nb) {
+        return a && b && a < b + nb && b < a + na;
+    };
+    const float *outs[2] = {d_color, d_alpha};
+    const int64_t nouts[2] = {n3, n1};
+    for (int i = 0; i < 2; ++i) {
+        if (overlap(outs[i], nouts[i], color, n3) || overlap(outs[i], nouts[i], alpha, n1) ||
+            overlap(outs[i], nouts[i], d_rgb, 3 * npix) || overlap(outs[i], nouts[i], d_acc, npix))
+            return fail(QK_EINVAL, "an output overlaps an input");
+    }
+    if (overlap(d_color, n3, d_alpha, n1)) return fail(QK_EINVAL, "d_color overlaps d_alpha");
+    return QK_OK;
+}
+
+qk_status qk_composite_backward(qk_context *ctx, void *hip_stream, int32_t L, int32_t H,
+                                int32_t W, const float *color, const float *alpha,
+                                const float *d_rgb, const float *d_acc, float *d_color,
+                                float *d_alpha) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = qk_composite_backward_check(L, H, W, color, alpha, d_rgb, d_acc, d_color,
+                                               d_alpha);
+    if (st != QK_OK) return st;
+    qk::CompBwdParams p{color, alpha, d_rgb, d_acc, d_color, d_alpha, L, (int64_t)H * W};
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipError_t e = qk::launch_composite_backward(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "composite backward launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -106,6 +106,45 @@ __global__ void __launch_bounds__(kBlock) k_composite_adjoint(const BwdParams p)
 }
 
 // ---------------------------------------------------------------------------
+// Standalone composite adjoint (the operator O on its own), one thread per
+// pixel: d rgb / d c_l = T_l a_l, d rgb / d a_l = T_l (c_l - B_{l+1}) and
+// d acc / d a_l = T_l P_{l+1}, with B_{l+1} the composite of the layers
+// behind l and P_{l+1} the product of their (1 - a).  The front-to-back
+// pass parks T_l in d_alpha (each thread touches only its own pixel); the
+// back-to-front pass accumulates B and P and overwrites it.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_composite_backward(const CompBwdParams p) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= p.npix) return;
+    float T = 1.0f;
+    for (int l = 0; l < p.L; ++l) {
+        const int64_t e = (int64_t)l * p.npix + q;
+        p.d_alpha[e] = T;
+        T *= 1.0f - p.alpha[e];
+    }
+    const float g0 = p.d_rgb[q * 3 + 0], g1 = p.d_rgb[q * 3 + 1], g2 = p.d_rgb[q * 3 + 2];
+    const float gA = p.d_acc != nullptr ? p.d_acc[q] : 0.0f;
+    float B0 = 0.f, B1 = 0.f, B2 = 0.f, P = 1.0f;
+    for (int l = p.L - 1; l >= 0; --l) {
+        const int64_t e = (int64_t)l * p.npix + q;
+        const float Tl = p.d_alpha[e];
+        const float a = p.alpha[e];
+        const float c0 = p.color[e * 3 + 0], c1 = p.color[e * 3 + 1], c2 = p.color[e * 3 + 2];
+        if (p.d_color != nullptr) {
+            const float Ta = Tl * a;
+            p.d_color[e * 3 + 0] = g0 * Ta;
+            p.d_color[e * 3 + 1] = g1 * Ta;
+            p.d_color[e * 3 + 2] = g2 * Ta;
+        }
+        p.d_alpha[e] = Tl * (g0 * (c0 - B0) + g1 * (c1 - B1) + g2 * (c2 - B2) + gA * P);
+        B0 = fmaf(a, c0 - B0, B0);
+        B1 = fmaf(a, c1 - B1, B1);
+        B2 = fmaf(a, c2 - B2, B2);
+        P *= 1.0f - a;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One view's sample of one layer-pixel: position (double, as in the float32
 // forward), its derivative with respect to depth, the four clamped taps and
 // their bilinear weights (zero for taps outside the map).
@@ -619,6 +658,12 @@ __global__ void __launch_bounds__(kBlock) k_reduce_wgrad(const BwdParams p) {
 }
 
 }  // namespace
+
+hipError_t launch_composite_backward(const CompBwdParams &p, hipStream_t s) {
+    const int64_t blocks = (p.npix + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_composite_backward, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
 
 hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s) {
     if (p.C != 8 && p.C != 16) return hipErrorInvalidValue;

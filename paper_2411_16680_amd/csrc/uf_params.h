@@ -54,6 +54,18 @@ struct CompParams {
     int64_t npix;
 };
 
+// Adjoint of the standalone composite.
+struct CompBwdParams {
+    const float *color;    // [L][H][W][3]
+    const float *alpha;    // [L][H][W]
+    const float *d_rgb;    // [H][W][3]
+    const float *d_acc;    // [H][W] or NULL (zero)
+    float *d_color;        // [L][H][W][3] or NULL (not written)
+    float *d_alpha;        // [L][H][W]
+    int32_t L;
+    int64_t npix;
+};
+
 }  // namespace qk
 
 namespace qk {

@@ -28,7 +28,8 @@ MODE = {"residual": 0, "paper": 1}
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
-           "qk_composite", "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
+           "qk_composite", "qk_composite_backward", "qk_composite_backward_check",
+           "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
            "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
            "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
            "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check", "qk_ldm_decode",
@@ -125,6 +126,9 @@ def load() -> ctypes.CDLL:
     L.qk_composite.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p]
+    cb_args = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 6
+    L.qk_composite_backward.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + cb_args
+    L.qk_composite_backward_check.argtypes = cb_args
     L.qk_camera_tables.argtypes = [ctypes.c_int32, P(qk_camera), P(ctypes.c_int32), P(qk_camera),
                                    ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
     render_args = [ctypes.c_int32, P(qk_camera), P(qk_image), P(qk_camera), ctypes.c_float,
@@ -156,7 +160,8 @@ def load() -> ctypes.CDLL:
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
                  "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
-                 "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
+                 "qk_composite_backward", "qk_composite_backward_check", "qk_render_ibr",
+                 "qk_render_ibr_check", "qk_render_to_views",
                  "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
                  "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
                  "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check",
@@ -367,6 +372,26 @@ def composite(ctx: Context, color, alpha, rgb_out, acc_out=None, stream=None):
     L, H, W = (int(s) for s in alpha.shape)
     _check(ctx._lib.qk_composite(ctx.handle, _stream_handle(stream), L, H, W, _ptr(color),
                                  _ptr(alpha), _ptr(rgb_out), _ptr(acc_out)))
+
+
+def _cb_args(color, alpha, d_rgb, d_acc, d_color, d_alpha):
+    L, H, W = (int(s) for s in alpha.shape)
+    return (L, H, W, _ptr(color), _ptr(alpha), _ptr(d_rgb), _ptr(d_acc), _ptr(d_color),
+            _ptr(d_alpha))
+
+
+def composite_backward(ctx: Context, color, alpha, d_rgb, d_alpha, d_color=None, d_acc=None,
+                       stream=None):
+    """qk_composite_backward: color [L][H][W][3], alpha [L][H][W], d_rgb
+    [H][W][3] (and d_acc [H][W] or None) float32 device tensors ->
+    d_color [L][H][W][3] (or None), d_alpha [L][H][W]."""
+    _check(ctx._lib.qk_composite_backward(ctx.handle, _stream_handle(stream),
+                                          *_cb_args(color, alpha, d_rgb, d_acc, d_color, d_alpha)))
+
+
+def composite_backward_check(color, alpha, d_rgb, d_alpha, d_color=None, d_acc=None) -> int:
+    return int(load().qk_composite_backward_check(*_cb_args(color, alpha, d_rgb, d_acc, d_color,
+                                                            d_alpha)))
 
 
 def _render_args(in_cams, images, novel, near, far, logits, H, W, rgb_out, acc_out, depth_out):

@@ -64,23 +64,27 @@ def scene_to_device(scene, device="cuda") -> List[DeviceLevel]:
 
 def run_level(ctx: lib.Context, scene, dl: DeviceLevel, *, steps: Optional[int] = None,
               precision: Optional[str] = None, attn_form: str = "standard",
-              mode: str = "residual", stream=None):
-    """``steps`` Update & Fuse steps (the first reads the input state, later
-    ones update the output state in place), compositing on the last step
-    when the level composites."""
+              mode: str = "residual", stream=None, composite: Optional[bool] = None,
+              from_output: bool = False):
+    """``steps`` Update & Fuse steps (the first reads the input state, or the
+    output state when ``from_output``; later ones update the output state in
+    place), compositing on the last step when ``composite`` (default: when
+    the level composites)."""
     steps = scene.steps if steps is None else steps
+    composite = dl.composite if composite is None else composite
     precision = precision or ("bf16" if scene.dtype == "bf16" else "fp32")
     wts = dl.extra.get("qk_weights")
     if wts is None:                    # built once (the tensors stay in dl.weights)
         wts = dl.extra["qk_weights"] = lib.make_weights(dl.weights, heads=dl.heads)
     for s in range(steps):
-        src = (dl.F, dl.depth, dl.alpha) if s == 0 else (dl.F_out, dl.depth_out, dl.alpha_out)
+        first_in = s == 0 and not from_output
+        src = (dl.F, dl.depth, dl.alpha) if first_in else (dl.F_out, dl.depth_out, dl.alpha_out)
         last = s == steps - 1
         lib.update_fuse(ctx, scene.in_cams, dl.feats, scene.novel, scene.near, scene.far,
                         wts, src, (dl.F_out, dl.depth_out, dl.alpha_out),
                         precision=precision, attn_form=attn_form, mode=mode,
-                        rgb_out=dl.rgb if (last and dl.composite) else None,
-                        acc_out=dl.acc if (last and dl.composite) else None, stream=stream)
+                        rgb_out=dl.rgb if (last and composite) else None,
+                        acc_out=dl.acc if (last and composite) else None, stream=stream)
 
 
 def run_scene(ctx: lib.Context, scene, dls: List[DeviceLevel], **kw):

@@ -454,3 +454,28 @@ def test_upsample2x_and_decode_checks():
     assert lib.ldm_decode_check(F, d, a, ws, wd, wc, 2.0, 1.0) == lib.QK_EINVAL
     assert lib.ldm_decode_check(F, None, a, ws, wd, wc, 0.5, 20.0) == lib.QK_EINVAL
     assert lib.ldm_decode_check(_FakeT((4, 5, 6, 32), 0x300008), d, a, ws, wd, wc, 0.5, 20.0) == lib.QK_EINVAL
+
+
+def test_composite_backward_checks():
+    c, a = _FakeT((3, 4, 5, 3), 0x100000), _FakeT((3, 4, 5), 0x200000)
+    g, gA = _FakeT((4, 5, 3), 0x300000), _FakeT((4, 5), 0x310000)
+    dc, da = _FakeT((3, 4, 5, 3), 0x400000), _FakeT((3, 4, 5), 0x500000)
+    assert lib.composite_backward_check(c, a, g, da, dc, gA) == lib.QK_OK
+    assert lib.composite_backward_check(c, a, g, da) == lib.QK_OK         # d_color, d_acc NULL
+    assert lib.composite_backward_check(c, a, None, da) == lib.QK_EINVAL
+    assert lib.composite_backward_check(c, a, g, None) == lib.QK_EINVAL
+    assert lib.composite_backward_check(c, _FakeT((0, 4, 5), 0x200000), g, da) == lib.QK_ESHAPE
+    assert lib.composite_backward_check(c, a, _FakeT((4, 5, 3), 0x300002), da) == lib.QK_EINVAL
+    # an output on top of an input, or on the other output
+    assert lib.composite_backward_check(c, a, g, _FakeT((3, 4, 5), 0x200000 + 16)) == lib.QK_EINVAL
+    assert "overlap" in lib.load().qk_last_error().decode()
+    assert lib.composite_backward_check(c, a, g, da, _FakeT((3, 4, 5, 3), 0x500000 - 64)) == lib.QK_EINVAL
+
+
+def test_composite_backward_null_context_rejected():
+    import torch
+    t3 = torch.zeros((2, 3, 4, 3))
+    t1 = torch.zeros((2, 3, 4))
+    st = lib.load().qk_composite_backward(None, None, *lib._cb_args(t3, t1, torch.zeros(3, 4, 3),
+                                                                    None, None, t1))
+    assert st == lib.QK_EINVAL

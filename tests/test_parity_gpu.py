@@ -11,9 +11,11 @@ the arithmetic of each form (design notes, "Tolerances"):
   * depth' : in disparity, as a fraction of one step's largest update
     (0.5/L)(1/near - 1/far) -- relative depth error is not a stable measure
     near the far plane, where a small disparity error is a large depth error.
-Multi-step runs compound: the second step samples at positions moved by the
-first step's depth error, so their bounds on the intermediate outputs scale
-with the step count.  Every measured error is written to parity_report.json
+Two-step runs are checked step by step: the second step starts from the
+GPU's own first-step state, read back exactly, so both steps are held to
+the single-step bounds; the rendered image of the two steps end to end is
+held to the RGB targets against the oracle's two steps from the inputs.
+Every measured error is written to parity_report.json
 in the directory QK_REPORT_DIR names, when it is set.
 """
 
@@ -61,27 +63,12 @@ def psnr(a, b):
 def compare(gpu, ref, form, scene, level, rows=None, composite=True, label=""):
     """Compare GPU outputs (full arrays) with oracle outputs (packed rows)."""
     t = dict(TOL[form])
-    steps = scene.steps
-    if steps > 1:                  # compounding through the reprojection (see module doc)
-        for k in ("F_abs", "alpha", "disp"):
-            t[k] *= 5.0 * steps if form == "fp32" else 2.5 * steps
     sel = (lambda a: a) if rows is None else (lambda a: a[:, rows])
     F = sel(gpu["F"]); d = sel(gpu["depth"]); a = sel(gpu["alpha"])
     step_range = (0.5 / level.L) * (1.0 / scene.near - 1.0 / scene.far)
     errs = {}
     excess = np.abs(F - ref["F"]) - t["F_rel"] * np.abs(ref["F"])
-    if steps > 1:
-        # In a later step a layer-pixel samples where the previous step's
-        # depth put it: a rounding-level disparity error there (up to ~0.2 of
-        # one step's update in the bfloat16 form, ~1 px at this rig's focal
-        # length and baseline) moves the sample along i.i.d. N(0, 1) feature
-        # maps, so a few F' values differ by O(|grad I| x shift).  The bound
-        # holds for all but 0.1 % of values; the rest stay within twice it.
-        errs["F_excess"] = float(np.percentile(excess, 99.9))
-        errs["F_excess_max"] = float(np.max(excess))
-        assert errs["F_excess_max"] <= 2.0 * t["F_abs"], (label, "F max", errs)
-    else:
-        errs["F_excess"] = float(np.max(excess))
+    errs["F_excess"] = float(np.max(excess))
     errs["F_maxabs"] = float(np.max(np.abs(F - ref["F"])))
     errs["F_rms"] = float(np.sqrt(np.mean((F - ref["F"]) ** 2)))
     errs["alpha"] = float(np.max(np.abs(a - ref["alpha"])))
@@ -145,17 +132,51 @@ def test_c1_full(ctx, form, attn):
     compare(gpu, ref, form, sc, sc.levels[0], label=f"c1 {attn}")
 
 
+def check_rgb(gpu_rgb, ref_rgb, form, label):
+    """The rendered image alone against the RGB targets of its form."""
+    e = float(np.max(np.abs(gpu_rgb - ref_rgb)))
+    q = psnr(gpu_rgb, ref_rgb)
+    _say(label, form, f"rgb max-abs {e:.3g} psnr {q:.4g} dB")
+    REPORT.append({"case": label, "form": form, "rgb": e, "psnr": q})
+    assert e <= TOL[form]["rgb"], (label, "rgb", e)
+    if form == "bf16":
+        assert q >= 45.0, (label, "psnr", q)
+    return e, q
+
+
 @pytest.mark.parametrize("attn", ATTN)
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
 def test_c2_two_steps_sampled_rows(ctx, form, attn):
+    """Two Update & Fuse steps at 480x270 (V = 4, C = 32, L = 16).  Each step
+    is compared with the oracle's step from the same input: step 1 from the
+    scene's state, step 2 from the GPU's step-1 output read back exactly
+    (bfloat16 and float32 values are exact in float64), both to the
+    single-step bounds.  The two steps end to end -- the GPU's image against
+    the oracle's two steps from the scene's state -- are held to the RGB
+    targets."""
     _say("c2 sampled", form, attn)
     sc = synth.make_inputs(2)
     if form == "bf16":
         sc = synth.to_bf16(sc)
+    assert sc.steps == 2
+    lvl = sc.levels[0]
     rows = [0, 1, 63, 64, 134, 135, 201, 268, 269]
-    ref = oracle.run_level(sc, sc.levels[0], rows=rows)
-    gpu, _ = run_gpu_level(ctx, sc, attn_form=attn)
-    compare(gpu, ref, form, sc, sc.levels[0], rows=rows, label=f"c2 {attn}")
+    dl = runner.level_to_device(lvl)
+    # step 1 (no composite)
+    runner.run_level(ctx, sc, dl, steps=1, attn_form=attn, composite=False)
+    g1 = runner.level_outputs_numpy(dl)
+    ref1 = oracle.update_fuse(sc.in_cams, sc.novel, sc.near, sc.far, lvl, rows=rows)
+    compare(g1, ref1, form, sc, lvl, rows=rows, composite=False, label=f"c2 step 1 {attn}")
+    # step 2, in place on the GPU's state, composited
+    runner.run_level(ctx, sc, dl, steps=1, attn_form=attn, from_output=True)
+    g2 = runner.level_outputs_numpy(dl)
+    ref2 = oracle.update_fuse(sc.in_cams, sc.novel, sc.near, sc.far, lvl, F=g1["F"],
+                              depth=g1["depth"], alpha=g1["alpha"], rows=rows)
+    ref2["rgb"], ref2["acc"] = oracle.composite(ref2["color"], ref2["alpha"])
+    compare(g2, ref2, form, sc, lvl, rows=rows, label=f"c2 step 2 {attn}")
+    # both steps end to end
+    ref = oracle.run_level(sc, lvl, rows=rows)
+    check_rgb(g2["rgb"][rows], ref["rgb"], form, f"c2 two steps end to end {attn}")
 
 
 @pytest.fixture(scope="module")
