@@ -136,6 +136,17 @@ def attention(F, S, heads, dh, Wq, Wk, Wv, Wo, folded: bool = False):
     return out, p
 
 
+def blend_logits(F, S, heads, dh, Wq, Wk) -> np.ndarray:
+    """One layer-pixel's blend-weight logits [V] (first head's attention
+    logits, before the softmax)."""
+    F, S, Wq, Wk = map(_f64, (F, S, Wq, Wk))
+    C = F.shape[0]
+    V, Cf = S.shape
+    out = np.zeros(V)
+    lib().or_blend_logits(_d(F), C, _d(S), V, Cf, heads, dh, _d(Wq), _d(Wk), _d(out))
+    return out
+
+
 def decode(Fp, w_sigma, w_depth, W_color, alpha, depth, li, L, near, far, mode=0):
     """Returns (alpha', depth', color'[3])."""
     Fp, w_sigma, w_depth, W_color = map(_f64, (Fp, w_sigma, w_depth, W_color))
@@ -385,8 +396,8 @@ def _as_f64_array(a: np.ndarray) -> np.ndarray:
 
 def update_fuse(in_cams, novel, near, far, level, *, F=None, depth=None, alpha=None,
                 rows: Optional[Sequence[int]] = None, mode: int = 0, attn_form: int = 0,
-                want_samples: bool = False, feats64: Optional[List[np.ndarray]] = None
-                ) -> Dict[str, np.ndarray]:
+                want_samples: bool = False, feats64: Optional[List[np.ndarray]] = None,
+                want_logits: bool = False) -> Dict[str, np.ndarray]:
     """One Update & Fuse step of ``level`` (a ``synth.Level``) on the given
     rows (default: all).  ``F``/``depth``/``alpha`` override the level's state
     (full-size arrays, used for multi-step runs)."""
@@ -412,6 +423,7 @@ def update_fuse(in_cams, novel, near, far, level, *, F=None, depth=None, alpha=N
     a_out = np.zeros((L, R, W))
     c_out = np.zeros((L, R, W, 3))
     s_out = np.zeros((L, R, W, V, Cf)) if want_samples else None
+    g_out = np.zeros((L, R, W, V)) if want_logits else None
     rc = lib().or_update_fuse(
         V, _d(Kin), _d(Ein), cam_wh.ctypes.data_as(_ip), fptrs, feat_hw.ctypes.data_as(_ip), Cf,
         _d(Kn), _d(En), nov_wh.ctypes.data_as(_ip), ctypes.c_double(near), ctypes.c_double(far),
@@ -419,12 +431,15 @@ def update_fuse(in_cams, novel, near, far, level, *, F=None, depth=None, alpha=N
         _d(w["Wq"]), _d(w["Wk"]), _d(w["Wv"]), _d(w["Wo"]), _d(w["w_sigma"]), _d(w["w_depth"]),
         _d(w["W_color"]), int(mode), int(attn_form), rows.ctypes.data_as(_ip), R,
         _d(F_out), _d(d_out), _d(a_out), _d(c_out),
-        _d(s_out) if s_out is not None else ctypes.cast(None, _dp))
+        _d(s_out) if s_out is not None else ctypes.cast(None, _dp),
+        _d(g_out) if g_out is not None else ctypes.cast(None, _dp))
     if rc != 0:
         raise ValueError("oracle update_fuse failed (singular camera?)")
     out = {"F": F_out, "depth": d_out, "alpha": a_out, "color": c_out, "rows": rows}
     if s_out is not None:
         out["samples"] = s_out
+    if g_out is not None:
+        out["blend_logit"] = g_out
     return out
 
 

@@ -265,6 +265,30 @@ OR_EXPORT void or_attention(const double *F, int C, const double *S, int V, int 
     free(xn); free(q); free(k); free(v); free(o); free(a);
 }
 
+/* Blend-weight logits (Sec. 3.2.3, the blend weights): the pre-softmax
+ * attention logits of the first head of the final fusion block,
+ * a_m = (N(F) W_q)_0 . (s_m W_k)_0 / sqrt(d_h) for each view m; the softmax
+ * over the views is applied by the render, after upsampling. */
+OR_EXPORT void or_blend_logits(const double *F, int C, const double *S, int V, int Cf,
+                               int heads, int dh, const double *Wq, const double *Wk,
+                               double *logits)
+{
+    int hd = heads * dh;
+    double *xn = malloc(sizeof(double) * C);
+    double *q = malloc(sizeof(double) * hd);
+    double *k = malloc(sizeof(double) * hd);
+    or_rmsnorm(F, C, xn);
+    vecmat(xn, Wq, C, hd, q);
+    double scale = 1.0 / sqrt((double)dh);
+    for (int m = 0; m < V; ++m) {
+        vecmat(S + (size_t)m * Cf, Wk, Cf, hd, k);
+        double s = 0.0;
+        for (int j = 0; j < dh; ++j) s += q[j] * k[j];
+        logits[m] = s * scale;
+    }
+    free(xn); free(q); free(k);
+}
+
 /* One-to-many (folded) attention (Sec. 3.3, "Optimized Attention", and the
  * appendix on its complexity): the key projection is folded into the query,
  * q~_i = N(F) W_i^q (W_i^k)^T / sqrt(d_h), and the value projection into the
@@ -478,7 +502,9 @@ OR_EXPORT void or_composite_backward(int L, long npix, const double *color, cons
 /*            w_depth[C], W_color[C][3]                                      */
 /* Outputs, packed over the selected rows (R = nrows):                       */
 /*   F_out[L][R][W][C], depth_out[L][R][W], alpha_out[L][R][W],              */
-/*   color_out[L][R][W][3]; samples_out[L][R][W][V][Cf] if non-NULL.         */
+/*   color_out[L][R][W][3]; samples_out[L][R][W][V][Cf] if non-NULL;        */
+/*   logits_out[L][R][W][V] if non-NULL: the blend-weight logits of the      */
+/*   step's attention (or_blend_logits).                                     */
 /* attn_form: 0 standard, 1 one-to-many (folded).                            */
 /* ------------------------------------------------------------------------ */
 
@@ -492,7 +518,7 @@ OR_EXPORT int or_update_fuse(int V, const double *Kin, const double *Ein, const 
                              const double *w_depth, const double *W_color, int mode,
                              int attn_form, const int *rows, int nrows, double *F_out,
                              double *depth_out, double *alpha_out, double *color_out,
-                             double *samples_out)
+                             double *samples_out, double *logits_out)
 {
     double Kns[9];
     or_scale_intrinsics(Kn, nov_wh[0], nov_wh[1], W, H, Kns);
@@ -534,6 +560,9 @@ OR_EXPORT int or_update_fuse(int V, const double *Kin, const double *Ein, const 
             }
             if (samples_out)
                 memcpy(samples_out + dst * (size_t)V * Cf, S, sizeof(double) * (size_t)V * Cf);
+            if (logits_out)
+                or_blend_logits(F + src * C, C, S, V, Cf, heads, dh, Wq, Wk,
+                                logits_out + dst * (size_t)V);
             if (attn_form == 0)
                 or_attention(F + src * C, C, S, V, Cf, heads, dh, Wq, Wk, Wv, Wo, Fp, NULL);
             else

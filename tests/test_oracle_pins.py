@@ -254,6 +254,44 @@ def test_attention_view_permutation_invariance():
     np.testing.assert_allclose(a, b, atol=1e-13)
 
 
+@pytest.mark.parametrize("heads,dh,C,Cf,V", [(1, 16, 16, 16, 4), (1, 32, 32, 32, 8),
+                                             (2, 8, 16, 12, 5)])
+def test_blend_logits_are_the_attention_logits(heads, dh, C, Cf, V):
+    # the blend weights are the final attention's weights with the softmax
+    # delayed: the softmax of the logits is the first head's attention
+    # weights (which the SDPA pin above fixes)
+    Wq, Wk, Wv, Wo = _weights(C, Cf, heads, dh, seed=3 * C + V)
+    for _ in range(4):
+        F = RNG.standard_normal(C) * 2
+        S = RNG.standard_normal((V, Cf))
+        lg = oracle.blend_logits(F, S, heads, dh, Wq, Wk)
+        _, p = oracle.attention(F, S, heads, dh, Wq, Wk, Wv, Wo)
+        e = np.exp(lg - lg.max())
+        np.testing.assert_allclose(e / e.sum(), p[0], atol=1e-13)
+    # identical views: equal logits; zero keys: zero logits
+    S = np.tile(RNG.standard_normal(Cf), (V, 1))
+    lg = oracle.blend_logits(RNG.standard_normal(C), S, heads, dh, Wq, Wk)
+    np.testing.assert_allclose(lg, np.full(V, lg[0]), rtol=1e-14)
+    assert np.all(oracle.blend_logits(RNG.standard_normal(C), RNG.standard_normal((V, Cf)), heads,
+                                      dh, Wq, np.zeros_like(Wk)) == 0.0)
+
+
+def test_update_fuse_blend_logits_match_the_step_samples():
+    # the whole step's logits output equals the per-layer-pixel definition on
+    # the step's own samples (which the sample pins fix)
+    sc = synth.make_inputs(1)
+    lvl = sc.levels[0]
+    rows = [0, 17, 47]
+    out = oracle.update_fuse(sc.in_cams, sc.novel, sc.near, sc.far, lvl, rows=rows,
+                             want_samples=True, want_logits=True)
+    w = lvl.weights
+    for (l, r, x) in [(0, 0, 0), (1, 1, 30), (3, 2, 63), (2, 0, 5)]:
+        F = lvl.F[l, rows[r], x].astype(np.float64)
+        ref = oracle.blend_logits(F, out["samples"][l, r, x], lvl.heads, lvl.head_dim, w["Wq"],
+                                  w["Wk"])
+        np.testing.assert_array_equal(out["blend_logit"][l, r, x], ref)
+
+
 @pytest.mark.parametrize("heads,dh,C,Cf", [(1, 16, 16, 16), (2, 8, 16, 16), (4, 8, 32, 24)])
 def test_folded_equals_standard_attention(heads, dh, C, Cf):
     # one-to-many attention folds W_k into the query and W_val into W_O
