@@ -12,6 +12,7 @@
  * Entry points (all but qk_ldm_init, qk_composite and qk_camera_tables with
  * a dry-run `_check` of their arguments):
  *   qk_update_fuse           one Update & Fuse step (+ composite), Sec. 3.2.2-3.3
+ *   qk_update_fuse_noalloc   the same with a fixed scratch, no device allocation
  *   qk_update_fuse_backward  its adjoint into features, LDM and weights
  *   qk_ldm_init              learned initialisation of an LDM, Sec. 3.2
  *   qk_composite             front-to-back over composite, Sec. 3.1
@@ -197,6 +198,28 @@ QK_API qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V,
                          qk_attn_form attn_form, qk_update_mode update_mode,
                          const qk_ldm *ldm_in, const qk_ldm *ldm_out,
                          float *rgb_out, float *acc_alpha_out);
+
+/* qk_update_fuse without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, checks, kernels and results as
+ * qk_update_fuse.  Where qk_update_fuse keeps intermediate data in the
+ * context's workspaces (grown with hipMalloc on first use) -- the folded
+ * weights of QK_ATTN_FOLDED and the e4m3 scales of QK_PREC_BF16_FP8PROJ --
+ * this entry point uses a fixed scratch array of 8256 floats (33 KiB) in
+ * device memory instead, one per GPU, held until the process ends.  Limit:
+ * the folded weights, 2 heads C C_feat floats, must fit 8192 floats (every
+ * shape the folded kernels support does); larger returns QK_EUNSUPPORTED.
+ * Every call on a GPU shares that GPU's scratch and overwrites what it
+ * needs (the running maximum of the e4m3 scales is cleared by a kernel, not
+ * a memset): calls that overlap on one GPU, on different streams or from
+ * different threads, race on it. */
+QK_API qk_status qk_update_fuse_noalloc(qk_context *ctx, void *hip_stream, int32_t V,
+                                        const qk_camera *in_cams, const qk_feature_map *feats,
+                                        const qk_camera *novel, float near_, float far_,
+                                        const qk_weights *weights, qk_precision precision,
+                                        qk_attn_form attn_form, qk_update_mode update_mode,
+                                        const qk_ldm *ldm_in, const qk_ldm *ldm_out,
+                                        float *rgb_out, float *acc_alpha_out);
 
 /* Dry run of qk_update_fuse's argument checks: returns the status the call
  * would return before enqueuing anything, without touching a device.  Takes

@@ -29,6 +29,7 @@ hipError_t launch_layer_collapse(const CollapseParams &p, int num_cu, hipStream_
 hipError_t launch_ray_encoding(const RayParams &p, hipStream_t s);
 hipError_t launch_upsample2x(const Up2Params &p, hipStream_t s);
 hipError_t launch_ldm_decode(const DecodeParams &p, hipStream_t s);
+hipError_t scratch_address(int device, float **out);
 }  // namespace qk
 
 struct qk_context {
@@ -46,6 +47,7 @@ struct qk_context {
     size_t cfrag_elems = 0;
     float *rws = nullptr;        // low-resolution projected ray encodings
     size_t rws_elems = 0;
+    float *scratch = nullptr;    // this device's fixed scratch (allocation-free entry point)
 };
 
 namespace {
@@ -566,8 +568,13 @@ qk_status qk_context_create(int device, qk_context **out) {
     int cu = 0;
     e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return fail(QK_EHIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    // the device's fixed scratch (a static device array), looked up once
+    float *scr = nullptr;
+    e = qk::scratch_address(device, &scr);
+    if (e != hipSuccess) return fail(QK_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
     qk_context *ctx = new qk_context{device};
     ctx->num_cu = cu > 0 ? cu : 1;
+    ctx->scratch = scr;
     *out = ctx;
     return QK_OK;
 }
@@ -614,11 +621,18 @@ qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams, const qk_fea
                              update_mode, ldm_in, ldm_out, rgb_out, acc_alpha_out);
 }
 
-qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
-                         const qk_feature_map *feats, const qk_camera *novel, float near_,
-                         float far_, const qk_weights *w, qk_precision precision,
-                         qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
-                         const qk_ldm *out, float *rgb_out, float *acc_out) {
+}  // extern "C"
+
+namespace {
+
+// qk_update_fuse and its allocation-free variant.  fixed == NULL: the folded
+// weights and the e4m3 scales go to the context's workspaces (grown on
+// demand); otherwise to `fixed` (kScratchFloats floats; nothing allocated).
+qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                           const qk_feature_map *feats, const qk_camera *novel, float near_,
+                           float far_, const qk_weights *w, qk_precision precision,
+                           qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
+                           const qk_ldm *out, float *rgb_out, float *acc_out, float *fixed) {
     if (!ctx) return fail(QK_EINVAL, "context is NULL");
     qk_status st = check_update_fuse(V, in_cams, feats, novel, near_, far_, w, precision,
                                      attn_form, update_mode, in, out, rgb_out, acc_out);
@@ -688,7 +702,13 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         // caller's stream, into the context's workspace
         const size_t per = (size_t)w->heads * w->C * w->C_feat;     // per folded matrix set
         const size_t need = 2 * per;
-        if (ctx->wfold_elems < need) {
+        float *wf = ctx->wfold;
+        if (fixed != nullptr) {
+            if (need > (size_t)qk::kScratchFold)
+                return fail(QK_EUNSUPPORTED, "folded weights of %zu floats exceed the fixed scratch "
+                            "of %d", need, qk::kScratchFold);
+            wf = fixed;
+        } else if (ctx->wfold_elems < need) {
             if (ctx->wfold) {
                 hipError_t se = hipStreamSynchronize(stream);
                 if (se != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
@@ -699,8 +719,9 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
             if (hipMalloc(&ctx->wfold, need * sizeof(float)) != hipSuccess)
                 return fail(QK_ENOMEM, "workspace of %zu floats", need);
             ctx->wfold_elems = need;
+            wf = ctx->wfold;
         }
-        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, ctx->wfold, ctx->wfold + per,
+        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per,
                           w->C, w->C_feat, w->head_dim, w->heads,
                           1.0f / std::sqrt((float)w->head_dim)};
         hipError_t fe = qk::launch_fold_weights(fp, stream);
@@ -709,8 +730,12 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         p.Wvo = fp.Wvo;
     }
     if (precision == QK_PREC_BF16_FP8PROJ) {
-        st = grow(&ctx->f8, &ctx->f8_elems, 8, stream);
-        if (st != QK_OK) return st;
+        float *f8 = fixed != nullptr ? fixed + qk::kScratchFold : nullptr;
+        if (f8 == nullptr) {
+            st = grow(&ctx->f8, &ctx->f8_elems, 8, stream);
+            if (st != QK_OK) return st;
+            f8 = ctx->f8;
+        }
         qk::F8Params fp8;
         std::memset(&fp8, 0, sizeof(fp8));
         for (int m = 0; m < V; ++m) {
@@ -726,15 +751,41 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
         fp8.Cf = w->C_feat;
         fp8.hd = fold ? w->C_feat : w->heads * w->head_dim;
         fp8.fold = fold ? 1 : 0;
-        fp8.amax_bits = reinterpret_cast<unsigned *>(ctx->f8 + 7);
-        fp8.scales = ctx->f8;
+        fp8.amax_bits = reinterpret_cast<unsigned *>(f8 + 7);
+        fp8.scales = f8;
         hipError_t e8 = qk::launch_fp8_scales(fp8, stream);
         if (e8 != hipSuccess) return fail(QK_EHIP, "fp8 scale launch: %s", hipGetErrorString(e8));
-        p.f8_scales = ctx->f8;
+        p.f8_scales = f8;
     }
     hipError_t e = qk::launch_update_fuse(p, in->C, w->head_dim, (int)precision, fold, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "update_fuse launch: %s", hipGetErrorString(e));
     return QK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                         const qk_feature_map *feats, const qk_camera *novel, float near_,
+                         float far_, const qk_weights *w, qk_precision precision,
+                         qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
+                         const qk_ldm *out, float *rgb_out, float *acc_out) {
+    return update_fuse_impl(ctx, hip_stream, V, in_cams, feats, novel, near_, far_, w, precision,
+                            attn_form, update_mode, in, out, rgb_out, acc_out, nullptr);
+}
+
+qk_status qk_update_fuse_noalloc(qk_context *ctx, void *hip_stream, int32_t V,
+                                 const qk_camera *in_cams, const qk_feature_map *feats,
+                                 const qk_camera *novel, float near_, float far_,
+                                 const qk_weights *w, qk_precision precision,
+                                 qk_attn_form attn_form, qk_update_mode update_mode,
+                                 const qk_ldm *in, const qk_ldm *out, float *rgb_out,
+                                 float *acc_out) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    if (ctx->scratch == nullptr) return fail(QK_EHIP, "the device's fixed scratch is unknown");
+    return update_fuse_impl(ctx, hip_stream, V, in_cams, feats, novel, near_, far_, w, precision,
+                            attn_form, update_mode, in, out, rgb_out, acc_out, ctx->scratch);
 }
 
 qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, int32_t W,

@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "uf_params.h"
@@ -1191,6 +1192,39 @@ hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s) {
     const int n = 2 * f.heads * f.C * f.Cf;
     hipLaunchKernelGGL(k_fold_weights, dim3((n + 255) / 256), dim3(256), 0, s, f);
     return hipGetLastError();
+}
+
+// Device scratch of the allocation-free entry point (folded weights, e4m3
+// scales): one copy per GPU, held until the process ends; calls on one GPU
+// share it.  Host code must not pass `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory): scratch_address() looks up
+// each device's copy once, with that device current, and kernels take that
+// address.
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+// Address of `scratch` on `device` (made current for the lookup, then
+// restored).  Looked up on the first call for that device, cached after.
+hipError_t scratch_address(int device, float **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device] == nullptr) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_composite(const CompParams &p, hipStream_t s) {

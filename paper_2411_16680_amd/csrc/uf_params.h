@@ -6,6 +6,13 @@ namespace qk {
 
 constexpr int kMaxViews = 16;
 
+// Fixed scratch of the allocation-free Update & Fuse entry point (floats):
+// the folded weights W_qk, W_vo (2 heads C C_feat <= kScratchFold) and, after
+// them, the e4m3 scales (7) and running maximum (1).
+constexpr int kScratchFold = 8192;
+constexpr int kScratchFloats = kScratchFold + 64;
+constexpr int kMaxDevices = 64;
+
 // One Update & Fuse launch over one LDM level.  Per view m, cam[m] holds the
 // reprojection table p = A (u, v, 1)^T + b / d: A row-major (9 floats), then
 // b (3 floats), composed in double on the host.

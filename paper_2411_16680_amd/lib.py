@@ -27,6 +27,7 @@ MODE = {"residual": 0, "paper": 1}
 
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
+           "qk_update_fuse_noalloc",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_composite_backward", "qk_composite_backward_check",
            "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
@@ -116,6 +117,7 @@ def load() -> ctypes.CDLL:
                P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p]
     L.qk_update_fuse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
     L.qk_update_fuse_check.argtypes = uf_args
+    L.qk_update_fuse_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
     bwd_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
                 ctypes.c_float, P(qk_weights), ctypes.c_int, P(qk_ldm), P(qk_ldm), ctypes.c_void_p,
                 P(qk_ldm), P(qk_ldm), P(ctypes.c_void_p), P(qk_weight_grads)]
@@ -158,7 +160,7 @@ def load() -> ctypes.CDLL:
     L.qk_ldm_decode.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + dec_args
     L.qk_ldm_decode_check.argtypes = dec_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
-                 "qk_update_fuse_check", "qk_update_fuse_backward",
+                 "qk_update_fuse_noalloc", "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_composite_backward", "qk_composite_backward_check", "qk_render_ibr",
                  "qk_render_ibr_check", "qk_render_to_views",
@@ -288,6 +290,16 @@ def update_fuse(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in,
     args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
                           ldm_in, ldm_out, rgb_out, acc_out)
     _check(ctx._lib.qk_update_fuse(ctx.handle, _stream_handle(stream), *args))
+
+
+def update_fuse_noalloc(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out,
+                        *, precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
+                        acc_out=None, stream=None):
+    """qk_update_fuse_noalloc: qk_update_fuse with the device's fixed scratch
+    instead of allocated workspaces (same arguments as ``update_fuse``)."""
+    args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
+                          ldm_in, ldm_out, rgb_out, acc_out)
+    _check(ctx._lib.qk_update_fuse_noalloc(ctx.handle, _stream_handle(stream), *args))
 
 
 def update_fuse_check(in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
