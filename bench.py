@@ -557,6 +557,40 @@ def time_chain(ctx, reps: int = 20):
     return out
 
 
+PIPELINE_WORKLOAD = ("the whole frame at 1080p, V=8, C=32, bf16: ray-direction encoding of the "
+                     "four-level pyramid (36x60 .. 288x480), learned initialisation, the five "
+                     "chained steps of the paper's network table (24 -> 6 layers, 36x64 -> "
+                     "288x512, heads 4/4/4/2/1, a residual CNN block after each attention), "
+                     "blend-weight logits of the last attention, unactivated decode and the "
+                     "final render at 1920x1080 (Eq. 1)")
+
+
+def time_pipeline(ctx, reps: int = 20):
+    """The whole frame (runner.run_pipeline) in the one-to-many and the
+    standard form: average time of one frame (all its launches) with HIP
+    events on the stream."""
+    import torch
+    from paper_2411_16680_amd import runner, synth
+    pl = synth.make_pipeline()
+    dp = runner.pipeline_to_device(pl)
+    stream = torch.cuda.current_stream()
+    out = {"workload": PIPELINE_WORKLOAD, "out_res": f"{pl.out_hw[1]}x{pl.out_hw[0]}",
+           "views": pl.chain.V}
+    for attn in ("folded", "standard"):
+        for _ in range(3):
+            runner.run_pipeline(ctx, pl, dp, attn_form=attn, stream=stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            runner.run_pipeline(ctx, pl, dp, attn_form=attn, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[attn] = {"frame_ms": ms, "frames_per_s": 1000.0 / ms}
+    return out
+
+
 def time_composite(ctx, L: int = 4, H: int = 1080, W: int = 1920, reps: int = 50):
     """The standalone front-to-back composite (qk_composite) over a 1080p LDM
     of L layers: its average launch time with HIP events on its stream and
@@ -682,6 +716,10 @@ def main():
                     help="for rocprofv3: run --steps chains of the paper's five-step schedule "
                          "(1080p inputs, V=8, bf16, one-to-many attention) and exit without "
                          "timing")
+    ap.add_argument("--profile-pipeline", action="store_true",
+                    help="for rocprofv3: run --steps whole frames (ray encoding, init, five "
+                         "steps, final render; 1080p, V=8, bf16, one-to-many attention) and exit "
+                         "without timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-run", action="store_true",
@@ -718,6 +756,15 @@ def main():
             runner.run_chain(ctx, ch, dc, attn_form="folded")
             torch.cuda.synchronize()
         log(f"profile chains: {args.steps} done")
+        return
+
+    if args.profile_pipeline:
+        pl = synth.make_pipeline()
+        dp = runner.pipeline_to_device(pl)
+        for s in range(args.steps):
+            runner.run_pipeline(ctx, pl, dp, attn_form="folded")
+            torch.cuda.synchronize()
+        log(f"profile frames: {args.steps} done")
         return
 
     log("drawing the 1080p multi-scale workload (V=8)")
@@ -832,6 +879,13 @@ def main():
         f"(one-to-many attention), {chain['standard']['chain_ms']:.3f} ms (standard)")
     torch.cuda.empty_cache()
 
+    pipeline = time_pipeline(ctx)
+    log(f"whole frame (paper's network at 1080p, final render): "
+        f"{pipeline['folded']['frame_ms']:.3f} ms (one-to-many attention, "
+        f"{pipeline['folded']['frames_per_s']:.0f} frames/s), "
+        f"{pipeline['standard']['frame_ms']:.3f} ms (standard)")
+    torch.cuda.empty_cache()
+
     composite = time_composite(ctx)
     log(f"standalone composite: {composite['avg_launch_ms'] * 1000:.1f} us, "
         f"{composite['achieved']:.0f} GB/s ({composite['frac'] * 100:.0f} % of HBM peak)")
@@ -910,6 +964,7 @@ def main():
         "layer_collapse": collapse,
         "ray_encoding": ray,
         "chain": chain,
+        "frame_pipeline": pipeline,
         "cpu_baseline": cpu,
         "training_step": train,
         "serving": serving,

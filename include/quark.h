@@ -13,6 +13,7 @@
  * a dry-run `_check` of their arguments):
  *   qk_update_fuse           one Update & Fuse step (+ composite), Sec. 3.2.2-3.3
  *   qk_update_fuse_noalloc   the same with a fixed scratch, no device allocation
+ *   qk_batch_update_fuse     several requests' steps in one launch (serving)
  *   qk_update_fuse_backward  its adjoint into features, LDM and weights
  *   qk_ldm_init              learned initialisation of an LDM, Sec. 3.2
  *   qk_composite             front-to-back over composite, Sec. 3.1
@@ -24,6 +25,7 @@
  *   qk_ray_encoding          ray-direction encoding of the views, Sec. 3.2.1-3.2.2
  *   qk_upsample2x            2x resolution transition, Sec. 3.2.2
  *   qk_ldm_decode            absolute decode of an encoded LDM, Sec. 3.2.2-3.2.3
+ *   qk_ldm_decode_logits     unactivated decode of the final volume, Sec. 3.2.3
  *   qk_camera_tables         the composed reprojection tables (host only)
  *
  * Conventions for every entry point
@@ -190,14 +192,19 @@ QK_API qk_status qk_context_destroy(qk_context *ctx);
  * C = 32: the paper's four heads of its 32 channels); otherwise
  * QK_EUNSUPPORTED.  QK_PREC_FP32 needs dtype
  * QK_F32, QK_PREC_BF16 and QK_PREC_BF16_FP8PROJ need QK_BF16 (else
- * QK_EDTYPE). */
+ * QK_EDTYPE).
+ * blend_logit_out, device [L][H][W][V] float or NULL: the blend-weight
+ * logits of Sec. 3.2.3 -- the step's pre-softmax attention logits
+ * a_m = q . k_m / sqrt(head_dim) (one-to-many form: q~ . s_m, the same
+ * value), for the final fusion block whose softmax the render applies after
+ * its upsampling.  One head only (else QK_EUNSUPPORTED). */
 QK_API qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V,
                          const qk_camera *in_cams, const qk_feature_map *feats,
                          const qk_camera *novel, float near_, float far_,
                          const qk_weights *weights, qk_precision precision,
                          qk_attn_form attn_form, qk_update_mode update_mode,
                          const qk_ldm *ldm_in, const qk_ldm *ldm_out,
-                         float *rgb_out, float *acc_alpha_out);
+                         float *rgb_out, float *acc_alpha_out, float *blend_logit_out);
 
 /* qk_update_fuse without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses
@@ -219,7 +226,47 @@ QK_API qk_status qk_update_fuse_noalloc(qk_context *ctx, void *hip_stream, int32
                                         const qk_weights *weights, qk_precision precision,
                                         qk_attn_form attn_form, qk_update_mode update_mode,
                                         const qk_ldm *ldm_in, const qk_ldm *ldm_out,
-                                        float *rgb_out, float *acc_alpha_out);
+                                        float *rgb_out, float *acc_alpha_out,
+                                        float *blend_logit_out);
+
+/* ---- Batched Update & Fuse (serving: several requests in one launch) ----
+ * One request of a batch: the arguments of qk_update_fuse for one LDM level
+ * of one request (precision and attention form are the batch's). */
+typedef struct {
+    int32_t V;
+    const qk_camera *in_cams;       /* host [V] */
+    const qk_feature_map *feats;    /* host [V] of device maps */
+    const qk_camera *novel;         /* host */
+    float near_, far_;
+    const qk_weights *weights;      /* host struct of device pointers */
+    qk_update_mode update_mode;
+    const qk_ldm *ldm_in;           /* host struct of device pointers */
+    const qk_ldm *ldm_out;
+    float *rgb_out;                 /* device [H][W][3] or NULL */
+    float *acc_alpha_out;           /* device [H][W] or NULL */
+} qk_request_desc;
+
+/* Update & Fuse of n_req requests (1..64) in one kernel launch (Sec. 3.2.2
+ * step, as qk_update_fuse, per request): requests may differ in LDM grid
+ * (L, H, W), view count, cameras, feature maps, frustum, weights, update
+ * mode and whether they composite; they share the feature width C, the
+ * heads and head width, the precision (QK_PREC_BF16 only) and the attention
+ * form.  Each request's outputs equal those of qk_update_fuse on its own,
+ * bit for bit (the same per-tile kernel body).  Requests must not share
+ * output buffers.  The requests' launch parameters (about 2.7 KiB each) go
+ * to the device through pinned host staging in the context; the folded
+ * weights of QK_ATTN_FOLDED take 2 heads C C_feat floats per request of the
+ * context's workspace (both grown on demand, which synchronises the stream).
+ * Errors (nothing enqueued): any request's qk_update_fuse error, prefixed
+ * with its index; QK_ESHAPE (n_req); QK_EUNSUPPORTED (another precision,
+ * requests of different C / heads, a grid of 2^31 tiles or more). */
+QK_API qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
+                                      const qk_request_desc *reqs, qk_precision precision,
+                                      qk_attn_form attn_form);
+
+/* Dry run of qk_batch_update_fuse's argument checks (no device use). */
+QK_API qk_status qk_batch_update_fuse_check(int32_t n_req, const qk_request_desc *reqs,
+                                            qk_precision precision, qk_attn_form attn_form);
 
 /* Dry run of qk_update_fuse's argument checks: returns the status the call
  * would return before enqueuing anything, without touching a device.  Takes
@@ -230,7 +277,7 @@ QK_API qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams,
                                qk_precision precision, qk_attn_form attn_form,
                                qk_update_mode update_mode, const qk_ldm *ldm_in,
                                const qk_ldm *ldm_out, float *rgb_out,
-                               float *acc_alpha_out);
+                               float *acc_alpha_out, float *blend_logit_out);
 
 /* Learned initialisation of an LDM (Sec. 3.2, "Initialization"): one
  * C-channel feature f0 broadcast over every layer-pixel, each layer flat at
@@ -599,6 +646,27 @@ QK_API qk_status qk_ldm_decode(qk_context *ctx, void *hip_stream, const qk_ldm *
 QK_API qk_status qk_ldm_decode_check(const qk_ldm *ldm, const float *w_sigma,
                                      const float *w_depth, const float *W_color, float near_,
                                      float far_, const float *color_out);
+
+/* Unactivated decode of the final feature volume (Sec. 3.2.3: the final
+ * LDM's depth and density are linear projections of V, activated only after
+ * the render's bilinear upsampling): for every layer-pixel
+ *   depth_logit = F . w_depth,  sigma_logit = F . w_sigma,
+ * the inputs qk_render_ibr takes.  Float32 arithmetic.
+ *   ldm          F [L][H][W][C] (QK_F32 or QK_BF16, C in {8, 16, 32, 64})
+ *                read; its depth and alpha are not used
+ *   w_sigma, w_depth  device float32 [C]
+ *   depth_logit, sigma_logit  device float32 [L][H][W], written, not
+ *                overlapping
+ * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned, overlapping),
+ * QK_ESHAPE, QK_EDTYPE, QK_EUNSUPPORTED (C, 2^38 elements or more). */
+QK_API qk_status qk_ldm_decode_logits(qk_context *ctx, void *hip_stream, const qk_ldm *ldm,
+                               const float *w_sigma, const float *w_depth, float *depth_logit,
+                               float *sigma_logit);
+
+/* Dry run of qk_ldm_decode_logits's argument checks (no device use). */
+QK_API qk_status qk_ldm_decode_logits_check(const qk_ldm *ldm, const float *w_sigma,
+                                     const float *w_depth, const float *depth_logit,
+                                     const float *sigma_logit);
 
 QK_API const char *qk_last_error(void);
 QK_API const char *qk_version(void);

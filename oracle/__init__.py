@@ -510,6 +510,70 @@ def run_chain(ch, attn_form: int = 0):
     return outs, rgb, acc
 
 
+def volume_logits(F, w_sigma, w_depth):
+    """The final LDM's unactivated attributes (Sec. 3.2.3: linear
+    projections, activated only after the render's upsampling): returns
+    (depth_logit, sigma_logit) = (F . w_depth, F . w_sigma) per layer-pixel."""
+    F = _as_f64_array(F)
+    return F @ _f64(w_depth), F @ _f64(w_sigma)
+
+
+def encode_pyramid(pl):
+    """Every pyramid level's maps plus their ray-direction encoding (Sec.
+    3.2.1; the paper's low-resolution form, one projection per level)."""
+    ch = pl.chain
+    out = []
+    for k, lvl in enumerate(ch.feats):
+        enc = []
+        for m, f in enumerate(lvl):
+            f64 = _as_f64_array(f)
+            Hf, Wf = f64.shape[:2]
+            enc.append(f64 + ray_encoding_lowres(ch.in_cams[m], ch.novel, ch.near, ch.far,
+                                                 pl.Wr[k], pl.low_hw, Hf, Wf))
+        out.append(enc)
+    return out
+
+
+def run_pipeline(pl, attn_form: int = 0, rows: Optional[Sequence[int]] = None):
+    """The whole frame of a ``synth.PipelineScene``: the ray-encoded pyramid;
+    the learned initialisation (f0 broadcast, flat layers at the anchors,
+    alpha 1/2) as the first step's LDM; the chained steps (transition,
+    absolute decode of the step's input, Update & Fuse, residual CNN block),
+    the last of which also gives the blend-weight logits of its attention;
+    the unactivated decode of the final feature volume; and the final render
+    (Eq. 1: upsample, activate, blend the input images, composite) at the
+    output grid, on ``rows`` of it (default all).  Returns (per-step outputs,
+    render outputs, encoded pyramid)."""
+    ch = pl.chain
+    feats = encode_pyramid(pl)
+    s0 = ch.steps[0]
+    F, d, a = ldm_init(s0.L, s0.H, s0.W, pl.f0, ch.near, ch.far)
+    outs = []
+    n = len(ch.steps)
+    for i, st in enumerate(ch.steps):
+        w = ch.weights[i]
+        if i > 0:
+            F = outs[-1]["F_next"]
+            if st.collapse:
+                F = layer_collapse(F, *ch.collapse_w[i])
+            if st.upsample:
+                F = upsample2x(F)
+            d, a, _ = decode_volume(F, w["w_sigma"], w["w_depth"], w["W_color"], ch.near, ch.far)
+        out = update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F, depth=d,
+                          alpha=a, mode=1, attn_form=attn_form, feats64=feats[st.level],
+                          want_logits=(i == n - 1))
+        out["F_in"], out["depth_in"], out["alpha_in"] = F, d, a
+        out["F_next"] = residual_conv(out["F"], *ch.conv_w[i]) if st.conv else out["F"]
+        outs.append(out)
+    w = ch.weights[-1]
+    dl, sl = volume_logits(outs[-1]["F_next"], w["w_sigma"], w["w_depth"])
+    H, W = pl.out_hw
+    r = render_ibr(ch.in_cams, pl.images, ch.novel, ch.near, ch.far, dl, sl,
+                   outs[-1]["blend_logit"], H, W, rows=rows)
+    r["depth_logit"], r["sigma_logit"] = dl, sl
+    return outs, r, feats
+
+
 def run_scene(scene, *, rows_per_level=None, mode: int = 0, attn_form: int = 0):
     """All levels of a scene.  ``rows_per_level`` is a list (one entry per
     level, None = all rows)."""

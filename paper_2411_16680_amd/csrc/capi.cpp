@@ -10,12 +10,15 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "quark.h"
 #include "uf_params.h"
 
 namespace qk {
 hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool fold, hipStream_t s);
+hipError_t launch_update_fuse_batch(const UFParams *reqs, const UFBatch &b, int C, int hd,
+                                    int prec, bool fold, hipStream_t s);
 hipError_t launch_fp8_scales(const F8Params &p, hipStream_t s);
 hipError_t launch_fold_weights(const FoldParams &f, hipStream_t s);
 hipError_t launch_composite(const CompParams &p, hipStream_t s);
@@ -48,6 +51,12 @@ struct qk_context {
     float *rws = nullptr;        // low-resolution projected ray encodings
     size_t rws_elems = 0;
     float *scratch = nullptr;    // this device's fixed scratch (allocation-free entry point)
+    float *bdesc = nullptr;      // batched requests' launch parameters (device)
+    size_t bdesc_elems = 0;
+    void *bhost = nullptr;       // their pinned host staging
+    size_t bhost_bytes = 0;
+    hipEvent_t bevent = nullptr; // recorded after the staging copy
+    bool bevent_live = false;
 };
 
 namespace {
@@ -169,7 +178,7 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
                             const qk_camera *novel, float near_, float far_, const qk_weights *w,
                             qk_precision precision, qk_attn_form attn_form,
                             qk_update_mode update_mode, const qk_ldm *in, const qk_ldm *out,
-                            float *rgb_out, float *acc_out) {
+                            float *rgb_out, float *acc_out, float *blend_out) {
     if (!in_cams || !feats || !novel || !w || !in || !out)
         return fail(QK_EINVAL, "NULL argument");
     if (V < 1 || V > qk::kMaxViews)
@@ -208,6 +217,11 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
         !aligned4(out->alpha) || (rgb_out && !aligned4(rgb_out)) || (acc_out && !aligned4(acc_out)))
         return fail(QK_EINVAL, "float buffers must be 4-byte aligned");
     if (acc_out && !rgb_out) return fail(QK_EINVAL, "acc_alpha_out needs rgb_out");
+    if (blend_out && !aligned4(blend_out)) return fail(QK_EINVAL, "blend_logit_out must be 4-byte aligned");
+    if (blend_out && (w->heads != 1 || w->head_dim != in->C))
+        return fail(QK_EUNSUPPORTED, "blend_logit_out needs one attention head (got %d)", w->heads);
+    if (blend_out && (int64_t)in->L * in->H * in->W * V >= ((int64_t)1 << 40))
+        return fail(QK_EUNSUPPORTED, "blend logits too large");
     const int64_t elems = (int64_t)in->L * in->H * in->W * in->C;
     if (elems >= (int64_t)1 << 31)
         return fail(QK_EUNSUPPORTED, "LDM of %lld elements exceeds 2^31", (long long)elems);
@@ -580,7 +594,8 @@ qk_status qk_context_create(int device, qk_context **out) {
 }
 
 qk_status qk_context_destroy(qk_context *ctx) {
-    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag || ctx->rws)) {
+    if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag || ctx->rws ||
+                ctx->bdesc || ctx->bhost || ctx->bevent)) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
@@ -589,6 +604,10 @@ qk_status qk_context_destroy(qk_context *ctx) {
         if (ctx->vws) (void)hipFree(ctx->vws);
         if (ctx->cfrag) (void)hipFree(ctx->cfrag);
         if (ctx->rws) (void)hipFree(ctx->rws);
+        if (ctx->bevent) (void)hipEventSynchronize(ctx->bevent);
+        if (ctx->bdesc) (void)hipFree(ctx->bdesc);
+        if (ctx->bhost) (void)hipHostFree(ctx->bhost);
+        if (ctx->bevent) (void)hipEventDestroy(ctx->bevent);
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
@@ -616,29 +635,21 @@ qk_status qk_update_fuse_check(int32_t V, const qk_camera *in_cams, const qk_fea
                                const qk_weights *weights, qk_precision precision,
                                qk_attn_form attn_form, qk_update_mode update_mode,
                                const qk_ldm *ldm_in, const qk_ldm *ldm_out, float *rgb_out,
-                               float *acc_alpha_out) {
+                               float *acc_alpha_out, float *blend_logit_out) {
     return check_update_fuse(V, in_cams, feats, novel, near_, far_, weights, precision, attn_form,
-                             update_mode, ldm_in, ldm_out, rgb_out, acc_alpha_out);
+                             update_mode, ldm_in, ldm_out, rgb_out, acc_alpha_out, blend_logit_out);
 }
 
 }  // extern "C"
 
 namespace {
 
-// qk_update_fuse and its allocation-free variant.  fixed == NULL: the folded
-// weights and the e4m3 scales go to the context's workspaces (grown on
-// demand); otherwise to `fixed` (kScratchFloats floats; nothing allocated).
-qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
-                           const qk_feature_map *feats, const qk_camera *novel, float near_,
-                           float far_, const qk_weights *w, qk_precision precision,
-                           qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
-                           const qk_ldm *out, float *rgb_out, float *acc_out, float *fixed) {
-    if (!ctx) return fail(QK_EINVAL, "context is NULL");
-    qk_status st = check_update_fuse(V, in_cams, feats, novel, near_, far_, w, precision,
-                                     attn_form, update_mode, in, out, rgb_out, acc_out);
-    if (st != QK_OK) return st;
-
-    qk::UFParams p;
+// The launch parameters of one checked Update & Fuse request: camera
+// tables (composed in double), pointers, and the tiling of its grid.
+qk_status fill_uf_params(int32_t V, const qk_camera *in_cams, const qk_feature_map *feats,
+                         const qk_camera *novel, float near_, float far_, const qk_weights *w,
+                         qk_update_mode update_mode, const qk_ldm *in, const qk_ldm *out,
+                         float *rgb_out, float *acc_out, float *blend_out, qk::UFParams &p) {
     std::memset(&p, 0, sizeof(p));
     for (int m = 0; m < V; ++m) {
         p.feat[m] = feats[m].data;
@@ -659,6 +670,7 @@ qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const q
     p.alpha_out = out->alpha;
     p.rgb = rgb_out;
     p.acc = acc_out;
+    p.blend_logit = blend_out;
     p.Wq = w->Wq;
     p.Wk = w->Wk;
     p.Wv = w->Wv;
@@ -690,6 +702,27 @@ qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const q
     const int64_t tiles = xy * p.chunks;
     if (tiles >= ((int64_t)1 << 31)) return fail(QK_EUNSUPPORTED, "grid too large");
     p.n_tiles = (int32_t)tiles;
+    return QK_OK;
+}
+
+// qk_update_fuse and its allocation-free variant.  fixed == NULL: the folded
+// weights and the e4m3 scales go to the context's workspaces (grown on
+// demand); otherwise to `fixed` (kScratchFloats floats; nothing allocated).
+qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const qk_camera *in_cams,
+                           const qk_feature_map *feats, const qk_camera *novel, float near_,
+                           float far_, const qk_weights *w, qk_precision precision,
+                           qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
+                           const qk_ldm *out, float *rgb_out, float *acc_out, float *blend_out,
+                           float *fixed) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = check_update_fuse(V, in_cams, feats, novel, near_, far_, w, precision,
+                                     attn_form, update_mode, in, out, rgb_out, acc_out, blend_out);
+    if (st != QK_OK) return st;
+
+    qk::UFParams p;
+    st = fill_uf_params(V, in_cams, feats, novel, near_, far_, w, update_mode, in, out, rgb_out,
+                        acc_out, blend_out, p);
+    if (st != QK_OK) return st;
 
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
@@ -770,9 +803,9 @@ qk_status qk_update_fuse(qk_context *ctx, void *hip_stream, int32_t V, const qk_
                          const qk_feature_map *feats, const qk_camera *novel, float near_,
                          float far_, const qk_weights *w, qk_precision precision,
                          qk_attn_form attn_form, qk_update_mode update_mode, const qk_ldm *in,
-                         const qk_ldm *out, float *rgb_out, float *acc_out) {
+                         const qk_ldm *out, float *rgb_out, float *acc_out, float *blend_out) {
     return update_fuse_impl(ctx, hip_stream, V, in_cams, feats, novel, near_, far_, w, precision,
-                            attn_form, update_mode, in, out, rgb_out, acc_out, nullptr);
+                            attn_form, update_mode, in, out, rgb_out, acc_out, blend_out, nullptr);
 }
 
 qk_status qk_update_fuse_noalloc(qk_context *ctx, void *hip_stream, int32_t V,
@@ -781,11 +814,126 @@ qk_status qk_update_fuse_noalloc(qk_context *ctx, void *hip_stream, int32_t V,
                                  const qk_weights *w, qk_precision precision,
                                  qk_attn_form attn_form, qk_update_mode update_mode,
                                  const qk_ldm *in, const qk_ldm *out, float *rgb_out,
-                                 float *acc_out) {
+                                 float *acc_out, float *blend_out) {
     if (!ctx) return fail(QK_EINVAL, "context is NULL");
     if (ctx->scratch == nullptr) return fail(QK_EHIP, "the device's fixed scratch is unknown");
     return update_fuse_impl(ctx, hip_stream, V, in_cams, feats, novel, near_, far_, w, precision,
-                            attn_form, update_mode, in, out, rgb_out, acc_out, ctx->scratch);
+                            attn_form, update_mode, in, out, rgb_out, acc_out, blend_out,
+                            ctx->scratch);
+}
+
+qk_status qk_batch_update_fuse_check(int32_t n_req, const qk_request_desc *reqs,
+                                     qk_precision precision, qk_attn_form attn_form) {
+    if (!reqs) return fail(QK_EINVAL, "reqs is NULL");
+    if (n_req < 1 || n_req > qk::kMaxBatch)
+        return fail(QK_ESHAPE, "n_req = %d outside 1..%d", n_req, qk::kMaxBatch);
+    if (precision != QK_PREC_BF16)
+        return fail(QK_EUNSUPPORTED, "batches run the bfloat16 form (QK_PREC_BF16)");
+    int64_t tiles = 0;
+    for (int r = 0; r < n_req; ++r) {
+        const qk_request_desc &q = reqs[r];
+        qk_status st = check_update_fuse(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_,
+                                         q.weights, precision, attn_form, q.update_mode,
+                                         q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out, nullptr);
+        if (st != QK_OK) {
+            const std::string msg = g_err;
+            return fail(st, "request %d: %s", r, msg.c_str());
+        }
+        const qk_weights *w0 = reqs[0].weights;
+        if (q.weights->C != w0->C || q.weights->heads != w0->heads ||
+            q.weights->head_dim != w0->head_dim)
+            return fail(QK_EUNSUPPORTED, "request %d: every request needs C, heads and head_dim "
+                        "of request 0", r);
+        qk::UFParams p;
+        st = fill_uf_params(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_, q.weights,
+                            q.update_mode, q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out,
+                            nullptr, p);
+        if (st != QK_OK) return st;
+        tiles += p.n_tiles;
+    }
+    if (tiles >= ((int64_t)1 << 31)) return fail(QK_EUNSUPPORTED, "batch grid too large");
+    return QK_OK;
+}
+
+qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
+                               const qk_request_desc *reqs, qk_precision precision,
+                               qk_attn_form attn_form) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = qk_batch_update_fuse_check(n_req, reqs, precision, attn_form);
+    if (st != QK_OK) return st;
+    std::vector<qk::UFParams> ps((size_t)n_req);
+    qk::UFBatch b;
+    std::memset(&b, 0, sizeof(b));
+    b.n_req = n_req;
+    int64_t tiles = 0;
+    for (int r = 0; r < n_req; ++r) {
+        const qk_request_desc &q = reqs[r];
+        st = fill_uf_params(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_, q.weights,
+                            q.update_mode, q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out,
+                            nullptr, ps[r]);
+        if (st != QK_OK) return st;
+        b.tile_start[r] = (int32_t)tiles;
+        tiles += ps[r].n_tiles;
+    }
+    b.tile_start[n_req] = (int32_t)tiles;
+    b.total_tiles = (int32_t)tiles;
+
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const qk_weights *w0 = reqs[0].weights;
+    const bool fold = attn_form == QK_ATTN_FOLDED;
+    if (fold) {
+        // each request's folded weights in its own slice of the workspace
+        const size_t per = (size_t)w0->heads * w0->C * w0->C_feat;
+        st = grow(&ctx->wfold, &ctx->wfold_elems, 2 * per * (size_t)n_req, stream);
+        if (st != QK_OK) return st;
+        for (int r = 0; r < n_req; ++r) {
+            const qk_weights *w = reqs[r].weights;
+            float *wf = ctx->wfold + 2 * per * (size_t)r;
+            qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per, w->C, w->C_feat,
+                              w->head_dim, w->heads, 1.0f / std::sqrt((float)w->head_dim)};
+            hipError_t fe = qk::launch_fold_weights(fp, stream);
+            if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
+            ps[r].Wqk = fp.Wqk;
+            ps[r].Wvo = fp.Wvo;
+        }
+    }
+    // the requests' parameters to the device: pinned staging, reused once
+    // the previous call's copy has completed
+    const size_t bytes = sizeof(qk::UFParams) * (size_t)n_req;
+    st = grow(&ctx->bdesc, &ctx->bdesc_elems, (bytes + 3) / 4, stream);
+    if (st != QK_OK) return st;
+    hipError_t e;
+    if (ctx->bevent == nullptr) {
+        e = hipEventCreateWithFlags(&ctx->bevent, hipEventDisableTiming);
+        if (e != hipSuccess) return fail(QK_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    if (ctx->bevent_live) {
+        e = hipEventSynchronize(ctx->bevent);
+        if (e != hipSuccess) return fail(QK_EHIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+        ctx->bevent_live = false;
+    }
+    if (ctx->bhost_bytes < bytes) {
+        if (ctx->bhost) (void)hipHostFree(ctx->bhost);
+        ctx->bhost = nullptr;
+        ctx->bhost_bytes = 0;
+        e = hipHostMalloc(&ctx->bhost, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(QK_ENOMEM, "pinned staging of %zu bytes", bytes);
+        ctx->bhost_bytes = bytes;
+    }
+    std::memcpy(ctx->bhost, ps.data(), bytes);
+    e = hipMemcpyAsync(ctx->bdesc, ctx->bhost, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "parameter upload: %s", hipGetErrorString(e));
+    e = hipEventRecord(ctx->bevent, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+    ctx->bevent_live = true;
+    e = qk::launch_update_fuse_batch(reinterpret_cast<const qk::UFParams *>(ctx->bdesc), b, w0->C,
+                                     w0->head_dim, (int)precision, fold, stream);
+    if (e != hipSuccess) return fail(QK_EHIP, "batched update_fuse launch: %s", hipGetErrorString(e));
+    return QK_OK;
 }
 
 qk_status qk_composite(qk_context *ctx, void *hip_stream, int32_t L, int32_t H, int32_t W,
@@ -1250,9 +1398,41 @@ qk_status qk_ldm_decode(qk_context *ctx, void *hip_stream, const qk_ldm *ldm,
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     qk::DecodeParams p{ldm->F, w_sigma, w_depth, W_color, ldm->depth, ldm->alpha, color_out,
                        ldm->L, ldm->H, ldm->W, ldm->C, ldm->dtype == QK_BF16 ? 1 : 0,
-                       (float)(1.0 / (double)near_), (float)(1.0 / (double)far_)};
+                       (float)(1.0 / (double)near_), (float)(1.0 / (double)far_), 0};
     hipError_t e = qk::launch_ldm_decode(p, reinterpret_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(QK_EHIP, "decode launch: %s", hipGetErrorString(e));
+    return QK_OK;
+}
+
+qk_status qk_ldm_decode_logits_check(const qk_ldm *ldm, const float *w_sigma, const float *w_depth,
+                              const float *depth_logit, const float *sigma_logit) {
+    if (!ldm || !depth_logit || !sigma_logit) return fail(QK_EINVAL, "NULL argument");
+    qk_ldm v = *ldm;                 // the decode's checks, on the logit outputs
+    v.depth = const_cast<float *>(depth_logit);
+    v.alpha = const_cast<float *>(sigma_logit);
+    qk_status st = check_decode(&v, w_sigma, w_depth, w_sigma, 0.5f, 1.0f, nullptr);
+    if (st != QK_OK) return st;
+    const int64_t n = (int64_t)ldm->L * ldm->H * ldm->W;
+    const float *a = depth_logit, *b = sigma_logit;
+    if (a < b + n && b < a + n) return fail(QK_EINVAL, "depth_logit overlaps sigma_logit");
+    return QK_OK;
+}
+
+qk_status qk_ldm_decode_logits(qk_context *ctx, void *hip_stream, const qk_ldm *ldm,
+                        const float *w_sigma, const float *w_depth, float *depth_logit,
+                        float *sigma_logit) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    qk_status st = qk_ldm_decode_logits_check(ldm, w_sigma, w_depth, depth_logit, sigma_logit);
+    if (st != QK_OK) return st;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk::DecodeParams p{ldm->F, w_sigma, w_depth, w_sigma, depth_logit, sigma_logit, nullptr,
+                       ldm->L, ldm->H, ldm->W, ldm->C, ldm->dtype == QK_BF16 ? 1 : 0,
+                       1.0f, 1.0f, 1};
+    hipError_t e = qk::launch_ldm_decode(p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(QK_EHIP, "logits launch: %s", hipGetErrorString(e));
     return QK_OK;
 }
 

@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(256) k_ldm_decode(const DecodeParams p) {
     __shared__ float w[C * 5];
     for (int i = threadIdx.x; i < C * 5; i += 256) {
         const int c = i / 5, k = i - 5 * c;
-        w[i] = k == 0 ? p.w_sigma[c] : k == 1 ? p.w_depth[c] : p.W_color[3 * c + k - 2];
+        w[i] = k == 0 ? p.w_sigma[c] : k == 1 ? p.w_depth[c]
+             : p.logits ? 0.0f : p.W_color[3 * c + k - 2];
     }
     __syncthreads();
     const int64_t hw = (int64_t)p.H * p.W;
@@ -171,6 +172,11 @@ __global__ void __launch_bounds__(256) k_ldm_decode(const DecodeParams p) {
             x1 = fmaf(f[j], wc[3], x1);
             x2 = fmaf(f[j], wc[4], x2);
         }
+    }
+    if (p.logits) {                  // the unactivated depth and density
+        p.depth[q] = xd;
+        p.alpha[q] = xs;
+        return;
     }
     const float L = (float)p.L;
     const float delta = ((float)(p.L - li) - 0.5f) / L;

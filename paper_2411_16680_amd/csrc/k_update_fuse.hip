@@ -505,10 +505,52 @@ struct Occupancy {
 // value projection into the output (W_v W_o); the per-view work is a dot
 // product and a weighted sum on the samples themselves (for C = 8 the same
 // MFMA loop, with the blended sample standing in for keys and values).
-template <int C, bool BF16, bool FOLD, bool F8, int HD>
+//
+// VAR selects the variant: kPlain, one level, its parameters in the kernel
+// argument; kBlend, the same that also writes the blend-weight logits (one
+// head); kBatch, several requests (levels of different size, view count,
+// cameras, maps and weights) in one launch -- request r owns the global
+// tiles [tile_start[r], tile_start[r + 1]) and its parameters are read from
+// device memory (uniform per workgroup).
+constexpr int kPlain = 0, kBlend = 1, kBatch = 2;
+
+template <bool BATCH>
+struct UFArgs {
+    UFParams p;
+};
+template <>
+struct UFArgs<true> {
+    const UFParams *reqs;
+    UFBatch b;
+};
+
+// XCD-aware remap of the dispatch order: workgroups are dispatched to the 8
+// XCDs round-robin; each XCD walks one contiguous band of the nt tiles (rows
+// of one level, L2 locality of the epipolar bands).
+__device__ __forceinline__ int xcd_tile(int i, int nt) {
+    const int xcd = i & 7, loc = i >> 3, q = nt >> 3, rem = nt & 7;
+    return (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+}
+
+template <int C, bool BF16, bool FOLD, bool F8, int HD, int VAR>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((FOLD && HD != C) ? 2 : Occupancy<C, BF16, FOLD>::waves)))
-k_update_fuse(const UFParams p) {
+k_update_fuse(const UFArgs<VAR == kBatch> args) {
+    constexpr bool BATCH = VAR == kBatch;
+    static_assert(VAR != kBlend || HD == C, "blend-weight logits: one head");
+    // this workgroup's request and tile
+    int req = 0, tile;
+    if constexpr (BATCH) {
+        const int t = xcd_tile(blockIdx.x, args.b.total_tiles);
+        for (int i = 1; i < args.b.n_req; ++i) req = (t >= args.b.tile_start[i]) ? i : req;
+        tile = t - args.b.tile_start[req];
+    } else {
+        tile = xcd_tile(blockIdx.x, args.p.n_tiles);
+    }
+    const UFParams &p = [&]() -> const UFParams & {
+        if constexpr (BATCH) return args.reqs[req];
+        else return args.p;
+    }();
     static_assert(!F8 || BF16, "e4m3 projections take bfloat16 storage");
     static_assert(HD == C || (C >= 32 && (HD == 8 || (HD >= 16 && C % HD == 0))),
                   "several heads: C >= 32, head width 8 or a multiple of 16");
@@ -614,16 +656,9 @@ k_update_fuse(const UFParams p) {
     }
     __syncthreads();
 
-    // ---- tile of this workgroup: XCD-aware remap of the dispatch order so
-    // that each XCD (dispatched round-robin) walks one contiguous band of rows
+    // ---- the tile's place in the level
     const int wave = tid >> 6, lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
-    int tile;
-    {
-        const int nt = p.n_tiles, i = blockIdx.x;
-        const int xcd = i & 7, loc = i >> 3, q = nt >> 3, rem = nt & 7;
-        tile = (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
-    }
     const int chunk = tile % p.chunks;
     const int rest = tile / p.chunks;
     const int xb = rest % p.x_blocks;
@@ -763,7 +798,7 @@ k_update_fuse(const UFParams p) {
             using TapsT = typename std::conditional<TAPK, TapsK<BF16>, Taps<C, BF16>>::type;
             int2 *tT = reinterpret_cast<int2 *>(sO[wave]);   // free until o is written
             // one view: blend -> keys -> logits -> online softmax -> values
-            auto view_step = [&](const TapsT &cur) {
+            auto view_step = [&](const TapsT &cur, int m) {
                 // B operands: the blended sample (one per K chunk), or for C = 8
                 // the weighted taps of each 16-pixel row-group
                 constexpr int NA = TAPK ? 4 : KC;
@@ -839,6 +874,16 @@ k_update_fuse(const UFParams p) {
                         lg[t] = result_pixel_sum<C>(part) * (scale * kscale);
                     }
                 }
+                if constexpr (VAR == kBlend) {
+                    // blend-weight logits (one head): written by the lane that
+                    // holds channel 0 of the pixel in the result layout
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int t = (G == 1) ? s * TPH : s;
+                        const int xe = x0w + 16 * sd(t) + n;
+                        if (ed(t) == 0 && xe < p.W) p.blend_logit[(rowbase + xe) * p.V + m] = lg[s];
+                    }
+                }
                 // online softmax with a lazily moved reference: weights are
                 // exp(logit - M) while the logit stays within e^8 of M; only
                 // a logit beyond that (always the first view, rarely another)
@@ -892,11 +937,11 @@ k_update_fuse(const UFParams p) {
             for (int m = 0; m < p.V; m += 2) {
                 issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, tb);
                 __builtin_amdgcn_sched_barrier(0);
-                view_step(ta);
+                view_step(ta, m);
                 __builtin_amdgcn_sched_barrier(0);
                 issue_any<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, ta);
                 __builtin_amdgcn_sched_barrier(0);
-                if (m + 1 < p.V) view_step(tb);
+                if (m + 1 < p.V) view_step(tb, m + 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
 
@@ -939,7 +984,7 @@ k_update_fuse(const UFParams p) {
             float Mx[HQ], Zs[HQ];
 #pragma unroll
             for (int hq = 0; hq < HQ; ++hq) { Mx[hq] = -1e30f; Zs[hq] = 0.0f; }
-            auto view_step = [&](const Taps<C, BF16> &cur) {
+            auto view_step = [&](const Taps<C, BF16> &cur, int m) {
                 float sv[KC][8];
                 blend_taps<C, BF16>(cur, sv);
                 stage_sample<C>(tO, pl_ld, ch_ld, pl_b, ch0, sv);
@@ -951,6 +996,10 @@ k_update_fuse(const UFParams p) {
 #pragma unroll
                         for (int i = 0; i < 8; ++i) part = fmaf(qa[hq][kc][i], sv[kc][i], part);
                     const float a = operand_pixel_sum<C>(part);
+                    if constexpr (VAR == kBlend) {
+                        // blend-weight logit: the lane holding channel 0
+                        if (ch0 == 0 && a_ok) p.blend_logit[(rowbase + xa) * p.V + m] = a;
+                    }
                     float diff = a - Mx[hq];
                     if (diff > 8.0f) {             // lazily moved reference (see above)
                         const float r = __expf(-diff);
@@ -977,11 +1026,11 @@ k_update_fuse(const UFParams p) {
             for (int m = 0; m < p.V; m += 2) {
                 issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, tb);
                 __builtin_amdgcn_sched_barrier(0);
-                view_step(ta);
+                view_step(ta, m);
                 __builtin_amdgcn_sched_barrier(0);
                 issue_taps<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, ta);
                 __builtin_amdgcn_sched_barrier(0);
-                if (m + 1 < p.V) view_step(tb);
+                if (m + 1 < p.V) view_step(tb, m + 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
@@ -1106,15 +1155,45 @@ __global__ void __launch_bounds__(256) k_composite(const CompParams p) {
 // ---------------------------------------------------------------------------
 // Launchers (host side of this translation unit)
 // ---------------------------------------------------------------------------
+// One level (batch == nullptr), or a batch of requests whose parameters
+// are at `reqs` in device memory.
+struct UFLaunch {
+    const UFParams *p;          // host copy (single) or nullptr
+    const UFParams *reqs;       // device array (batch) or nullptr
+    const UFBatch *batch;
+};
+
 template <int C, bool BF16, bool FOLD, bool F8, int HD>
-static hipError_t launch_uf(const UFParams &p, hipStream_t s) {
-    hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8, HD>), dim3(p.n_tiles), dim3(256), 0, s, p);
+static hipError_t launch_uf(const UFLaunch &l, hipStream_t s) {
+    if (l.batch != nullptr) {
+        // batches: the bfloat16 forms without e4m3 projections
+        if constexpr (BF16 && !F8) {
+            const UFArgs<true> a{l.reqs, *l.batch};
+            hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8, HD, kBatch>),
+                               dim3(l.batch->total_tiles), dim3(256), 0, s, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (l.p->blend_logit != nullptr) {
+        // blend-weight logits: one head, no e4m3 projections
+        if constexpr (HD == C && !F8) {
+            const UFArgs<false> a{*l.p};
+            hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8, HD, kBlend>), dim3(l.p->n_tiles),
+                               dim3(256), 0, s, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        const UFArgs<false> a{*l.p};
+        hipLaunchKernelGGL((k_update_fuse<C, BF16, FOLD, F8, HD, kPlain>), dim3(l.p->n_tiles),
+                           dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 // prec: 0 float32, 1 bfloat16, 2 bfloat16 storage with e4m3 projections
 template <int C, int HD>
-static hipError_t launch_c(const UFParams &p, int prec, bool fold, hipStream_t s) {
+static hipError_t launch_c(const UFLaunch &p, int prec, bool fold, hipStream_t s) {
     if constexpr (HD != C && C != 32) {          // several heads, standard form only
         if (fold) return hipErrorInvalidValue;
         if (prec == 2) return launch_uf<C, true, false, true, HD>(p, s);
@@ -1132,7 +1211,7 @@ static hipError_t launch_c(const UFParams &p, int prec, bool fold, hipStream_t s
 }
 
 // hd: the width of one head (C for a single head)
-hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool fold, hipStream_t s) {
+static hipError_t launch_any(const UFLaunch &p, int C, int hd, int prec, bool fold, hipStream_t s) {
     switch (C * 1000 + hd) {
         case 8008: return launch_c<8, 8>(p, prec, fold, s);
         case 16016: return launch_c<16, 16>(p, prec, fold, s);
@@ -1144,6 +1223,17 @@ hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool f
         case 64016: return launch_c<64, 16>(p, prec, fold, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_update_fuse(const UFParams &p, int C, int hd, int prec, bool fold, hipStream_t s) {
+    const UFLaunch l{&p, nullptr, nullptr};
+    return launch_any(l, C, hd, prec, fold, s);
+}
+
+hipError_t launch_update_fuse_batch(const UFParams *reqs, const UFBatch &b, int C, int hd,
+                                    int prec, bool fold, hipStream_t s) {
+    const UFLaunch l{nullptr, reqs, &b};
+    return launch_any(l, C, hd, prec, fold, s);
 }
 
 // Folded weights of one-to-many attention, per head h of width d = hd

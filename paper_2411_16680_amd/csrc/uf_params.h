@@ -31,6 +31,7 @@ struct UFParams {
     float *alpha_out;
     float *rgb;            // may be NULL (no composite)
     float *acc;            // may be NULL
+    float *blend_logit;    // [L][H][W][V] attention logits (one head), or NULL
 
     const float *Wq, *Wk, *Wv, *Wo, *w_sigma, *w_depth, *W_color;
     const float *Wqk, *Wvo;    // folded weights (one-to-many form), C x C
@@ -43,6 +44,16 @@ struct UFParams {
     int32_t chunks;
     float inv_near, inv_far;
     int32_t mode;              // 0 residual, 1 paper decode
+};
+
+// A batch of Update & Fuse requests in one launch (the requests' UFParams
+// are in device memory): request r owns global tiles
+// [tile_start[r], tile_start[r + 1]).
+constexpr int kMaxBatch = 64;
+struct UFBatch {
+    int32_t tile_start[kMaxBatch + 1];
+    int32_t n_req;
+    int32_t total_tiles;
 };
 
 struct FoldParams {
@@ -247,6 +258,7 @@ struct DecodeParams {
     float *depth, *alpha, *color;   // [L][H][W], [L][H][W], [L][H][W][3] or null
     int32_t L, H, W, C, bf16;
     float inv_near, inv_far;
+    int32_t logits;                 // 1: write F.w_depth, F.w_sigma unactivated
 };
 
 }  // namespace qk

@@ -27,14 +27,15 @@ MODE = {"residual": 0, "paper": 1}
 
 # symbols include/quark.h declares (checked by the CPU tests)
 EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
-           "qk_update_fuse_noalloc",
+           "qk_update_fuse_noalloc", "qk_batch_update_fuse", "qk_batch_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_composite_backward", "qk_composite_backward_check",
            "qk_render_ibr", "qk_render_ibr_check", "qk_render_to_views",
            "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
            "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
            "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check", "qk_ldm_decode",
-           "qk_ldm_decode_check", "qk_camera_tables", "qk_last_error", "qk_version"]
+           "qk_ldm_decode_check", "qk_ldm_decode_logits", "qk_ldm_decode_logits_check",
+           "qk_camera_tables", "qk_last_error", "qk_version"]
 
 
 class QuarkError(RuntimeError):
@@ -90,6 +91,14 @@ class qk_weights(ctypes.Structure):
                 ("head_dim", ctypes.c_int32)]
 
 
+class qk_request_desc(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_int32), ("in_cams", ctypes.c_void_p), ("feats", ctypes.c_void_p),
+                ("novel", ctypes.c_void_p), ("near_", ctypes.c_float), ("far_", ctypes.c_float),
+                ("weights", ctypes.c_void_p), ("update_mode", ctypes.c_int),
+                ("ldm_in", ctypes.c_void_p), ("ldm_out", ctypes.c_void_p),
+                ("rgb_out", ctypes.c_void_p), ("acc_alpha_out", ctypes.c_void_p)]
+
+
 class qk_weight_grads(ctypes.Structure):
     _fields_ = [("Wq", ctypes.c_void_p), ("Wk", ctypes.c_void_p), ("Wv", ctypes.c_void_p),
                 ("Wo", ctypes.c_void_p), ("w_sigma", ctypes.c_void_p),
@@ -114,10 +123,14 @@ def load() -> ctypes.CDLL:
     L.qk_context_destroy.argtypes = [ctypes.c_void_p]
     uf_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
                ctypes.c_float, P(qk_weights), ctypes.c_int, ctypes.c_int, ctypes.c_int,
-               P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p]
+               P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.qk_update_fuse.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
     L.qk_update_fuse_check.argtypes = uf_args
     L.qk_update_fuse_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + uf_args
+    L.qk_batch_update_fuse.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       P(qk_request_desc), ctypes.c_int, ctypes.c_int]
+    L.qk_batch_update_fuse_check.argtypes = [ctypes.c_int32, P(qk_request_desc), ctypes.c_int,
+                                             ctypes.c_int]
     bwd_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
                 ctypes.c_float, P(qk_weights), ctypes.c_int, P(qk_ldm), P(qk_ldm), ctypes.c_void_p,
                 P(qk_ldm), P(qk_ldm), P(ctypes.c_void_p), P(qk_weight_grads)]
@@ -159,15 +172,19 @@ def load() -> ctypes.CDLL:
                 ctypes.c_float, ctypes.c_void_p]
     L.qk_ldm_decode.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + dec_args
     L.qk_ldm_decode_check.argtypes = dec_args
+    lg_args = [P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.qk_ldm_decode_logits.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + lg_args
+    L.qk_ldm_decode_logits_check.argtypes = lg_args
     for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
-                 "qk_update_fuse_noalloc", "qk_update_fuse_check", "qk_update_fuse_backward",
+                 "qk_update_fuse_noalloc", "qk_batch_update_fuse", "qk_batch_update_fuse_check", "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_composite_backward", "qk_composite_backward_check", "qk_render_ibr",
                  "qk_render_ibr_check", "qk_render_to_views",
                  "qk_render_to_views_check", "qk_residual_conv", "qk_residual_conv_check",
                  "qk_layer_collapse", "qk_layer_collapse_check", "qk_ray_encoding",
                  "qk_ray_encoding_check", "qk_upsample2x", "qk_upsample2x_check",
-                 "qk_ldm_decode", "qk_ldm_decode_check", "qk_camera_tables"):
+                 "qk_ldm_decode", "qk_ldm_decode_check", "qk_ldm_decode_logits",
+                 "qk_ldm_decode_logits_check", "qk_camera_tables"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -261,7 +278,7 @@ class Context:
 
 
 def _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode, ldm_in,
-             ldm_out, rgb_out, acc_out):
+             ldm_out, rgb_out, acc_out, blend_out=None):
     V = len(in_cams)
     cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
     fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]), int(f.shape[1]))
@@ -277,38 +294,82 @@ def _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mo
             PREC[precision] if isinstance(precision, str) else int(precision),
             ATTN[attn_form] if isinstance(attn_form, str) else int(attn_form),
             MODE[mode] if isinstance(mode, str) else int(mode),
-            ctypes.byref(lin), ctypes.byref(lout), _ptr(rgb_out), _ptr(acc_out)]
+            ctypes.byref(lin), ctypes.byref(lout), _ptr(rgb_out), _ptr(acc_out),
+            _ptr(blend_out)]
     return args, keep
 
 
 def update_fuse(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
                 precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
-                acc_out=None, stream=None):
+                acc_out=None, blend_logit_out=None, stream=None):
     """qk_update_fuse.  ``ldm_in``/``ldm_out`` are (F, depth, alpha) tuples of
     device tensors (or prebuilt qk_ldm); ``feats`` a list of [Hf][Wf][C]
-    device tensors; ``weights`` a dict of float32 device tensors."""
+    device tensors; ``weights`` a dict of float32 device tensors;
+    ``blend_logit_out`` an optional [L][H][W][V] float32 tensor."""
     args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
-                          ldm_in, ldm_out, rgb_out, acc_out)
+                          ldm_in, ldm_out, rgb_out, acc_out, blend_logit_out)
     _check(ctx._lib.qk_update_fuse(ctx.handle, _stream_handle(stream), *args))
 
 
 def update_fuse_noalloc(ctx: Context, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out,
                         *, precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
-                        acc_out=None, stream=None):
+                        acc_out=None, blend_logit_out=None, stream=None):
     """qk_update_fuse_noalloc: qk_update_fuse with the device's fixed scratch
     instead of allocated workspaces (same arguments as ``update_fuse``)."""
     args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
-                          ldm_in, ldm_out, rgb_out, acc_out)
+                          ldm_in, ldm_out, rgb_out, acc_out, blend_logit_out)
     _check(ctx._lib.qk_update_fuse_noalloc(ctx.handle, _stream_handle(stream), *args))
 
 
 def update_fuse_check(in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
                       precision="fp32", attn_form="standard", mode="residual", rgb_out=None,
-                      acc_out=None) -> int:
+                      acc_out=None, blend_logit_out=None) -> int:
     """qk_update_fuse_check: the status qk_update_fuse would return (no device use)."""
     args, keep = _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mode,
-                          ldm_in, ldm_out, rgb_out, acc_out)
+                          ldm_in, ldm_out, rgb_out, acc_out, blend_logit_out)
     return int(load().qk_update_fuse_check(*args))
+
+
+class Request:
+    """One request of a batched Update & Fuse: the keyword arguments of
+    ``update_fuse`` for one level (precision and attention form are the
+    batch's)."""
+
+    def __init__(self, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
+                 mode="residual", rgb_out=None, acc_out=None):
+        V = len(in_cams)
+        self.cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+        self.fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]),
+                                                         int(f.shape[1])) for f in feats])
+        self.nov = make_camera(novel)
+        self.wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
+        self.lin = ldm_in if isinstance(ldm_in, qk_ldm) else make_ldm(*ldm_in)
+        self.lout = ldm_out if isinstance(ldm_out, qk_ldm) else make_ldm(*ldm_out)
+        if not self.lout.F:
+            self.lout.C, self.lout.dtype = self.lin.C, self.lin.dtype
+        self.desc = qk_request_desc(
+            V, ctypes.addressof(self.cams), ctypes.addressof(self.fm),
+            ctypes.addressof(self.nov), float(near), float(far), ctypes.addressof(self.wts),
+            MODE[mode] if isinstance(mode, str) else int(mode), ctypes.addressof(self.lin),
+            ctypes.addressof(self.lout), _ptr(rgb_out), _ptr(acc_out))
+
+
+def _batch_args(requests, precision, attn_form):
+    arr = (qk_request_desc * len(requests))(*[r.desc for r in requests])
+    return (len(requests), arr, PREC[precision] if isinstance(precision, str) else int(precision),
+            ATTN[attn_form] if isinstance(attn_form, str) else int(attn_form)), arr
+
+
+def batch_update_fuse(ctx: Context, requests, *, precision="bf16", attn_form="standard",
+                      stream=None):
+    """qk_batch_update_fuse: ``requests`` a list of ``Request``; one launch."""
+    args, keep = _batch_args(requests, precision, attn_form)
+    _check(ctx._lib.qk_batch_update_fuse(ctx.handle, _stream_handle(stream), *args))
+
+
+def batch_update_fuse_check(requests, *, precision="bf16", attn_form="standard") -> int:
+    args, keep = _batch_args(requests, precision, attn_form)
+    return int(load().qk_batch_update_fuse_check(*args))
 
 
 WEIGHT_NAMES = ("Wq", "Wk", "Wv", "Wo", "w_sigma", "w_depth", "W_color")
@@ -565,6 +626,25 @@ def ldm_decode(ctx: Context, F, depth, alpha, w_sigma, w_depth, W_color, near: f
 def ldm_decode_check(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out=None) -> int:
     args, keep = _dec_args(F, depth, alpha, w_sigma, w_depth, W_color, near, far, color_out)
     return int(load().qk_ldm_decode_check(*args))
+
+
+def _lg_args(F, w_sigma, w_depth, depth_logit, sigma_logit):
+    L, H, W, C = (int(d) for d in F.shape)
+    ldm = qk_ldm(_ptr(F), None, None, L, H, W, C, _dtype_code(F))
+    return (ctypes.byref(ldm), _ptr(w_sigma), _ptr(w_depth), _ptr(depth_logit),
+            _ptr(sigma_logit)), ldm
+
+
+def ldm_logits(ctx: Context, F, w_sigma, w_depth, depth_logit, sigma_logit, stream=None):
+    """qk_ldm_decode_logits: F [L][H][W][C] float32 / bfloat16 -> the unactivated
+    depth_logit, sigma_logit [L][H][W] float32 (the render's inputs)."""
+    args, keep = _lg_args(F, w_sigma, w_depth, depth_logit, sigma_logit)
+    _check(ctx._lib.qk_ldm_decode_logits(ctx.handle, _stream_handle(stream), *args))
+
+
+def ldm_logits_check(F, w_sigma, w_depth, depth_logit, sigma_logit) -> int:
+    args, keep = _lg_args(F, w_sigma, w_depth, depth_logit, sigma_logit)
+    return int(load().qk_ldm_decode_logits_check(*args))
 
 
 def camera_tables(in_cams, feat_hw: Sequence, novel, H: int, W: int) -> np.ndarray:

@@ -213,3 +213,107 @@ def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard"
                                w["w_depth"], w["W_color"], ch.near, ch.far, color_out=dc.color,
                                stream=stream)
                 lib.composite(ctx, dc.color, dc.alpha_out[i], dc.rgb, dc.acc, stream=stream)
+
+
+# ---------------------------------------------------------------------------
+# The whole frame: ray-encoded pyramid, learned initialisation, the chained
+# steps, and the final render of the last step's LDM (Eq. 1)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DevicePipeline:
+    chain: DeviceChain
+    feats_raw: List[List]              # per level, the V maps as the encoder gave them
+    feats: List[List]                  # per level, work copies that receive the encoding
+    Wr: List[object]                   # per level [32][C] float32
+    f0: object                         # [C] float32
+    blend_logit: object                # [L][H][W][V] float32, the last step's
+    depth_logit: object                # [L][H][W] float32, the final volume's
+    sigma_logit: object
+    images: List[object]               # V RGBA8 [H][W][4]
+    rgb: object                        # [H][W][3] float32
+    acc: object                        # [H][W]
+    depth: object                      # [H][W]
+
+
+def pipeline_to_device(pl, device="cuda") -> DevicePipeline:
+    import torch
+    ch = pl.chain
+    dc = chain_to_device(ch, device)
+    feats = [[torch.empty_like(f) for f in lvl] for lvl in dc.feats]
+    Wr = [_to_dev(np.ascontiguousarray(w, dtype=np.float32), device) for w in pl.Wr]
+    last = ch.steps[-1]
+    shp = (last.L, last.H, last.W)
+    f32 = dict(dtype=torch.float32, device=device)
+    H, W = pl.out_hw
+    return DevicePipeline(dc, dc.feats, feats, Wr,
+                          _to_dev(np.ascontiguousarray(pl.f0, dtype=np.float32), device),
+                          torch.empty(shp + (ch.V,), **f32), torch.empty(shp, **f32),
+                          torch.empty(shp, **f32), [_to_dev(im, device) for im in pl.images],
+                          torch.empty((H, W, 3), **f32), torch.empty((H, W), **f32),
+                          torch.empty((H, W), **f32))
+
+
+def run_pipeline(ctx: lib.Context, pl, dp: DevicePipeline, attn_form: str = "standard",
+                 stream=None):
+    """One frame.  (1) The pyramid, copied from the encoder's maps, receives
+    each level's ray-direction encoding (qk_ray_encoding, evaluated on the
+    low-resolution grid).  (2) The first step starts from the learned
+    initialisation (qk_ldm_init: f0 broadcast, flat layers at the anchors).
+    (3) Every step: its transition from the previous step's output
+    (qk_layer_collapse, qk_upsample2x) and the absolute decode of its input
+    (qk_ldm_decode) for steps after the first, Update & Fuse with the
+    absolute decode (qk_update_fuse; the last step also writes the
+    blend-weight logits of its attention), and its residual CNN block
+    (qk_residual_conv).  (4) The final volume's unactivated depth and density
+    (qk_ldm_logits) and the final render at the output grid (qk_render_ibr:
+    upsample, activate, blend the input images, composite)."""
+    import torch
+    ch, dc = pl.chain, dp.chain
+    prec = "bf16" if ch.dtype == "bf16" else "fp32"
+    ctxm = torch.cuda.stream(stream) if stream is not None else None
+    if ctxm is not None:
+        ctxm.__enter__()
+    try:
+        for k, lvl in enumerate(dp.feats):
+            for dst, src in zip(lvl, dp.feats_raw[k]):
+                dst.copy_(src)
+    finally:
+        if ctxm is not None:
+            ctxm.__exit__(None, None, None)
+    for k, lvl in enumerate(dp.feats):
+        lib.ray_encoding(ctx, ch.in_cams, ch.novel, ch.near, ch.far, dp.Wr[k], lvl,
+                         low_hw=pl.low_hw, stream=stream)
+    lib.ldm_init(ctx, dp.f0, ch.near, ch.far, (dc.F0, dc.depth[0], dc.alpha[0]), stream=stream)
+    F = dc.F0
+    n = len(ch.steps)
+    for i, st in enumerate(ch.steps):
+        w = dc.weights[i]
+        if i > 0:
+            prev = ch.steps[i - 1]
+            F = dc.F_conv[i - 1] if prev.conv else dc.F_out[i - 1]
+            if st.collapse:
+                W1, W2 = dc.collapse_w[i]
+                lib.layer_collapse(ctx, F, W1, W2, dc.tmp[i], stream=stream)
+                F = dc.tmp[i]
+            if st.upsample:
+                lib.upsample2x(ctx, F, dc.F_in[i], stream=stream)
+                F = dc.F_in[i]
+            lib.ldm_decode(ctx, F, dc.depth[i], dc.alpha[i], w["w_sigma"], w["w_depth"],
+                           w["W_color"], ch.near, ch.far, stream=stream)
+        lib.update_fuse(ctx, ch.in_cams, dp.feats[st.level], ch.novel, ch.near, ch.far,
+                        dc.qkw[i], (F, dc.depth[i], dc.alpha[i]),
+                        (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
+                        precision=prec, attn_form=attn_form, mode="paper",
+                        blend_logit_out=dp.blend_logit if i == n - 1 else None, stream=stream)
+        if st.conv:
+            K1, K2 = dc.conv_w[i]
+            lib.residual_conv(ctx, dc.F_out[i], K1, K2, dc.F_conv[i], stream=stream)
+    last = ch.steps[-1]
+    Ff = dc.F_conv[-1] if last.conv else dc.F_out[-1]
+    w = dc.weights[-1]
+    lib.ldm_logits(ctx, Ff, w["w_sigma"], w["w_depth"], dp.depth_logit, dp.sigma_logit,
+                   stream=stream)
+    lib.render_ibr(ctx, ch.in_cams, dp.images, ch.novel, ch.near, ch.far,
+                   (dp.depth_logit, dp.sigma_logit, dp.blend_logit), dp.rgb, acc_out=dp.acc,
+                   depth_out=dp.depth, stream=stream)

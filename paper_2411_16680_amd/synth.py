@@ -208,6 +208,24 @@ def _sorted_depths(rng, L, H, W, lo, hi, dist: str, mode: str) -> np.ndarray:
     return d.astype(np.float32)
 
 
+def _smooth_image(rng, H: int, W: int, block: int) -> np.ndarray:
+    """An RGBA8 image whose colours are a bilinear field over uniform
+    random bytes on a ``block``-pixel grid (alpha 255): piecewise smooth, as
+    photographs are, rather than i.i.d. per pixel."""
+    gh, gw = H // block + 2, W // block + 2
+    g = rng.uniform(0.0, 255.0, size=(gh, gw, 3))
+    ys = (np.arange(H) + 0.5) / block
+    xs = (np.arange(W) + 0.5) / block
+    y0 = np.floor(ys).astype(int); x0 = np.floor(xs).astype(int)
+    fy = (ys - y0)[:, None, None]; fx = (xs - x0)[None, :, None]
+    v = (g[y0][:, x0] * (1 - fy) * (1 - fx) + g[y0 + 1][:, x0] * fy * (1 - fx)
+         + g[y0][:, x0 + 1] * (1 - fy) * fx + g[y0 + 1][:, x0 + 1] * fy * fx)
+    im = np.empty((H, W, 4), dtype=np.uint8)
+    im[..., :3] = np.clip(np.rint(v), 0, 255).astype(np.uint8)
+    im[..., 3] = 255
+    return im
+
+
 def _alpha(rng, shape, dist: str) -> np.ndarray:
     if dist == "uniform":
         a = rng.uniform(0.0, 1.0, size=shape)
@@ -586,6 +604,46 @@ def make_chain(*, V: int = 8, steps=QUARK_STEPS, feat_hw=QUARK_FEAT_HW, C: int =
         kw.append((_normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C)),
                    _normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C))) if st.conv else None)
     return ChainScene(in_cams, novel, 0.5, 20.0, C, list(steps), feats, F0, weights, cw, kw, dtype)
+
+
+@dataclass
+class PipelineScene:
+    """The whole frame: a chain (its F0 unused: the first step starts from the
+    learned initialisation), the initial feature f0, one ray-encoding
+    projection per pyramid level on a low-resolution grid, and the full
+    resolution RGBA8 input images the final render blends."""
+    chain: ChainScene
+    f0: np.ndarray                 # [C] float32, the learned initial feature
+    Wr: List[np.ndarray]           # per pyramid level [32][C] float32
+    low_hw: tuple                  # grid on which the ray encoding is evaluated
+    images: List[np.ndarray]       # V arrays [H][W][4] uint8 (RGBA8, alpha 255)
+    out_hw: tuple                  # output (H, W) of the final render
+
+
+def make_pipeline(*, V: int = 8, steps=QUARK_STEPS, feat_hw=QUARK_FEAT_HW, C: int = 32,
+                  input_hw=(1080, 1920), low_hw: Optional[tuple] = None, dtype: str = "bf16",
+                  seed: int = 1011, image_block: int = 16) -> PipelineScene:
+    """``make_chain``'s draws (same seed), then from a second generator
+    (seed + 7919): f0 N(0, 1), per level Wr N(0, 1/32), the V images at the
+    input / output grid: piecewise smooth colour fields (bilinear over
+    uniform bytes on an ``image_block``-pixel grid; 0: uniform bytes per
+    pixel), alpha 255.  The ray encoding is evaluated on the coarsest
+    pyramid grid unless ``low_hw`` is given."""
+    ch = make_chain(V=V, steps=steps, feat_hw=feat_hw, C=C, input_hw=input_hw, dtype=dtype,
+                    seed=seed)
+    rng = np.random.default_rng(seed + 7919)
+    f0 = _normal(rng, (C,))
+    Wr = [_normal(rng, (32, C), 1.0 / math.sqrt(32.0)) for _ in feat_hw]
+    H, W = input_hw
+    images = []
+    for _ in range(V):
+        if image_block > 0:
+            images.append(_smooth_image(rng, H, W, image_block))
+        else:
+            im = rng.integers(0, 256, size=(H, W, 4), dtype=np.uint8)
+            im[..., 3] = 255
+            images.append(im)
+    return PipelineScene(ch, f0, Wr, tuple(low_hw or feat_hw[0]), images, (H, W))
 
 
 def to_bf16(scene: Scene) -> Scene:

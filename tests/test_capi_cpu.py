@@ -181,6 +181,32 @@ def test_heads():
     assert "folded" in lib.load().qk_last_error().decode()
 
 
+def test_blend_logit_output_checks():
+    sc, feats, wts, ldm = _args(C=32, L=2, H=6, W=10, V=3)
+    bl = _FakeT((2, 6, 10, 3), 0x800000)
+    assert _check(sc, feats, wts, ldm, blend_logit_out=bl) == lib.QK_OK
+    assert _check(sc, feats, wts, ldm, blend_logit_out=_FakeT((2, 6, 10, 3), 0x800002)) == \
+        lib.QK_EINVAL
+    sc, f, w, l = _args(C=32, heads=4, head_dim=8, L=2, H=6, W=10, V=3)
+    assert _check(sc, f, w, l, blend_logit_out=bl) == lib.QK_EUNSUPPORTED
+    assert "one attention head" in lib.load().qk_last_error().decode()
+
+
+def test_ldm_decode_logits_checks():
+    import torch
+    F = _FakeT((4, 5, 6, 32), 0x300000, torch.bfloat16)
+    ws, wd = _FakeT((32,), 0x500000), _FakeT((32,), 0x510000)
+    dl, sl = _FakeT((4, 5, 6), 0x400000), _FakeT((4, 5, 6), 0x410000)
+    assert lib.ldm_logits_check(F, ws, wd, dl, sl) == lib.QK_OK
+    assert lib.ldm_logits_check(F, ws, wd, None, sl) == lib.QK_EINVAL
+    assert lib.ldm_logits_check(F, ws, wd, dl, _FakeT((4, 5, 6), 0x400000 + 64)) == lib.QK_EINVAL
+    assert "overlaps" in lib.load().qk_last_error().decode()
+    assert lib.ldm_logits_check(_FakeT((4, 5, 6, 24), 0x300000), ws, wd, dl, sl) == \
+        lib.QK_EUNSUPPORTED
+    assert lib.ldm_logits_check(_FakeT((4, 5, 6, 32), 0x300000, torch.float16), ws, wd, dl,
+                                sl) == lib.QK_EDTYPE
+
+
 def test_null_context_rejected_before_device_use():
     sc, feats, wts, ldm = _args()
     args, keep = lib._uf_args(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, "fp32",
@@ -479,3 +505,28 @@ def test_composite_backward_null_context_rejected():
     st = lib.load().qk_composite_backward(None, None, *lib._cb_args(t3, t1, torch.zeros(3, 4, 3),
                                                                     None, None, t1))
     assert st == lib.QK_EINVAL
+
+
+def test_batch_update_fuse_checks():
+    reqs = []
+    for i, (H, W, V) in enumerate(((6, 10, 3), (4, 21, 2), (5, 7, 4))):
+        sc, f, w, l = _args(C=32, L=2, H=H, W=W, V=V, dtype="bf16")
+        reqs.append(lib.Request(sc.in_cams, f, sc.novel, sc.near, sc.far, w, l, l))
+    assert lib.batch_update_fuse_check(reqs) == lib.QK_OK
+    assert lib.batch_update_fuse_check(reqs, attn_form="folded") == lib.QK_OK
+    assert lib.batch_update_fuse_check(reqs, precision="fp32") == lib.QK_EUNSUPPORTED
+    assert lib.batch_update_fuse_check([]) == lib.QK_ESHAPE
+    assert lib.batch_update_fuse_check(reqs * 22) == lib.QK_ESHAPE          # 66 > 64
+    # a request of another width
+    sc, f, w, l = _args(C=16, L=2, H=6, W=10, V=3, dtype="bf16")
+    assert lib.batch_update_fuse_check(reqs + [lib.Request(sc.in_cams, f, sc.novel, sc.near,
+                                                           sc.far, w, l, l)]) == \
+        lib.QK_EUNSUPPORTED
+    # a bad request is named by its index
+    sc, f, w, l = _args(C=32, L=2, H=6, W=10, V=3, dtype="bf16")
+    bad = lib.Request(sc.in_cams, f, sc.novel, 5.0, 5.0, w, l, l)
+    assert lib.batch_update_fuse_check(reqs[:2] + [bad]) == lib.QK_EINVAL
+    assert "request 2" in lib.load().qk_last_error().decode()
+    assert lib.load().qk_batch_update_fuse(None, None, *lib._batch_args(reqs, "bf16",
+                                                                        "standard")[0]) == \
+        lib.QK_EINVAL

@@ -61,9 +61,13 @@ def _check_step(label, got_F, got_d, got_a, ref, L, near, far, tol):
     assert e_d <= tol["disp"], (label, "disp")
 
 
-def check_chain_stepwise(ch, dc, attn, form, rows_of, tag):
+def check_chain_stepwise(ch, dc, attn, form, rows_of, tag, first_input=None, composite=True):
     """Every kernel of a chain the GPU has run, each from the GPU's own input
-    to it, on the rows ``rows_of(step)`` of each step."""
+    to it, on the rows ``rows_of(step)`` of each step.  ``first_input``: the
+    first step's input volume when it is not decoded (the learned
+    initialisation, checked by the caller); ``composite``: whether the last
+    step's output LDM was composited (else its update's depth' and alpha'
+    are checked like any step's)."""
     tol = TOL[form]
     band = 1.0 / ch.near - 1.0 / ch.far
     af = 1 if attn == "folded" else 0
@@ -71,7 +75,7 @@ def check_chain_stepwise(ch, dc, attn, form, rows_of, tag):
         rows = rows_of(st)
         label = f"{tag} {attn} step {i} ({st.L}x{st.H}x{st.W}, {st.heads} heads)"
         if i == 0:
-            F_in = _np(dc.F0)
+            F_in = _np(dc.F0) if first_input is None else first_input
         else:
             # the transition, from the GPU's previous output
             src = _np(dc.F_conv[i - 1] if ch.steps[i - 1].conv else dc.F_out[i - 1])
@@ -92,19 +96,20 @@ def check_chain_stepwise(ch, dc, attn, form, rows_of, tag):
                 assert r <= 1.0, (label, "transition")
         # the decode of the step's input
         w = ch.weights[i]
-        dr, ar, _ = oracle.decode_volume(F_in[:, rows], w["w_sigma"], w["w_depth"], w["W_color"],
-                                         ch.near, ch.far)
         d_in, a_in = _np(dc.depth[i]), _np(dc.alpha[i])
-        e_dd = float(np.max(np.abs(1 / d_in[:, rows] - 1 / dr))) / band
-        e_da = float(np.max(np.abs(a_in[:, rows] - ar)))
-        _say(label, f"decode disp/band {e_dd:.3g} alpha {e_da:.3g}")
-        assert e_dd <= 1e-5 and e_da <= 1e-5, (label, "decode")
+        if i > 0 or first_input is None:
+            dr, ar, _ = oracle.decode_volume(F_in[:, rows], w["w_sigma"], w["w_depth"],
+                                             w["W_color"], ch.near, ch.far)
+            e_dd = float(np.max(np.abs(1 / d_in[:, rows] - 1 / dr))) / band
+            e_da = float(np.max(np.abs(a_in[:, rows] - ar)))
+            _say(label, f"decode disp/band {e_dd:.3g} alpha {e_da:.3g}")
+            assert e_dd <= 1e-5 and e_da <= 1e-5, (label, "decode")
         # the update, from the GPU's decoded input (the last step's depth'
         # and alpha' are the decode of its CNN block's output, checked below)
         last = i == len(ch.steps) - 1
         ref = oracle.update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F_in,
                                  depth=d_in, alpha=a_in, rows=rows, mode=1, attn_form=af)
-        skip = last and st.conv
+        skip = last and st.conv and composite
         _check_step(label, _np(dc.F_out[i])[:, rows],
                     None if skip else _np(dc.depth_out[i])[:, rows],
                     None if skip else _np(dc.alpha_out[i])[:, rows], ref, st.L, ch.near, ch.far,
@@ -124,7 +129,7 @@ def check_chain_stepwise(ch, dc, attn, form, rows_of, tag):
             rms = float(np.sqrt(np.mean(Fo ** 2)))
             _say(label, f"residual block error / bound {worst:.3g} (input rms {rms:.3g})")
             assert worst <= 1.0, (label, "conv")
-        if last:
+        if last and composite:
             if st.conv:
                 # the output LDM: decode of the block's output, composited
                 dr, ar, cr = oracle.decode_volume(_np(dc.F_conv[i])[:, rows], w["w_sigma"],
@@ -164,9 +169,9 @@ SMALL = {
 # positions moved by the earlier steps' rounding-level depth differences,
 # and at this grid's focal length a fraction of a pixel on an i.i.d. map is
 # an O(1) change of the sample.  Measured max-abs 0.025-0.030 over runs; the
-# bound sits just above it, with the PSNR floor just below what was measured.
+# bound sits just above it.  The PSNR target holds (measured 51 dB).
 BF16_CHAIN_RGB = 3.5e-2
-BF16_CHAIN_PSNR = 38.0
+BF16_CHAIN_PSNR = 45.0
 
 
 @pytest.mark.parametrize("attn", ["folded", "standard"])

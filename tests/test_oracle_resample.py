@@ -62,3 +62,39 @@ def test_decode_volume_is_the_per_pixel_decode_in_band():
         assert np.all(1 / d[li] >= lo - 1e-12) and np.all(1 / d[li] <= lo + band / L + 1e-12)
     a1, d1, c1 = oracle.decode(F[1, 1, 2], ws, wd, Wc, 0.5, 1.0, 1, L, near, far, mode=1)
     assert (a1, d1) == (a[1, 1, 2], d[1, 1, 2]) and np.array_equal(c1, c[1, 1, 2])
+
+
+def test_volume_logits_activate_to_the_decode():
+    # the final LDM's unactivated attributes: sigmoid of the density logit is
+    # the decoded alpha, and the paper's depth activation of the depth logit
+    # is the decoded depth (decode_volume, pinned by the anchor bands)
+    r = np.random.default_rng(8)
+    L, H, W, C = 3, 2, 4, 8
+    F = r.standard_normal((L, H, W, C))
+    ws, wd, wc = r.standard_normal(C), r.standard_normal(C), r.standard_normal((C, 3))
+    near, far = 0.5, 20.0
+    dl, sl = oracle.volume_logits(F, ws, wd)
+    d, a, _ = oracle.decode_volume(F, ws, wd, wc, near, far)
+    np.testing.assert_allclose(1.0 / (1.0 + np.exp(-sl)), a, rtol=1e-14)
+    band = 1.0 / near - 1.0 / far
+    li = np.arange(L)[:, None, None]
+    delta = (L - li - 0.5) / L
+    np.testing.assert_allclose(1.0 / ((delta + 0.5 / L * np.tanh(dl)) * band + 1.0 / far), d,
+                               rtol=1e-13)
+
+
+def test_pipeline_with_zero_ray_projection_starts_from_the_init():
+    # with every ray-encoding projection zero the encoded pyramid is the raw
+    # one, and the first step's input state is the learned initialisation
+    from paper_2411_16680_amd import synth
+    pl = synth.make_pipeline(V=2, steps=(synth.ChainStep(2, 3, 5, 0, 1, False, False, False),),
+                             feat_hw=((3, 5),), input_hw=(6, 10), dtype="f32", seed=4)
+    pl.Wr = [np.zeros_like(w) for w in pl.Wr]
+    outs, r, feats = oracle.run_pipeline(pl)
+    for m in range(2):
+        np.testing.assert_array_equal(feats[0][m], pl.chain.feats[0][m].astype(np.float64))
+    F, d, a = oracle.ldm_init(2, 3, 5, pl.f0, pl.chain.near, pl.chain.far)
+    np.testing.assert_array_equal(outs[0]["F_in"], F)
+    np.testing.assert_array_equal(outs[0]["depth_in"], d)
+    assert outs[0]["blend_logit"].shape == (2, 3, 5, 2)
+    assert r["rgb"].shape == (6, 10, 3)
