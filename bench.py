@@ -673,30 +673,57 @@ def time_training_step(ctx, steps: int = 50, warmup: int = 5):
 
 
 def run_serving(n_requests: int = 2000, rate: float = 60.0, n_scenes: int = 16,
-                n_streams: int = 4):
+                n_streams: int = 4, sweep=(120.0, 240.0, 480.0, 960.0), sweep_requests: int = 400):
     """The serving workload: Poisson arrivals, 16 resident scenes (V in
-    {4, 6, 8}, 1080p feature pyramids), outputs 640x360 / 1280x720 /
-    1920x1080, one learned init + bf16 Update & Fuse per level + composite
-    per request, 200 GB admission budget.  Latency = completion - arrival."""
+    {4, 6, 8}, 1080p pyramids and input images), outputs 640x360 /
+    1280x720 / 1920x1080, each request the whole frame (ray encoding, init,
+    five chained steps, final render at its size; requests admitted at one
+    poll share one launch per Update & Fuse step), bfloat16, one-to-many
+    attention, 200 GB admission budget.  Latency = completion - arrival.
+    Then a sweep of higher rates (``sweep_requests`` each) for the
+    saturation point: the highest rate whose p99 stays under 33 ms."""
     import torch
     from paper_2411_16680_amd import serve, synth
     scenes, model, reqs = synth.make_serving(n_scenes=n_scenes, n_requests=n_requests, rate=rate)
-    pyr = {s.scene_id: synth.device_pyramid(s) for s in scenes}
+    res = {s.scene_id: (synth.device_pyramid(s), synth.device_images(s)) for s in scenes}
     torch.cuda.synchronize()
-    ex = serve.GpuExecutor({s.scene_id: s for s in scenes}, pyr, model, n_streams=n_streams)
-    # warm-up: each output size once on every stream (allocator, code objects)
+    ex = serve.GpuExecutor({s.scene_id: s for s in scenes}, res, model, n_streams=n_streams)
+    # warm-up: each output size on every stream, alone and in batches
     warm = []
-    for i, (W, H) in enumerate(synth.SERVE_OUTPUTS * n_streams):
+    for i, (W, H) in enumerate(synth.SERVE_OUTPUTS * (2 * n_streams)):
         r = reqs[i % len(reqs)]
-        warm.append(synth.ServeRequest(-1 - i, r.scene_id, W, H, r.novel, 0.0))
+        K = r.novel.K * np.array([[W / r.width], [H / r.height], [1.0]])
+        warm.append(synth.ServeRequest(-1 - i, r.scene_id, W, H,
+                                       synth.Camera(K, r.novel.E.copy(), W, H),
+                                       0.0 if i % 2 else 0.002 * i))
     serve.Server(ex, 200 * 10 ** 9).run(warm)
     torch.cuda.synchronize()
     srv = serve.Server(ex, 200 * 10 ** 9)
     jobs = srv.run(reqs, deadline=1.0 / 30.0)
     st = serve.summarize(jobs)
+    resident = sum(t.numel() * t.element_size() for p, ims in res.values()
+                   for t in [x for lv in p for x in lv] + list(ims))
     st.update({"rate_rps": rate, "scenes": n_scenes, "streams": n_streams,
-               "resident_scene_bytes": int(sum(sum(t.numel() * t.element_size() for t in lv)
-                                               for p in pyr.values() for lv in p))})
+               "resident_scene_bytes": int(resident),
+               "work": "whole frame per request (ray encoding, init, 5 chained steps, final "
+                       "render), bf16, one-to-many attention, batched Update & Fuse per poll"})
+    rows = []
+    best = rate if st.get("p99_ms", math.inf) < 33.0 else None
+    for r in sweep:
+        # the same scenes (same seed); the arrivals at rate r
+        _, _, rq = synth.make_serving(n_scenes=n_scenes, n_requests=sweep_requests, rate=r)
+        js = serve.Server(ex, 200 * 10 ** 9).run(rq, deadline=1.0 / 30.0)
+        sm = serve.summarize(js)
+        rows.append({"rate_rps": r, "p50_ms": sm.get("p50_ms"), "p99_ms": sm.get("p99_ms"),
+                     "throughput_rps": sm.get("throughput_rps"),
+                     "frac_under_slo": sm.get("frac_under_slo"), "requests": sweep_requests})
+        log(f"serving sweep {r:.0f}/s: p50 {sm.get('p50_ms', math.nan):.2f} ms, "
+            f"p99 {sm.get('p99_ms', math.nan):.2f} ms, {sm.get('throughput_rps', math.nan):.0f} "
+            f"req/s done")
+        if sm.get("p99_ms", math.inf) < 33.0:
+            best = r
+    st["saturation_sweep"] = rows
+    st["max_rate_p99_under_33ms"] = best
     return st
 
 

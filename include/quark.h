@@ -244,12 +244,14 @@ typedef struct {
     const qk_ldm *ldm_out;
     float *rgb_out;                 /* device [H][W][3] or NULL */
     float *acc_alpha_out;           /* device [H][W] or NULL */
+    float *blend_logit_out;         /* device [L][H][W][V] or NULL (one head) */
 } qk_request_desc;
 
 /* Update & Fuse of n_req requests (1..64) in one kernel launch (Sec. 3.2.2
  * step, as qk_update_fuse, per request): requests may differ in LDM grid
  * (L, H, W), view count, cameras, feature maps, frustum, weights, update
- * mode and whether they composite; they share the feature width C, the
+ * mode and whether they composite or write blend-weight logits (as
+ * qk_update_fuse's blend_logit_out); they share the feature width C, the
  * heads and head width, the precision (QK_PREC_BF16 only) and the attention
  * form.  Each request's outputs equal those of qk_update_fuse on its own,
  * bit for bit (the same per-tile kernel body).  Requests must not share

@@ -834,7 +834,8 @@ qk_status qk_batch_update_fuse_check(int32_t n_req, const qk_request_desc *reqs,
         const qk_request_desc &q = reqs[r];
         qk_status st = check_update_fuse(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_,
                                          q.weights, precision, attn_form, q.update_mode,
-                                         q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out, nullptr);
+                                         q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out,
+                                         q.blend_logit_out);
         if (st != QK_OK) {
             const std::string msg = g_err;
             return fail(st, "request %d: %s", r, msg.c_str());
@@ -847,7 +848,7 @@ qk_status qk_batch_update_fuse_check(int32_t n_req, const qk_request_desc *reqs,
         qk::UFParams p;
         st = fill_uf_params(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_, q.weights,
                             q.update_mode, q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out,
-                            nullptr, p);
+                            q.blend_logit_out, p);
         if (st != QK_OK) return st;
         tiles += p.n_tiles;
     }
@@ -870,7 +871,7 @@ qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
         const qk_request_desc &q = reqs[r];
         st = fill_uf_params(q.V, q.in_cams, q.feats, q.novel, q.near_, q.far_, q.weights,
                             q.update_mode, q.ldm_in, q.ldm_out, q.rgb_out, q.acc_alpha_out,
-                            nullptr, ps[r]);
+                            q.blend_logit_out, ps[r]);
         if (st != QK_OK) return st;
         b.tile_start[r] = (int32_t)tiles;
         tiles += ps[r].n_tiles;

@@ -44,6 +44,11 @@
 
 #include "uf_params.h"
 
+// Multiply-adds are fused only within one expression (never across
+// statements), so every variant of the kernel body -- one level, one level
+// with blend logits, a batch -- rounds alike and gives bit-identical results.
+#pragma clang fp contract(on)
+
 namespace qk {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -874,14 +879,18 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                         lg[t] = result_pixel_sum<C>(part) * (scale * kscale);
                     }
                 }
-                if constexpr (VAR == kBlend) {
+                if constexpr (VAR == kBlend || (VAR == kBatch && HD == C)) {
                     // blend-weight logits (one head): written by the lane that
-                    // holds channel 0 of the pixel in the result layout
+                    // holds channel 0 of the pixel in the result layout (in a
+                    // batch, for the requests that ask for them)
+                    if (VAR == kBlend || p.blend_logit != nullptr) {
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) {
-                        const int t = (G == 1) ? s * TPH : s;
-                        const int xe = x0w + 16 * sd(t) + n;
-                        if (ed(t) == 0 && xe < p.W) p.blend_logit[(rowbase + xe) * p.V + m] = lg[s];
+                        for (int s = 0; s < NS; ++s) {
+                            const int t = (G == 1) ? s * TPH : s;
+                            const int xe = x0w + 16 * sd(t) + n;
+                            if (ed(t) == 0 && xe < p.W)
+                                p.blend_logit[(rowbase + xe) * p.V + m] = lg[s];
+                        }
                     }
                 }
                 // online softmax with a lazily moved reference: weights are
@@ -996,9 +1005,10 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
 #pragma unroll
                         for (int i = 0; i < 8; ++i) part = fmaf(qa[hq][kc][i], sv[kc][i], part);
                     const float a = operand_pixel_sum<C>(part);
-                    if constexpr (VAR == kBlend) {
+                    if constexpr (VAR == kBlend || (VAR == kBatch && HQ == 1)) {
                         // blend-weight logit: the lane holding channel 0
-                        if (ch0 == 0 && a_ok) p.blend_logit[(rowbase + xa) * p.V + m] = a;
+                        if ((VAR == kBlend || p.blend_logit != nullptr) && ch0 == 0 && a_ok)
+                            p.blend_logit[(rowbase + xa) * p.V + m] = a;
                     }
                     float diff = a - Mx[hq];
                     if (diff > 8.0f) {             // lazily moved reference (see above)

@@ -96,7 +96,8 @@ class qk_request_desc(ctypes.Structure):
                 ("novel", ctypes.c_void_p), ("near_", ctypes.c_float), ("far_", ctypes.c_float),
                 ("weights", ctypes.c_void_p), ("update_mode", ctypes.c_int),
                 ("ldm_in", ctypes.c_void_p), ("ldm_out", ctypes.c_void_p),
-                ("rgb_out", ctypes.c_void_p), ("acc_alpha_out", ctypes.c_void_p)]
+                ("rgb_out", ctypes.c_void_p), ("acc_alpha_out", ctypes.c_void_p),
+                ("blend_logit_out", ctypes.c_void_p)]
 
 
 class qk_weight_grads(ctypes.Structure):
@@ -336,7 +337,7 @@ class Request:
     batch's)."""
 
     def __init__(self, in_cams, feats, novel, near, far, weights, ldm_in, ldm_out, *,
-                 mode="residual", rgb_out=None, acc_out=None):
+                 mode="residual", rgb_out=None, acc_out=None, blend_logit_out=None):
         V = len(in_cams)
         self.cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
         self.fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]),
@@ -351,7 +352,7 @@ class Request:
             V, ctypes.addressof(self.cams), ctypes.addressof(self.fm),
             ctypes.addressof(self.nov), float(near), float(far), ctypes.addressof(self.wts),
             MODE[mode] if isinstance(mode, str) else int(mode), ctypes.addressof(self.lin),
-            ctypes.addressof(self.lout), _ptr(rgb_out), _ptr(acc_out))
+            ctypes.addressof(self.lout), _ptr(rgb_out), _ptr(acc_out), _ptr(blend_logit_out))
 
 
 def _batch_args(requests, precision, attn_form):

@@ -129,46 +129,30 @@ class DeviceChain:
     acc: Optional[object] = None
 
 
-def chain_to_device(ch, device="cuda") -> DeviceChain:
-    import torch
-    tdt = torch.bfloat16 if ch.dtype == "bf16" else torch.float32
+def chain_tensors(ch, device="cuda"):
+    """A chain scene's data on the device: the pyramid [level][view], the
+    per-step weight dicts, and the collapse and conv weight pairs."""
     feats = [[_to_dev(f, device) for f in lvl] for lvl in ch.feats]
     ws = [{k: _to_dev(np.ascontiguousarray(v, dtype=np.float32), device) for k, v in w.items()}
           for w in ch.weights]
-    qkw = [lib.make_weights(w, heads=st.heads) for w, st in zip(ws, ch.steps)]
     cw = [None if c is None else tuple(_to_dev(np.ascontiguousarray(a, dtype=np.float32), device)
                                        for a in c) for c in ch.collapse_w]
     kw = [None if c is None else tuple(_to_dev(np.ascontiguousarray(a, dtype=np.float32), device)
                                        for a in c) for c in ch.conv_w]
-    C = ch.C
-    F_in, tmp, depth, alpha, F_out, d_out, a_out, F_conv = [], [], [], [], [], [], [], []
-    prev = None
-    for i, st in enumerate(ch.steps):
-        shp = (st.L, st.H, st.W)
-        if i > 0:                      # the transition must produce this step's grid
-            want = (prev[0] // 2 if st.collapse else prev[0],
-                    2 * prev[1] if st.upsample else prev[1], 2 * prev[2] if st.upsample else prev[2])
-            if shp != want or (st.collapse and prev[0] % 2):
-                raise ValueError(f"step {i}: grid {shp} does not follow {prev} by its transition")
-        if i > 0 and st.collapse:
-            tmp.append(torch.empty((st.L,) + prev[1:] + (C,), dtype=tdt, device=device))
-        else:
-            tmp.append(None)
-        F_in.append(torch.empty(shp + (C,), dtype=tdt, device=device)
-                    if i > 0 and st.upsample else None)
-        depth.append(torch.empty(shp, dtype=torch.float32, device=device))
-        alpha.append(torch.empty(shp, dtype=torch.float32, device=device))
-        F_out.append(torch.empty(shp + (C,), dtype=tdt, device=device))
-        F_conv.append(torch.empty(shp + (C,), dtype=tdt, device=device) if st.conv else None)
-        d_out.append(torch.empty(shp, dtype=torch.float32, device=device))
-        a_out.append(torch.empty(shp, dtype=torch.float32, device=device))
-        prev = shp
+    return feats, ws, cw, kw
+
+
+def chain_to_device(ch, device="cuda") -> DeviceChain:
+    import torch
+    feats, ws, cw, kw = chain_tensors(ch, device)
+    qkw = [lib.make_weights(w, heads=st.heads) for w, st in zip(ws, ch.steps)]
     last = ch.steps[-1]
-    rgb = torch.empty((last.H, last.W, 3), dtype=torch.float32, device=device)
+    chain_kw, _ = frame_buffers(ch.steps, ch.C, ch.V, (last.H, last.W), ch.dtype, device)
+    chain_kw["F0"].copy_(_to_dev(ch.F0, device))
     color = (torch.empty((last.L, last.H, last.W, 3), dtype=torch.float32, device=device)
              if last.conv else None)
-    return DeviceChain(feats, _to_dev(ch.F0, device), ws, qkw, cw, kw, F_in, F_conv, tmp, depth,
-                       alpha, F_out, d_out, a_out, rgb, color)
+    return DeviceChain(feats=feats, weights=ws, qkw=qkw, collapse_w=cw, conv_w=kw, color=color,
+                       **chain_kw)
 
 
 def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard", stream=None):
@@ -236,84 +220,168 @@ class DevicePipeline:
     depth: object                      # [H][W]
 
 
-def pipeline_to_device(pl, device="cuda") -> DevicePipeline:
+def frame_buffers(steps, C: int, V: int, out_hw, dtype: str, device="cuda"):
+    """One frame's own device buffers for the chained steps ``steps``: per
+    step the transition outputs, the decoded input state, the update's
+    output and the residual block's output (as in ``chain_to_device``), the
+    first step's initial volume, the last step's blend-weight logits, the
+    final volume's logits and the render's outputs on ``out_hw``.  Returns
+    the keyword arguments of ``DeviceChain`` (without data or weights) and of
+    ``DevicePipeline``'s per-frame fields."""
     import torch
-    ch = pl.chain
-    dc = chain_to_device(ch, device)
-    feats = [[torch.empty_like(f) for f in lvl] for lvl in dc.feats]
-    Wr = [_to_dev(np.ascontiguousarray(w, dtype=np.float32), device) for w in pl.Wr]
-    last = ch.steps[-1]
-    shp = (last.L, last.H, last.W)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
     f32 = dict(dtype=torch.float32, device=device)
-    H, W = pl.out_hw
-    return DevicePipeline(dc, dc.feats, feats, Wr,
-                          _to_dev(np.ascontiguousarray(pl.f0, dtype=np.float32), device),
-                          torch.empty(shp + (ch.V,), **f32), torch.empty(shp, **f32),
-                          torch.empty(shp, **f32), [_to_dev(im, device) for im in pl.images],
-                          torch.empty((H, W, 3), **f32), torch.empty((H, W), **f32),
-                          torch.empty((H, W), **f32))
+    F_in, tmp, depth, alpha, F_out, d_out, a_out, F_conv = [], [], [], [], [], [], [], []
+    prev = None
+    for i, st in enumerate(steps):
+        shp = (st.L, st.H, st.W)
+        if i > 0:                      # the transition must produce this step's grid
+            want = (prev[0] // 2 if st.collapse else prev[0],
+                    2 * prev[1] if st.upsample else prev[1], 2 * prev[2] if st.upsample else prev[2])
+            if shp != want or (st.collapse and prev[0] % 2):
+                raise ValueError(f"step {i}: grid {shp} does not follow {prev} by its transition")
+        tmp.append(torch.empty((st.L,) + prev[1:] + (C,), dtype=tdt, device=device)
+                   if i > 0 and st.collapse else None)
+        F_in.append(torch.empty(shp + (C,), dtype=tdt, device=device)
+                    if i > 0 and st.upsample else None)
+        depth.append(torch.empty(shp, **f32))
+        alpha.append(torch.empty(shp, **f32))
+        F_out.append(torch.empty(shp + (C,), dtype=tdt, device=device))
+        F_conv.append(torch.empty(shp + (C,), dtype=tdt, device=device) if st.conv else None)
+        d_out.append(torch.empty(shp, **f32))
+        a_out.append(torch.empty(shp, **f32))
+        prev = shp
+    s0, last = steps[0], steps[-1]
+    lshp = (last.L, last.H, last.W)
+    H, W = out_hw
+    chain = dict(F0=torch.empty((s0.L, s0.H, s0.W, C), dtype=tdt, device=device), F_in=F_in,
+                 F_conv=F_conv, tmp=tmp, depth=depth, alpha=alpha, F_out=F_out, depth_out=d_out,
+                 alpha_out=a_out, rgb=torch.empty((H, W, 3), **f32))
+    frame = dict(blend_logit=torch.empty(lshp + (V,), **f32), depth_logit=torch.empty(lshp, **f32),
+                 sigma_logit=torch.empty(lshp, **f32), rgb=chain["rgb"],
+                 acc=torch.empty((H, W), **f32), depth=torch.empty((H, W), **f32))
+    return chain, frame
+
+
+def make_device_pipeline(steps, C: int, feats_raw, weights, collapse_w, conv_w, Wr, f0, images,
+                         out_hw, dtype: str, device="cuda") -> DevicePipeline:
+    """A frame's ``DevicePipeline``: its own buffers (``frame_buffers``) and
+    work copies of the pyramid, around shared device tensors -- the scene's
+    pyramid ``feats_raw`` [level][view] and ``images``, and the network's
+    weights (per step dicts, collapse and conv pairs, per level Wr, f0)."""
+    import torch
+    V = len(feats_raw[0])
+    chain_kw, frame_kw = frame_buffers(steps, C, V, out_hw, dtype, device)
+    qkw = [lib.make_weights(w, heads=st.heads) for w, st in zip(weights, steps)]
+    dc = DeviceChain(feats=feats_raw, weights=weights, qkw=qkw, collapse_w=collapse_w,
+                     conv_w=conv_w, **chain_kw)
+    feats = [[torch.empty_like(f) for f in lvl] for lvl in feats_raw]
+    return DevicePipeline(dc, feats_raw, feats, Wr, f0, images=images, **frame_kw)
+
+
+def pipeline_to_device(pl, device="cuda") -> DevicePipeline:
+    ch = pl.chain
+    feats, ws, cw, kw = chain_tensors(ch, device)
+    Wr = [_to_dev(np.ascontiguousarray(w, dtype=np.float32), device) for w in pl.Wr]
+    f0 = _to_dev(np.ascontiguousarray(pl.f0, dtype=np.float32), device)
+    images = [_to_dev(im, device) for im in pl.images]
+    return make_device_pipeline(ch.steps, ch.C, feats, ws, cw, kw, Wr, f0, images, pl.out_hw,
+                                ch.dtype, device)
 
 
 def run_pipeline(ctx: lib.Context, pl, dp: DevicePipeline, attn_form: str = "standard",
                  stream=None):
-    """One frame.  (1) The pyramid, copied from the encoder's maps, receives
-    each level's ray-direction encoding (qk_ray_encoding, evaluated on the
-    low-resolution grid).  (2) The first step starts from the learned
-    initialisation (qk_ldm_init: f0 broadcast, flat layers at the anchors).
-    (3) Every step: its transition from the previous step's output
-    (qk_layer_collapse, qk_upsample2x) and the absolute decode of its input
-    (qk_ldm_decode) for steps after the first, Update & Fuse with the
-    absolute decode (qk_update_fuse; the last step also writes the
-    blend-weight logits of its attention), and its residual CNN block
-    (qk_residual_conv).  (4) The final volume's unactivated depth and density
-    (qk_ldm_logits) and the final render at the output grid (qk_render_ibr:
-    upsample, activate, blend the input images, composite)."""
+    """One frame (``run_pipelines`` of one)."""
+    run_pipelines(ctx, [(pl.chain, pl.low_hw, dp)], attn_form=attn_form, stream=stream)
+
+
+def run_pipelines(ctx: lib.Context, frames, attn_form: str = "standard", stream=None):
+    """Whole frames, ``frames`` a list of (scene, low_hw, DevicePipeline)
+    where the scene gives in_cams, novel, near, far, steps and dtype (a
+    ``synth.ChainScene`` or the like).  Per frame: (1) the pyramid, copied
+    from the encoder's maps, receives each level's ray-direction encoding
+    (qk_ray_encoding, evaluated on the low-resolution grid); (2) the first
+    step starts from the learned initialisation (qk_ldm_init: f0 broadcast,
+    flat layers at the anchors); (3) every step: its transition from the
+    previous step's output (qk_layer_collapse, qk_upsample2x) and the
+    absolute decode of its input (qk_ldm_decode) after the first, Update &
+    Fuse with the absolute decode (the last step also writes the
+    blend-weight logits of its attention) and its residual CNN block
+    (qk_residual_conv); (4) the final volume's unactivated depth and density
+    (qk_ldm_decode_logits) and the final render at the output grid
+    (qk_render_ibr).  With several bfloat16 frames each step's Update & Fuse
+    of every frame is one qk_batch_update_fuse launch (the frames share the
+    network, so C and the heads); otherwise one qk_update_fuse per frame."""
     import torch
-    ch, dc = pl.chain, dp.chain
-    prec = "bf16" if ch.dtype == "bf16" else "fp32"
+    steps = frames[0][0].steps
+    prec = "bf16" if frames[0][0].dtype == "bf16" else "fp32"
+    batched = len(frames) > 1 and prec == "bf16"
     ctxm = torch.cuda.stream(stream) if stream is not None else None
     if ctxm is not None:
         ctxm.__enter__()
     try:
-        for k, lvl in enumerate(dp.feats):
-            for dst, src in zip(lvl, dp.feats_raw[k]):
-                dst.copy_(src)
+        for _, _, dp in frames:
+            for k, lvl in enumerate(dp.feats):
+                for dst, src in zip(lvl, dp.feats_raw[k]):
+                    dst.copy_(src)
     finally:
         if ctxm is not None:
             ctxm.__exit__(None, None, None)
-    for k, lvl in enumerate(dp.feats):
-        lib.ray_encoding(ctx, ch.in_cams, ch.novel, ch.near, ch.far, dp.Wr[k], lvl,
-                         low_hw=pl.low_hw, stream=stream)
-    lib.ldm_init(ctx, dp.f0, ch.near, ch.far, (dc.F0, dc.depth[0], dc.alpha[0]), stream=stream)
-    F = dc.F0
-    n = len(ch.steps)
-    for i, st in enumerate(ch.steps):
-        w = dc.weights[i]
-        if i > 0:
-            prev = ch.steps[i - 1]
-            F = dc.F_conv[i - 1] if prev.conv else dc.F_out[i - 1]
-            if st.collapse:
-                W1, W2 = dc.collapse_w[i]
-                lib.layer_collapse(ctx, F, W1, W2, dc.tmp[i], stream=stream)
-                F = dc.tmp[i]
-            if st.upsample:
-                lib.upsample2x(ctx, F, dc.F_in[i], stream=stream)
-                F = dc.F_in[i]
-            lib.ldm_decode(ctx, F, dc.depth[i], dc.alpha[i], w["w_sigma"], w["w_depth"],
-                           w["W_color"], ch.near, ch.far, stream=stream)
-        lib.update_fuse(ctx, ch.in_cams, dp.feats[st.level], ch.novel, ch.near, ch.far,
-                        dc.qkw[i], (F, dc.depth[i], dc.alpha[i]),
-                        (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
-                        precision=prec, attn_form=attn_form, mode="paper",
-                        blend_logit_out=dp.blend_logit if i == n - 1 else None, stream=stream)
+    for sc, low_hw, dp in frames:
+        for k, lvl in enumerate(dp.feats):
+            lib.ray_encoding(ctx, sc.in_cams, sc.novel, sc.near, sc.far, dp.Wr[k], lvl,
+                             low_hw=low_hw, stream=stream)
+        dc = dp.chain
+        lib.ldm_init(ctx, dp.f0, sc.near, sc.far, (dc.F0, dc.depth[0], dc.alpha[0]),
+                     stream=stream)
+    n = len(steps)
+    for i, st in enumerate(steps):
+        ins = []
+        for sc, _, dp in frames:
+            dc = dp.chain
+            w = dc.weights[i]
+            F = dc.F0
+            if i > 0:
+                prev = steps[i - 1]
+                F = dc.F_conv[i - 1] if prev.conv else dc.F_out[i - 1]
+                if st.collapse:
+                    W1, W2 = dc.collapse_w[i]
+                    lib.layer_collapse(ctx, F, W1, W2, dc.tmp[i], stream=stream)
+                    F = dc.tmp[i]
+                if st.upsample:
+                    lib.upsample2x(ctx, F, dc.F_in[i], stream=stream)
+                    F = dc.F_in[i]
+                lib.ldm_decode(ctx, F, dc.depth[i], dc.alpha[i], w["w_sigma"], w["w_depth"],
+                               w["W_color"], sc.near, sc.far, stream=stream)
+            ins.append(F)
+        blend = i == n - 1
+        if batched:
+            reqs = [lib.Request(sc.in_cams, dp.feats[st.level], sc.novel, sc.near, sc.far,
+                                dp.chain.qkw[i], (F, dp.chain.depth[i], dp.chain.alpha[i]),
+                                (dp.chain.F_out[i], dp.chain.depth_out[i], dp.chain.alpha_out[i]),
+                                mode="paper", blend_logit_out=dp.blend_logit if blend else None)
+                    for (sc, _, dp), F in zip(frames, ins)]
+            lib.batch_update_fuse(ctx, reqs, precision=prec, attn_form=attn_form, stream=stream)
+        else:
+            for (sc, _, dp), F in zip(frames, ins):
+                dc = dp.chain
+                lib.update_fuse(ctx, sc.in_cams, dp.feats[st.level], sc.novel, sc.near, sc.far,
+                                dc.qkw[i], (F, dc.depth[i], dc.alpha[i]),
+                                (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
+                                precision=prec, attn_form=attn_form, mode="paper",
+                                blend_logit_out=dp.blend_logit if blend else None, stream=stream)
         if st.conv:
-            K1, K2 = dc.conv_w[i]
-            lib.residual_conv(ctx, dc.F_out[i], K1, K2, dc.F_conv[i], stream=stream)
-    last = ch.steps[-1]
-    Ff = dc.F_conv[-1] if last.conv else dc.F_out[-1]
-    w = dc.weights[-1]
-    lib.ldm_logits(ctx, Ff, w["w_sigma"], w["w_depth"], dp.depth_logit, dp.sigma_logit,
-                   stream=stream)
-    lib.render_ibr(ctx, ch.in_cams, dp.images, ch.novel, ch.near, ch.far,
-                   (dp.depth_logit, dp.sigma_logit, dp.blend_logit), dp.rgb, acc_out=dp.acc,
-                   depth_out=dp.depth, stream=stream)
+            for _, _, dp in frames:
+                dc = dp.chain
+                K1, K2 = dc.conv_w[i]
+                lib.residual_conv(ctx, dc.F_out[i], K1, K2, dc.F_conv[i], stream=stream)
+    last = steps[-1]
+    for sc, _, dp in frames:
+        dc = dp.chain
+        Ff = dc.F_conv[-1] if last.conv else dc.F_out[-1]
+        w = dc.weights[-1]
+        lib.ldm_logits(ctx, Ff, w["w_sigma"], w["w_depth"], dp.depth_logit, dp.sigma_logit,
+                       stream=stream)
+        lib.render_ibr(ctx, sc.in_cams, dp.images, sc.novel, sc.near, sc.far,
+                       (dp.depth_logit, dp.sigma_logit, dp.blend_logit), dp.rgb,
+                       acc_out=dp.acc, depth_out=dp.depth, stream=stream)

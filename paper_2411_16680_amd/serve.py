@@ -1,23 +1,30 @@
 """Request loop for novel-view serving: continuous admission of requests,
-each rendered by a fresh layered depth map (the paper makes and discards an
-LDM per frame, Sec. 3; 30 frames/s is its real-time target, Sec. 1).
+each rendered by the paper's whole per-frame method on a fresh layered
+depth map (the paper makes and discards an LDM per frame, Sec. 3; 30
+frames/s is its real-time target, Sec. 1).
 
-A request names a resident scene (input cameras and its encoded feature
-pyramid), an output size and a novel camera.  Its work is one learned
-initialisation plus one Update & Fuse step per pyramid level (independent
-per-level states), the finest level composited to RGB -- all in libquark.
+A request names a resident scene (input cameras, encoded feature pyramid
+and input images), an output size and a novel camera.  Its work is one
+frame: the ray-direction encoding of the scene's pyramid for its camera, the
+learned initialisation, the chained Update & Fuse steps of the network
+(collapse, upsampling, decode, attention, residual CNN blocks), the blend
+weights of the last attention and the final render at the requested size --
+all in libquark.
 
 Scheduling:
   * Requests are admitted first come, first served as they arrive -- no
     batch boundary: a request starts as soon as it fits.
   * Admission is bounded by an HBM budget: a request reserves the bytes of
-    its LDMs and output; if the head of the queue does not fit, it waits for
+    its frame's buffers; if the head of the queue does not fit, it waits for
     completions (head-of-line order is kept); a request that could never fit
     is rejected.
-  * Admitted requests go round-robin onto a few HIP streams (default
-    priority), each with its own libquark context, so requests overlap on
-    the device.  A request's result does not depend on what else runs: the
-    forward kernels have no atomics and every request owns its buffers.
+  * The requests admitted at one poll form a batch: each Update & Fuse step
+    of all of them is one launch (qk_batch_update_fuse), the other kernels
+    run per request.  Batches go round-robin onto a few HIP streams (default
+    priority), each with its own libquark context, so batches overlap on the
+    device.  A request's result does not depend on what else runs: the
+    forward kernels have no atomics, every request owns its buffers, and a
+    batched step equals the request's own step bit for bit.
   * Failures are per request (a rejected argument, an unknown scene, a
     missed deadline, a cancellation); the loop keeps going.
 
@@ -36,7 +43,7 @@ from typing import Callable, Deque, Dict, List, Optional
 
 import numpy as np
 
-from . import lib, synth
+from . import lib, runner, synth
 
 QUEUED, RUNNING, DONE, FAILED, REJECTED, CANCELLED = (
     "queued", "running", "done", "failed", "rejected", "cancelled")
@@ -53,6 +60,7 @@ class Job:
     t_done: float = math.nan
     handle: object = None
     rgb: object = None
+    frame: object = None
 
     @property
     def latency(self) -> float:
@@ -74,6 +82,17 @@ class Executor:
         that cannot run (the loop marks it failed)."""
         raise NotImplementedError
 
+    def launch_batch(self, jobs: List[Job]) -> list:
+        """Enqueue several requests admitted together; returns, per job, its
+        handle or the exception that stopped it."""
+        out = []
+        for job in jobs:
+            try:
+                out.append(self.launch(job))
+            except Exception as e:                 # per-request failure
+                out.append(e)
+        return out
+
     def done(self, handle) -> bool:
         raise NotImplementedError
 
@@ -81,14 +100,26 @@ class Executor:
         pass
 
 
-def request_bytes(req: synth.ServeRequest, ldm_bytes_per_elem: int = 2) -> int:
-    """HBM a request holds while it runs: per level an LDM of
-    L x H x W x C features plus depth and alpha (float32), and the float32
-    RGB output."""
-    total = req.width * req.height * 3 * 4
-    for k, C, L in synth.SERVE_LEVELS:
-        n = L * (req.height // k) * (req.width // k)
-        total += n * (C * ldm_bytes_per_elem + 8)
+def request_bytes(req: synth.ServeRequest, V: int = 8, steps=synth.QUARK_STEPS, C: int = 32,
+                  feat_hw=synth.QUARK_FEAT_HW, elem: int = 2) -> int:
+    """HBM a request holds while it runs: its frame's buffers -- the
+    ray-encoded copy of the pyramid, per step the volumes (input
+    transitions, update output, residual block output, elem bytes per
+    feature) and float32 depth / alpha planes (input and output), the
+    initial volume, the last step's blend logits (V per layer-pixel) and the
+    final logits, and the float32 RGB, alpha and depth of the output."""
+    total = sum(h * w * C * elem for h, w in feat_hw) * V
+    for i, st in enumerate(steps):
+        n = st.L * st.H * st.W
+        vols = 1 + (i > 0 and st.upsample) + (i > 0 and st.collapse) + bool(st.conv)
+        if i > 0 and st.collapse:            # collapsed, before upsampling
+            vols -= 1
+            total += n // (4 if st.upsample else 1) * C * elem
+        total += vols * n * C * elem + 4 * n * 4
+    s0, last = steps[0], steps[-1]
+    total += s0.L * s0.H * s0.W * C * elem
+    total += last.L * last.H * last.W * (V + 2) * 4
+    total += req.width * req.height * (3 + 2) * 4
     return total
 
 
@@ -140,6 +171,7 @@ class Server:
             else:
                 still.append(job)
         self.running = still
+        batch = []
         while self.queue:
             job = self.queue[0]
             if job.req.arrival > now:
@@ -155,15 +187,18 @@ class Server:
             self.queue.popleft()
             job.bytes = need
             job.t_start = now
-            try:
-                job.handle = self.ex.launch(job)
-            except Exception as e:                     # per-request failure
-                job.status = FAILED
-                job.error = str(e)
-                continue
-            job.status = RUNNING
-            self.used += need
-            self.running.append(job)
+            self.used += need                          # reserved at admission
+            batch.append(job)
+        if batch:
+            for job, h in zip(batch, self.ex.launch_batch(batch)):
+                if isinstance(h, Exception):           # per-request failure
+                    job.status = FAILED
+                    job.error = str(h)
+                    self.used -= job.bytes
+                    continue
+                job.handle = h
+                job.status = RUNNING
+                self.running.append(job)
 
     def idle(self) -> bool:
         return not self.queue and not self.running
@@ -214,71 +249,111 @@ def summarize(jobs: List[Job], slo: float = 1.0 / 30.0) -> dict:
 # Device executor
 # ----------------------------------------------------------------------------
 
-class GpuExecutor(Executor):
-    """Runs requests through libquark on ``n_streams`` HIP streams (default
-    priority), one libquark context per stream.  Scenes' pyramids stay
-    resident; each request's LDMs and RGB are allocated on its stream from
-    torch's caching allocator (no device allocation once warm)."""
+@dataclass
+class FrameScene:
+    """What a frame reads of its scene and request (``runner.run_pipelines``)."""
+    in_cams: list
+    novel: object
+    near: float
+    far: float
+    steps: list
+    dtype: str = "bf16"
 
-    def __init__(self, scenes: Dict[int, synth.ServeScene], pyramids: Dict[int, list],
+
+class GpuExecutor(Executor):
+    """Runs requests' frames through libquark, a batch of requests admitted
+    together at a time, batches round-robin over ``n_streams`` HIP streams
+    (default priority), one libquark context per stream.  Scenes' pyramids
+    and images stay resident (``resident[scene_id] = (pyramid, images)``);
+    the network's weights are on the device once; each request's frame
+    buffers come from torch's caching allocator on its batch's stream (no
+    device allocation once warm)."""
+
+    MAX_BATCH = 64
+
+    def __init__(self, scenes: Dict[int, synth.ServeScene], resident: Dict[int, tuple],
                  model: synth.ServeModel, *, n_streams: int = 4, attn_form: str = "folded",
-                 device: int = 0, keep_rgb: bool = False):
+                 device: int = 0, keep_frames: bool = False):
         import torch
         self.torch = torch
         self.scenes = scenes
-        self.pyr = pyramids
+        self.resident = resident
         self.model = model
         self.attn_form = attn_form
         dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
         self.ctxs = [lib.Context(device) for _ in range(n_streams)]
-        self.w = [{k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(dev)
-                   for k, v in wl.items()} for wl in model.weights]
-        self.f0 = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev)
-                   for f in model.f0]
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        self.w = [{k: t(v) for k, v in wl.items()} for wl in model.weights]
+        self.cw = [None if c is None else tuple(t(a) for a in c) for c in model.collapse_w]
+        self.kw = [None if c is None else tuple(t(a) for a in c) for c in model.conv_w]
+        self.Wr = [t(w) for w in model.Wr]
+        self.f0 = t(model.f0)
         self.dev = dev
-        self.keep_rgb = keep_rgb
+        self.keep_frames = keep_frames
         self.rr = 0
 
     def bytes_needed(self, req):
-        return request_bytes(req)
+        sc = self.scenes.get(req.scene_id)
+        m = self.model
+        return request_bytes(req, V=sc.V if sc is not None else 8, steps=m.steps, C=m.C,
+                             feat_hw=sc.feat_hw if sc is not None else synth.QUARK_FEAT_HW)
 
     def launch(self, job: Job):
+        return self.launch_batch([job])[0]
+
+    def launch_batch(self, jobs: List[Job]) -> list:
+        out = []
+        ok = []
+        for job in jobs:
+            if job.req.scene_id not in self.scenes:
+                out.append(lib.QuarkError(lib.QK_EINVAL, f"unknown scene {job.req.scene_id}"))
+            else:
+                out.append(None)
+                ok.append(job)
+        for k in range(0, len(ok), self.MAX_BATCH):
+            part = ok[k:k + self.MAX_BATCH]
+            try:
+                handles = self._run(part)
+            except Exception as e:               # the library refused the batch
+                handles = [e] * len(part)
+            for job, h in zip(part, handles):
+                out[jobs.index(job)] = h
+        return out
+
+    def _run(self, jobs: List[Job]) -> list:
         torch = self.torch
-        req = job.req
-        sc = self.scenes.get(req.scene_id)
-        if sc is None:
-            raise lib.QuarkError(lib.QK_EINVAL, f"unknown scene {req.scene_id}")
+        m = self.model
         i = self.rr
         self.rr = (self.rr + 1) % len(self.streams)
         s, ctx = self.streams[i], self.ctxs[i]
-        m = self.model
+        frames = []
         with torch.cuda.stream(s):
-            rgb = torch.empty((req.height, req.width, 3), device=self.dev, dtype=torch.float32)
-            bufs = []
-            for li, (k, C, L) in enumerate(synth.SERVE_LEVELS):
-                H, W = req.height // k, req.width // k
-                F = torch.empty((L, H, W, C), device=self.dev, dtype=torch.bfloat16)
-                d = torch.empty((L, H, W), device=self.dev, dtype=torch.float32)
-                a = torch.empty((L, H, W), device=self.dev, dtype=torch.float32)
-                bufs.append((F, d, a))
-                lib.ldm_init(ctx, self.f0[li], m.near, m.far, (F, d, a), stream=s)
-                last = li == len(synth.SERVE_LEVELS) - 1
-                lib.update_fuse(ctx, sc.in_cams, self.pyr[req.scene_id][li], req.novel, m.near,
-                                m.far, self.w[li], (F, d, a), (F, d, a), precision="bf16",
-                                attn_form=self.attn_form, mode="residual",
-                                rgb_out=rgb if last else None, stream=s)
+            for job in jobs:
+                req = job.req
+                sc = self.scenes[req.scene_id]
+                pyr, images = self.resident[req.scene_id]
+                dp = runner.make_device_pipeline(m.steps, m.C, pyr, self.w, self.cw, self.kw,
+                                                 self.Wr, self.f0, images,
+                                                 (req.height, req.width), "bf16", self.dev)
+                frames.append((FrameScene(sc.in_cams, req.novel, m.near, m.far, m.steps),
+                               m.low_hw, dp))
+            runner.run_pipelines(ctx, frames, attn_form=self.attn_form, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        job.rgb = rgb
-        return (ev, bufs)
+        handles = []
+        for job, (_, _, dp) in zip(jobs, frames):
+            job.rgb = dp.rgb
+            handles.append((ev, dp))
+        return handles
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def release(self, job: Job, handle) -> None:
-        handle[1].clear()              # LDMs go back to the stream's cache
-        if not self.keep_rgb:
+        if self.keep_frames:
+            job.frame = handle[1]
+        else:
             job.rgb = None
 
 

@@ -667,18 +667,18 @@ def to_bf16(scene: Scene) -> Scene:
 # Serving workload (many scenes, Poisson requests)
 # ----------------------------------------------------------------------------
 
-SERVE_LEVELS = ((8, 64, 32), (4, 32, 16), (2, 16, 8), (1, 8, 4))   # (k, C, L)
 SERVE_OUTPUTS = ((640, 360), (1280, 720), (1920, 1080))
 
 
 @dataclass
 class ServeScene:
     scene_id: int
-    in_cams: List[Camera]          # on the 1920x1080 input grid
+    in_cams: List[Camera]          # on the input image grid
     centre: np.ndarray             # the point every input camera looks at
     centroid: np.ndarray           # mean of the input camera centres
-    feat_hw: List[tuple]           # per level (Hf, Wf)
-    seed: int                      # seed of its feature pyramid
+    feat_hw: List[tuple]           # per pyramid level (Hf, Wf)
+    img_hw: tuple                  # the input images' grid (H, W)
+    seed: int                      # seed of its pyramid and images
 
     @property
     def V(self) -> int:
@@ -697,24 +697,35 @@ class ServeRequest:
 
 @dataclass
 class ServeModel:
-    """Per-level weights and learned initial features (shared by scenes)."""
+    """The network every request runs (shared by scenes): the chained steps,
+    their weights, the layer-collapse and residual-block weights, the learned
+    initial feature and the per-level ray-encoding projections."""
+    steps: List[ChainStep]
+    C: int
     weights: List[Dict[str, np.ndarray]]
-    f0: List[np.ndarray]
+    collapse_w: List[Optional[tuple]]
+    conv_w: List[Optional[tuple]]
+    f0: np.ndarray
+    Wr: List[np.ndarray]
+    low_hw: tuple
     near: float = 0.5
     far: float = 20.0
 
 
 def make_serving(n_scenes: int = 16, n_requests: int = 2000, rate: float = 60.0,
                  seed: int = 5000, views=(4, 6, 8), outputs=SERVE_OUTPUTS,
-                 input_hw=(1080, 1920)):
-    """Scenes, a model and a Poisson request stream.  Each scene has V in
+                 input_hw=(1080, 1920), steps=QUARK_STEPS, feat_hw=QUARK_FEAT_HW, C: int = 32):
+    """Scenes, the network and a Poisson request stream.  Each scene has V in
     ``views`` cameras evenly on a 0.5 m arc of a radius-1.5 m ring facing
-    its centre (60 degree field of view); its feature pyramid has the four
-    levels of ``SERVE_LEVELS`` (drawn on the device from ``seed``).  A
-    request picks a scene and an output size uniformly; its novel camera
-    sits uniformly in a 0.3 m ball around the scene's camera centroid,
-    looking at the centre, 60 degree field of view.  Arrivals are a Poisson
-    process of ``rate`` per second."""
+    its centre (60 degree field of view), a feature pyramid of ``feat_hw``
+    levels with C channels and V input images on ``input_hw`` (both drawn on
+    the device from the scene's seed).  The network: per step attention and
+    decode weights, collapse MLPs and residual-block kernels (std
+    1/sqrt(fan_in)), f0 N(0, 1), per level Wr N(0, 1/32).  A request picks a
+    scene and an output size uniformly; its novel camera sits uniformly in
+    a 0.3 m ball around the scene's camera centroid, looking at the centre,
+    60 degree field of view.  Arrivals are a Poisson process of ``rate`` per
+    second."""
     rng = np.random.default_rng(seed)
     FH, FW = input_hw
     scenes = []
@@ -723,13 +734,17 @@ def make_serving(n_scenes: int = 16, n_requests: int = 2000, rate: float = 60.0,
         cams, _ = _arc_rig(rng, V, 0.5, 1.5, FW, FH, 60.0)
         centres = np.stack([-c.E[:3, :3].T @ c.E[:3, 3] for c in cams])
         scenes.append(ServeScene(s, cams, np.array([0.0, 0.0, 1.5]), centres.mean(axis=0),
-                                 [(FH // k, FW // k) for k, _, _ in SERVE_LEVELS],
-                                 seed + 1 + s))
-    weights, f0 = [], []
-    for k, C, L in SERVE_LEVELS:
-        weights.append(_weights(rng, C, C, 1, C))
-        f0.append(_normal(rng, (C,)))
-    model = ServeModel(weights, f0)
+                                 [tuple(hw) for hw in feat_hw], tuple(input_hw), seed + 1 + s))
+    weights, cw, kw = [], [], []
+    for st in steps:
+        weights.append(_weights(rng, C, C, st.heads, C // st.heads))
+        cw.append((_normal(rng, (2 * C, C), 1.0 / math.sqrt(2 * C)),
+                   _normal(rng, (C, C), 1.0 / math.sqrt(C))) if st.collapse else None)
+        kw.append((_normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C)),
+                   _normal(rng, (3, 3, C, C), 1.0 / math.sqrt(9.0 * C))) if st.conv else None)
+    f0 = _normal(rng, (C,))
+    Wr = [_normal(rng, (32, C), 1.0 / math.sqrt(32.0)) for _ in feat_hw]
+    model = ServeModel(list(steps), C, weights, cw, kw, f0, Wr, tuple(feat_hw[0]))
     reqs = []
     t = 0.0
     for i in range(n_requests):
@@ -747,15 +762,33 @@ def make_serving(n_scenes: int = 16, n_requests: int = 2000, rate: float = 60.0,
     return scenes, model, reqs
 
 
-def device_pyramid(scene: ServeScene, device="cuda", dtype: str = "bf16"):
+def device_pyramid(scene: ServeScene, C: int = 32, device="cuda", dtype: str = "bf16"):
     """The scene's feature pyramid, drawn on the device with a seeded torch
     generator: [level][view] tensors [Hf][Wf][C], standard normal."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(scene.seed))
     tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
-    pyr = []
-    for (k, C, L), (Hf, Wf) in zip(SERVE_LEVELS, scene.feat_hw):
-        pyr.append([torch.randn((Hf, Wf, C), generator=g, device=device, dtype=torch.float32)
-                    .to(tdt) for _ in range(scene.V)])
-    return pyr
+    return [[torch.randn((Hf, Wf, C), generator=g, device=device, dtype=torch.float32).to(tdt)
+             for _ in range(scene.V)] for (Hf, Wf) in scene.feat_hw]
+
+
+def device_images(scene: ServeScene, block: int = 16, device="cuda"):
+    """The scene's V input images, RGBA8 [H][W][4] on the device: bilinear
+    colour fields over uniform random bytes on a ``block``-pixel grid (a
+    seeded torch generator of its own), alpha 255."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(scene.seed) + 104729)
+    H, W = scene.img_hw
+    gh, gw = H // block + 2, W // block + 2
+    out = []
+    for _ in range(scene.V):
+        grid = torch.rand((1, 3, gh, gw), generator=g, device=device) * 255.0
+        up = torch.nn.functional.interpolate(grid, scale_factor=block, mode="bilinear",
+                                             align_corners=False)[0, :, :H, :W]
+        im = torch.empty((H, W, 4), dtype=torch.uint8, device=device)
+        im[..., :3] = up.permute(1, 2, 0).round().clamp(0, 255).to(torch.uint8)
+        im[..., 3] = 255
+        out.append(im)
+    return out

@@ -104,11 +104,24 @@ def test_poisson_stream_statistics():
     assert st["throughput_rps"] == pytest.approx(60.0, rel=0.2)
 
 
-def test_request_bytes_match_ldm_sizes():
-    r = _reqs([0.0], 1920, 1080)[0]
-    F_bytes = sum(L * (1080 // k) * (1920 // k) * C * 2 for k, C, L in synth.SERVE_LEVELS)
-    assert F_bytes == 4 * 66_355_200 * 2                 # 531 MB of bfloat16 features
-    assert serve.request_bytes(r) > F_bytes
+@pytest.mark.parametrize("V,wh", [(8, (1920, 1080)), (4, (640, 360)), (6, (1280, 720))])
+def test_request_bytes_match_the_frame_buffers(V, wh):
+    """The admission estimate equals what a frame allocates: its buffers
+    (runner.frame_buffers, allocated here on the CPU) and the ray-encoded
+    copy of the pyramid."""
+    import torch
+    from paper_2411_16680_amd import runner
+    r = _reqs([0.0], *wh)[0]
+    chain, frame = runner.frame_buffers(synth.QUARK_STEPS, 32, V, (wh[1], wh[0]), "bf16",
+                                        device="cpu")
+    seen, total = set(), 0
+    for t in list(chain.values()) + list(frame.values()):
+        for x in (t if isinstance(t, list) else [t]):
+            if x is not None and id(x) not in seen:
+                seen.add(id(x))
+                total += x.numel() * x.element_size()
+    total += sum(h * w * 32 * 2 for h, w in synth.QUARK_FEAT_HW) * V
+    assert serve.request_bytes(r, V=V) == total
 
 
 def test_novel_cameras_in_ball_and_facing_centre():
