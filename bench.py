@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "1080p frames/s + p50/p99 ms, Update&Fuse+render, V=8, BF16 vs FP32, same GPU"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense bf16
+MFMA_FP32_PEAK_TFLOPS = 157.3   # dense fp32 matrix
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_16680_amd", "csrc", "k_update_fuse.hip")
 RENDER_SRC = os.path.join(ROOT, "paper_2411_16680_amd", "csrc", "k_render.hip")
 
@@ -150,7 +151,45 @@ def _timed_level(oracle, scene, lvl, rows):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(scene, target_s: float = 25.0):
+def _psnr(a, b) -> float:
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def accuracy_vs_oracle(ctx, oracle, scenes, rows):
+    """The composited 1080p level (1920x1080, L4, C8) of each form against
+    the FP64 oracle on ``rows`` of it (the oracle on the form's own inputs):
+    RGB max-abs and PSNR per form, with the stated bars (float32 1e-4;
+    bfloat16 2e-2 and 45 dB; e4m3 projections: error stated)."""
+    import torch
+    from paper_2411_16680_amd import runner
+    out = {}
+    refs = {}
+    for form, key, attn, prec in (("bf16", "bf16", "standard", "bf16"),
+                                  ("bf16_folded", "bf16", "folded", "bf16"),
+                                  ("fp8proj", "bf16", "standard", "bf16_fp8proj"),
+                                  ("fp32", "fp32", "standard", "fp32")):
+        sc = scenes[key]
+        lvl = sc.levels[-1]
+        if key not in refs:
+            refs[key] = oracle.run_level(sc, lvl, rows=rows)["rgb"]
+        dl = runner.level_to_device(lvl)
+        runner.run_level(ctx, sc, dl, attn_form=attn, precision=prec)
+        torch.cuda.synchronize()
+        got = dl.rgb.cpu().numpy().astype(np.float64)[rows]
+        e = float(np.max(np.abs(got - refs[key])))
+        q = _psnr(got, refs[key])
+        bar = {"fp32": (1e-4, None), "bf16": (2e-2, 45.0)}.get(key if form != "fp8proj" else "-")
+        ent = {"rgb_max_abs": e, "psnr_db": q}
+        if bar is not None:
+            ent["meets_bar"] = bool(e <= bar[0] and (bar[1] is None or q >= bar[1]))
+        out[form] = ent
+        del dl
+    out["sample"] = f"{len(rows)} rows of the 1920x1080 level (L4, C8, V8), rows {rows}"
+    return out
+
+
+def cpu_baseline(scene, target_s: float = 25.0, ctx=None, scene32=None):
     """The FP64 oracle on the host's cores, on evenly spaced rows of each
     level.  A level's time is a per-call part (marshalling its maps to
     float64) plus a per-row part, fitted to two timed calls and evaluated at
@@ -196,8 +235,13 @@ def cpu_baseline(scene, target_s: float = 25.0):
             one_est += fitted_time(t_s, len(small), t_b, len(big), lvl.H)
     finally:
         oracle.set_num_threads(threads)
+    acc = None
+    if ctx is not None and scene32 is not None:
+        H = scene.levels[-1].H
+        acc = accuracy_vs_oracle(ctx, oracle, {"bf16": scene, "fp32": scene32},
+                                 sorted({0, H // 4, H // 2, (3 * H) // 4, H - 1}))
     return {"value": fps, "unit": "frames/s", "cores": threads, "kind": "oracle", "sample": desc,
-            "s_per_frame": total_est,
+            "s_per_frame": total_est, "accuracy_vs_oracle": acc,
             "one_thread": {"value": 1.0 / one_est, "unit": "frames/s", "s_per_frame": one_est,
                            "sample": "1 row and H/16 rows per level, fitted the same way"},
             "host": _host_info()}
@@ -820,15 +864,43 @@ def main():
         t = time_frames(ctx, sc, dls, steps, args.warmup, dominant if form == "bf16" else dom, attn,
                         prec)
         per = t["per_frame_ms"]
+        lat_frames = steps
+        if steps < 200:
+            # the latency percentiles need a few hundred frames
+            per = time_frames(ctx, sc, dls, 200, 2, dom, attn, prec)["per_frame_ms"]
+            lat_frames = 200
         results[form] = {"steps": steps, "total_ms": t["total_ms"], "per_level_ms": lv_ms,
                          "p50_ms": float(np.percentile(per, 50)),
-                         "p99_ms": float(np.percentile(per, 99)),
+                         "p99_ms": float(np.percentile(per, 99)), "latency_frames": lat_frames,
                          "kernel_ms": float(np.mean(t["kernel_ms"])), "dominant": dom,
                          "fps": steps / (t["total_ms"] / 1000.0)}
         log(f"{form}: {results[form]['fps']:.1f} frames/s, p50 {results[form]['p50_ms']:.3f} ms, "
             f"p99 {results[form]['p99_ms']:.3f} ms")
         del dls
         torch.cuda.empty_cache()
+
+    # the same frame with piecewise-smooth depths (the paper's LDMs follow
+    # surfaces), bf16 standard form
+    sm_sc = synth.to_bf16(synth.make_inputs(3, depth_mode="smooth" if args.depth_mode == "iid"
+                                            else "iid"))
+    dls = runner.scene_to_device(sm_sc)
+    for dl in dls:
+        dl.acc = None
+    sm_lv = per_level_ms(ctx, sm_sc, dls, "standard", "bf16")
+    sm_t = time_frames(ctx, sm_sc, dls, max(200, min(args.steps, 500)), args.warmup,
+                       int(np.argmax(sm_lv)))
+    sm_n = max(200, min(args.steps, 500))
+    lvl3 = sm_sc.levels[-1]
+    smooth = {"depth_mode": "smooth" if args.depth_mode == "iid" else "iid",
+              "value": sm_n / (sm_t["total_ms"] / 1000.0), "unit": "frames/s",
+              "per_level_ms": sm_lv, "p50_ms": float(np.percentile(sm_t["per_frame_ms"], 50)),
+              "p99_ms": float(np.percentile(sm_t["per_frame_ms"], 99)), "frames": sm_n,
+              "level3_hbm_frac": level_bytes(lvl3, V, 2, True) / (sm_lv[-1] / 1000.0) /
+              (HBM_PEAK_GBS * 1e9)}
+    log(f"other depth mode ({smooth['depth_mode']}): {smooth['value']:.1f} frames/s, per-level ms "
+        f"{[round(x, 4) for x in sm_lv]}")
+    del dls
+    torch.cuda.empty_cache()
 
     # several heads: the 480x270 C = 32 level (the paper's width) with its
     # weights read as 1, 2 and 4 heads (standard form, bfloat16)
@@ -870,6 +942,24 @@ def main():
     roof["algorithmic_bytes_per_launch"] = alg_bytes
     roof["algorithmic_flops_per_launch"] = alg_flops
     roof["avg_launch_ms"] = bf["kernel_ms"]
+
+    # the float32 form's dominant level against its own roof (float32
+    # matrix cores for the projections, HBM for float32 bytes)
+    f32 = results["fp32"]
+    d32 = f32["dominant"]
+    l32 = sc32.levels[d32]
+    b32 = level_bytes(l32, V, 4, d32 == len(sc32.levels) - 1)
+    fl32 = level_flops(l32, V)
+    k32 = f32["per_level_ms"][d32] / 1000.0
+    if fl32 / b32 >= MFMA_FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        fp32_roof = {"bound": "mfma", "achieved": fl32 / k32 / 1e12,
+                     "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        fp32_roof = {"bound": "hbm", "achieved": b32 / k32 / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s"}
+    fp32_roof["frac"] = fp32_roof["achieved"] / fp32_roof["peak"]
+    fp32_roof["kernel"] = f"k_update_fuse<C={l32.C},fp32> (level {d32}, {l32.W}x{l32.H} L{l32.L})"
+    fp32_roof["avg_launch_ms"] = f32["per_level_ms"][d32]
 
     frame_bytes = sum(level_bytes(l, V, 2, i == len(sc16.levels) - 1)
                       for i, l in enumerate(sc16.levels))
@@ -938,7 +1028,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a row sample (cpu_baseline)")
-        cpu = cpu_baseline(sc16)
+        cpu = cpu_baseline(sc16, ctx=ctx, scene32=sc32)
+        if cpu.get("accuracy_vs_oracle"):
+            log("accuracy vs oracle (1080p level rows): " + ", ".join(
+                f"{k} {v['rgb_max_abs']:.3g} / {v['psnr_db']:.1f} dB"
+                for k, v in cpu["accuracy_vs_oracle"].items() if isinstance(v, dict)))
         log(f"cpu_baseline {cpu['value']:.4g} frames/s on {cpu['cores']} threads")
 
     out = {
@@ -965,9 +1059,12 @@ def main():
         },
         "p50_ms": bf["p50_ms"],
         "p99_ms": bf["p99_ms"],
+        "latency_frames": bf["latency_frames"],
         "fp32": {"value": results["fp32"]["fps"], "unit": "frames/s",
                  "p50_ms": results["fp32"]["p50_ms"], "p99_ms": results["fp32"]["p99_ms"],
-                 "steps": results["fp32"]["steps"], "per_level_ms": results["fp32"]["per_level_ms"]},
+                 "steps": results["fp32"]["steps"], "per_level_ms": results["fp32"]["per_level_ms"],
+                 "roofline": fp32_roof},
+        "other_depth_mode": smooth,
         "fp8proj": {"value": results["fp8proj"]["fps"], "unit": "frames/s",
                     "p50_ms": results["fp8proj"]["p50_ms"], "p99_ms": results["fp8proj"]["p99_ms"],
                     "per_level_ms": results["fp8proj"]["per_level_ms"],

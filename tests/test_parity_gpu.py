@@ -36,8 +36,10 @@ TOL = {
     "fp32": {"rgb": 1e-4, "acc": 1e-4, "alpha": 1e-4, "disp": 1e-3, "F_abs": 2e-4, "F_rel": 2e-4},
     "bf16": {"rgb": 2e-2, "acc": 2e-2, "alpha": 2e-2, "disp": 1e-1, "F_abs": 4e-2, "F_rel": 1.6e-2},
     # e4m3 projections: each operand rounds to 3 mantissa bits (relative
-    # 2^-4), about 8x the bfloat16 rounding, through the same chain
-    "fp8": {"rgb": 8e-2, "acc": 8e-2, "alpha": 8e-2, "disp": 0.6, "F_abs": 0.3, "F_rel": 0.13},
+    # 2^-4), about 8x the bfloat16 rounding, through the same chain; the
+    # RGB bar sits just above the measured envelope (worst 0.047 max-abs,
+    # 41.9 dB over these cases), which misses the bfloat16 bar -- stated
+    "fp8": {"rgb": 5.5e-2, "acc": 5.5e-2, "alpha": 8e-2, "disp": 0.6, "F_abs": 0.3, "F_rel": 0.13},
 }
 PREC = {"fp32": "fp32", "bf16": "bf16", "fp8": "bf16_fp8proj"}
 REPORT = []
@@ -91,7 +93,7 @@ def compare(gpu, ref, form, scene, level, rows=None, composite=True, label=""):
         if form == "bf16":
             assert errs["psnr"] >= 45.0, (label, "psnr", errs)
         if form == "fp8":
-            assert errs["psnr"] >= 30.0, (label, "psnr", errs)
+            assert errs["psnr"] >= 40.0, (label, "psnr", errs)
     return errs
 
 
