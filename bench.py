@@ -576,8 +576,9 @@ CHAIN_WORKLOAD = ("the five Update & Fuse steps of the paper's network table at 
 
 
 def time_chain(ctx, reps: int = 20):
-    """The chained schedule, in the paper's one-to-many form and in the
-    standard form: average time of one whole chain (all its launches) with
+    """The chained schedule, in the paper's one-to-many form, the standard
+    form and per step the faster of the two ("auto": one-to-many on the
+    one-head step): average time of one whole chain (all its launches) with
     HIP events on the stream."""
     import torch
     from paper_2411_16680_amd import runner, synth
@@ -586,7 +587,7 @@ def time_chain(ctx, reps: int = 20):
     stream = torch.cuda.current_stream()
     out = {"workload": CHAIN_WORKLOAD,
            "layer_pixel_views": sum(st.L * st.H * st.W for st in ch.steps) * ch.V}
-    for attn in ("folded", "standard"):
+    for attn in ("folded", "standard", "auto"):
         for _ in range(3):
             runner.run_chain(ctx, ch, dc, attn_form=attn, stream=stream)
         a = torch.cuda.Event(enable_timing=True)
@@ -610,8 +611,9 @@ PIPELINE_WORKLOAD = ("the whole frame at 1080p, V=8, C=32, bf16: ray-direction e
 
 
 def time_pipeline(ctx, reps: int = 20):
-    """The whole frame (runner.run_pipeline) in the one-to-many and the
-    standard form: average time of one frame (all its launches) with HIP
+    """The whole frame (runner.run_pipeline) in the one-to-many form, the
+    standard form and "auto" (one-to-many on the one-head step, standard on
+    the others): average time of one frame (all its launches) with HIP
     events on the stream."""
     import torch
     from paper_2411_16680_amd import runner, synth
@@ -620,7 +622,7 @@ def time_pipeline(ctx, reps: int = 20):
     stream = torch.cuda.current_stream()
     out = {"workload": PIPELINE_WORKLOAD, "out_res": f"{pl.out_hw[1]}x{pl.out_hw[0]}",
            "views": pl.chain.V}
-    for attn in ("folded", "standard"):
+    for attn in ("folded", "standard", "auto"):
         for _ in range(3):
             runner.run_pipeline(ctx, pl, dp, attn_form=attn, stream=stream)
         a = torch.cuda.Event(enable_timing=True)
@@ -750,7 +752,9 @@ def run_serving(n_requests: int = 2000, rate: float = 60.0, n_scenes: int = 16,
     st.update({"rate_rps": rate, "scenes": n_scenes, "streams": n_streams,
                "resident_scene_bytes": int(resident),
                "work": "whole frame per request (ray encoding, init, 5 chained steps, final "
-                       "render), bf16, one-to-many attention, batched Update & Fuse per poll"})
+                       "render), bf16, attention per step in the faster form (one-to-many on "
+                       "the one-head step, standard on the others), batched Update & Fuse per "
+                       "poll"})
     rows = []
     best = rate if st.get("p99_ms", math.inf) < 33.0 else None
     for r in sweep:
@@ -993,14 +997,17 @@ def main():
 
     chain = time_chain(ctx)
     log(f"chained paper schedule: {chain['folded']['chain_ms']:.3f} ms per chain of 5 steps "
-        f"(one-to-many attention), {chain['standard']['chain_ms']:.3f} ms (standard)")
+        f"(one-to-many attention), {chain['standard']['chain_ms']:.3f} ms (standard), "
+        f"{chain['auto']['chain_ms']:.3f} ms (per step the faster form)")
     torch.cuda.empty_cache()
 
     pipeline = time_pipeline(ctx)
     log(f"whole frame (paper's network at 1080p, final render): "
         f"{pipeline['folded']['frame_ms']:.3f} ms (one-to-many attention, "
         f"{pipeline['folded']['frames_per_s']:.0f} frames/s), "
-        f"{pipeline['standard']['frame_ms']:.3f} ms (standard)")
+        f"{pipeline['standard']['frame_ms']:.3f} ms (standard), "
+        f"{pipeline['auto']['frame_ms']:.3f} ms (per step the faster form, "
+        f"{pipeline['auto']['frames_per_s']:.0f} frames/s)")
     torch.cuda.empty_cache()
 
     composite = time_composite(ctx)

@@ -579,8 +579,13 @@ QK_API qk_status qk_layer_collapse_check(const qk_ldm *ldm_in, const float *W1, 
  *   C        8, 16, 32 or 64
  *   dtype    of the feature maps (QK_F32 or QK_BF16)
  *   low_H, low_W  the low-resolution grid, or both 0
- *   feats    host [V]: device [H][W][C] maps, 16-byte aligned, read and
- *            written in place; no two may overlap
+ *   feats    host [V]: device [H][W][C] maps, 16-byte aligned, written;
+ *            no two may overlap.  Each map's `src` is NULL (the map is read
+ *            and written in place) or a device [H][W][C] map of the same
+ *            grid and dtype, 16-byte aligned, that is read instead, the
+ *            encoded result going to `data` (src may equal data; otherwise
+ *            it may not overlap any map's data).  The out-of-place form
+ *            spares a caller that keeps the encoder's maps a copy per call.
  * Workspace (low-resolution form): V h w C floats in the context.
  * Errors (nothing enqueued): QK_EINVAL (NULL, misaligned or overlapping
  * buffers, bad camera, near/far), QK_ESHAPE (dims, V out of range, a
@@ -588,8 +593,9 @@ QK_API qk_status qk_layer_collapse_check(const qk_ldm *ldm_in, const float *W1, 
  * (C, a map of 2^40 elements or more, a workspace of 2^31 floats or
  * more). */
 typedef struct {
-    void *data;           /* device [H][W][C], read and written */
+    void *data;           /* device [H][W][C], written (and read when src is NULL) */
     int32_t H, W;
+    const void *src;      /* NULL, or device [H][W][C] read instead of data */
 } qk_feature_map_inout;
 
 QK_API qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V,

@@ -490,18 +490,30 @@ qk_status check_ray(int32_t V, const qk_camera *in_cams, const qk_camera *novel,
             return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
         if ((int64_t)feats[m].H * feats[m].W * C >= ((int64_t)1 << 40))
             return fail(QK_EUNSUPPORTED, "feature map %d too large", m);
+        if (feats[m].src && !aligned16(feats[m].src))
+            return fail(QK_EINVAL, "source map %d must be 16-byte aligned", m);
     }
-    // each map is read and written in place by its own threads: two views
-    // sharing memory would race
-    for (int a = 0; a < V; ++a)
+    // each map is written by its own threads: two views sharing memory would
+    // race, and so would a source map that overlaps a map being written
+    // (other than its own, read and written in place)
+    for (int a = 0; a < V; ++a) {
+        const int64_t na = (int64_t)feats[a].H * feats[a].W * C * esize;
+        const char *pa = static_cast<const char *>(feats[a].data);
         for (int b = a + 1; b < V; ++b) {
-            const char *pa = static_cast<const char *>(feats[a].data);
             const char *pb = static_cast<const char *>(feats[b].data);
-            const int64_t na = (int64_t)feats[a].H * feats[a].W * C * esize;
             const int64_t nb = (int64_t)feats[b].H * feats[b].W * C * esize;
             if (pa < pb + nb && pb < pa + na)
                 return fail(QK_EINVAL, "feature maps %d and %d overlap", a, b);
         }
+        const char *sa = static_cast<const char *>(feats[a].src);
+        if (!sa || sa == pa) continue;
+        for (int b = 0; b < V; ++b) {
+            const char *pb = static_cast<const char *>(feats[b].data);
+            const int64_t nb = (int64_t)feats[b].H * feats[b].W * C * esize;
+            if (sa < pb + nb && pb < sa + na)
+                return fail(QK_EINVAL, "source map %d overlaps feature map %d", a, b);
+        }
+    }
     return QK_OK;
 }
 
@@ -1339,6 +1351,7 @@ qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk
             p.o[m][r] = s;
         }
         p.feat[m] = feats[m].data;
+        p.src[m] = feats[m].src ? feats[m].src : feats[m].data;
         p.fH[m] = feats[m].H;
         p.fW[m] = feats[m].W;
         maxpix = std::max(maxpix, (int64_t)feats[m].H * feats[m].W);

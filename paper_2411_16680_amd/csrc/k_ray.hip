@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(256) k_ray_encoding(const RayParams p) {
 #pragma unroll
     for (int c8 = 0; c8 < C / 8; ++c8) {
         float a[8];
-        load8<BF16>(p.feat[m], q * C + 8 * c8, a);
+        load8<BF16>(p.src[m], q * C + 8 * c8, a);
         project8_w<C>(e, p, wbuf, 8 * c8, a);
         store8<BF16>(p.feat[m], q * C + 8 * c8, a);
     }
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(256) k_ray_upsample_add(const RayParams p) {
     load8<false>(R, (x0 - cx_lo) * C + c0, t0);
     load8<false>(R, (x1 - cx_lo) * C + c0, t1);
     const int64_t q = (int64_t)y * fw + x;
-    load8<BF16>(p.feat[m], q * C + c0, a);
+    load8<BF16>(p.src[m], q * C + c0, a);
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[j] += fmaf(lx, t1[j] - t0[j], t0[j]);
     store8<BF16>(p.feat[m], q * C + c0, a);
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(256) k_ray_upsample_add_any(const RayParams p)
     load8<false>(Pm, ((int64_t)y0 * lw + x1) * C, t10);
     load8<false>(Pm, ((int64_t)y1 * lw + x0) * C, t01);
     load8<false>(Pm, ((int64_t)y1 * lw + x1) * C, t11);
-    load8<BF16>(p.feat[m], q * C + c0, a);
+    load8<BF16>(p.src[m], q * C + c0, a);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const float top = fmaf(lx, t10[j] - t00[j], t00[j]);

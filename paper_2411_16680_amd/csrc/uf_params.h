@@ -229,7 +229,8 @@ namespace qk {
 struct RayParams {
     double D[kMaxViews][9];         // (u, v, 1) on view m's grid -> ray direction, novel frame
     double o[kMaxViews][3];         // view m's centre in the novel frame
-    void *feat[kMaxViews];          // [Hf][Wf][C], float32 or bfloat16, in place
+    void *feat[kMaxViews];          // [Hf][Wf][C], float32 or bfloat16, written
+    const void *src[kMaxViews];     // the map read (feat[m] itself when in place)
     int32_t fH[kMaxViews], fW[kMaxViews];
     double kx0, kx1, ky0, ky1;      // (2/W_n) K_n[0][0..1], (2/H_n) K_n[1][0..1]
     double inv_band;                // 1/far - 1/near

@@ -54,7 +54,8 @@ class qk_feature_map(ctypes.Structure):
 
 
 class qk_feature_map_inout(ctypes.Structure):
-    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("src", ctypes.c_void_p)]
 
 
 class qk_image(ctypes.Structure):
@@ -564,11 +565,18 @@ def layer_collapse_check(F_in, W1, W2, F_out) -> int:
                                               ctypes.byref(b)))
 
 
-def _ray_args(in_cams, novel, near, far, Wr, feats, low_hw):
+def _ray_args(in_cams, novel, near, far, Wr, feats, low_hw, src=None):
     V = len(in_cams)
     cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
+    srcs = [None] * len(feats) if src is None else list(src)
+    if len(srcs) != len(feats):
+        raise ValueError("src needs one map per feature map")
+    for f, s_ in zip(feats, srcs):
+        if s_ is not None and (tuple(s_.shape) != tuple(f.shape) or s_.dtype != f.dtype):
+            raise ValueError("a source map needs its feature map's shape and dtype")
     maps = (qk_feature_map_inout * V)(*[qk_feature_map_inout(_ptr(f), int(f.shape[0]),
-                                                             int(f.shape[1])) for f in feats])
+                                                             int(f.shape[1]), _ptr(s))
+                                        for f, s in zip(feats, srcs)])
     nov = make_camera(novel)
     C = int(Wr.shape[1]) if Wr is not None else 0
     lh, lw = (0, 0) if low_hw is None else (int(low_hw[0]), int(low_hw[1]))
@@ -577,19 +585,22 @@ def _ray_args(in_cams, novel, near, far, Wr, feats, low_hw):
 
 
 def ray_encoding(ctx: Context, in_cams, novel, near: float, far: float, Wr, feats, low_hw=None,
-                 stream=None):
+                 stream=None, src=None):
     """qk_ray_encoding: adds each view's ray-direction encoding to its
-    feature map in place; Wr [32][C] float32, feats[m] [Hf][Wf][C] float32
-    or bfloat16 device tensors (one dtype); low_hw = (h, w) evaluates the
+    feature map; Wr [32][C] float32, feats[m] [Hf][Wf][C] float32 or
+    bfloat16 device tensors (one dtype); low_hw = (h, w) evaluates the
     encoding on that grid and upsamples it (the paper's form), None per
-    pixel."""
-    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw)
+    pixel.  src (optional, one per map, entries may be None): the maps read,
+    the encoded result going to feats; without it the maps are encoded in
+    place."""
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw, src)
     _check(ctx._lib.qk_ray_encoding(ctx.handle, _stream_handle(stream), *args))
 
 
-def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats, low_hw=None) -> int:
+def ray_encoding_check(in_cams, novel, near: float, far: float, Wr, feats, low_hw=None,
+                       src=None) -> int:
     """qk_ray_encoding_check: the status qk_ray_encoding would return."""
-    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw)
+    args, keep = _ray_args(in_cams, novel, near, far, Wr, feats, low_hw, src)
     return int(load().qk_ray_encoding_check(*args))
 
 

@@ -155,6 +155,16 @@ def chain_to_device(ch, device="cuda") -> DeviceChain:
                        **chain_kw)
 
 
+def step_form(attn_form: str, step) -> str:
+    """The attention form a step runs in: ``attn_form`` itself, or for
+    "auto" the one-to-many form on a step with one head and the standard
+    form on a step with several (the faster of the two on MI355X at the
+    paper's head counts; both compute the same attention)."""
+    if attn_form != "auto":
+        return attn_form
+    return "folded" if int(step.heads) == 1 else "standard"
+
+
 def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard", stream=None):
     """The steps in order.  Step i > 0 takes step i - 1's output features,
     collapses their layers (qk_layer_collapse) and / or doubles their grid
@@ -185,7 +195,7 @@ def run_chain(ctx: lib.Context, ch, dc: DeviceChain, attn_form: str = "standard"
         lib.update_fuse(ctx, ch.in_cams, dc.feats[st.level], ch.novel, ch.near, ch.far, dc.qkw[i],
                         (F, dc.depth[i], dc.alpha[i]),
                         (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
-                        precision=prec, attn_form=attn_form, mode="paper",
+                        precision=prec, attn_form=step_form(attn_form, st), mode="paper",
                         rgb_out=dc.rgb if comp else None, acc_out=dc.acc if comp else None,
                         stream=stream)
         if st.conv:
@@ -298,9 +308,11 @@ def run_pipeline(ctx: lib.Context, pl, dp: DevicePipeline, attn_form: str = "sta
 def run_pipelines(ctx: lib.Context, frames, attn_form: str = "standard", stream=None):
     """Whole frames, ``frames`` a list of (scene, low_hw, DevicePipeline)
     where the scene gives in_cams, novel, near, far, steps and dtype (a
-    ``synth.ChainScene`` or the like).  Per frame: (1) the pyramid, copied
-    from the encoder's maps, receives each level's ray-direction encoding
-    (qk_ray_encoding, evaluated on the low-resolution grid); (2) the first
+    ``synth.ChainScene`` or the like).  Per frame: (1) each level's
+    ray-direction encoding (qk_ray_encoding, evaluated on the
+    low-resolution grid) is added to the encoder's maps, written to the
+    frame's own pyramid (out of place: the encoder's maps stay as they are
+    for the next frame); (2) the first
     step starts from the learned initialisation (qk_ldm_init: f0 broadcast,
     flat layers at the anchors); (3) every step: its transition from the
     previous step's output (qk_layer_collapse, qk_upsample2x) and the
@@ -312,25 +324,13 @@ def run_pipelines(ctx: lib.Context, frames, attn_form: str = "standard", stream=
     (qk_render_ibr).  With several bfloat16 frames each step's Update & Fuse
     of every frame is one qk_batch_update_fuse launch (the frames share the
     network, so C and the heads); otherwise one qk_update_fuse per frame."""
-    import torch
     steps = frames[0][0].steps
     prec = "bf16" if frames[0][0].dtype == "bf16" else "fp32"
     batched = len(frames) > 1 and prec == "bf16"
-    ctxm = torch.cuda.stream(stream) if stream is not None else None
-    if ctxm is not None:
-        ctxm.__enter__()
-    try:
-        for _, _, dp in frames:
-            for k, lvl in enumerate(dp.feats):
-                for dst, src in zip(lvl, dp.feats_raw[k]):
-                    dst.copy_(src)
-    finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
     for sc, low_hw, dp in frames:
         for k, lvl in enumerate(dp.feats):
             lib.ray_encoding(ctx, sc.in_cams, sc.novel, sc.near, sc.far, dp.Wr[k], lvl,
-                             low_hw=low_hw, stream=stream)
+                             low_hw=low_hw, stream=stream, src=dp.feats_raw[k])
         dc = dp.chain
         lib.ldm_init(ctx, dp.f0, sc.near, sc.far, (dc.F0, dc.depth[0], dc.alpha[0]),
                      stream=stream)
@@ -361,14 +361,15 @@ def run_pipelines(ctx: lib.Context, frames, attn_form: str = "standard", stream=
                                 (dp.chain.F_out[i], dp.chain.depth_out[i], dp.chain.alpha_out[i]),
                                 mode="paper", blend_logit_out=dp.blend_logit if blend else None)
                     for (sc, _, dp), F in zip(frames, ins)]
-            lib.batch_update_fuse(ctx, reqs, precision=prec, attn_form=attn_form, stream=stream)
+            lib.batch_update_fuse(ctx, reqs, precision=prec, attn_form=step_form(attn_form, st),
+                                  stream=stream)
         else:
             for (sc, _, dp), F in zip(frames, ins):
                 dc = dp.chain
                 lib.update_fuse(ctx, sc.in_cams, dp.feats[st.level], sc.novel, sc.near, sc.far,
                                 dc.qkw[i], (F, dc.depth[i], dc.alpha[i]),
                                 (dc.F_out[i], dc.depth_out[i], dc.alpha_out[i]),
-                                precision=prec, attn_form=attn_form, mode="paper",
+                                precision=prec, attn_form=step_form(attn_form, st), mode="paper",
                                 blend_logit_out=dp.blend_logit if blend else None, stream=stream)
         if st.conv:
             for _, _, dp in frames:

@@ -272,7 +272,7 @@ class GpuExecutor(Executor):
     MAX_BATCH = 64
 
     def __init__(self, scenes: Dict[int, synth.ServeScene], resident: Dict[int, tuple],
-                 model: synth.ServeModel, *, n_streams: int = 4, attn_form: str = "folded",
+                 model: synth.ServeModel, *, n_streams: int = 4, attn_form: str = "auto",
                  device: int = 0, keep_frames: bool = False):
         import torch
         self.torch = torch

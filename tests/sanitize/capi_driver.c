@@ -143,9 +143,18 @@ int main(void) {
     qk_ldm cout_ = {P(0x380000), NULL, NULL, L / 2, H, W, 32, QK_BF16};
     expect("collapse ok", qk_layer_collapse_check(&vin, P(0x500000), P(0x510000), &cout_), QK_OK);
     qk_feature_map_inout fio[V];
-    for (int m = 0; m < V; ++m) { fio[m].data = P(0x100000 + 0x10000 * m); fio[m].H = H; fio[m].W = W; }
+    for (int m = 0; m < V; ++m) {
+        fio[m].data = P(0x100000 + 0x10000 * m); fio[m].H = H; fio[m].W = W; fio[m].src = NULL;
+    }
     expect("ray ok", qk_ray_encoding_check(V, cams, &nov, 0.5f, 20.0f, P(0x500000), 32, QK_BF16, 3, 5,
                                            fio), QK_OK);
+    fio[1].src = P(0x900000);
+    expect("ray src ok", qk_ray_encoding_check(V, cams, &nov, 0.5f, 20.0f, P(0x500000), 32, QK_BF16,
+                                               3, 5, fio), QK_OK);
+    fio[1].src = fio[0].data;
+    expect("ray src overlap", qk_ray_encoding_check(V, cams, &nov, 0.5f, 20.0f, P(0x500000), 32,
+                                                    QK_BF16, 3, 5, fio), QK_EINVAL);
+    fio[1].src = NULL;
     expect("ray grid", qk_ray_encoding_check(V, cams, &nov, 0.5f, 20.0f, P(0x500000), 32, QK_BF16, 0,
                                              5, fio), QK_ESHAPE);
     expect("upsample ok", qk_upsample2x_check(P(0x100000), P(0x200000), 2, H, W, 8, QK_F32), QK_OK);

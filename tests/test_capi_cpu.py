@@ -458,6 +458,26 @@ def test_ray_encoding_checks():
     assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, low_hw=(-1, -1)) == lib.QK_ESHAPE
     assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
                                   low_hw=(1 << 14, 1 << 14)) == lib.QK_EUNSUPPORTED
+    # out of place: a source map is read, the encoded map written to data;
+    # it may be the map itself, or any buffer that overlaps no map written
+    srcs = [_FakeT((9, 13, 16), 0x1000000 * (m + 1)) for m in range(3)]
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, src=srcs) == lib.QK_OK
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
+                                  src=[feats[0], None, srcs[2]]) == lib.QK_OK
+    # two sources may share memory (both only read)
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
+                                  src=[srcs[0], srcs[0], srcs[0]]) == lib.QK_OK
+    for bad in ([srcs[0], feats[0], srcs[2]],                        # another view's map
+                [_FakeT((9, 13, 16), 0x100000 + 64), None, None]):   # its own map, shifted
+        assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, src=bad) == lib.QK_EINVAL
+        assert "source map" in lib.load().qk_last_error().decode()
+    assert lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
+                                  src=[_FakeT((9, 13, 16), 0x1000008), None, None]) == lib.QK_EINVAL
+    with pytest.raises(ValueError):
+        lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats, src=srcs[:2])
+    with pytest.raises(ValueError):
+        lib.ray_encoding_check(cams, nov, 0.5, 20.0, Wr, feats,
+                               src=[_FakeT((9, 12, 16), 0x1000000), None, None])
 
 
 def test_upsample2x_and_decode_checks():

@@ -70,7 +70,7 @@ def check_chain_stepwise(ch, dc, attn, form, rows_of, tag, first_input=None, com
     are checked like any step's)."""
     tol = TOL[form]
     band = 1.0 / ch.near - 1.0 / ch.far
-    af = 1 if attn == "folded" else 0
+
     for i, st in enumerate(ch.steps):
         rows = rows_of(st)
         label = f"{tag} {attn} step {i} ({st.L}x{st.H}x{st.W}, {st.heads} heads)"
@@ -108,7 +108,8 @@ def check_chain_stepwise(ch, dc, attn, form, rows_of, tag, first_input=None, com
         # and alpha' are the decode of its CNN block's output, checked below)
         last = i == len(ch.steps) - 1
         ref = oracle.update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, ch.level(i), F=F_in,
-                                 depth=d_in, alpha=a_in, rows=rows, mode=1, attn_form=af)
+                                 depth=d_in, alpha=a_in, rows=rows, mode=1,
+                                 attn_form=1 if runner.step_form(attn, st) == "folded" else 0)
         skip = last and st.conv and composite
         _check_step(label, _np(dc.F_out[i])[:, rows],
                     None if skip else _np(dc.depth_out[i])[:, rows],
@@ -174,7 +175,7 @@ BF16_CHAIN_RGB = 3.5e-2
 BF16_CHAIN_PSNR = 45.0
 
 
-@pytest.mark.parametrize("attn", ["folded", "standard"])
+@pytest.mark.parametrize("attn", ["folded", "standard", "auto"])
 @pytest.mark.parametrize("form", ["bf16", "fp32"])
 def test_small_chain(ctx, form, attn):
     steps = SMALL[form]

@@ -112,7 +112,8 @@ def check_pipeline_stepwise(pl, dp, attn, form, rows_of, out_rows, tag):
     lvl = _chain_with_maps(ch, enc).level(i)
     ref = oracle.update_fuse(ch.in_cams, ch.novel, ch.near, ch.far, lvl, F=F_in,
                              depth=_np(dc.depth[i]), alpha=_np(dc.alpha[i]), rows=rows, mode=1,
-                             attn_form=1 if attn == "folded" else 0, want_logits=True)
+                             attn_form=1 if runner.step_form(attn, st) == "folded" else 0,
+                             want_logits=True)
     got = _np(dp.blend_logit)[:, rows]
     a = ref["blend_logit"]
     b = (3e-2 + 1e-2 * np.abs(a)) if form == "bf16" else 1e-4 * (1 + np.abs(a))
@@ -160,7 +161,7 @@ BF16_FRAME_RGB = 0.12
 BF16_FRAME_PSNR = 45.0
 
 
-@pytest.mark.parametrize("attn", ["folded", "standard"])
+@pytest.mark.parametrize("attn", ["folded", "standard", "auto"])
 @pytest.mark.parametrize("form", ["bf16", "fp32"])
 def test_small_pipeline(ctx, form, attn):
     pl = synth.make_pipeline(V=3, steps=SMALL_STEPS[form], feat_hw=((6, 10), (12, 20), (24, 40)),

@@ -168,6 +168,33 @@ def test_in_place_twice_and_nothing_else_written(ctx):
         assert torch.all(b[h * wd * 32:] == 7.25).item()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("low_hw", [None, (9, 16)], ids=["per-pixel", "low-9x16"])
+def test_out_of_place_equals_in_place(ctx, low_hw, dtype):
+    """Reading each map from a source and writing the encoded map elsewhere
+    gives the in-place result bit for bit and leaves the sources as they
+    were; a source that is the map itself is the in-place form."""
+    rs = synth.make_ray(V=3, W=64, H=36, levels=((1, 16),), seed=8)
+    w = torch.from_numpy(rs.Wr[0]).cuda()
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(4)
+    hws = [(36, 64), (17, 31), (9, 64)]
+    src = [torch.randn((h, wd, 16), generator=g, device="cuda").to(tdt) for h, wd in hws]
+    keep = [t.clone() for t in src]
+    inplace = [t.clone() for t in src]
+    lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, inplace, low_hw=low_hw)
+    out = [torch.full_like(t, 3.0) for t in src]
+    lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, out, low_hw=low_hw, src=src)
+    same = [t.clone() for t in src]
+    lib.ray_encoding(ctx, rs.in_cams, rs.novel, rs.near, rs.far, w, same, low_hw=low_hw,
+                     src=[same[0], None, same[2]])
+    torch.cuda.synchronize()
+    for m in range(3):
+        assert torch.equal(out[m], inplace[m]), m
+        assert torch.equal(same[m], inplace[m]), m
+        assert torch.equal(src[m], keep[m]), m
+
+
 @pytest.mark.parametrize("low_hw", [None, (135, 240)], ids=["per-pixel", "low-135x240"])
 def test_full_size_pyramid(ctx, low_hw):
     """The 1080p, V = 8 rig: all four pyramid levels (C = 64, 32, 16, 8 on

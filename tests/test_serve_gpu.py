@@ -82,7 +82,7 @@ def test_served_1080p_frame_matches_oracle(setup):
                           feats, None, model.weights, model.collapse_w, model.conv_w, "bf16")
     pl = synth.PipelineScene(ch, model.f0, model.Wr, model.low_hw,
                              [im.cpu().numpy() for im in images], (H, W))
-    check_pipeline_stepwise(pl, job.frame, "folded", "bf16",
+    check_pipeline_stepwise(pl, job.frame, "auto", "bf16",
                             lambda st: sorted({0, st.H // 2, st.H - 1}),
                             sorted({0, H // 3, H - 1}), f"served {W}x{H} V{sc.V}")
 
