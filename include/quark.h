@@ -464,8 +464,12 @@ QK_API qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const 
  *   2. over composite of the projected planes, front to back (layer 0
  *      nearest the novel camera): rgb += T P(sigma) P(a),
  *      T *= 1 - P(sigma); acc = 1 - T.
- * Float32 arithmetic (reprojection in double); the splat uses float atomics,
- * so the order of the additions into a view pixel, and its last bits, vary
+ * Float32 arithmetic (reprojection in double).  Up to 128 layers (and view
+ * sides below 65535, at most 2^31 layer-pixel-views) the sums of step 1 are
+ * taken in 64-bit fixed point (each contribution w * (a, sigma), a float32
+ * product, rounded to the nearest 2^-32) and the result is bitwise
+ * reproducible; beyond that the planes are summed with float atomics, so
+ * the order of the additions into a view pixel, and its last bits, vary
  * from run to run.
  *
  *   V          number of views, 1..16; in_cams host [V]
@@ -474,8 +478,11 @@ QK_API qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const 
  *              depth > 0
  *   views      host [V]: device rgb [Hm][Wm][3] float32 and acc [Hm][Wm]
  *              float32 or NULL, with the view's grid
- * Workspace: the projected planes, sum over views of L Hm Wm 4 floats, in
- * the context (grown on demand like the others).
+ * Workspace, in the context (grown on demand like the others): up to 128
+ * layers, one 32-byte record per layer-pixel-view whose footprint meets the
+ * view (at most 8 V L H W floats) plus 3 counters per tile of 32 x th view
+ * pixels (th = 16 for L <= 4, halved as L doubles); beyond, the projected
+ * planes, sum over views of L Hm Wm 4 floats.
  * Errors (nothing enqueued): QK_EINVAL (NULL or misaligned buffer, bad
  * camera), QK_ESHAPE (non-positive dims, V out of range), QK_EUNSUPPORTED
  * (an LDM or a workspace of 2^31 elements or more). */

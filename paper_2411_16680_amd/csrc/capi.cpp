@@ -1204,10 +1204,46 @@ qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
     if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    st = grow(&ctx->vws, &ctx->vws_elems, (size_t)total, stream);
-    if (st != QK_OK) return st;
     qk::ViewsParams p;
     std::memset(&p, 0, sizeof(p));
+    // The binned form holds all layers of a tile in 64 KiB of LDS (tiles of
+    // 32 x th pixels, 32 bytes per pixel and layer: th = 16 for L <= 4,
+    // halved as L doubles) and indexes records and view coordinates in 32
+    // and 16 bits; other calls take the planes form.
+    const int64_t nrec = (int64_t)V * ldm->L * ldm->H * ldm->W;
+    bool small_views = true;
+    for (int m = 0; m < V; ++m) small_views = small_views && views[m].W < 65535 && views[m].H < 65535;
+    p.binned = ldm->L <= 128 && nrec < ((int64_t)1 << 31) && small_views;
+    size_t ws_floats = (size_t)total;
+    size_t rec_off = 0;
+    if (p.binned) {
+        p.tw = 32;
+        p.th = 32;
+        while (p.th > 1 && (int64_t)ldm->L * p.th * p.tw * 32 > 65536) p.th /= 2;
+        int32_t tiles = 0;
+        for (int m = 0; m < V; ++m) {
+            p.ntx[m] = (views[m].W + p.tw - 1) / p.tw;
+            p.nty[m] = (views[m].H + p.th - 1) / p.th;
+            p.tbase[m] = tiles;
+            tiles += p.ntx[m] * p.nty[m];
+        }
+        p.tbase[V] = tiles;
+        p.nbins = 4 * tiles;
+        // count [nbins], start [nbins + 1, padded to nbins + 4], cursor
+        // [nbins], then the records (8 floats each); nbins is a multiple of
+        // 4, so every array starts on a 16-byte boundary
+        rec_off = (size_t)3 * p.nbins + 4;
+        ws_floats = rec_off + (size_t)8 * (size_t)nrec;
+    }
+    st = grow(&ctx->vws, &ctx->vws_elems, ws_floats, stream);
+    if (st != QK_OK) return st;
+    if (p.binned) {
+        uint32_t *u = reinterpret_cast<uint32_t *>(ctx->vws);
+        p.count = u;
+        p.start = u + p.nbins;
+        p.cursor = u + 2 * (size_t)p.nbins + 4;
+        p.rec = ctx->vws + rec_off;
+    }
     int64_t base = 0, maxpix = 0;
     for (int m = 0; m < V; ++m) {
         compose_table(novel, ldm->W, ldm->H, &in_cams[m], views[m].W, views[m].H, p.cam[m]);

@@ -188,6 +188,18 @@ struct ViewsParams {
     int32_t V, L, H, W;
     int64_t N;                      // L * H * W
     int64_t max_view_pixels;
+    // binned form (no projected layers in memory): tiles of tw x th view
+    // pixels, four bins per tile (the record classes), a bin's records
+    // contiguous in rec
+    int32_t binned;
+    int32_t tw, th;
+    int32_t ntx[kMaxViews], nty[kMaxViews];
+    int32_t tbase[kMaxViews + 1];   // first tile of view m in the list of all views' tiles
+    int32_t nbins;                  // 4 x tiles
+    uint32_t *count;                // [nbins] records per bin
+    uint32_t *start;                // [nbins + 1] exclusive prefix sums of count
+    uint32_t *cursor;               // [nbins] next free record of a bin
+    float *rec;                     // [V N][8]: fx, fy, corner, layer | r, g, b, alpha
 };
 
 }  // namespace qk

@@ -7,8 +7,10 @@ Bar, per view pixel: |error| <= 1e-4 + 1e-5 M, M = sum over layers of
 -- the magnitudes the composite adds up.  The splat is unnormalised, so
 where several layer-pixels crowd into one view pixel P(sigma) exceeds 1, T
 changes sign and grows, and the float32 rounding of the weights, payloads
-and atomic sums (each ~1e-7 relative, a few dozen per pixel) scales with M
-rather than with the result; positions are computed in double."""
+and sums (each ~1e-7 relative, a few dozen per pixel; the binned form's
+fixed-point rounding is 2^-33 per contribution) scales with M rather than
+with the result; positions are computed in double.  The binned form (up to
+128 layers) sums in fixed point, so two calls agree bit for bit."""
 
 import sys
 
@@ -95,6 +97,13 @@ CASES = {
     "one-view": dict(V=1, W=48, H=32, L=3, seed=12),
     "single-pixel-ldm": dict(V=3, W=1, H=1, L=2, view_hw=(7, 9), seed=13),
     "smooth-depth": dict(V=4, W=96, H=54, L=4, depth_mode="smooth", seed=14),
+    # the binned form's tiles: views a whole number of 32 x 32 tiles, tile
+    # heights 16 (L = 5) and 2 (L = 40); more than 128 layers take the
+    # planes form
+    "whole-tiles-64x64": dict(V=3, W=64, H=64, L=4, seed=18),
+    "tiles-L5": dict(V=3, W=70, H=45, L=5, seed=19),
+    "tiles-L40": dict(V=2, W=40, H=24, L=40, seed=20),
+    "planes-form-L130": dict(V=2, W=6, H=4, L=130, view_hw=(9, 11), seed=22),
 }
 
 
@@ -129,3 +138,23 @@ def test_workspace_reuse_smaller_then_larger(ctx):
     _compare("reuse-big", ctx, big)
     _compare("reuse-small", ctx, small)
     _compare("reuse-big-again", ctx, big)
+
+
+def test_forms_alternate_on_one_context(ctx):
+    """The planes form (more than 128 layers) and the binned form share the
+    context's workspace: each call lays it out afresh."""
+    planes = synth.make_views(V=2, W=6, H=4, L=130, view_hw=(9, 11), seed=23)
+    binned = synth.make_views(V=3, W=50, H=30, L=3, seed=24)
+    _compare("alt-binned", ctx, binned)
+    _compare("alt-planes", ctx, planes)
+    _compare("alt-binned-again", ctx, binned)
+
+
+def test_binned_form_is_reproducible(ctx):
+    """Two calls on the 1080p configuration's rig (a smaller grid) give the
+    same bits: the binned form's sums are exact fixed-point integers."""
+    vs = synth.make_views(V=4, W=480, H=270, L=4, seed=25)
+    a, aa = _gpu(ctx, vs)
+    b, bb = _gpu(ctx, vs)
+    for m in range(vs.V):
+        assert np.array_equal(a[m], b[m]) and np.array_equal(aa[m], bb[m]), m
