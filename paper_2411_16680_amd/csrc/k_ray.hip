@@ -235,12 +235,16 @@ __global__ void __launch_bounds__(256) k_ray_encoding(const RayParams p) {
     const int y = (int)(q / fw), x = (int)(q - (int64_t)y * fw);
     float e[32];
     ray_sinusoids(p, m, x, y, e);
+    // all of the pixel's channels are read before any is written: the source
+    // may be the map itself, and the compiler cannot move a load of one
+    // pointer above a store through another that may alias it
+    float a[C / 8][8];
+#pragma unroll
+    for (int c8 = 0; c8 < C / 8; ++c8) load8<BF16>(p.src[m], q * C + 8 * c8, a[c8]);
 #pragma unroll
     for (int c8 = 0; c8 < C / 8; ++c8) {
-        float a[8];
-        load8<BF16>(p.src[m], q * C + 8 * c8, a);
-        project8_w<C>(e, p, wbuf, 8 * c8, a);
-        store8<BF16>(p.feat[m], q * C + 8 * c8, a);
+        project8_w<C>(e, p, wbuf, 8 * c8, a[c8]);
+        store8<BF16>(p.feat[m], q * C + 8 * c8, a[c8]);
     }
 }
 
