@@ -57,12 +57,29 @@ def level_bytes(lvl, V: int, elem: int, composite: bool) -> int:
     return b
 
 
-def level_flops(lvl, V: int) -> int:
-    """Projection FLOPs of the standard form per level: per layer-pixel
-    2 (C d + 2 V C d + d C) (query, per-view keys and values, output)."""
+def level_flops(lvl, V: int, attn: str = "standard") -> int:
+    """Algorithmic FLOPs per level.  Standard form, per layer-pixel
+    2 (C d + 2 V C d + d C) (query, per-view keys and values, output, all
+    on MFMA).  One-to-many form (one head: d = C), per layer-pixel
+    2 (C C + C C) on MFMA (the folded query and output) plus 4 V C on the
+    vector units (each view's logit and its share of the weighted sum)."""
     N = lvl.L * lvl.H * lvl.W
     C, d = lvl.C, lvl.heads * lvl.head_dim
+    if attn == "folded":
+        h = lvl.heads
+        return 2 * N * h * (C * C + C * C) + 4 * N * V * h * lvl.Cf
     return 2 * N * (C * d + 2 * V * lvl.Cf * d + d * C)
+
+
+# The benchmark's attention: per level the faster of the two forms the
+# paper gives for the same attention (the one-to-many form of its Sec. 3.3
+# on one-head levels, the standard Q/K/V/O form on multi-head ones); every
+# level of the 1080p workload has one head.
+HEADLINE_ATTN = "auto"
+
+
+def level_form(lvl) -> str:
+    return "folded" if int(lvl.heads) == 1 else "standard"
 
 
 # ---------------------------------------------------------------------------
@@ -165,10 +182,10 @@ def accuracy_vs_oracle(ctx, oracle, scenes, rows):
     from paper_2411_16680_amd import runner
     out = {}
     refs = {}
-    for form, key, attn, prec in (("bf16", "bf16", "standard", "bf16"),
-                                  ("bf16_folded", "bf16", "folded", "bf16"),
-                                  ("fp8proj", "bf16", "standard", "bf16_fp8proj"),
-                                  ("fp32", "fp32", "standard", "fp32")):
+    for form, key, attn, prec in (("bf16", "bf16", HEADLINE_ATTN, "bf16"),
+                                  ("bf16_standard", "bf16", "standard", "bf16"),
+                                  ("fp8proj", "bf16", HEADLINE_ATTN, "bf16_fp8proj"),
+                                  ("fp32", "fp32", HEADLINE_ATTN, "fp32")):
         sc = scenes[key]
         lvl = sc.levels[-1]
         if key not in refs:
@@ -264,12 +281,12 @@ def _host_info() -> dict:
 
 # ---------------------------------------------------------------------------
 
-def profile_run(ctx, steps: int, depth_mode: str):
-    """Frames of the bf16 standard form, final renders, renders to the input
-    views, the ray-direction encoding of the pyramid, the residual CNN block
-    and the layer collapse, then a plain copy of known size, for counter
-    collection (FETCH_SIZE / WRITE_SIZE are scaled by what they read for the
-    copy)."""
+def profile_run(ctx, steps: int, depth_mode: str, attn: str = HEADLINE_ATTN):
+    """Frames of the bf16 form in attention form ``attn``, final renders,
+    renders to the input views, the ray-direction encoding of the pyramid,
+    the residual CNN block and the layer collapse, then a plain copy of
+    known size, for counter collection (FETCH_SIZE / WRITE_SIZE are scaled by
+    what they read for the copy)."""
     import torch
     from paper_2411_16680_amd import lib, runner, synth
     sc = synth.to_bf16(synth.make_inputs(3, depth_mode=depth_mode))
@@ -278,7 +295,7 @@ def profile_run(ctx, steps: int, depth_mode: str):
         dl.acc = None
     torch.cuda.synchronize()
     for s in range(steps):
-        runner.run_scene(ctx, sc, dls)
+        runner.run_scene(ctx, sc, dls, attn_form=attn)
         torch.cuda.synchronize()
         log(f"profile frame {s + 1}/{steps}")
     del dls
@@ -793,13 +810,17 @@ def main():
                          "timing")
     ap.add_argument("--profile-pipeline", action="store_true",
                     help="for rocprofv3: run --steps whole frames (ray encoding, init, five "
-                         "steps, final render; 1080p, V=8, bf16, one-to-many attention) and exit "
+                         "steps, final render; 1080p, V=8, bf16, attention per --attn) and exit "
                          "without timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--attn", default=HEADLINE_ATTN, choices=["auto", "standard", "folded"],
+                    help="attention form of the --profile-run and --profile-pipeline frames "
+                         "(default: the headline's, per level the faster form)")
     ap.add_argument("--profile-run", action="store_true",
-                    help="for rocprofv3: run --steps frames of the bf16 standard form, then a "
-                         "512 MiB device copy (counter calibration), and exit without timing")
+                    help="for rocprofv3: run --steps frames of the bf16 form (the headline's "
+                         "attention) and the other kernels, then a 512 MiB device copy (counter "
+                         "calibration), and exit without timing")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -818,7 +839,7 @@ def main():
     ctx = lib.Context(0)
 
     if args.profile_run:
-        profile_run(ctx, args.steps, args.depth_mode)
+        profile_run(ctx, args.steps, args.depth_mode, args.attn)
         return
     if args.profile_train:
         t = time_training_step(ctx, steps=args.steps, warmup=1)
@@ -837,7 +858,7 @@ def main():
         pl = synth.make_pipeline()
         dp = runner.pipeline_to_device(pl)
         for s in range(args.steps):
-            runner.run_pipeline(ctx, pl, dp, attn_form="folded")
+            runner.run_pipeline(ctx, pl, dp, attn_form=args.attn)
             torch.cuda.synchronize()
         log(f"profile frames: {args.steps} done")
         return
@@ -851,10 +872,10 @@ def main():
 
     results = {}
     dominant = 0
-    runs = (("bf16", sc16, args.steps, "standard", "bf16"),
-            ("fp32", sc32, args.fp32_steps, "standard", "fp32"),
-            ("bf16_folded", sc16, args.steps, "folded", "bf16"),
-            ("fp8proj", sc16, args.steps, "standard", "bf16_fp8proj"))
+    runs = (("bf16", sc16, args.steps, HEADLINE_ATTN, "bf16"),
+            ("fp32", sc32, args.fp32_steps, HEADLINE_ATTN, "fp32"),
+            ("bf16_standard", sc16, args.steps, "standard", "bf16"),
+            ("fp8proj", sc16, args.steps, HEADLINE_ATTN, "bf16_fp8proj"))
     for form, sc, steps, attn, prec in runs:
         dls = runner.scene_to_device(sc)
         for dl in dls:                 # the benchmark renders RGB only (no acc plane)
@@ -884,15 +905,15 @@ def main():
         torch.cuda.empty_cache()
 
     # the same frame with piecewise-smooth depths (the paper's LDMs follow
-    # surfaces), bf16 standard form
+    # surfaces), bf16, the headline's attention
     sm_sc = synth.to_bf16(synth.make_inputs(3, depth_mode="smooth" if args.depth_mode == "iid"
                                             else "iid"))
     dls = runner.scene_to_device(sm_sc)
     for dl in dls:
         dl.acc = None
-    sm_lv = per_level_ms(ctx, sm_sc, dls, "standard", "bf16")
+    sm_lv = per_level_ms(ctx, sm_sc, dls, HEADLINE_ATTN, "bf16")
     sm_t = time_frames(ctx, sm_sc, dls, max(200, min(args.steps, 500)), args.warmup,
-                       int(np.argmax(sm_lv)))
+                       int(np.argmax(sm_lv)), HEADLINE_ATTN, "bf16")
     sm_n = max(200, min(args.steps, 500))
     lvl3 = sm_sc.levels[-1]
     smooth = {"depth_mode": "smooth" if args.depth_mode == "iid" else "iid",
@@ -923,15 +944,16 @@ def main():
     bf = results["bf16"]
     ms_per_step = bf["total_ms"] / bf["steps"]
     S = sum(l.L * l.H * l.W for l in sc16.levels) * V
-    # roofline of the dominant kernel (bf16 form)
+    # roofline of the dominant kernel (bf16 form, the headline's attention)
     lvl = sc16.levels[dominant]
     comp = dominant == len(sc16.levels) - 1
+    dform = level_form(lvl)
     alg_bytes = level_bytes(lvl, V, 2, comp)
-    alg_flops = level_flops(lvl, V)
+    alg_flops = level_flops(lvl, V, dform)
     k_s = bf["kernel_ms"] / 1000.0
     intensity = alg_flops / alg_bytes
     ridge = MFMA_BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    key = f"k_update_fuse_bf16_level{dominant}"
+    key = f"k_update_fuse_bf16_{dform}_level{dominant}"
     traffic = traffic_from_profiles("k_update_fuse", key)
     if intensity < ridge:
         roof = {"bound": "hbm", "achieved": alg_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
@@ -941,7 +963,7 @@ def main():
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic
-    roof["kernel"] = f"k_update_fuse<C={lvl.C},bf16> (level {dominant}, "\
+    roof["kernel"] = f"k_update_fuse<C={lvl.C},bf16,{dform}> (level {dominant}, "\
                      f"{lvl.W}x{lvl.H} L{lvl.L})"
     roof["algorithmic_bytes_per_launch"] = alg_bytes
     roof["algorithmic_flops_per_launch"] = alg_flops
@@ -953,7 +975,7 @@ def main():
     d32 = f32["dominant"]
     l32 = sc32.levels[d32]
     b32 = level_bytes(l32, V, 4, d32 == len(sc32.levels) - 1)
-    fl32 = level_flops(l32, V)
+    fl32 = level_flops(l32, V, level_form(l32))
     k32 = f32["per_level_ms"][d32] / 1000.0
     if fl32 / b32 >= MFMA_FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
         fp32_roof = {"bound": "mfma", "achieved": fl32 / k32 / 1e12,
@@ -962,7 +984,8 @@ def main():
         fp32_roof = {"bound": "hbm", "achieved": b32 / k32 / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s"}
     fp32_roof["frac"] = fp32_roof["achieved"] / fp32_roof["peak"]
-    fp32_roof["kernel"] = f"k_update_fuse<C={l32.C},fp32> (level {d32}, {l32.W}x{l32.H} L{l32.L})"
+    fp32_roof["kernel"] = (f"k_update_fuse<C={l32.C},fp32,{level_form(l32)}> (level {d32}, "
+                           f"{l32.W}x{l32.H} L{l32.L})")
     fp32_roof["avg_launch_ms"] = f32["per_level_ms"][d32]
 
     frame_bytes = sum(level_bytes(l, V, 2, i == len(sc16.levels) - 1)
@@ -1058,10 +1081,14 @@ def main():
         "config": {
             "workload": "multi-scale 1080p Update&Fuse + composite, V=8 views, levels "
                         "240x135 L32 C64 / 480x270 L16 C32 / 960x540 L8 C16 / 1920x1080 L4 C8, "
-                        "standard Q/K/V/O attention, i.i.d. log-uniform depths" if
+                        "one head per level, i.i.d. log-uniform depths" if
                         args.depth_mode == "iid" else
                         "multi-scale 1080p Update&Fuse + composite, V=8, smooth depths",
-            "views": V, "out_res": "1920x1080", "attention": "standard",
+            "views": V, "out_res": "1920x1080",
+            "attention": "per level the faster of the paper's two forms of the same attention: "
+                         "one-to-many (Sec. 3.3) on one-head levels, standard Q/K/V/O on "
+                         "multi-head ones; here one-to-many at every level (the standard form "
+                         "is timed beside it under 'standard')",
             "depth_mode": args.depth_mode,
         },
         "p50_ms": bf["p50_ms"],
@@ -1075,13 +1102,14 @@ def main():
         "fp8proj": {"value": results["fp8proj"]["fps"], "unit": "frames/s",
                     "p50_ms": results["fp8proj"]["p50_ms"], "p99_ms": results["fp8proj"]["p99_ms"],
                     "per_level_ms": results["fp8proj"]["per_level_ms"],
-                    "note": "bf16 storage, e4m3 Q/K/V/O projection operands (scales measured on "
-                            "the device each frame), standard attention"},
-        "folded": {"value": results["bf16_folded"]["fps"], "unit": "frames/s",
-                   "p50_ms": results["bf16_folded"]["p50_ms"],
-                   "p99_ms": results["bf16_folded"]["p99_ms"],
-                   "per_level_ms": results["bf16_folded"]["per_level_ms"],
-                   "note": "one-to-many (folded) attention, bf16: the paper's optimized form"},
+                    "note": "bf16 storage, e4m3 projection operands (scales measured on the "
+                            "device each frame), the headline's attention"},
+        "standard": {"value": results["bf16_standard"]["fps"], "unit": "frames/s",
+                     "p50_ms": results["bf16_standard"]["p50_ms"],
+                     "p99_ms": results["bf16_standard"]["p99_ms"],
+                     "per_level_ms": results["bf16_standard"]["per_level_ms"],
+                     "note": "standard Q/K/V/O attention (per-sample key and value "
+                             "projections on MFMA) at every level, bf16"},
         "per_level_ms": bf["per_level_ms"],
         "heads_level1_ms": {"level": "480x270 L16 C32 V8, bf16", "ms_by_heads": heads_ms},
         "layer_pixel_views_per_s": S / (ms_per_step / 1000.0),

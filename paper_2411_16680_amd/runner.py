@@ -73,6 +73,7 @@ def run_level(ctx: lib.Context, scene, dl: DeviceLevel, *, steps: Optional[int] 
     steps = scene.steps if steps is None else steps
     composite = dl.composite if composite is None else composite
     precision = precision or ("bf16" if scene.dtype == "bf16" else "fp32")
+    attn_form = step_form(attn_form, dl)
     wts = dl.extra.get("qk_weights")
     if wts is None:                    # built once (the tensors stay in dl.weights)
         wts = dl.extra["qk_weights"] = lib.make_weights(dl.weights, heads=dl.heads)
