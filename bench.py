@@ -176,8 +176,9 @@ def _psnr(a, b) -> float:
 def accuracy_vs_oracle(ctx, oracle, scenes, rows):
     """The composited 1080p level (1920x1080, L4, C8) of each form against
     the FP64 oracle on ``rows`` of it (the oracle on the form's own inputs):
-    RGB max-abs and PSNR per form, with the stated bars (float32 1e-4;
-    bfloat16 2e-2 and 45 dB; e4m3 projections: error stated)."""
+    RGB max-abs and PSNR per form, each marked against its stated bar
+    (float32 1e-4; bfloat16 2e-2 and 45 dB, the e4m3 projection variant
+    against the bfloat16 bar)."""
     import torch
     from paper_2411_16680_amd import runner
     out = {}
@@ -196,10 +197,11 @@ def accuracy_vs_oracle(ctx, oracle, scenes, rows):
         got = dl.rgb.cpu().numpy().astype(np.float64)[rows]
         e = float(np.max(np.abs(got - refs[key])))
         q = _psnr(got, refs[key])
-        bar = {"fp32": (1e-4, None), "bf16": (2e-2, 45.0)}.get(key if form != "fp8proj" else "-")
-        ent = {"rgb_max_abs": e, "psnr_db": q}
-        if bar is not None:
-            ent["meets_bar"] = bool(e <= bar[0] and (bar[1] is None or q >= bar[1]))
+        # the stated bars: float32 1e-4; bfloat16 2e-2 and 45 dB, also for
+        # the e4m3 projection variant, whose error is reported against it
+        bar = {"fp32": (1e-4, None), "bf16": (2e-2, 45.0)}[key]
+        ent = {"rgb_max_abs": e, "psnr_db": q,
+               "meets_bar": bool(e <= bar[0] and (bar[1] is None or q >= bar[1]))}
         out[form] = ent
         del dl
     out["sample"] = f"{len(rows)} rows of the 1920x1080 level (L4, C8, V8), rows {rows}"
@@ -1103,7 +1105,8 @@ def main():
                     "p50_ms": results["fp8proj"]["p50_ms"], "p99_ms": results["fp8proj"]["p99_ms"],
                     "per_level_ms": results["fp8proj"]["per_level_ms"],
                     "note": "bf16 storage, e4m3 projection operands (scales measured on the "
-                            "device each frame), the headline's attention"},
+                            "device each frame), the headline's attention",
+                    "accuracy_vs_oracle": (cpu or {}).get("accuracy_vs_oracle", {}).get("fp8proj")},
         "standard": {"value": results["bf16_standard"]["fps"], "unit": "frames/s",
                      "p50_ms": results["bf16_standard"]["p50_ms"],
                      "p99_ms": results["bf16_standard"]["p99_ms"],
