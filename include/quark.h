@@ -121,9 +121,14 @@ typedef struct {
     int32_t width, height;
 } qk_camera;
 
+/* One view's encoded feature map.  dtype: QK_F32 under QK_PREC_FP32,
+ * QK_BF16 under the bfloat16 precisions (the LDM's dtype); C: the weights'
+ * C_feat.  A map whose dtype or C disagrees is rejected (QK_EDTYPE,
+ * QK_ESHAPE). */
 typedef struct {
-    const void *data;     /* device, [H][W][C] contiguous, dtype of the LDM */
-    int32_t H, W;
+    const void *data;     /* device, [H][W][C] contiguous */
+    qk_dtype dtype;
+    int32_t H, W, C;
 } qk_feature_map;
 
 typedef struct {
@@ -152,15 +157,20 @@ typedef struct qk_context qk_context;
 
 /* Create a context bound to HIP device `device`.  The context owns device
  * workspaces that grow on demand and live until qk_context_destroy: the
- * folded weights of the one-to-many form (2 C C_feat floats), the e4m3
- * scales (8 floats), the
- * backward pass's scratch (16 bytes per layer-pixel when d_rgb is given,
- * plus 5 KiB per backward workgroup) and the projected planes of the render
- * to input views (16 bytes per layer and view pixel).  Growing one synchronises the
- * caller's stream and allocates.  A context may be used from one host
+ * folded weights of the one-to-many form (2 C C_feat floats per request),
+ * the e4m3 scales (8 floats), the backward pass's scratch (16 bytes per
+ * layer-pixel when d_rgb is given, plus 5 KiB per backward workgroup), the
+ * render to input views' records (32 bytes per layer-pixel-view) or
+ * projected planes, the low-resolution ray encodings, the residual block's
+ * weight fragments and the batched launch's parameter table.  Growing one
+ * synchronises the caller's stream and allocates.  `workspace_bytes` caps
+ * their total (0: no cap): a call whose workspace would pass the cap
+ * returns QK_ENOMEM, the message naming the bytes it needed (launches of
+ * the same call before the failing growth may have been enqueued; they
+ * write only the context's workspace).  A context may be used from one host
  * thread at a time; calls that share it on different streams race on its
- * workspaces.  Errors: QK_EINVAL (out == NULL), QK_EHIP. */
-QK_API qk_status qk_context_create(int device, qk_context **out);
+ * workspaces.  Errors: QK_EINVAL (out == NULL, no such device), QK_EHIP. */
+QK_API qk_status qk_context_create(int device, size_t workspace_bytes, qk_context **out);
 QK_API qk_status qk_context_destroy(qk_context *ctx);
 
 /* One Update & Fuse step of one LDM level (Sec. 3.2.2 "Iterative Updates",

@@ -38,6 +38,8 @@ hipError_t scratch_address(int device, float **out);
 struct qk_context {
     int device;
     int num_cu = 0;
+    size_t ws_cap = 0;           // cap on the device workspaces' total bytes (0: none)
+    size_t ws_bytes = 0;         // their current total
     float *wfold = nullptr;      // folded-weight workspace (one-to-many form)
     size_t wfold_elems = 0;
     float *bws = nullptr;        // backward workspace: composite adjoint + partials
@@ -237,6 +239,12 @@ qk_status check_update_fuse(int32_t V, const qk_camera *in_cams, const qk_featur
             return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
         if (feats[m].H < 1 || feats[m].W < 1)
             return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
+        if (feats[m].dtype != need)
+            return fail(QK_EDTYPE, "feature map %d has dtype %d, precision %d needs %d", m,
+                        (int)feats[m].dtype, (int)precision, (int)need);
+        if (feats[m].C != w->C_feat)
+            return fail(QK_ESHAPE, "feature map %d has C = %d, the weights' C_feat is %d", m,
+                        feats[m].C, w->C_feat);
         // the gather addresses a map as one buffer with 32-bit byte offsets
         const int64_t fbytes = (int64_t)feats[m].H * feats[m].W * w->C_feat *
                                (precision == QK_PREC_FP32 ? 4 : 2);
@@ -335,6 +343,12 @@ qk_status check_backward(int32_t V, const qk_camera *in_cams, const qk_feature_m
             return fail(QK_EINVAL, "feature map %d must be 16-byte aligned", m);
         if (feats[m].H < 1 || feats[m].W < 1)
             return fail(QK_ESHAPE, "feature map %d has grid %dx%d", m, feats[m].W, feats[m].H);
+        if (feats[m].dtype != QK_F32)
+            return fail(QK_EDTYPE, "feature map %d has dtype %d; the backward takes float32", m,
+                        (int)feats[m].dtype);
+        if (feats[m].C != w->C_feat)
+            return fail(QK_ESHAPE, "feature map %d has C = %d, the weights' C_feat is %d", m,
+                        feats[m].C, w->C_feat);
         if ((int64_t)feats[m].H * feats[m].W * w->C_feat >= (int64_t)1 << 31)
             return fail(QK_EUNSUPPORTED, "feature map %d exceeds 2^31 elements", m);
     }
@@ -348,13 +362,20 @@ qk_status check_backward(int32_t V, const qk_camera *in_cams, const qk_feature_m
 
 // Grow a context buffer to at least `need` floats (synchronising the stream
 // before a buffer in use is replaced).
-qk_status grow(float **buf, size_t *have, size_t need, hipStream_t stream) {
+// Grow one of the context's device workspaces to `need` floats (never
+// shrinks), within the context's cap on their total.
+qk_status grow(qk_context *ctx, float **buf, size_t *have, size_t need, hipStream_t stream) {
     if (*have >= need) return QK_OK;
+    const size_t total = ctx->ws_bytes - *have * sizeof(float) + need * sizeof(float);
+    if (ctx->ws_cap != 0 && total > ctx->ws_cap)
+        return fail(QK_ENOMEM, "workspace of %zu bytes in all would pass the context's cap of %zu",
+                    total, ctx->ws_cap);
     if (*buf) {
         hipError_t se = hipStreamSynchronize(stream);
         if (se != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
         (void)hipFree(*buf);
         *buf = nullptr;
+        ctx->ws_bytes -= *have * sizeof(float);
         *have = 0;
     }
     if (hipMalloc(buf, need * sizeof(float)) != hipSuccess) {
@@ -362,6 +383,7 @@ qk_status grow(float **buf, size_t *have, size_t need, hipStream_t stream) {
         return fail(QK_ENOMEM, "workspace of %zu floats", need);
     }
     *have = need;
+    ctx->ws_bytes += need * sizeof(float);
     return QK_OK;
 }
 
@@ -584,7 +606,7 @@ const char *qk_last_error(void) { return g_err.c_str(); }
 
 const char *qk_version(void) { return "libquark 0.1.0 gfx950"; }
 
-qk_status qk_context_create(int device, qk_context **out) {
+qk_status qk_context_create(int device, size_t workspace_bytes, qk_context **out) {
     if (!out) return fail(QK_EINVAL, "out is NULL");
     *out = nullptr;
     int n = 0;
@@ -600,6 +622,7 @@ qk_status qk_context_create(int device, qk_context **out) {
     if (e != hipSuccess) return fail(QK_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
     qk_context *ctx = new qk_context{device};
     ctx->num_cu = cu > 0 ? cu : 1;
+    ctx->ws_cap = workspace_bytes;
     ctx->scratch = scr;
     *out = ctx;
     return QK_OK;
@@ -753,17 +776,9 @@ qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const q
                 return fail(QK_EUNSUPPORTED, "folded weights of %zu floats exceed the fixed scratch "
                             "of %d", need, qk::kScratchFold);
             wf = fixed;
-        } else if (ctx->wfold_elems < need) {
-            if (ctx->wfold) {
-                hipError_t se = hipStreamSynchronize(stream);
-                if (se != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
-                (void)hipFree(ctx->wfold);
-                ctx->wfold = nullptr;
-                ctx->wfold_elems = 0;
-            }
-            if (hipMalloc(&ctx->wfold, need * sizeof(float)) != hipSuccess)
-                return fail(QK_ENOMEM, "workspace of %zu floats", need);
-            ctx->wfold_elems = need;
+        } else {
+            st = grow(ctx, &ctx->wfold, &ctx->wfold_elems, need, stream);
+            if (st != QK_OK) return st;
             wf = ctx->wfold;
         }
         qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per,
@@ -777,7 +792,7 @@ qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const q
     if (precision == QK_PREC_BF16_FP8PROJ) {
         float *f8 = fixed != nullptr ? fixed + qk::kScratchFold : nullptr;
         if (f8 == nullptr) {
-            st = grow(&ctx->f8, &ctx->f8_elems, 8, stream);
+            st = grow(ctx, &ctx->f8, &ctx->f8_elems, 8, stream);
             if (st != QK_OK) return st;
             f8 = ctx->f8;
         }
@@ -901,7 +916,7 @@ qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
     if (fold) {
         // each request's folded weights in its own slice of the workspace
         const size_t per = (size_t)w0->heads * w0->C * w0->C_feat;
-        st = grow(&ctx->wfold, &ctx->wfold_elems, 2 * per * (size_t)n_req, stream);
+        st = grow(ctx, &ctx->wfold, &ctx->wfold_elems, 2 * per * (size_t)n_req, stream);
         if (st != QK_OK) return st;
         for (int r = 0; r < n_req; ++r) {
             const qk_weights *w = reqs[r].weights;
@@ -917,7 +932,7 @@ qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
     // the requests' parameters to the device: pinned staging, reused once
     // the previous call's copy has completed
     const size_t bytes = sizeof(qk::UFParams) * (size_t)n_req;
-    st = grow(&ctx->bdesc, &ctx->bdesc_elems, (bytes + 3) / 4, stream);
+    st = grow(ctx, &ctx->bdesc, &ctx->bdesc_elems, (bytes + 3) / 4, stream);
     if (st != QK_OK) return st;
     hipError_t e;
     if (ctx->bevent == nullptr) {
@@ -1095,7 +1110,7 @@ qk_status qk_update_fuse_backward(qk_context *ctx, void *hip_stream, int32_t V,
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     const size_t n_comp = d_rgb ? 4 * (size_t)p.N : 0;
     const size_t n_part = (size_t)p.blocks * qk::kGradTiles * qk::kGradTileElems;
-    st = grow(&ctx->bws, &ctx->bws_elems, n_comp + n_part, stream);
+    st = grow(ctx, &ctx->bws, &ctx->bws_elems, n_comp + n_part, stream);
     if (st != QK_OK) return st;
     p.partials = ctx->bws;
     p.comp = d_rgb ? ctx->bws + n_part : nullptr;
@@ -1235,7 +1250,7 @@ qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
         rec_off = (size_t)3 * p.nbins + 4;
         ws_floats = rec_off + (size_t)8 * (size_t)nrec;
     }
-    st = grow(&ctx->vws, &ctx->vws_elems, ws_floats, stream);
+    st = grow(ctx, &ctx->vws, &ctx->vws_elems, ws_floats, stream);
     if (st != QK_OK) return st;
     if (p.binned) {
         uint32_t *u = reinterpret_cast<uint32_t *>(ctx->vws);
@@ -1287,7 +1302,7 @@ qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *in, 
     if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    st = grow(&ctx->cfrag, &ctx->cfrag_elems, 2 * 9 * 2 * 64 * 4, stream);
+    st = grow(ctx, &ctx->cfrag, &ctx->cfrag_elems, 2 * 9 * 2 * 64 * 4, stream);
     if (st != QK_OK) return st;
     qk::ConvParams p;
     std::memset(&p, 0, sizeof(p));
@@ -1352,7 +1367,7 @@ qk_status qk_ray_encoding(qk_context *ctx, void *hip_stream, int32_t V, const qk
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (low_H > 0) {
-        st = grow(&ctx->rws, &ctx->rws_elems, (size_t)V * low_H * low_W * C, stream);
+        st = grow(ctx, &ctx->rws, &ctx->rws_elems, (size_t)V * low_H * low_W * C, stream);
         if (st != QK_OK) return st;
     }
     qk::RayParams p;

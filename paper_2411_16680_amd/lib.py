@@ -50,7 +50,8 @@ class qk_camera(ctypes.Structure):
 
 
 class qk_feature_map(ctypes.Structure):
-    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("C", ctypes.c_int32)]
 
 
 class qk_feature_map_inout(ctypes.Structure):
@@ -121,7 +122,7 @@ def load() -> ctypes.CDLL:
     L.qk_last_error.restype = ctypes.c_char_p
     L.qk_version.restype = ctypes.c_char_p
     P = ctypes.POINTER
-    L.qk_context_create.argtypes = [ctypes.c_int, P(ctypes.c_void_p)]
+    L.qk_context_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(ctypes.c_void_p)]
     L.qk_context_destroy.argtypes = [ctypes.c_void_p]
     uf_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
                ctypes.c_float, P(qk_weights), ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -221,6 +222,14 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else int(t.data_ptr())
 
 
+def _fmap(f) -> "qk_feature_map":
+    """One view's feature map [H][W][C] (its dtype and C as the tensor has
+    them; the library checks them against the call's precision and
+    weights)."""
+    return qk_feature_map(_ptr(f), _dtype_code(f), int(f.shape[0]), int(f.shape[1]),
+                          int(f.shape[2]) if len(f.shape) > 2 else 0)
+
+
 def _dtype_code(t) -> int:
     import torch
     if t.dtype == torch.bfloat16:
@@ -260,10 +269,11 @@ def _stream_handle(stream) -> Optional[int]:
 class Context:
     """A libquark context bound to one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
+        """workspace_bytes: cap on the context's device workspaces (0: none)."""
         self._lib = load()
         h = ctypes.c_void_p()
-        _check(self._lib.qk_context_create(int(device), ctypes.byref(h)))
+        _check(self._lib.qk_context_create(int(device), int(workspace_bytes), ctypes.byref(h)))
         self.handle = h
         self.device = device
 
@@ -283,7 +293,7 @@ def _uf_args(in_cams, feats, novel, near, far, weights, precision, attn_form, mo
              ldm_out, rgb_out, acc_out, blend_out=None):
     V = len(in_cams)
     cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
-    fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]), int(f.shape[1]))
+    fm = (qk_feature_map * V)(*[_fmap(f)
                                  for f in feats])
     nov = make_camera(novel)
     wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
@@ -341,8 +351,7 @@ class Request:
                  mode="residual", rgb_out=None, acc_out=None, blend_logit_out=None):
         V = len(in_cams)
         self.cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
-        self.fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]),
-                                                         int(f.shape[1])) for f in feats])
+        self.fm = (qk_feature_map * V)(*[_fmap(f) for f in feats])
         self.nov = make_camera(novel)
         self.wts = weights if isinstance(weights, qk_weights) else make_weights(weights)
         self.lin = ldm_in if isinstance(ldm_in, qk_ldm) else make_ldm(*ldm_in)
@@ -385,7 +394,7 @@ def _bwd_args(in_cams, feats, novel, near, far, weights, mode, ldm_in, ldm_out, 
               d_in, d_feats, d_weights):
     V = len(in_cams)
     cams = (qk_camera * V)(*[make_camera(c) for c in in_cams])
-    fm = (qk_feature_map * V)(*[qk_feature_map(_ptr(f), int(f.shape[0]), int(f.shape[1]))
+    fm = (qk_feature_map * V)(*[_fmap(f)
                                  for f in feats])
     nov = make_camera(novel)
     wts = weights if isinstance(weights, qk_weights) else make_weights(weights)

@@ -35,8 +35,10 @@ int main(void) {
     for (int m = 0; m < V; ++m) {
         camera(&cams[m], 0.1 * m, W, H);
         fm[m].data = P(0x100000 + 0x10000 * m);
+        fm[m].dtype = QK_BF16;
         fm[m].H = H;
         fm[m].W = W;
+        fm[m].C = C;
     }
     camera(&nov, 0.05, W, H);
     qk_weights w = {P(0x600000), P(0x610000), P(0x620000), P(0x630000), P(0x640000),
@@ -48,6 +50,16 @@ int main(void) {
     expect("update_fuse ok", qk_update_fuse_check(V, cams, fm, &nov, 0.5f, 20.0f, &w, QK_PREC_BF16,
                                                    QK_ATTN_STANDARD, QK_UPDATE_RESIDUAL, &in, &out,
                                                    rgb, acc, bl), QK_OK);
+    fm[1].dtype = QK_F32;
+    expect("update_fuse map dtype", qk_update_fuse_check(V, cams, fm, &nov, 0.5f, 20.0f, &w, QK_PREC_BF16,
+                                                   QK_ATTN_STANDARD, QK_UPDATE_RESIDUAL, &in, &out,
+                                                   rgb, acc, bl), QK_EDTYPE);
+    fm[1].dtype = QK_BF16;
+    fm[1].C = 16;
+    expect("update_fuse map C", qk_update_fuse_check(V, cams, fm, &nov, 0.5f, 20.0f, &w, QK_PREC_BF16,
+                                                   QK_ATTN_STANDARD, QK_UPDATE_RESIDUAL, &in, &out,
+                                                   rgb, acc, bl), QK_ESHAPE);
+    fm[1].C = C;
     expect("update_fuse dtype", qk_update_fuse_check(V, cams, fm, &nov, 0.5f, 20.0f, &w, QK_PREC_FP32,
                                                       QK_ATTN_STANDARD, QK_UPDATE_RESIDUAL, &in,
                                                       &out, rgb, acc, NULL), QK_EDTYPE);
@@ -99,16 +111,22 @@ int main(void) {
     /* backward: float32, one head of 16 */
     qk_weights w16 = {P(0x600000), P(0x610000), P(0x620000), P(0x630000), P(0x640000),
                       P(0x650000), P(0x660000), 16, 16, 1, 16};
+    qk_feature_map fm32[V];
+    for (int m = 0; m < V; ++m) {
+        fm32[m] = fm[m];
+        fm32[m].dtype = QK_F32;
+        fm32[m].C = 16;
+    }
     qk_ldm in32 = {P(0x300000), P(0x400000), P(0x500000), L, H, W, 16, QK_F32};
     qk_ldm out32 = {P(0x310000), P(0x410000), P(0x510000), L, H, W, 16, QK_F32};
     qk_ldm din = {P(0x320000), P(0x420000), P(0x520000), L, H, W, 16, QK_F32};
     float *dfe[V] = {P(0x800000), P(0x810000), P(0x820000)};
     qk_weight_grads dw = {P(0x900000), P(0x910000), P(0x920000), P(0x930000), P(0x940000),
                           P(0x950000), P(0x960000)};
-    expect("backward ok", qk_update_fuse_backward_check(V, cams, fm, &nov, 0.5f, 20.0f, &w16,
+    expect("backward ok", qk_update_fuse_backward_check(V, cams, fm32, &nov, 0.5f, 20.0f, &w16,
                                                         QK_UPDATE_RESIDUAL, &in32, &out32, rgb,
                                                         NULL, &din, dfe, &dw), QK_OK);
-    expect("backward width", qk_update_fuse_backward_check(V, cams, fm, &nov, 0.5f, 20.0f, &w,
+    expect("backward width", qk_update_fuse_backward_check(V, cams, fm32, &nov, 0.5f, 20.0f, &w,
                                                            QK_UPDATE_RESIDUAL, &in, &out, rgb,
                                                            NULL, &din, dfe, &dw),
            QK_EDTYPE);
@@ -173,9 +191,9 @@ int main(void) {
 
     /* without a GPU, creating a context reports an error */
     qk_context *ctx = NULL;
-    qk_status st = qk_context_create(0, &ctx);
+    qk_status st = qk_context_create(0, 0, &ctx);
     if (st == QK_OK) qk_context_destroy(ctx);
-    expect("context (NULL out)", qk_context_create(0, NULL), QK_EINVAL);
+    expect("context (NULL out)", qk_context_create(0, 0, NULL), QK_EINVAL);
     printf("%s: %d failures (%s)\n", qk_version(), fails, st == QK_OK ? "a device" : "no device");
     return fails ? 1 : 0;
 }

@@ -102,6 +102,27 @@ def _check(sc, feats, wts, ldm, **kw):
     return lib.update_fuse_check(sc.in_cams, feats, sc.novel, sc.near, sc.far, wts, ldm, ldm, **kw)
 
 
+def test_feature_maps_carry_dtype_and_channels():
+    """Each map states its dtype and C; one that disagrees with the
+    precision's storage type or the weights' C_feat is rejected before any
+    launch."""
+    import torch
+    sc, feats, wts, ldm = _args(C=16, dtype="bf16")
+    assert _check(sc, feats, wts, ldm, precision="bf16") == lib.QK_OK
+    wrong = list(feats)
+    wrong[1] = _FakeT((12, 20, 16), 0x210000, torch.float32)
+    assert _check(sc, wrong, wts, ldm, precision="bf16") == lib.QK_EDTYPE
+    assert "feature map 1" in lib.load().qk_last_error().decode()
+    wrong[1] = _FakeT((12, 20, 8), 0x210000, torch.bfloat16)
+    assert _check(sc, wrong, wts, ldm, precision="bf16") == lib.QK_ESHAPE
+    assert "C_feat" in lib.load().qk_last_error().decode()
+    # float32 maps under a bfloat16 precision, and the reverse
+    sc, feats, wts, ldm = _args(C=16)
+    assert _check(sc, feats, wts, ldm) == lib.QK_OK
+    bf = [_FakeT((12, 20, 16), 0x200000 + 0x10000 * i, torch.bfloat16) for i in range(3)]
+    assert _check(sc, bf, wts, ldm) == lib.QK_EDTYPE
+
+
 def test_valid_arguments_pass():
     for C in (8, 16, 32, 64):
         sc, feats, wts, ldm = _args(C=C)
@@ -220,7 +241,7 @@ def test_context_create_without_gpu_reports_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
-    st = lib.load().qk_context_create(0, ctypes.byref(h))
+    st = lib.load().qk_context_create(0, 0, ctypes.byref(h))
     assert st in (lib.QK_EHIP, lib.QK_EINVAL)
     with pytest.raises(lib.QuarkError):
         lib.Context(0)

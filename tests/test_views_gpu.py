@@ -158,3 +158,23 @@ def test_binned_form_is_reproducible(ctx):
     b, bb = _gpu(ctx, vs)
     for m in range(vs.V):
         assert np.array_equal(a[m], b[m]) and np.array_equal(aa[m], bb[m]), m
+
+
+def test_workspace_cap():
+    """A context created with a workspace cap serves calls whose workspace
+    fits and rejects, before any launch, a call that would grow it past the
+    cap; the rejected call's outputs stay untouched."""
+    capped = lib.Context(0, workspace_bytes=1 << 20)
+    small = synth.make_views(V=2, W=16, H=8, L=2, seed=26)
+    _compare("capped-small", capped, small)
+    big = synth.make_views(V=2, W=96, H=64, L=4, seed=27)      # ~400 KB of records per view
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    rgbs = [torch.full((h, w, 3), 7.0, device="cuda") for h, w in big.view_hw]
+    with pytest.raises(lib.QuarkError) as e:
+        lib.render_to_views(capped, big.in_cams, big.novel, dev(big.depth), dev(big.alpha),
+                            dev(big.color), rgbs)
+    assert e.value.status == lib.QK_ENOMEM and "cap" in str(e.value)
+    torch.cuda.synchronize()
+    assert all(bool(torch.all(r == 7.0)) for r in rgbs)
+    # the same context still serves what fits
+    _compare("capped-small-again", capped, small)
