@@ -797,9 +797,9 @@ def run_serving(n_requests: int = 2000, rate: float = 60.0, n_scenes: int = 16,
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--fp32-steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--fp32-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth-mode", default="iid", choices=["iid", "smooth"])
     ap.add_argument("--no-train", action="store_true", help="skip the forward+adjoint timing")
