@@ -7,9 +7,12 @@
 //
 // One thread per output pixel, 16 x 16 pixel tiles (a wave covers 16 x 4), so
 // the neighbouring threads that share low-resolution logit taps and, at
-// similar depths, image taps sit in the same wave.  The per-view softmax of
-// the blend logits runs online (running maximum, rescaled sums), so neither
-// the weights nor the per-view samples are stored.
+// similar depths, image taps sit in the same wave.  With V a multiple of 4
+// (template NV4 = V / 4) each layer first reads the four taps' V blend logits
+// as float4 vectors, upsamples all of them and takes their maximum, so the
+// per-view loop only exponentiates; other view counts run the softmax online
+// (running maximum, rescaled sums).  Neither the weights nor the per-view
+// samples are stored.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -43,6 +46,7 @@ __device__ inline float chan(unsigned t, int c) {
 
 __device__ inline float sigmoid_(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
+template <int NV4>
 __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
     // XCD-aware tile order: workgroups are dispatched round-robin over the
     // 8 XCDs, so workgroup i is given tile (i % 8) * per + i / 8 and each XCD
@@ -94,19 +98,9 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
         const float *S = p.sigma_logit + li * hw;
         const float alpha = sigmoid_(lerp_f(S[t00], S[t10], S[t01], S[t11]));
 
-        // blend: online softmax over the views of the upsampled logits
-        const float *B = p.blend_logit + li * hw * V;
-        float mx = -3.0e38f, z = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-        for (int m = 0; m < V; ++m) {
-            const float xb = lerp_f(B[t00 * V + m], B[t10 * V + m], B[t01 * V + m], B[t11 * V + m]);
-            if (xb > mx) {                           // move the reference
-                const float r = __expf(mx - xb);
-                z *= r; c0 *= r; c1 *= r; c2 *= r;
-                mx = xb;
-            }
-            const float e = __expf(xb - mx);
-
-            // back-projection of image m through this depth
+        // one view's image, back-projected through this layer's depth and
+        // sampled bilinearly (texels 0..255)
+        auto sample_view = [&](int m, float &s0, float &s1, float &s2) {
             const double *A = p.cam[m];
             const double pz = fma(A[6], u, fma(A[7], v, fma(A[11], disp, A[8])));
             const double qx = fma(A[0], u, fma(A[1], v, fma(A[9], disp, A[2])));
@@ -134,13 +128,65 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
             const unsigned a10 = load_texel(rs, (vx1 && vy0) ? o + 4 : kTapOOB);
             const unsigned a01 = load_texel(rs, (vx0 && vy1) ? o + 4 * iw : kTapOOB);
             const unsigned a11 = load_texel(rs, (vx1 && vy1) ? o + 4 * iw + 4 : kTapOOB);
-            const float s0 = w00 * chan(a00, 0) + w10 * chan(a10, 0) + w01 * chan(a01, 0) + w11 * chan(a11, 0);
-            const float s1 = w00 * chan(a00, 1) + w10 * chan(a10, 1) + w01 * chan(a01, 1) + w11 * chan(a11, 1);
-            const float s2 = w00 * chan(a00, 2) + w10 * chan(a10, 2) + w01 * chan(a01, 2) + w11 * chan(a11, 2);
-            z += e;
-            c0 = fmaf(e, s0, c0);
-            c1 = fmaf(e, s1, c1);
-            c2 = fmaf(e, s2, c2);
+            s0 = w00 * chan(a00, 0) + w10 * chan(a10, 0) + w01 * chan(a01, 0) + w11 * chan(a11, 0);
+            s1 = w00 * chan(a00, 1) + w10 * chan(a10, 1) + w01 * chan(a01, 1) + w11 * chan(a11, 1);
+            s2 = w00 * chan(a00, 2) + w10 * chan(a10, 2) + w01 * chan(a01, 2) + w11 * chan(a11, 2);
+        };
+
+        // blend: softmax over the views of the upsampled logits
+        const float *B = p.blend_logit + li * hw * V;
+        float z = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        if constexpr (NV4 > 0) {
+            // all views' logits first (16-byte loads: V = 4 NV4 floats per
+            // tap, and each tap's row starts on a 16-byte boundary), then
+            // their maximum, then the views
+            constexpr int NV = 4 * NV4;
+            const float4 *B00 = reinterpret_cast<const float4 *>(B + t00 * NV);
+            const float4 *B10 = reinterpret_cast<const float4 *>(B + t10 * NV);
+            const float4 *B01 = reinterpret_cast<const float4 *>(B + t01 * NV);
+            const float4 *B11 = reinterpret_cast<const float4 *>(B + t11 * NV);
+            float xb[NV];
+#pragma unroll
+            for (int c = 0; c < NV4; ++c) {
+                const float4 a = B00[c], b = B10[c], d = B01[c], e = B11[c];
+                xb[4 * c + 0] = lerp_f(a.x, b.x, d.x, e.x);
+                xb[4 * c + 1] = lerp_f(a.y, b.y, d.y, e.y);
+                xb[4 * c + 2] = lerp_f(a.z, b.z, d.z, e.z);
+                xb[4 * c + 3] = lerp_f(a.w, b.w, d.w, e.w);
+            }
+            float mx = xb[0];
+#pragma unroll
+            for (int m = 1; m < NV; ++m) mx = fmaxf(mx, xb[m]);
+            // the views one after another (unrolled, the loop body's live
+            // values would take the register file; the index is uniform)
+#pragma unroll 1
+            for (int m = 0; m < NV; ++m) {
+                const float e = __expf(xb[m] - mx);
+                float s0, s1, s2;
+                sample_view(m, s0, s1, s2);
+                z += e;
+                c0 = fmaf(e, s0, c0);
+                c1 = fmaf(e, s1, c1);
+                c2 = fmaf(e, s2, c2);
+            }
+        } else {
+            // online: running maximum, sums rescaled when it moves
+            float mx = -3.0e38f;
+            for (int m = 0; m < V; ++m) {
+                const float xb = lerp_f(B[t00 * V + m], B[t10 * V + m], B[t01 * V + m], B[t11 * V + m]);
+                if (xb > mx) {                       // move the reference
+                    const float r = __expf(mx - xb);
+                    z *= r; c0 *= r; c1 *= r; c2 *= r;
+                    mx = xb;
+                }
+                const float e = __expf(xb - mx);
+                float s0, s1, s2;
+                sample_view(m, s0, s1, s2);
+                z += e;
+                c0 = fmaf(e, s0, c0);
+                c1 = fmaf(e, s1, c1);
+                c2 = fmaf(e, s2, c2);
+            }
         }
         const float k = Tr * alpha * (1.0f / 255.0f) / z;   // beta = e / z; texels v / 255
         out0 = fmaf(k, c0, out0);
@@ -161,7 +207,17 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
 
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s) {
     const int tiles = ((p.W + 15) / 16) * ((p.H + 15) / 16);
-    hipLaunchKernelGGL(k_render_ibr, dim3(tiles), dim3(256), 0, s, p);
+    const dim3 g(tiles), b(256);
+    // the vector path reads 16 bytes at a time: V a multiple of 4 and the
+    // logits 16-byte aligned (the C-ABI asks only for 4)
+    const bool vec = p.V % 4 == 0 && (reinterpret_cast<uintptr_t>(p.blend_logit) & 15) == 0;
+    switch (vec ? p.V / 4 : 0) {
+    case 1: hipLaunchKernelGGL(k_render_ibr<1>, g, b, 0, s, p); break;
+    case 2: hipLaunchKernelGGL(k_render_ibr<2>, g, b, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(k_render_ibr<3>, g, b, 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_render_ibr<4>, g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL(k_render_ibr<0>, g, b, 0, s, p); break;
+    }
     return hipGetLastError();
 }
 

@@ -81,6 +81,9 @@ CASES = {
     "wide-fov-behind": dict(V=6, W=64, H=36, s=2, L=3, arc=4.0, radius=1.5, hfov=140.0, seed=12),
     "images-larger-than-output": dict(V=3, W=40, H=24, s=4, L=3, img_hw=(96, 160), seed=13),
     "single-pixel-output": dict(V=2, W=1, H=1, L=2, lowres_hw=(1, 1), img_hw=(9, 7), seed=14),
+    # view counts that are multiples of 4 read the logits as 16-byte vectors
+    "V12": dict(V=12, W=44, H=26, s=2, L=2, seed=18),
+    "V8-s2": dict(V=8, W=50, H=30, s=2, L=3, seed=19),
 }
 
 
@@ -126,3 +129,23 @@ def test_render_is_deterministic_and_stream_ordered(ctx):
     b = _gpu_render(ctx, rs)
     for k in a:
         assert np.array_equal(a[k], b[k])
+
+
+def test_logits_aligned_to_4_bytes_only(ctx):
+    """Blend logits that are 4- but not 16-byte aligned (V = 8) take the
+    online-softmax path instead of the 16-byte loads and still match the
+    oracle."""
+    rs = synth.make_render(V=8, W=50, H=30, s=2, L=3, seed=20)
+    imgs, (dl, sl, bl) = _device(rs)
+    buf = torch.empty(bl.numel() + 1, device="cuda")
+    bl_off = buf[1:].view(bl.shape)
+    bl_off.copy_(bl)
+    assert bl_off.data_ptr() % 16 == 4
+    rgb = torch.full((rs.H, rs.W, 3), float("nan"), device="cuda")
+    acc = torch.full((rs.H, rs.W), float("nan"), device="cuda")
+    dep = torch.full((rs.H, rs.W), float("nan"), device="cuda")
+    lib.render_ibr(ctx, rs.in_cams, imgs, rs.novel, rs.near, rs.far, (dl, sl, bl_off), rgb,
+                   acc_out=acc, depth_out=dep)
+    torch.cuda.synchronize()
+    got = {"rgb": rgb.cpu().numpy(), "acc": acc.cpu().numpy(), "depth": dep.cpu().numpy()}
+    _compare("logits-4-byte-aligned", got, _oracle(rs))
