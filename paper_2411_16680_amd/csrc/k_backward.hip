@@ -389,7 +389,10 @@ k_uf_backward(const BwdParams p) {
         }
 
         // ---- pass 1 over the views: online softmax of a_m = q~ . s_m and
-        //      ob = sum_m p_m s_m
+        //      ob = sum_m p_m s_m.  The weights are exp(a_m - mx) for a
+        //      reference mx moved only when a logit passes it by more than 8
+        //      (always at the first view), as in the forward kernel; pass 2
+        //      uses the same reference.
         float mx = -1e30f, z = 0.f, ob[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) ob[c] = 0.f;
@@ -402,12 +405,19 @@ k_uf_backward(const BwdParams p) {
             float a = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) a = fmaf(qt[c], s[c], a);
-            const float mn = fmaxf(mx, a);
-            const float sc = __expf(mx - mn), pw = __expf(a - mn);
-            z = fmaf(z, sc, pw);
+            float diff = a - mx;
+            if (diff > 8.0f) {
+                const float r = __expf(-diff);
+                z *= r;
 #pragma unroll
-            for (int c = 0; c < C; ++c) ob[c] = fmaf(ob[c], sc, pw * s[c]);
-            mx = mn;
+                for (int c = 0; c < C; ++c) ob[c] *= r;
+                mx = a;
+                diff = 0.0f;
+            }
+            const float pw = __expf(diff);
+            z += pw;
+#pragma unroll
+            for (int c = 0; c < C; ++c) ob[c] = fmaf(pw, s[c], ob[c]);
         }
         const float iz = 1.0f / z;
 #pragma unroll

@@ -491,13 +491,16 @@ __device__ inline void lds_write4(float *dst, const float *f) {
     *reinterpret_cast<float4 *>(dst) = make_float4(f[0], f[1], f[2], f[3]);
 }
 
-// Register budget per instance: the waves per SIMD each form reaches
-// (float32 forms keep the compiler's default).  At four waves (128 VGPRs)
-// the C = 16 standard form parks three values in scratch outside the view
-// loop; the extra wave is worth more (levels 1-2: -7 %).
+// Register budget per instance: the waves per SIMD each form reaches.  At
+// four waves (128 VGPRs) the C = 16 standard form parks three values in
+// scratch outside the view loop; the extra wave is worth more (levels 1-2:
+// -7 %).  Float32: the one-to-many form at C <= 32 gets three waves (168
+// VGPRs; at C = 8 five values go to scratch, level 3 -10 %); the float32
+// standard form keeps the compiler's default (at three waves it would spill
+// dozens of values).
 template <int C, bool BF16, bool FOLD>
 struct Occupancy {
-    static constexpr int waves = !BF16 ? 1 : (C > 32) ? 2 : 4;
+    static constexpr int waves = !BF16 ? ((FOLD && C <= 32) ? 3 : 1) : (C > 32) ? 2 : 4;
 };
 
 // FOLD = false: standard cross-attention (per-sample key and value
@@ -539,7 +542,9 @@ __device__ __forceinline__ int xcd_tile(int i, int nt) {
 
 template <int C, bool BF16, bool FOLD, bool F8, int HD, int VAR>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((FOLD && HD != C) ? 2 : Occupancy<C, BF16, FOLD>::waves)))
+__attribute__((amdgpu_waves_per_eu((FOLD && HD != C) ? 2
+                                   : (!BF16 && VAR == kBlend) ? 1    // its extra stores spill at 3
+                                   : Occupancy<C, BF16, FOLD>::waves)))
 k_update_fuse(const UFArgs<VAR == kBatch> args) {
     constexpr bool BATCH = VAR == kBatch;
     static_assert(VAR != kBlend || HD == C, "blend-weight logits: one head");
