@@ -808,7 +808,7 @@ def main():
                          "960x540 V=4) and exit without timing")
     ap.add_argument("--profile-chain", action="store_true",
                     help="for rocprofv3: run --steps chains of the paper's five-step schedule "
-                         "(1080p inputs, V=8, bf16, one-to-many attention) and exit without "
+                         "(1080p inputs, V=8, bf16, attention per --attn) and exit without "
                          "timing")
     ap.add_argument("--profile-pipeline", action="store_true",
                     help="for rocprofv3: run --steps whole frames (ray encoding, init, five "
@@ -817,8 +817,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--attn", default=HEADLINE_ATTN, choices=["auto", "standard", "folded"],
-                    help="attention form of the --profile-run and --profile-pipeline frames "
-                         "(default: the headline's, per level the faster form)")
+                    help="attention form of the --profile-run, --profile-chain and "
+                         "--profile-pipeline runs (default: the headline's, per level or step "
+                         "the faster form)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3: run --steps frames of the bf16 form (the headline's "
                          "attention) and the other kernels, then a 512 MiB device copy (counter "
@@ -851,7 +852,7 @@ def main():
         ch = synth.make_chain()
         dc = runner.chain_to_device(ch)
         for s in range(args.steps):
-            runner.run_chain(ctx, ch, dc, attn_form="folded")
+            runner.run_chain(ctx, ch, dc, attn_form=args.attn)
             torch.cuda.synchronize()
         log(f"profile chains: {args.steps} done")
         return

@@ -207,6 +207,12 @@ __device__ inline typename CoordT<BF16>::type cam_entry(const UFParams &p, int m
     else return p.camd[m][k];
 }
 
+template <bool BF16>
+__device__ inline const typename CoordT<BF16>::type *cam_row(const UFParams &p, int m) {
+    if constexpr (BF16) return p.cam[m];
+    else return p.camd[m];
+}
+
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
 
@@ -302,30 +308,26 @@ __device__ inline void raw_unpack(const RawTap<BF16> &r, float *f) {
     }
 }
 
-// Back-projection of one layer-pixel into view m (the first half of the
-// bilinear sample): p = A_m (u, v, 1) + b_m / d; a point with p_z <= 1e-6
-// (behind the view) samples zero.  Computes this lane's four tap addresses
-// (half-pixel centres) and issues the loads of channels ch0 + 32 kc + [0, 8).
-// A tap outside the map has weight 0 and its load is unconditional, at the
-// out-of-range offset kTapOOB (it reads zeros).
+// Back-projection of one layer-pixel into one view (the first half of the
+// bilinear sample): p = A (u, v, 1) + b / d from the view's camera entries
+// cam[0..11]; a point with p_z <= 1e-6 (behind the view) samples zero.
+// Gives the four taps' byte offsets in the view's map, without the channel
+// part (half-pixel centres; a tap outside the map gets weight 0 and the
+// out-of-range offset kTapOOB, so its load reads zeros), and their weights.
+struct TapProj {
+    int o[4];
+    float w[4];
+};
+
 template <int C, bool BF16>
-__device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16>::type uc,
-                                  typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
-                                  bool a_ok, int ch0, Taps<C, BF16> &tp) {
+__device__ inline void project_view(const typename CoordT<BF16>::type *cam, int fw, int fh,
+                                    typename CoordT<BF16>::type uc, typename CoordT<BF16>::type vc,
+                                    typename CoordT<BF16>::type invdc, bool a_ok, TapProj &tp) {
     using Coord = typename CoordT<BF16>::type;
-    using T = typename Op<BF16>::T;
-    constexpr int KC = Shape<C>::KC;
-    const __amdgpu_buffer_rsrc_t fr = feat_rsrc<C, BF16>(p, m);
-    const int fh = p.fH[m], fw = p.fW[m];
-    const Coord pz = fma(cam_entry<BF16>(p, m, 6), uc,
-                         fma(cam_entry<BF16>(p, m, 7), vc,
-                             fma(cam_entry<BF16>(p, m, 11), invdc, cam_entry<BF16>(p, m, 8))));
-    const Coord qx = fma(cam_entry<BF16>(p, m, 0), uc,
-                         fma(cam_entry<BF16>(p, m, 1), vc,
-                             fma(cam_entry<BF16>(p, m, 9), invdc, cam_entry<BF16>(p, m, 2))));
-    const Coord qy = fma(cam_entry<BF16>(p, m, 3), uc,
-                         fma(cam_entry<BF16>(p, m, 4), vc,
-                             fma(cam_entry<BF16>(p, m, 10), invdc, cam_entry<BF16>(p, m, 5))));
+    constexpr int E = (int)sizeof(typename Op<BF16>::T);
+    const Coord pz = fma(cam[6], uc, fma(cam[7], vc, fma(cam[11], invdc, cam[8])));
+    const Coord qx = fma(cam[0], uc, fma(cam[1], vc, fma(cam[9], invdc, cam[2])));
+    const Coord qy = fma(cam[3], uc, fma(cam[4], vc, fma(cam[10], invdc, cam[5])));
     const Coord rz = recip(pz);
     const Coord fxc = qx * rz - (Coord)0.5, fyc = qy * rz - (Coord)0.5;
     const bool ok = a_ok && (pz > (Coord)1e-6) && (fxc > (Coord)-2) && (fxc < (Coord)(fw + 1)) &&
@@ -339,18 +341,54 @@ __device__ inline void issue_taps(const UFParams &p, int m, typename CoordT<BF16
     tp.w[1] = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
     tp.w[2] = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
     tp.w[3] = (vx1 && vy1) ? wx * wy : 0.0f;
-    constexpr int E = (int)sizeof(T);
-    const int o = ((iy * fw + ix) * C + ch0) * E;
-    const int o00 = (vx0 && vy0) ? o : kTapOOB;
-    const int o10 = (vx1 && vy0) ? o + C * E : kTapOOB;
-    const int o01 = (vx0 && vy1) ? o + fw * C * E : kTapOOB;
-    const int o11 = (vx1 && vy1) ? o + (fw + 1) * C * E : kTapOOB;
+    const int o = (iy * fw + ix) * C * E;
+    tp.o[0] = (vx0 && vy0) ? o : kTapOOB;
+    tp.o[1] = (vx1 && vy0) ? o + C * E : kTapOOB;
+    tp.o[2] = (vx0 && vy1) ? o + fw * C * E : kTapOOB;
+    tp.o[3] = (vx1 && vy1) ? o + (fw + 1) * C * E : kTapOOB;
+}
+
+// Projection groups (GR = 4, C >= 32): the four lanes that load one pixel's
+// taps (a quad) take the views four at a time: lane k of the quad projects
+// the pixel into view m0 + k, and view m0 + K reaches the whole quad from its
+// lane K by a DPP quad permutation -- one projection per lane for four views
+// instead of one per view.  GR = 1: each lane projects every view itself
+// (C = 16, two lanes per pixel, where pairs save less than the registers
+// they hold cost; and the bfloat16 one-to-many form at C = 64, measured
+// slower grouped at the same occupancy).  The results are identical.
+template <int GR, int K>
+__device__ inline int group_bcast(int v) {
+    static_assert(GR == 1 || GR == 4, "a pixel's load group is one lane or a quad");
+    if constexpr (GR == 1) return v;
+    else return __builtin_amdgcn_update_dpp(0, v, K * 0x55, 0xf, 0xf, true);
+}
+
+// Issues the loads of view m (lane K of the group projected it): channels
+// ch0 + 32 kc + [0, 8) of the four taps.
+template <int C, bool BF16, int GR, int K>
+__device__ inline void issue_group(const UFParams &p, int m, const TapProj &pr, int ch0,
+                                   Taps<C, BF16> &tp) {
+    constexpr int KC = Shape<C>::KC;
+    constexpr int E = (int)sizeof(typename Op<BF16>::T);
+    const __amdgpu_buffer_rsrc_t fr = feat_rsrc<C, BF16>(p, m);
+    int o[4];
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-        buf_load<BF16>(fr, o00 + 32 * kc * E, tp.t[kc][0]);
-        buf_load<BF16>(fr, o10 + 32 * kc * E, tp.t[kc][1]);
-        buf_load<BF16>(fr, o01 + 32 * kc * E, tp.t[kc][2]);
-        buf_load<BF16>(fr, o11 + 32 * kc * E, tp.t[kc][3]);
+    for (int j = 0; j < 4; ++j) {
+        o[j] = group_bcast<GR, K>(pr.o[j]) + ch0 * E;
+        tp.w[j] = __int_as_float(group_bcast<GR, K>(__float_as_int(pr.w[j])));
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) buf_load<BF16>(fr, o[j] + 32 * kc * E, tp.t[kc][j]);
+}
+
+// Calls f(integral_constant<int, K>) for K = B .. N - 1.
+template <int B, int N, typename F>
+__device__ inline void static_for(F &&f) {
+    if constexpr (B < N) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, N>(f);
     }
 }
 
@@ -408,7 +446,7 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
     const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
     const bool vx0 = (unsigned)ix < (unsigned)fw, vx1 = (unsigned)(ix + 1) < (unsigned)fw;
     const bool vy0 = (unsigned)iy < (unsigned)fh, vy1 = (unsigned)(iy + 1) < (unsigned)fh;
-    // byte offsets as in issue_taps (an out-of-map tap reads zeros at kTapOOB)
+    // byte offsets as in project_view (an out-of-map tap reads zeros at kTapOOB)
     constexpr int E = (int)sizeof(T);
     const int o = (iy * fw + ix) * C * E;
     int4 ow0, ow1;       // (byte offset, weight bits) of taps 00, 10 | 01, 11
@@ -432,14 +470,6 @@ __device__ inline void issue_tapk(const UFParams &p, int m, typename CoordT<BF16
         tp.w[j] = __int_as_float(e.y);
         buf_load<BF16>(fr, e.x, tp.t[j]);
     }
-}
-
-template <int C, bool BF16, typename TP>
-__device__ inline void issue_any(const UFParams &p, int m, typename CoordT<BF16>::type uc,
-                                 typename CoordT<BF16>::type vc, typename CoordT<BF16>::type invdc,
-                                 bool a_ok, int ch0, int r, int g, int2 *tT, TP &tp) {
-    if constexpr (Shape<C>::TAPK) issue_tapk<C, BF16>(p, m, uc, vc, invdc, a_ok, r, g, tT, tp);
-    else issue_taps<C, BF16>(p, m, uc, vc, invdc, a_ok, ch0, tp);
 }
 
 // Pair sums across lane rows (a row is 16 lanes): with both operands equal,
@@ -594,6 +624,12 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                   "tap exchange must fit the o tile it shares");
 
     __shared__ AF sfrag[FR::N][64];    // FP8 form: Q/K/V/O slots hold e4m3 codes in their first 8 B
+    // views per projection group (see group_bcast); with groups, camera
+    // entries and map sizes of every view in LDS (a lane projects into a
+    // view of its own)
+    constexpr int GR = (C == 32 || (C == 64 && !(BF16 && FOLD))) ? 4 : 1;
+    __shared__ Coord scam[GR > 1 ? kMaxViews * 12 : 1];
+    __shared__ int sfwh[GR > 1 ? kMaxViews * 2 : 1];
     __shared__ float sF[4][PIX * P];
     __shared__ float sO[4][PIX * P];   // o tile; for C = 8 also the tap exchange
 
@@ -663,6 +699,13 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
             }
         }
         sfrag[f][ln] = OP::make(vals);
+    }
+    if constexpr (GR > 1) {
+        for (int e = tid; e < p.V * 12; e += 256) scam[e] = cam_entry<BF16>(p, e / 12, e % 12);
+        for (int e = tid; e < p.V; e += 256) {
+            sfwh[2 * e] = p.fW[e];
+            sfwh[2 * e + 1] = p.fH[e];
+        }
     }
     __syncthreads();
 
@@ -793,6 +836,70 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
         const Coord invdc = recip((Coord)d);
         const float d_ld = TAPK ? d : (ld_ok ? p.depth_in[rowbase + x_ld] : 1.0f);
         const Coord invdc_ld = TAPK ? invdc : recip((Coord)d_ld);
+        // The view loop: two tap buffers in turn, so the loads of view m + 1
+        // are in flight while view m is processed, and no buffer is copied.
+        // The scheduling barriers keep the loads ahead of the arithmetic (left
+        // alone, the scheduler moves the next view's loads after this view's
+        // work, which serialises the views on memory latency).  The issues
+        // are unconditional (clamped view index; the extra loads at the end
+        // hit the cache) so the wait counts stay exact.
+        int2 *tT = reinterpret_cast<int2 *>(sO[wave]);   // C = 8 tap exchange
+        auto run_views = [&](auto &ta, auto &tb, auto &&view_step) {
+            if constexpr (TAPK) {
+                issue_tapk<C, BF16>(p, 0, uc_ld, vc, invdc_ld, ld_ok, n, g, tT, ta);
+                __builtin_amdgcn_sched_barrier(0);
+                for (int m = 0; m < p.V; m += 2) {
+                    issue_tapk<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, n, g, tT, tb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    view_step(ta, m);
+                    __builtin_amdgcn_sched_barrier(0);
+                    issue_tapk<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, n, g, tT, ta);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (m + 1 < p.V) view_step(tb, m + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                // views in groups of GR (see group_bcast); a group past the
+                // last view is not projected, and its clamped issue reads
+                // stale offsets through the last view's range-checked buffer
+                TapProj pr;
+                auto project = [&](int m0) {
+                    if constexpr (GR > 1) {
+                        const int mv = min(m0 + lane % GR, p.V - 1);
+                        project_view<C, BF16>(&scam[mv * 12], sfwh[2 * mv], sfwh[2 * mv + 1], uc_ld, vc,
+                                              invdc_ld, ld_ok, pr);
+                    } else {
+                        project_view<C, BF16>(cam_row<BF16>(p, m0), p.fW[m0], p.fH[m0], uc_ld, vc,
+                                              invdc_ld, ld_ok, pr);
+                    }
+                };
+                static_assert(GR == 1 || RL == GR, "a projection group is a pixel's load group");
+                constexpr int ST = (GR > 1) ? GR : 2;     // views per unrolled step
+                project(0);
+                issue_group<C, BF16, GR, 0>(p, 0, pr, ch_ld, ta);
+                __builtin_amdgcn_sched_barrier(0);
+                for (int m0 = 0; m0 < p.V; m0 += ST) {
+                    static_for<0, ST>([&](auto kk) {
+                        constexpr int k = decltype(kk)::value;
+                        auto &cur = (k % 2 == 0) ? ta : tb;
+                        auto &nxt = (k % 2 == 0) ? tb : ta;
+                        const int mn = min(m0 + k + 1, p.V - 1);
+                        if constexpr (GR == 1) {
+                            project(mn);
+                            issue_group<C, BF16, 1, 0>(p, mn, pr, ch_ld, nxt);
+                        } else if constexpr (k + 1 < GR) {
+                            issue_group<C, BF16, GR, k + 1>(p, mn, pr, ch_ld, nxt);
+                        } else {
+                            if (m0 + GR < p.V) project(m0 + GR);
+                            issue_group<C, BF16, GR, 0>(p, mn, pr, ch_ld, nxt);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (m0 + k < p.V) view_step(cur, m0 + k);
+                        __builtin_amdgcn_sched_barrier(0);
+                    });
+                }
+            }
+        };
         if constexpr (STDLOOP) {
             // ---- cross-attention over the views on MFMA: per-sample keys and
             // values (standard form) or, for C = 8 folded, the blended samples
@@ -806,7 +913,6 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
             for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
             using TapsT = typename std::conditional<TAPK, TapsK<BF16>, Taps<C, BF16>>::type;
-            int2 *tT = reinterpret_cast<int2 *>(sO[wave]);   // free until o is written
             // one view: blend -> keys -> logits -> online softmax -> values
             auto view_step = [&](const TapsT &cur, int m) {
                 // B operands: the blended sample (one per K chunk), or for C = 8
@@ -938,26 +1044,8 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                     for (int i = 0; i < 4; ++i) acc[t][i] = fmaf(pw[s], Vt[i], acc[t][i]);
                 }
             };
-            // Two tap buffers in turn: the loads of view m + 1 are in flight
-            // while view m is processed, and no buffer is copied.  The
-            // scheduling barriers keep the loads ahead of the arithmetic (left
-            // alone, the scheduler moves the next view's loads after this
-            // view's work, which serialises the views on memory latency).
             TapsT ta, tb;
-            issue_any<C, BF16>(p, 0, uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, ta);
-            __builtin_amdgcn_sched_barrier(0);
-            // The issues are unconditional (clamped view index; the extra loads
-            // at the end hit the cache) so the wait counts stay exact.
-            for (int m = 0; m < p.V; m += 2) {
-                issue_any<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, tb);
-                __builtin_amdgcn_sched_barrier(0);
-                view_step(ta, m);
-                __builtin_amdgcn_sched_barrier(0);
-                issue_any<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, n, g, tT, ta);
-                __builtin_amdgcn_sched_barrier(0);
-                if (m + 1 < p.V) view_step(tb, m + 1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            run_views(ta, tb, view_step);
 
             // o = acc / Z: result layout -> LDS -> operand layout
 #pragma unroll
@@ -1034,20 +1122,8 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                         for (int i = 0; i < 8; ++i) ob[hq][kc][i] = fmaf(pw, sv[kc][i], ob[hq][kc][i]);
                 }
             };
-            // two tap buffers in turn (see the standard loop)
             Taps<C, BF16> ta, tb;
-            issue_taps<C, BF16>(p, 0, uc_ld, vc, invdc_ld, ld_ok, ch_ld, ta);
-            __builtin_amdgcn_sched_barrier(0);
-            for (int m = 0; m < p.V; m += 2) {
-                issue_taps<C, BF16>(p, min(m + 1, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, tb);
-                __builtin_amdgcn_sched_barrier(0);
-                view_step(ta, m);
-                __builtin_amdgcn_sched_barrier(0);
-                issue_taps<C, BF16>(p, min(m + 2, p.V - 1), uc_ld, vc, invdc_ld, ld_ok, ch_ld, ta);
-                __builtin_amdgcn_sched_barrier(0);
-                if (m + 1 < p.V) view_step(tb, m + 1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            run_views(ta, tb, view_step);
 #pragma unroll
             for (int hq = 0; hq < HQ; ++hq) {
                 const float iz = recip(Zs[hq]);
