@@ -215,6 +215,10 @@ EDGE = [
     ("pad-views-C8-V5", dict(V=5, H=6, W=33, C=8, L=4)),
     ("pad-views-C16-V3", dict(V=3, H=6, W=19, C=16, L=2)),
     ("max-views-V16-C32", dict(V=16, H=4, W=40, C=32, L=2, arc=0.6)),
+    # C >= 32 projects the views four at a time: groups cut short at the end
+    ("view-groups-C32-V2", dict(V=2, H=3, W=29, C=32, L=2)),
+    ("view-groups-C32-V7", dict(V=7, H=4, W=35, C=32, L=3, arc=0.5)),
+    ("view-groups-C64-V6", dict(V=6, H=3, W=21, C=64, L=2, arc=0.5)),
     ("feature-grid-differs", dict(V=3, H=9, W=30, C=16, L=3, feat_hw=(5, 17))),
     ("wide-fov-many-invalid", dict(V=4, H=8, W=48, C=8, L=5, arc=1.2, radius=1.0, hfov=100.0)),
 ]
