@@ -354,8 +354,7 @@ __device__ inline void project_view(const typename CoordT<BF16>::type *cam, int 
 // lane K by a DPP quad permutation -- one projection per lane for four views
 // instead of one per view.  GR = 1: each lane projects every view itself
 // (C = 16, two lanes per pixel, where pairs save less than the registers
-// they hold cost; and the bfloat16 one-to-many form at C = 64, measured
-// slower grouped at the same occupancy).  The results are identical.
+// they hold cost).  The results are identical.
 template <int GR, int K>
 __device__ inline int group_bcast(int v) {
     static_assert(GR == 1 || GR == 4, "a pixel's load group is one lane or a quad");
@@ -524,13 +523,14 @@ __device__ inline void lds_write4(float *dst, const float *f) {
 // Register budget per instance: the waves per SIMD each form reaches.  At
 // four waves (128 VGPRs) the C = 16 standard form parks three values in
 // scratch outside the view loop; the extra wave is worth more (levels 1-2:
-// -7 %).  Float32: the one-to-many form at C <= 32 gets three waves (168
-// VGPRs; at C = 8 five values go to scratch, level 3 -10 %); the float32
-// standard form keeps the compiler's default (at three waves it would spill
-// dozens of values).
+// -7 %).  The bfloat16 one-to-many form at C = 64 is held to three waves
+// (168 VGPRs), which its LDS allows too.  Float32: the one-to-many form at
+// C <= 32 gets three waves (168 VGPRs; at C = 8 five values go to scratch,
+// level 3 -10 %); the float32 standard form keeps the compiler's default (at
+// three waves it would spill dozens of values).
 template <int C, bool BF16, bool FOLD>
 struct Occupancy {
-    static constexpr int waves = !BF16 ? ((FOLD && C <= 32) ? 3 : 1) : (C > 32) ? 2 : 4;
+    static constexpr int waves = !BF16 ? ((FOLD && C <= 32) ? 3 : 1) : (C > 32) ? (FOLD ? 3 : 2) : 4;
 };
 
 // FOLD = false: standard cross-attention (per-sample key and value
@@ -624,14 +624,29 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                   "tap exchange must fit the o tile it shares");
 
     __shared__ AF sfrag[FR::N][64];    // FP8 form: Q/K/V/O slots hold e4m3 codes in their first 8 B
-    // views per projection group (see group_bcast); with groups, camera
-    // entries and map sizes of every view in LDS (a lane projects into a
-    // view of its own)
-    constexpr int GR = (C == 32 || (C == 64 && !(BF16 && FOLD))) ? 4 : 1;
-    __shared__ Coord scam[GR > 1 ? kMaxViews * 12 : 1];
-    __shared__ int sfwh[GR > 1 ? kMaxViews * 2 : 1];
+    // views per projection group (see group_bcast); with groups, the camera
+    // entries and map sizes of every view sit in LDS (a lane projects into a
+    // view of its own), in a table of their own -- except in the bfloat16
+    // one-to-many form at C = 64, whose LDS allocation is at the limit of
+    // three workgroups per CU: there the table (12 floats and 2 ints per
+    // view) lives in the four pad floats that end every pixel row of the sF
+    // slices, which nothing else touches (a table of its own cost a
+    // workgroup per CU, and the pad reads cost registers elsewhere).
+    constexpr int GR = (C >= 32) ? 4 : 1;
+    constexpr bool PADTAB = GR > 1 && BF16 && FOLD && C == 64;
+    static_assert(!PADTAB || (P == C + 4 && 4 * PIX * 4 >= kMaxViews * 14),
+                  "the pad columns hold the camera table");
+    __shared__ Coord scam[(GR > 1 && !PADTAB) ? kMaxViews * 12 : 1];
+    __shared__ int sfwh[(GR > 1 && !PADTAB) ? kMaxViews * 2 : 1];
     __shared__ float sF[4][PIX * P];
     __shared__ float sO[4][PIX * P];   // o tile; for C = 8 also the tap exchange
+    // word w of the padded table: pad row w / 4 (rows run through the four
+    // slices), float w % 4; view m's entries are words 12 m .. 12 m + 11, its
+    // map width and height words 12 kMaxViews + 2 m and + 1
+    auto padw = [&](int w) -> float * {
+        const int r = w >> 2;
+        return &sF[r / PIX][(r % PIX) * P + C + (w & 3)];
+    };
 
     const int tid = threadIdx.x;
 
@@ -700,7 +715,13 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
         }
         sfrag[f][ln] = OP::make(vals);
     }
-    if constexpr (GR > 1) {
+    if constexpr (PADTAB) {
+        for (int e = tid; e < p.V * 12; e += 256) *padw(e) = p.cam[e / 12][e % 12];
+        for (int e = tid; e < p.V; e += 256) {
+            *padw(12 * kMaxViews + 2 * e) = __int_as_float(p.fW[e]);
+            *padw(12 * kMaxViews + 2 * e + 1) = __int_as_float(p.fH[e]);
+        }
+    } else if constexpr (GR > 1) {
         for (int e = tid; e < p.V * 12; e += 256) scam[e] = cam_entry<BF16>(p, e / 12, e % 12);
         for (int e = tid; e < p.V; e += 256) {
             sfwh[2 * e] = p.fW[e];
@@ -864,7 +885,19 @@ k_update_fuse(const UFArgs<VAR == kBatch> args) {
                 // stale offsets through the last view's range-checked buffer
                 TapProj pr;
                 auto project = [&](int m0) {
-                    if constexpr (GR > 1) {
+                    if constexpr (PADTAB) {
+                        const int mv = min(m0 + lane % GR, p.V - 1);
+                        float cam[12];
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            const float4 c4 = *reinterpret_cast<const float4 *>(padw(12 * mv + 4 * r));
+                            cam[4 * r] = c4.x; cam[4 * r + 1] = c4.y;
+                            cam[4 * r + 2] = c4.z; cam[4 * r + 3] = c4.w;
+                        }
+                        const float2 wh = *reinterpret_cast<const float2 *>(padw(12 * kMaxViews + 2 * mv));
+                        project_view<C, BF16>(cam, __float_as_int(wh.x), __float_as_int(wh.y), uc_ld, vc,
+                                              invdc_ld, ld_ok, pr);
+                    } else if constexpr (GR > 1) {
                         const int mv = min(m0 + lane % GR, p.V - 1);
                         project_view<C, BF16>(&scam[mv * 12], sfwh[2 * mv], sfwh[2 * mv + 1], uc_ld, vc,
                                               invdc_ld, ld_ok, pr);
