@@ -489,10 +489,10 @@ QK_API qk_status qk_render_ibr_check(int32_t V, const qk_camera *in_cams, const 
  *   views      host [V]: device rgb [Hm][Wm][3] float32 and acc [Hm][Wm]
  *              float32 or NULL, with the view's grid
  * Workspace, in the context (grown on demand like the others): up to 128
- * layers, one 32-byte record per layer-pixel-view whose footprint meets the
- * view (at most 8 V L H W floats) plus 3 counters per tile of 32 x th view
- * pixels (th = 16 for L <= 4, halved as L doubles); beyond, the projected
- * planes, sum over views of L Hm Wm 4 floats.
+ * layers, one 4-byte record (the layer-pixel's index) per layer-pixel-view
+ * whose footprint meets the view (at most V L H W words) plus 3 counters per
+ * tile of 32 x th view pixels (th = 16 for L <= 4, halved as L doubles);
+ * beyond, the projected planes, sum over views of L Hm Wm 4 floats.
  * Errors (nothing enqueued): QK_EINVAL (NULL or misaligned buffer, bad
  * camera), QK_ESHAPE (non-positive dims, V out of range), QK_EUNSUPPORTED
  * (an LDM or a workspace of 2^31 elements or more). */

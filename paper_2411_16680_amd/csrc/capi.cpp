@@ -1245,10 +1245,11 @@ qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
         p.tbase[V] = tiles;
         p.nbins = 4 * tiles;
         // count [nbins], start [nbins + 1, padded to nbins + 4], cursor
-        // [nbins], then the records (8 floats each); nbins is a multiple of
-        // 4, so every array starts on a 16-byte boundary
+        // [nbins], then the records (one 32-bit layer-pixel index each);
+        // nbins is a multiple of 4, so every array starts on a 16-byte
+        // boundary
         rec_off = (size_t)3 * p.nbins + 4;
-        ws_floats = rec_off + (size_t)8 * (size_t)nrec;
+        ws_floats = rec_off + (size_t)nrec;
     }
     st = grow(ctx, &ctx->vws, &ctx->vws_elems, ws_floats, stream);
     if (st != QK_OK) return st;
@@ -1257,7 +1258,7 @@ qk_status qk_render_to_views(qk_context *ctx, void *hip_stream, int32_t V,
         p.count = u;
         p.start = u + p.nbins;
         p.cursor = u + 2 * (size_t)p.nbins + 4;
-        p.rec = ctx->vws + rec_off;
+        p.rec = reinterpret_cast<int32_t *>(ctx->vws + rec_off);
     }
     int64_t base = 0, maxpix = 0;
     for (int m = 0; m < V; ++m) {

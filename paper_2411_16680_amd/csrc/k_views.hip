@@ -180,23 +180,35 @@ constexpr int kVbHash = 1 << kVbHashBits;       // LDS hash slots, > kVbChunk ke
 constexpr float kVbFix = 4294967296.0f;         // fixed-point scale of the tile sums, 2^32
 constexpr float kVbUnfix = 2.3283064365386963e-10f;   // 2^-32
 
+// 1 / x in double: the hardware reciprocal refined by one Newton step (its
+// relative error squares, far below what the coordinates need).  The binned
+// passes all reproject through it, so they agree bit for bit.
+__device__ inline double recip_d(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // The record of layer-pixel q in view m: its bin, or -1 when no tap lies in
-// the view.  The same reprojection as k_splat; a sample with fxc <= -1 or
-// fxc >= vW (likewise y) has no tap inside.
-__device__ inline int vbin_record(const ViewsParams &p, int m, int64_t q, float &fx, float &fy,
+// the view.  The reprojection of k_splat (reciprocals as above); a sample
+// with fxc <= -1 or fxc >= vW (likewise y) has no tap inside.  Every binned
+// pass calls it: the tile pass recomputes a record's footprint from the
+// layer-pixel index the write pass stored.
+// (The binned form runs only while V L H W < 2^31, so a layer-pixel index
+// and its divisions fit 32 bits.)
+__device__ inline int vbin_record(const ViewsParams &p, int m, int q, float &fx, float &fy,
                                   int &ix, int &iy, int &l) {
-    const int64_t hw = (int64_t)p.H * p.W;
-    l = (int)(q / hw);
-    const int64_t r = q - (int64_t)l * hw;
-    const int y = (int)(r / p.W), x = (int)(r - (int64_t)y * p.W);
+    const uint32_t hw = (uint32_t)p.H * (uint32_t)p.W, uq = (uint32_t)q;
+    l = (int)(uq / hw);
+    const uint32_t r = uq - (uint32_t)l * hw;
+    const int y = (int)(r / (uint32_t)p.W), x = (int)(r - (uint32_t)y * (uint32_t)p.W);
     const double u = (double)x + 0.5, v = (double)y + 0.5;
-    const double invd = 1.0 / (double)p.depth[q];
+    const double invd = recip_d((double)p.depth[q]);
     const double *A = p.cam[m];
     const int vw = p.vW[m], vh = p.vH[m];
     const double pz = fma(A[6], u, fma(A[7], v, fma(A[11], invd, A[8])));
     const double qx = fma(A[0], u, fma(A[1], v, fma(A[9], invd, A[2])));
     const double qy = fma(A[3], u, fma(A[4], v, fma(A[10], invd, A[5])));
-    const double rz = 1.0 / pz;
+    const double rz = recip_d(pz);
     const double fxc = qx * rz - 0.5, fyc = qy * rz - 0.5;
     if (!((pz > 1e-6) && (fxc > -1.0) && (fxc < (double)vw) && (fyc > -1.0) && (fyc < (double)vh)))
         return -1;
@@ -244,7 +256,7 @@ __global__ void __launch_bounds__(256) k_vbin_count(const ViewsParams p) {
         if (q >= p.N) break;
         float fx, fy;
         int ix, iy, l;
-        const int b = vbin_record(p, m, q, fx, fy, ix, iy, l);
+        const int b = vbin_record(p, m, (int)q, fx, fy, ix, iy, l);
         if (b >= 0) {
             const int sl = vbin_slot(hkey, b);
             if (sl >= 0) atomicAdd(&hcnt[sl], 1u);
@@ -311,22 +323,18 @@ __global__ void __launch_bounds__(256) k_vbin_write(const ViewsParams p) {
     const int64_t q0 = ((int64_t)blockIdx.x - (int64_t)m * cpv) * kVbChunk;
     int sl[kVbKpt], rb[kVbKpt];
     uint32_t rank[kVbKpt];
-    float rfx[kVbKpt], rfy[kVbKpt];
-    int rcorner[kVbKpt], rl[kVbKpt];
 #pragma unroll
     for (int k = 0; k < kVbKpt; ++k) {
         sl[k] = -1;
         rb[k] = 0;
         rank[k] = 0u;
-        rfx[k] = rfy[k] = 0.0f;
-        rcorner[k] = rl[k] = 0;
         const int64_t q = q0 + k * 256 + threadIdx.x;
         if (q >= p.N) continue;
-        int ix, iy;
-        const int b = vbin_record(p, m, q, rfx[k], rfy[k], ix, iy, rl[k]);
+        float fx, fy;
+        int ix, iy, l;
+        const int b = vbin_record(p, m, (int)q, fx, fy, ix, iy, l);
         if (b < 0) continue;
         rb[k] = b;
-        rcorner[k] = (ix + 1) | ((iy + 1) << 16);
         sl[k] = vbin_slot(hkey, b);
         if (sl[k] >= 0) rank[k] = atomicAdd(&hcnt[sl[k]], 1u);
     }
@@ -339,10 +347,7 @@ __global__ void __launch_bounds__(256) k_vbin_write(const ViewsParams p) {
         if (sl[k] < 0) continue;
         const uint32_t slot = hbase[sl[k]] + rank[k];
         if (slot >= p.start[rb[k] + 1]) continue;    // never taken: both passes bin alike
-        const int64_t q = q0 + k * 256 + threadIdx.x;
-        float4 *dst = reinterpret_cast<float4 *>(p.rec) + 2 * (int64_t)slot;
-        dst[0] = make_float4(rfx[k], rfy[k], __int_as_float(rcorner[k]), __int_as_float(rl[k]));
-        dst[1] = make_float4(p.color[q * 3 + 0], p.color[q * 3 + 1], p.color[q * 3 + 2], p.alpha[q]);
+        p.rec[slot] = (int)(q0 + k * 256 + threadIdx.x);
     }
 }
 
@@ -382,15 +387,19 @@ __global__ void __launch_bounds__(256) k_vbin_tile(const ViewsParams p) {
             }
         }
     }
-    const float4 *R = reinterpret_cast<const float4 *>(p.rec);
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         for (uint32_t i = rs[j] + threadIdx.x; i < re[j]; i += 256) {
-            const float4 h = R[2 * (int64_t)i], v = R[2 * (int64_t)i + 1];
-            const int corner = __float_as_int(h.z), l = __float_as_int(h.w);
-            if ((unsigned)l >= (unsigned)p.L) continue;    // only a record never written
-            const int ix = (corner & 0xffff) - 1, iy = ((corner >> 16) & 0xffff) - 1;
-            const float fx = h.x, fy = h.y;
+            // the record is the layer-pixel's index: its footprint is
+            // recomputed by the same function the binning passes ran (so it
+            // is the one they binned) and its payload read from the LDM
+            const int q = p.rec[i];
+            if ((unsigned)q >= (unsigned)p.N) continue;    // only a record never written
+            float fx, fy;
+            int ix, iy, l;
+            if (vbin_record(p, m, q, fx, fy, ix, iy, l) < 0) continue;   // not reached
+            const float4 v = make_float4(p.color[(int64_t)q * 3 + 0], p.color[(int64_t)q * 3 + 1],
+                                         p.color[(int64_t)q * 3 + 2], p.alpha[q]);
             const float w[4] = {(1.0f - fx) * (1.0f - fy), fx * (1.0f - fy), (1.0f - fx) * fy, fx * fy};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {

@@ -199,7 +199,7 @@ struct ViewsParams {
     uint32_t *count;                // [nbins] records per bin
     uint32_t *start;                // [nbins + 1] exclusive prefix sums of count
     uint32_t *cursor;               // [nbins] next free record of a bin
-    float *rec;                     // [V N][8]: fx, fy, corner, layer | r, g, b, alpha
+    int32_t *rec;                   // [V N]: the layer-pixel index of each record
 };
 
 }  // namespace qk

@@ -167,7 +167,7 @@ def test_workspace_cap():
     capped = lib.Context(0, workspace_bytes=1 << 20)
     small = synth.make_views(V=2, W=16, H=8, L=2, seed=26)
     _compare("capped-small", capped, small)
-    big = synth.make_views(V=2, W=96, H=64, L=4, seed=27)      # ~400 KB of records per view
+    big = synth.make_views(V=2, W=192, H=128, L=8, seed=27)    # ~0.8 MB of records per view
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     rgbs = [torch.full((h, w, 3), 7.0, device="cuda") for h, w in big.view_hw]
     with pytest.raises(lib.QuarkError) as e:
