@@ -214,7 +214,12 @@ __device__ inline const typename CoordT<BF16>::type *cam_row(const UFParams &p, 
 }
 
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double recip(double x) { return 1.0 / x; }
+// double: the hardware's reciprocal estimate refined by one Newton step (the
+// relative error squares, to about an ulp), instead of the IEEE division
+__device__ inline double recip(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 
 
 __device__ inline void lds_read8(const float *src, float *f) {
