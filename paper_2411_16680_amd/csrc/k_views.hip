@@ -387,30 +387,59 @@ __global__ void __launch_bounds__(256) k_vbin_tile(const ViewsParams p) {
             }
         }
     }
+    // the five ranges as one index space; a thread takes its records two
+    // at a time so both records' loads are in flight together (each record
+    // is a chain: its index, then the layer-pixel's depth and payload)
+    uint32_t cum[6];
+    cum[0] = 0u;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        for (uint32_t i = rs[j] + threadIdx.x; i < re[j]; i += 256) {
+    for (int j = 0; j < 5; ++j) cum[j + 1] = cum[j] + (re[j] - rs[j]);
+    const uint32_t total = cum[5];
+    constexpr int U = 2;
+    for (uint32_t k0 = threadIdx.x; k0 < total; k0 += 256u * U) {
+        int q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t k = k0 + 256u * u;
+            q[u] = -1;
+            if (k < total) {
+                int j = 0;
+#pragma unroll
+                for (int jj = 1; jj < 5; ++jj) j += (k >= cum[jj]) ? 1 : 0;
+                q[u] = p.rec[rs[j] + (k - cum[j])];
+            }
+        }
+        float fx[U], fy[U];
+        int ix[U], iy[U], l[U];
+        float4 v[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             // the record is the layer-pixel's index: its footprint is
             // recomputed by the same function the binning passes ran (so it
-            // is the one they binned) and its payload read from the LDM
-            const int q = p.rec[i];
-            if ((unsigned)q >= (unsigned)p.N) continue;    // only a record never written
-            float fx, fy;
-            int ix, iy, l;
-            if (vbin_record(p, m, q, fx, fy, ix, iy, l) < 0) continue;   // not reached
-            const float4 v = make_float4(p.color[(int64_t)q * 3 + 0], p.color[(int64_t)q * 3 + 1],
-                                         p.color[(int64_t)q * 3 + 2], p.alpha[q]);
-            const float w[4] = {(1.0f - fx) * (1.0f - fy), fx * (1.0f - fy), (1.0f - fx) * fy, fx * fy};
+            // is the one they binned) and its payload read from the LDM; an
+            // index out of range is only a record never written
+            ok[u] = (unsigned)q[u] < (unsigned)p.N;
+            const int qq = ok[u] ? q[u] : 0;
+            ok[u] = ok[u] && vbin_record(p, m, qq, fx[u], fy[u], ix[u], iy[u], l[u]) >= 0;
+            v[u] = make_float4(p.color[(int64_t)qq * 3 + 0], p.color[(int64_t)qq * 3 + 1],
+                               p.color[(int64_t)qq * 3 + 2], p.alpha[qq]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const float w[4] = {(1.0f - fx[u]) * (1.0f - fy[u]), fx[u] * (1.0f - fy[u]),
+                                (1.0f - fx[u]) * fy[u], fx[u] * fy[u]};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int x = ix + (k & 1), y = iy + (k >> 1);
+                const int x = ix[u] + (k & 1), y = iy[u] + (k >> 1);
                 const int lx = x - x0, ly = y - y0;
                 if (lx < 0 || lx >= tw || ly < 0 || ly >= th || x >= vw || y >= vh) continue;
-                unsigned long long *d = &tacc[4 * ((l * th + ly) * tw + lx)];
-                atomicAdd(d + 0, (unsigned long long)__float2ll_rn(w[k] * v.x * kVbFix));
-                atomicAdd(d + 1, (unsigned long long)__float2ll_rn(w[k] * v.y * kVbFix));
-                atomicAdd(d + 2, (unsigned long long)__float2ll_rn(w[k] * v.z * kVbFix));
-                atomicAdd(d + 3, (unsigned long long)__float2ll_rn(w[k] * v.w * kVbFix));
+                unsigned long long *d = &tacc[4 * ((l[u] * th + ly) * tw + lx)];
+                atomicAdd(d + 0, (unsigned long long)__float2ll_rn(w[k] * v[u].x * kVbFix));
+                atomicAdd(d + 1, (unsigned long long)__float2ll_rn(w[k] * v[u].y * kVbFix));
+                atomicAdd(d + 2, (unsigned long long)__float2ll_rn(w[k] * v[u].z * kVbFix));
+                atomicAdd(d + 3, (unsigned long long)__float2ll_rn(w[k] * v[u].w * kVbFix));
             }
         }
     }
