@@ -98,9 +98,14 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
         const float *S = p.sigma_logit + li * hw;
         const float alpha = sigmoid_(lerp_f(S[t00], S[t10], S[t01], S[t11]));
 
-        // one view's image, back-projected through this layer's depth and
-        // sampled bilinearly (texels 0..255)
-        auto sample_view = [&](int m, float &s0, float &s1, float &s2) {
+        // one view's image, back-projected through this layer's depth: the
+        // four texels' loads are issued here and blended later (blend_view),
+        // so the next view's loads are in flight while this one is blended
+        struct Tex {
+            unsigned a[4];
+            float w[4];
+        };
+        auto issue_view = [&](int m, Tex &t) {
             const double *A = p.cam[m];
             const double pz = fma(A[6], u, fma(A[7], v, fma(A[11], disp, A[8])));
             const double qx = fma(A[0], u, fma(A[1], v, fma(A[9], disp, A[2])));
@@ -118,19 +123,27 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
             const int ix = ok ? (int)xf : -4, iy = ok ? (int)yf : -4;
             const bool vx0 = (unsigned)ix < (unsigned)iw, vx1 = (unsigned)(ix + 1) < (unsigned)iw;
             const bool vy0 = (unsigned)iy < (unsigned)ih, vy1 = (unsigned)(iy + 1) < (unsigned)ih;
-            const float w00 = (vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f;
-            const float w10 = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
-            const float w01 = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
-            const float w11 = (vx1 && vy1) ? wx * wy : 0.0f;
+            t.w[0] = (vx0 && vy0) ? (1.0f - wx) * (1.0f - wy) : 0.0f;
+            t.w[1] = (vx1 && vy0) ? wx * (1.0f - wy) : 0.0f;
+            t.w[2] = (vx0 && vy1) ? (1.0f - wx) * wy : 0.0f;
+            t.w[3] = (vx1 && vy1) ? wx * wy : 0.0f;
             const __amdgpu_buffer_rsrc_t rs = image_rsrc(p, m);
             const int o = (iy * iw + ix) * 4;
-            const unsigned a00 = load_texel(rs, (vx0 && vy0) ? o : kTapOOB);
-            const unsigned a10 = load_texel(rs, (vx1 && vy0) ? o + 4 : kTapOOB);
-            const unsigned a01 = load_texel(rs, (vx0 && vy1) ? o + 4 * iw : kTapOOB);
-            const unsigned a11 = load_texel(rs, (vx1 && vy1) ? o + 4 * iw + 4 : kTapOOB);
-            s0 = w00 * chan(a00, 0) + w10 * chan(a10, 0) + w01 * chan(a01, 0) + w11 * chan(a11, 0);
-            s1 = w00 * chan(a00, 1) + w10 * chan(a10, 1) + w01 * chan(a01, 1) + w11 * chan(a11, 1);
-            s2 = w00 * chan(a00, 2) + w10 * chan(a10, 2) + w01 * chan(a01, 2) + w11 * chan(a11, 2);
+            t.a[0] = load_texel(rs, (vx0 && vy0) ? o : kTapOOB);
+            t.a[1] = load_texel(rs, (vx1 && vy0) ? o + 4 : kTapOOB);
+            t.a[2] = load_texel(rs, (vx0 && vy1) ? o + 4 * iw : kTapOOB);
+            t.a[3] = load_texel(rs, (vx1 && vy1) ? o + 4 * iw + 4 : kTapOOB);
+        };
+        // the bilinear sample of an issued view (texels 0..255)
+        auto blend_view = [&](const Tex &t, float &s0, float &s1, float &s2) {
+            s0 = t.w[0] * chan(t.a[0], 0) + t.w[1] * chan(t.a[1], 0) + t.w[2] * chan(t.a[2], 0) + t.w[3] * chan(t.a[3], 0);
+            s1 = t.w[0] * chan(t.a[0], 1) + t.w[1] * chan(t.a[1], 1) + t.w[2] * chan(t.a[2], 1) + t.w[3] * chan(t.a[3], 1);
+            s2 = t.w[0] * chan(t.a[0], 2) + t.w[1] * chan(t.a[1], 2) + t.w[2] * chan(t.a[2], 2) + t.w[3] * chan(t.a[3], 2);
+        };
+        auto sample_view = [&](int m, float &s0, float &s1, float &s2) {
+            Tex t;
+            issue_view(m, t);
+            blend_view(t, s0, s1, s2);
         };
 
         // blend: softmax over the views of the upsampled logits
@@ -157,17 +170,29 @@ __global__ void __launch_bounds__(256) k_render_ibr(const RenderParams p) {
             float mx = xb[0];
 #pragma unroll
             for (int m = 1; m < NV; ++m) mx = fmaxf(mx, xb[m]);
-            // the views one after another (unrolled, the loop body's live
-            // values would take the register file; the index is uniform)
+            // the views two at a time, two texel buffers in turn: the loads
+            // of the next view are issued before this one is blended (not
+            // unrolled further: the loop body's live values would take the
+            // register file; the index is uniform)
+            Tex ta, tb;
+            issue_view(0, ta);
 #pragma unroll 1
-            for (int m = 0; m < NV; ++m) {
-                const float e = __expf(xb[m] - mx);
+            for (int m = 0; m < NV; m += 2) {
                 float s0, s1, s2;
-                sample_view(m, s0, s1, s2);
-                z += e;
-                c0 = fmaf(e, s0, c0);
-                c1 = fmaf(e, s1, c1);
-                c2 = fmaf(e, s2, c2);
+                issue_view(m + 1, tb);               // NV is even
+                const float e0 = __expf(xb[m] - mx);
+                blend_view(ta, s0, s1, s2);
+                z += e0;
+                c0 = fmaf(e0, s0, c0);
+                c1 = fmaf(e0, s1, c1);
+                c2 = fmaf(e0, s2, c2);
+                if (m + 2 < NV) issue_view(m + 2, ta);
+                const float e1 = __expf(xb[m + 1] - mx);
+                blend_view(tb, s0, s1, s2);
+                z += e1;
+                c0 = fmaf(e1, s0, c0);
+                c1 = fmaf(e1, s1, c1);
+                c2 = fmaf(e1, s2, c2);
             }
         } else {
             // online: running maximum, sums rescaled when it moves
