@@ -840,6 +840,11 @@ def main():
         sys.exit(1)
     lib.load()
     ctx = lib.Context(0)
+    # the weights are the model's and do not change between frames: the
+    # context keeps what it derives from them (the one-to-many form's folded
+    # weights, which the paper computes once ahead of rendering; the residual
+    # block's fragments), made on the untimed first calls
+    ctx.weights_static(True)
 
     if args.profile_run:
         profile_run(ctx, args.steps, args.depth_mode, args.attn)

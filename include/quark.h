@@ -160,7 +160,7 @@ typedef struct qk_context qk_context;
  * folded weights of the one-to-many form (2 C C_feat floats per request),
  * the e4m3 scales (8 floats), the backward pass's scratch (16 bytes per
  * layer-pixel when d_rgb is given, plus 5 KiB per backward workgroup), the
- * render to input views' records (32 bytes per layer-pixel-view) or
+ * render to input views' records (4 bytes per layer-pixel-view) or
  * projected planes, the low-resolution ray encodings, the residual block's
  * weight fragments and the batched launch's parameter table.  Growing one
  * synchronises the caller's stream and allocates.  `workspace_bytes` caps
@@ -172,6 +172,24 @@ typedef struct qk_context qk_context;
  * workspaces.  Errors: QK_EINVAL (out == NULL, no such device), QK_EHIP. */
 QK_API qk_status qk_context_create(int device, size_t workspace_bytes, qk_context **out);
 QK_API qk_status qk_context_destroy(qk_context *ctx);
+
+/* Declare the float32 weight masters the calls pass as static (enable != 0)
+ * or not (0, the default).  Sec. 3.3 folds the key projection into the
+ * query and the value projection into the output once, ahead of rendering;
+ * while the weights are static the context likewise keeps the low-precision
+ * copies it derives from masters -- the one-to-many form's folded weights
+ * (qk_update_fuse, qk_batch_update_fuse) and the residual block's bfloat16
+ * fragments (qk_residual_conv) -- keyed by the masters' device pointers
+ * (and, for the folded weights, C, C_feat, heads, head_dim), and reuses them
+ * on later calls instead of deriving them again on each.  A copy is made on
+ * first use (it allocates, counts against the workspace cap and
+ * synchronises that call's stream, so every later call on any stream reads
+ * a complete copy); a context keeps at most 64, and derives the rest per
+ * call.  The caller must not change static masters in place: to change
+ * them, call this again (either value), which synchronises the device and
+ * drops every kept copy.  qk_update_fuse_noalloc always derives per call.
+ * Errors: QK_EINVAL (ctx == NULL), QK_EHIP. */
+QK_API qk_status qk_context_weights_static(qk_context *ctx, int enable);
 
 /* One Update & Fuse step of one LDM level (Sec. 3.2.2 "Iterative Updates",
  * Sec. 3.3 fusion block).  For every layer l, pixel p and view m: reproject

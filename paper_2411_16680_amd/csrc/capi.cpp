@@ -27,7 +27,7 @@ hipError_t launch_update_fuse_backward(const BwdParams &p, hipStream_t s);
 hipError_t launch_ldm_init(const InitParams &p, bool bf16, hipStream_t s);
 hipError_t launch_render_ibr(const RenderParams &p, hipStream_t s);
 hipError_t launch_render_to_views(const ViewsParams &p, hipStream_t s);
-hipError_t launch_residual_conv(const ConvParams &p, int num_cu, hipStream_t s);
+hipError_t launch_residual_conv(const ConvParams &p, int num_cu, bool frag_ready, hipStream_t s);
 hipError_t launch_layer_collapse(const CollapseParams &p, int num_cu, hipStream_t s);
 hipError_t launch_ray_encoding(const RayParams &p, hipStream_t s);
 hipError_t launch_upsample2x(const Up2Params &p, hipStream_t s);
@@ -59,6 +59,17 @@ struct qk_context {
     size_t bhost_bytes = 0;
     hipEvent_t bevent = nullptr; // recorded after the staging copy
     bool bevent_live = false;
+    // low-precision copies derived from float32 masters, kept while the
+    // caller declares its weights static (qk_context_weights_static)
+    struct Derived {
+        int kind;                    // kDerivedFold or kDerivedConv
+        const void *key[4];          // the masters' device pointers
+        int32_t dims[4];
+        float *buf;
+        size_t elems;
+    };
+    bool weights_static = false;
+    std::vector<Derived> derived;
 };
 
 namespace {
@@ -387,6 +398,94 @@ qk_status grow(qk_context *ctx, float **buf, size_t *have, size_t need, hipStrea
     return QK_OK;
 }
 
+// Derived weights (qk_context_weights_static): the folded attention weights
+// of the one-to-many form and the residual block's bfloat16 fragments.
+constexpr int kDerivedFold = 0, kDerivedConv = 1;
+constexpr size_t kDerivedMax = 64;     // entries a context keeps; beyond, derived per call
+
+// The cached copy for these masters, or NULL.
+float *derived_find(qk_context *ctx, int kind, const void *const key[4], const int32_t dims[4]) {
+    for (const auto &d : ctx->derived)
+        if (d.kind == kind && std::equal(d.key, d.key + 4, key) && std::equal(d.dims, d.dims + 4, dims))
+            return d.buf;
+    return nullptr;
+}
+
+// A new entry of `elems` floats, counted against the workspace cap; *out is
+// NULL (and the status QK_OK) when the context keeps no more entries.
+qk_status derived_add(qk_context *ctx, int kind, const void *const key[4], const int32_t dims[4],
+                      size_t elems, float **out) {
+    *out = nullptr;
+    if (ctx->derived.size() >= kDerivedMax) return QK_OK;
+    const size_t total = ctx->ws_bytes + elems * sizeof(float);
+    if (ctx->ws_cap != 0 && total > ctx->ws_cap)
+        return fail(QK_ENOMEM, "workspace of %zu bytes in all would pass the context's cap of %zu",
+                    total, ctx->ws_cap);
+    float *buf = nullptr;
+    if (hipMalloc(&buf, elems * sizeof(float)) != hipSuccess)
+        return fail(QK_ENOMEM, "derived weights of %zu floats", elems);
+    qk_context::Derived d;
+    d.kind = kind;
+    std::copy(key, key + 4, d.key);
+    std::copy(dims, dims + 4, d.dims);
+    d.buf = buf;
+    d.elems = elems;
+    ctx->derived.push_back(d);
+    ctx->ws_bytes += elems * sizeof(float);
+    *out = buf;
+    return QK_OK;
+}
+
+// Frees every cached copy; the device is synchronised first (enqueued work
+// may still read them).
+qk_status derived_clear(qk_context *ctx) {
+    if (ctx->derived.empty()) return QK_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(QK_EHIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+    for (const auto &d : ctx->derived) {
+        (void)hipFree(d.buf);
+        ctx->ws_bytes -= d.elems * sizeof(float);
+    }
+    ctx->derived.clear();
+    return QK_OK;
+}
+
+// The folded weights W_qk, W_vo of w: from the cache when the context's
+// weights are static (derived on first use, the stream then synchronised
+// so every later call, on any stream, reads a complete copy), else into
+// `dst` (2 per floats) on the caller's stream.
+qk_status fold_weights(qk_context *ctx, const qk_weights *w, float *dst, hipStream_t stream,
+                       float **wqk, float **wvo) {
+    const size_t per = (size_t)w->heads * w->C * w->C_feat;
+    float *wf = nullptr;
+    bool fresh = true;
+    if (ctx->weights_static) {
+        const void *key[4] = {w->Wq, w->Wk, w->Wv, w->Wo};
+        const int32_t dims[4] = {w->C, w->C_feat, w->heads, w->head_dim};
+        wf = derived_find(ctx, kDerivedFold, key, dims);
+        fresh = wf == nullptr;
+        if (fresh) {
+            qk_status st = derived_add(ctx, kDerivedFold, key, dims, 2 * per, &wf);
+            if (st != QK_OK) return st;
+        }
+    }
+    const bool cached = wf != nullptr;
+    if (!cached) wf = dst;
+    if (fresh) {
+        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per, w->C, w->C_feat,
+                          w->head_dim, w->heads, 1.0f / std::sqrt((float)w->head_dim)};
+        hipError_t fe = qk::launch_fold_weights(fp, stream);
+        if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
+        if (cached) {
+            fe = hipStreamSynchronize(stream);
+            if (fe != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(fe));
+        }
+    }
+    *wqk = wf;
+    *wvo = wf + per;
+    return QK_OK;
+}
+
 qk_status check_render(int32_t V, const qk_camera *in_cams, const qk_image *images,
                        const qk_camera *novel, float near_, float far_, const qk_ldm_logits *lg,
                        int32_t H, int32_t W, const float *rgb_out, const float *acc_out,
@@ -630,9 +729,10 @@ qk_status qk_context_create(int device, size_t workspace_bytes, qk_context **out
 
 qk_status qk_context_destroy(qk_context *ctx) {
     if (ctx && (ctx->wfold || ctx->bws || ctx->f8 || ctx->vws || ctx->cfrag || ctx->rws ||
-                ctx->bdesc || ctx->bhost || ctx->bevent)) {
+                ctx->bdesc || ctx->bhost || ctx->bevent || !ctx->derived.empty())) {
         int cur = -1;
         if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
+        (void)derived_clear(ctx);
         if (ctx->wfold) (void)hipFree(ctx->wfold);
         if (ctx->bws) (void)hipFree(ctx->bws);
         if (ctx->f8) (void)hipFree(ctx->f8);
@@ -646,6 +746,19 @@ qk_status qk_context_destroy(qk_context *ctx) {
         if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
     }
     delete ctx;
+    return QK_OK;
+}
+
+qk_status qk_context_weights_static(qk_context *ctx, int enable) {
+    if (!ctx) return fail(QK_EINVAL, "context is NULL");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(QK_EHIP, "hipGetDevice failed");
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+        return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    qk_status st = derived_clear(ctx);
+    if (cur != ctx->device) (void)hipSetDevice(cur);
+    if (st != QK_OK) return st;
+    ctx->weights_static = enable != 0;
     return QK_OK;
 }
 
@@ -770,24 +883,28 @@ qk_status update_fuse_impl(qk_context *ctx, void *hip_stream, int32_t V, const q
         // caller's stream, into the context's workspace
         const size_t per = (size_t)w->heads * w->C * w->C_feat;     // per folded matrix set
         const size_t need = 2 * per;
-        float *wf = ctx->wfold;
         if (fixed != nullptr) {
+            // the allocation-free entry point derives them every call
             if (need > (size_t)qk::kScratchFold)
                 return fail(QK_EUNSUPPORTED, "folded weights of %zu floats exceed the fixed scratch "
                             "of %d", need, qk::kScratchFold);
-            wf = fixed;
+            qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, fixed, fixed + per,
+                              w->C, w->C_feat, w->head_dim, w->heads,
+                              1.0f / std::sqrt((float)w->head_dim)};
+            hipError_t fe = qk::launch_fold_weights(fp, stream);
+            if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
+            p.Wqk = fp.Wqk;
+            p.Wvo = fp.Wvo;
         } else {
+            // the per-call workspace (also the fallback of a full cache)
             st = grow(ctx, &ctx->wfold, &ctx->wfold_elems, need, stream);
             if (st != QK_OK) return st;
-            wf = ctx->wfold;
+            float *wqk = nullptr, *wvo = nullptr;
+            st = fold_weights(ctx, w, ctx->wfold, stream, &wqk, &wvo);
+            if (st != QK_OK) return st;
+            p.Wqk = wqk;
+            p.Wvo = wvo;
         }
-        qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per,
-                          w->C, w->C_feat, w->head_dim, w->heads,
-                          1.0f / std::sqrt((float)w->head_dim)};
-        hipError_t fe = qk::launch_fold_weights(fp, stream);
-        if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
-        p.Wqk = fp.Wqk;
-        p.Wvo = fp.Wvo;
     }
     if (precision == QK_PREC_BF16_FP8PROJ) {
         float *f8 = fixed != nullptr ? fixed + qk::kScratchFold : nullptr;
@@ -919,14 +1036,11 @@ qk_status qk_batch_update_fuse(qk_context *ctx, void *hip_stream, int32_t n_req,
         st = grow(ctx, &ctx->wfold, &ctx->wfold_elems, 2 * per * (size_t)n_req, stream);
         if (st != QK_OK) return st;
         for (int r = 0; r < n_req; ++r) {
-            const qk_weights *w = reqs[r].weights;
-            float *wf = ctx->wfold + 2 * per * (size_t)r;
-            qk::FoldParams fp{w->Wq, w->Wk, w->Wv, w->Wo, wf, wf + per, w->C, w->C_feat,
-                              w->head_dim, w->heads, 1.0f / std::sqrt((float)w->head_dim)};
-            hipError_t fe = qk::launch_fold_weights(fp, stream);
-            if (fe != hipSuccess) return fail(QK_EHIP, "fold launch: %s", hipGetErrorString(fe));
-            ps[r].Wqk = fp.Wqk;
-            ps[r].Wvo = fp.Wvo;
+            float *wqk = nullptr, *wvo = nullptr;
+            st = fold_weights(ctx, reqs[r].weights, ctx->wfold + 2 * per * (size_t)r, stream, &wqk, &wvo);
+            if (st != QK_OK) return st;
+            ps[r].Wqk = wqk;
+            ps[r].Wvo = wvo;
         }
     }
     // the requests' parameters to the device: pinned staging, reused once
@@ -1303,20 +1417,43 @@ qk_status qk_residual_conv(qk_context *ctx, void *hip_stream, const qk_ldm *in, 
     if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
         return fail(QK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    st = grow(ctx, &ctx->cfrag, &ctx->cfrag_elems, 2 * 9 * 2 * 64 * 4, stream);
-    if (st != QK_OK) return st;
+    constexpr size_t kFragFloats = 2 * 9 * 2 * 64 * 4;
+    // the kernels' bfloat16 fragments: cached while the weights are static
+    // (derived on first use, the stream then synchronised), else per call
+    float *frag = nullptr;
+    bool fresh = true;
+    if (ctx->weights_static) {
+        const void *key[4] = {W1, W2, nullptr, nullptr};
+        const int32_t dims[4] = {0, 0, 0, 0};
+        frag = derived_find(ctx, kDerivedConv, key, dims);
+        fresh = frag == nullptr;
+        if (fresh) {
+            st = derived_add(ctx, kDerivedConv, key, dims, kFragFloats, &frag);
+            if (st != QK_OK) return st;
+        }
+    }
+    const bool cached = frag != nullptr;
+    if (!cached) {
+        st = grow(ctx, &ctx->cfrag, &ctx->cfrag_elems, kFragFloats, stream);
+        if (st != QK_OK) return st;
+        frag = ctx->cfrag;
+    }
     qk::ConvParams p;
     std::memset(&p, 0, sizeof(p));
     p.F = static_cast<const uint16_t *>(in->F);
     p.F_out = static_cast<uint16_t *>(out->F);
     p.W1 = W1;
     p.W2 = W2;
-    p.frag = reinterpret_cast<uint4 *>(ctx->cfrag);
+    p.frag = reinterpret_cast<uint4 *>(frag);
     p.L = in->L;
     p.H = in->H;
     p.W = in->W;
-    hipError_t e = qk::launch_residual_conv(p, ctx->num_cu, stream);
+    hipError_t e = qk::launch_residual_conv(p, ctx->num_cu, !fresh, stream);
     if (e != hipSuccess) return fail(QK_EHIP, "residual block launch: %s", hipGetErrorString(e));
+    if (cached && fresh) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(QK_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
     return QK_OK;
 }
 

@@ -213,14 +213,17 @@ __global__ void __launch_bounds__(256) k_residual_conv(const ConvParams p) {
 
 }  // namespace
 
-hipError_t launch_residual_conv(const ConvParams &pin, int num_cu, hipStream_t s) {
+hipError_t launch_residual_conv(const ConvParams &pin, int num_cu, bool frag_ready, hipStream_t s) {
     ConvParams p = pin;
     p.tiles_x = (p.W + TX - 1) / TX;
     p.tiles_y = (p.H + TY - 1) / TY;
     p.n_tiles = (int64_t)p.L * p.tiles_x * p.tiles_y;
-    hipLaunchKernelGGL(k_conv_frag, dim3((NFRAG + 255) / 256), dim3(256), 0, s, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (!frag_ready) {                           // else p.frag already holds them
+        hipLaunchKernelGGL(k_conv_frag, dim3((NFRAG + 255) / 256), dim3(256), 0, s, p);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     int64_t blocks = 2 * (int64_t)(num_cu > 0 ? num_cu : 256);
     if (blocks > p.n_tiles) blocks = p.n_tiles;
     hipLaunchKernelGGL(k_residual_conv, dim3((unsigned)blocks), dim3(256), 0, s, p);

@@ -26,7 +26,7 @@ ATTN = {"standard": 0, "folded": 1}
 MODE = {"residual": 0, "paper": 1}
 
 # symbols include/quark.h declares (checked by the CPU tests)
-EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_update_fuse", "qk_update_fuse_check",
+EXPORTS = ["qk_context_create", "qk_context_destroy", "qk_context_weights_static", "qk_update_fuse", "qk_update_fuse_check",
            "qk_update_fuse_noalloc", "qk_batch_update_fuse", "qk_batch_update_fuse_check",
            "qk_update_fuse_backward", "qk_update_fuse_backward_check", "qk_ldm_init",
            "qk_composite", "qk_composite_backward", "qk_composite_backward_check",
@@ -124,6 +124,7 @@ def load() -> ctypes.CDLL:
     P = ctypes.POINTER
     L.qk_context_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(ctypes.c_void_p)]
     L.qk_context_destroy.argtypes = [ctypes.c_void_p]
+    L.qk_context_weights_static.argtypes = [ctypes.c_void_p, ctypes.c_int]
     uf_args = [ctypes.c_int32, P(qk_camera), P(qk_feature_map), P(qk_camera), ctypes.c_float,
                ctypes.c_float, P(qk_weights), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                P(qk_ldm), P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -178,7 +179,7 @@ def load() -> ctypes.CDLL:
     lg_args = [P(qk_ldm), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.qk_ldm_decode_logits.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + lg_args
     L.qk_ldm_decode_logits_check.argtypes = lg_args
-    for name in ("qk_context_create", "qk_context_destroy", "qk_update_fuse",
+    for name in ("qk_context_create", "qk_context_destroy", "qk_context_weights_static", "qk_update_fuse",
                  "qk_update_fuse_noalloc", "qk_batch_update_fuse", "qk_batch_update_fuse_check", "qk_update_fuse_check", "qk_update_fuse_backward",
                  "qk_update_fuse_backward_check", "qk_ldm_init", "qk_composite",
                  "qk_composite_backward", "qk_composite_backward_check", "qk_render_ibr",
@@ -276,6 +277,12 @@ class Context:
         _check(self._lib.qk_context_create(int(device), int(workspace_bytes), ctypes.byref(h)))
         self.handle = h
         self.device = device
+
+    def weights_static(self, enable: bool = True):
+        """Declare the weight masters static (qk_context_weights_static): the
+        context keeps the copies it derives from them; calling it again
+        drops them (after a device synchronisation)."""
+        _check(self._lib.qk_context_weights_static(self.handle, 1 if enable else 0))
 
     def close(self):
         if self.handle:

@@ -283,6 +283,8 @@ class GpuExecutor(Executor):
         dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
         self.ctxs = [lib.Context(device) for _ in range(n_streams)]
+        for c in self.ctxs:                # the network's weights do not change while serving
+            c.weights_static(True)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
         self.w = [{k: t(v) for k, v in wl.items()} for wl in model.weights]
         self.cw = [None if c is None else tuple(t(a) for a in c) for c in model.collapse_w]

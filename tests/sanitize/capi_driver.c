@@ -194,6 +194,7 @@ int main(void) {
     qk_status st = qk_context_create(0, 0, &ctx);
     if (st == QK_OK) qk_context_destroy(ctx);
     expect("context (NULL out)", qk_context_create(0, 0, NULL), QK_EINVAL);
+    expect("weights static (NULL context)", qk_context_weights_static(NULL, 1), QK_EINVAL);
     printf("%s: %d failures (%s)\n", qk_version(), fails, st == QK_OK ? "a device" : "no device");
     return fails ? 1 : 0;
 }

@@ -28,7 +28,7 @@ hipError_t launch_render_ibr(const RenderParams &, hipStream_t) { return hipErro
 hipError_t launch_render_to_views(const ViewsParams &, hipStream_t) {
     return hipErrorInvalidValue;
 }
-hipError_t launch_residual_conv(const ConvParams &, int, hipStream_t) {
+hipError_t launch_residual_conv(const ConvParams &, int, bool, hipStream_t) {
     return hipErrorInvalidValue;
 }
 hipError_t launch_layer_collapse(const CollapseParams &, int, hipStream_t) {
